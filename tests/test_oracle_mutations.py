@@ -1,0 +1,53 @@
+"""Plant plausible mistakes in a temporary copy of the oracle and check that the
+pins catch every one (each mutated copy must fail tests/test_oracle_pins.py)."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = {
+    "drop_f_coupling": ("right = -f[m, q] * composite(S, dpm, dpq)",
+                        "right = 0.0 * composite(S, dpm, dpq)"),
+    "sign_of_f_coupling": ("left = -f[p, m] * composite(S, dpq, dmq)",
+                           "left = f[p, m] * composite(S, dpq, dmq)"),
+    "trace_instead_of_frobenius": ("E += float(np.sum(Tbar * (2.0 * Kpq + L)))",
+                                   "E += float(np.trace(Tbar @ (2.0 * Kpq + L)))"),
+    "swapped_pair_not_transposed": ("return T[(b, a)].T[np.ix_(perm, perm)]",
+                                    "return T[(b, a)][np.ix_(perm, perm)]"),
+    "composite_K_operands_swapped": ("return Up @ pb.K(p, q) @ Uq.T",
+                                     "return Uq @ pb.K(q, p) @ Up.T"),
+    "fock_block_scaled": ("self._F[(p, q)] = self.Q[p].T @ (self.eps[:, None] * self.Q[q])",
+                          "self._F[(p, q)] = 1.0001 * (self.Q[p].T @ (self.eps[:, None] * self.Q[q]))"),
+    "tbar_sign": ("Tbar = 2.0 * Tpq - Tpq.T\n                Kpq", "Tbar = 2.0 * Tpq + Tpq.T\n                Kpq"),
+    "wrong_2b_coefficient": ("+ [1.0 - n3_ij[p] for p in pairs]", "+ [1.0 - n3_i[p[0]] for p in pairs]"),
+    "density_GF_transpose": ("GF = Tpq.T @ Sd @ Tbar + Tbar @ Sd @ Tpq.T",
+                             "GF = Tpq.T @ Sd @ Tbar + Tbar @ Sd @ Tpq"),
+    "dF_second_sum_dropped": ("                    acc -= float(np.sum(Tbar * M))\n                dF",
+                              "                    acc -= 0.0\n                dF"),
+    "denominator_sign": ("self.f[p, p] - self.f[q, q]", "self.f[p, p] + self.f[q, q]"),
+    "dC_missing_transpose": ("dC[q] += G.T @ pb.C[p]", "dC[q] += 0.5 * (G + G.T) @ pb.C[p] if G.shape[0] == G.shape[1] else G.T @ pb.C[p]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    a, b = MUTATIONS[name]
+    src = open(os.path.join(ROOT, "oracle", "osv_oracle.py")).read()
+    assert a in src, f"mutation anchor for {name} not found"
+    for sub in ("oracle", "paper_2106_06149_amd", "tests"):
+        os.makedirs(tmp_path / sub)
+    open(tmp_path / "oracle" / "__init__.py", "w").close()
+    open(tmp_path / "oracle" / "osv_oracle.py", "w").write(src.replace(a, b, 1))
+    open(tmp_path / "paper_2106_06149_amd" / "__init__.py", "w").close()
+    shutil.copy(os.path.join(ROOT, "paper_2106_06149_amd", "synth.py"), tmp_path / "paper_2106_06149_amd")
+    shutil.copy(os.path.join(ROOT, "tests", "test_oracle_pins.py"), tmp_path / "tests")
+    shutil.copy(os.path.join(ROOT, "tests", "conftest.py"), tmp_path / "tests")
+    shutil.copytree(os.path.join(ROOT, "tests", "golden"), tmp_path / "tests" / "golden")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        str(tmp_path / "tests" / "test_oracle_pins.py")],
+                       cwd=str(tmp_path), capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutation {name} was not caught:\n{r.stdout[-2000:]}"
