@@ -1,0 +1,213 @@
+/*
+ * osv.h -- C ABI of libosvmbe: the per-cluster hot path of MBE(3)-OSV-MP2 on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Liang & Yang, "Third-order many-body expansion of OSV-MP2
+ * wavefunction for low-order scaling analytical gradient computation"
+ * (arXiv 2106.06149).  The library computes, for every selected 1-, 2- and
+ * 3-LMO cluster, the OSV pair amplitudes that solve the residual equations
+ * (eq:rij), the Hylleraas cluster energies (eq:ec), their many-body
+ * inclusion-exclusion (eq:mbe1; equivalent to the cluster amplitude
+ * expansions eq:tmbediag/eq:tmbeoff), and the exact first derivatives of the
+ * MBE energy with respect to the OSV-projected fitted integrals C_i, the
+ * occupied Fock matrix and the virtual orbital energies (the occupied and
+ * virtual density contributions of eq:do/eq:dv and the C-space analogue of
+ * eq:ec2eY), by Hylleraas stationarity.
+ *
+ * General conventions
+ *   - All functions return OSV_OK (0) or a negative status; nothing throws
+ *     across the ABI.  osv_last_error(ctx) returns a message for the last
+ *     failed call on that context (or on no context, for NULL).
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory.
+ *   - Work is enqueued on the caller's HIP stream (NULL = default stream).
+ *     Calls that return host values synchronise that stream before returning.
+ *   - Indices are 0-based.  Matrices are dense with the layout stated.
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef OSV_H
+#define OSV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  OSV_OK = 0,
+  OSV_E_ARG = -1,            /* bad size, NULL pointer, r_i out of range, unknown enum  */
+  OSV_E_HIP = -2,            /* HIP runtime error (message has the HIP error string)     */
+  OSV_E_NOMEM = -3,          /* device or host allocation failed                         */
+  OSV_E_NOT_CONVERGED = -4,  /* solve hit max_sweeps; info and amplitudes remain valid   */
+  OSV_E_NONFINITE = -5,      /* NaN/Inf in an input or in the residual                   */
+  OSV_E_STATE = -6,          /* energy/densities requested before a converged solve      */
+  OSV_E_DOMAIN = -7          /* a pair domain has rank 0 after the tau_S cut             */
+};
+
+/* arithmetic of the fitted-integral contraction K_ij = C_i C_j^T */
+enum {
+  OSV_FP64 = 0,   /* every step in FP64 (FP64 MFMA)                                      */
+  OSV_MIXED = 1   /* K_ij from C split into bfloat16 terms on bf16 MFMA with FP32        */
+                  /* accumulation of short k-chunks summed in FP64; FP64 elsewhere       */
+};
+
+/* cluster selection */
+enum {
+  OSV_SEL_DISTANCE = 0,  /* 2b: |x_i-x_j| <= cut2; 3b: all three distances <= cut3      */
+  OSV_SEL_OVERLAP = 1,   /* 2b: s2b_ij > l2b (eq:2bscreen); 3b: mean s2b > l3b (eq:3bscreen) */
+  OSV_SEL_FULL = 2       /* one cluster holding every LMO: plain OSV-MP2, no MBE          */
+};
+
+/* C dtype */
+enum { OSV_DT_F64 = 0, OSV_DT_F32 = 1 };
+
+typedef struct osv_ctx osv_ctx;  /* opaque; owns all internal device memory */
+
+/*
+ * The OSV-MP2 problem (statement of eq:rij, eq:ec and eq:osv).
+ *   nocc, nvir, naux   numbers of LMOs, canonical virtuals, fitting functions.
+ *   r        host  [nocc]   OSVs per LMO, 1 <= r_i; r_i + r_j <= OSV_MAX_DOMAIN for
+ *                           every selected pair (r_i <= OSV_MAX_DOMAIN for r_i alone).
+ *   Q        device nvir x sum(r), column-major (ld = nvir): block i = columns
+ *                           off_i .. off_i + r_i - 1 with off_i = sum_{k<i} r_k,
+ *                           orthonormal columns (Q_i^T Q_i = 1, eq:svd).
+ *   C        device sum(r) x naux, row-major (ld = naux): rows off_i.. hold
+ *                           C_i = Q_i^T B_i, the OSV-projected fitted integrals.
+ *   C_dtype  OSV_DT_F64 or OSV_DT_F32.
+ *   eps_vir  device [nvir]  canonical virtual orbital energies f_aa.
+ *   F_occ    device nocc x nocc row-major, symmetric; diagonal = f_ii.
+ *   centroid host  nocc x 3 (bohr); read by OSV_SEL_DISTANCE only, may be NULL otherwise.
+ * The library reads Q, C, eps_vir and F_occ in osv_build_pairs and again in
+ * osv_solve_clusters and osv_densities: they are borrowed, not copied, and must
+ * stay allocated and unchanged until osv_destroy (or the next build).
+ */
+typedef struct {
+  int32_t nocc, nvir, naux;
+  const int32_t *r;
+  const double *Q;
+  const void *C;
+  int32_t C_dtype;
+  const double *eps_vir;
+  const double *F_occ;
+  const double *centroid;
+} osv_system;
+
+/* Cluster selection (MBE(3) partitioning; screening eq:2bscreen/eq:3bscreen). */
+typedef struct {
+  int32_t mode;      /* OSV_SEL_*                                                   */
+  double cut2, cut3; /* bohr, inclusive, DISTANCE mode                              */
+  double l2b, l3b;   /* OVERLAP mode thresholds (paper defaults 1e-2 and 0.2)       */
+  double tau_S;      /* pair-domain overlap eigenvalues <= tau_S are dropped (1e-8) */
+} osv_select;
+
+typedef struct {
+  int64_t n1b, n2b, n3b;     /* selected clusters per order (FULL: n1b = n2b = n3b = 0) */
+  int64_t n_clusters;        /* all clusters (FULL: 1)                                  */
+  int64_t n_pair_blocks;     /* sum over clusters of its unordered LMO pairs incl. i=i  */
+  int64_t n_domains;         /* distinct orbital pairs (i <= j) with a pair domain      */
+  int64_t n_couplings;       /* distinct domain pairs coupled by eq:rij                 */
+} osv_counts;
+
+typedef struct {
+  int32_t sweeps;            /* largest number of Jacobi sweeps of any cluster          */
+  double max_residual;       /* largest final max_pairs ||W^T R W||_F of any cluster    */
+  int32_t converged;         /* 1 if every cluster met tau_R                             */
+  int64_t n_not_converged;   /* clusters that hit max_sweeps                             */
+} osv_solve_info;
+
+#define OSV_MAX_DOMAIN 100   /* largest pair-domain dimension r_i + r_j supported */
+
+/*
+ * osv_build_pairs -- Algorithm 1, pair tasks: select clusters, compute the
+ * orbital-pair blocks S_(i,j) = Q_i^T Q_j, F_(i,j) = Q_i^T diag(eps) Q_j and
+ * K_ij = C_i C_j^T for every orbital pair that shares a cluster, and prepare
+ * each pair domain [Q_i Q_j] (eq:aijkl): canonical orthogonalisation (tau_S),
+ * pseudo-canonical basis, K in that basis, and the domain-to-domain couplings
+ * that eq:rij needs.
+ *   sys, sel   problem and selection (see above); precision = OSV_FP64 / OSV_MIXED.
+ *   stream     HIP stream for all work.
+ *   out        host: receives a new context (NULL on failure).  Free with osv_destroy.
+ * Errors: OSV_E_ARG, OSV_E_NONFINITE (NaN/Inf in Q, C, eps_vir or F_occ),
+ * OSV_E_DOMAIN, OSV_E_NOMEM, OSV_E_HIP.  Synchronises the stream.
+ */
+int osv_build_pairs(const osv_system *sys, const osv_select *sel, int32_t precision,
+                    hipStream_t stream, osv_ctx **out);
+
+/* osv_query -- counts of the built context (host out).  OSV_E_ARG on NULL. */
+int osv_query(const osv_ctx *ctx, osv_counts *out);
+
+/*
+ * osv_solve_clusters -- solve eq:rij for every cluster (k restricted to the
+ * cluster's LMOs) by Jacobi sweeps preconditioned in each domain's
+ * pseudo-canonical basis, starting from T = 0.  A cluster stops when the
+ * largest ||W^T R W||_F over its pairs is below tau_R; its amplitudes are those
+ * at which that residual was evaluated.  Also evaluates each cluster's
+ * Hylleraas energy (eq:ec) and the inner products that dE/dF_occ needs.
+ *   tau_R       convergence threshold (e.g. 1e-10); max_sweeps >= 1.
+ *   info        host, may be NULL.
+ * Errors: OSV_E_ARG, OSV_E_NOT_CONVERGED (info filled, results usable but not
+ * converged), OSV_E_NONFINITE (residual not finite), OSV_E_HIP.  Synchronises.
+ */
+int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream_t stream,
+                       osv_solve_info *info);
+
+/*
+ * osv_energy -- MBE(3) inclusion-exclusion of the cluster energies (eq:mbe1):
+ *   E = sum_X c_X E^X with c_X = 1 (3b), 1 - n3(IJ) (2b), 1 - n2(I) + n3(I) (1b).
+ *   E         host, required.
+ *   E_orders  host [3] or NULL: E_1b, dE_2b, dE_3b (NaN for OSV_SEL_FULL).
+ *   E_cluster device [n_clusters] or NULL: E^X in canonical cluster order
+ *             (all 1b ascending, 2b lexicographic, 3b lexicographic).
+ * Errors: OSV_E_STATE before a successful solve, OSV_E_ARG, OSV_E_HIP.  Synchronises.
+ */
+int osv_energy(osv_ctx *ctx, hipStream_t stream, double *E, double *E_orders, double *E_cluster);
+
+/*
+ * osv_densities -- exact derivatives of the MBE energy at fixed Q (Hylleraas
+ * stationarity: the amplitudes contribute nothing):
+ *   dE_dC     device sum(r) x naux row-major FP64: dE/dC_i = sum_j (G_ij + G_ji^T) C_j
+ *             with G_ij = sum_X c_X U_i^T (2 Tbar_ij) U_j   (cf. eq:ec2eY).
+ *   dE_dFocc  device nocc x nocc row-major: dE/df_uv, every entry taken as an
+ *             independent variable (the result is symmetric; cf. eq:do).
+ *   dE_deps   device [nvir]: dE/deps_a = diag of the virtual density (cf. eq:dv).
+ *   Dvir_full device nvir x nvir row-major or NULL: sum_uv Q_u G^F_uv Q_v^T.
+ * Any of the first three may be NULL to skip it.  Outputs are overwritten.
+ * Errors: OSV_E_STATE before a successful solve, OSV_E_ARG, OSV_E_HIP.
+ */
+int osv_densities(osv_ctx *ctx, hipStream_t stream, double *dE_dC, double *dE_dFocc,
+                  double *dE_deps, double *Dvir_full);
+
+/*
+ * osv_plan_clusters -- host-only cluster selection for OSV_SEL_DISTANCE and
+ * OSV_SEL_FULL (no device work; usable without a GPU).
+ *   nocc, centroid (host nocc x 3), sel: as above.
+ *   counts     host out (n_couplings included).
+ *   lmos       host out or NULL: 3 int32 per cluster (unused slots -1), canonical order;
+ *              capacity cap clusters (OSV_E_ARG if too small).  FULL writes nothing here.
+ *   coef       host out or NULL: MBE coefficient c_X per cluster (capacity cap).
+ */
+int osv_plan_clusters(int32_t nocc, const double *centroid, const osv_select *sel,
+                      osv_counts *counts, int32_t *lmos, double *coef, int64_t cap);
+
+/* osv_destroy -- free a context and its device memory; NULL is a no-op. */
+void osv_destroy(osv_ctx *ctx);
+
+/* message of a status code (static string) */
+const char *osv_status_string(int status);
+
+/* last error message recorded on ctx (or the library-wide one for NULL); never NULL */
+const char *osv_last_error(const osv_ctx *ctx);
+
+/* stage timings of the last build/solve/energy/densities on ctx, milliseconds
+ * (HIP events on the caller's stream); host out [8]:
+ *   0 S/F blocks, 1 K blocks, 2 domain prep, 3 couplings, 4 solve, 5 energy,
+ *   6 adjoint (per domain), 7 back-transforms.  Values of stages not run are 0. */
+int osv_stage_times(const osv_ctx *ctx, double *ms8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OSV_H */

@@ -1,0 +1,148 @@
+"""Python face of libosvmbe: device tensors in, results out.  PyTorch provides
+device memory and the HIP stream; every computation runs in the library."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Selection:
+    def __init__(self, mode=L.OSV_SEL_DISTANCE, cut2=15.0, cut3=8.0, l2b=1e-2, l3b=0.2,
+                 tau_S=1e-8):
+        self.mode, self.cut2, self.cut3, self.l2b, self.l3b, self.tau_S = mode, cut2, cut3, l2b, l3b, tau_S
+
+    def c(self):
+        return L.OsvSelect(self.mode, self.cut2, self.cut3, self.l2b, self.l3b, self.tau_S)
+
+
+def plan_clusters(centroid: np.ndarray, sel: Selection):
+    """Host-only cluster selection (no GPU): counts, LMO triples (-1 padded), c_X."""
+    lib = L.load()
+    cen = np.ascontiguousarray(centroid, dtype=np.float64)
+    nocc = cen.shape[0]
+    counts = L.OsvCounts()
+    s = sel.c()
+    L.check(lib.osv_plan_clusters(nocc, cen.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
+                                  ctypes.byref(counts), None, None, 0))
+    n = counts.n_clusters
+    lmos = np.empty((n, 3), dtype=np.int32)
+    coef = np.empty(n, dtype=np.float64)
+    L.check(lib.osv_plan_clusters(nocc, cen.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
+                                  ctypes.byref(counts), lmos.ctypes.data_as(ctypes.c_void_p),
+                                  coef.ctypes.data_as(ctypes.c_void_p), n))
+    return counts.as_dict(), lmos, coef
+
+
+class OSVContext:
+    """One built problem.  The input tensors are borrowed by the library and kept
+    alive here until close()."""
+
+    def __init__(self, Q: torch.Tensor, C: torch.Tensor, eps_vir: torch.Tensor,
+                 F_occ: torch.Tensor, r, centroid=None, sel: Selection = None,
+                 precision: int = L.OSV_FP64):
+        self.lib = L.load()
+        self.device = Q.device
+        sel = sel or Selection()
+        self.r = np.ascontiguousarray(np.asarray(r), dtype=np.int32)
+        self.cen = None if centroid is None else np.ascontiguousarray(centroid, dtype=np.float64)
+        # Q is nvir x sum(r) column-major: we hold its transpose as a contiguous tensor
+        self.Q, self.C, self.eps, self.F = Q, C, eps_vir, F_occ
+        for name, t in (("Q", Q), ("C", C), ("eps_vir", eps_vir), ("F_occ", F_occ)):
+            if not t.is_cuda:
+                raise ValueError(f"{name} must be a device tensor")
+        if C.dtype not in (torch.float32, torch.float64):
+            raise ValueError("C must be float32 or float64")
+        nvir = eps_vir.shape[0]
+        self.nocc, self.nvir, self.naux = len(self.r), nvir, C.shape[1]
+        self.nosv = int(self.r.sum())
+        sysc = L.OsvSystem(self.nocc, nvir, self.naux,
+                           self.r.ctypes.data_as(ctypes.c_void_p), Q.data_ptr(), C.data_ptr(),
+                           L.OSV_DT_F32 if C.dtype == torch.float32 else L.OSV_DT_F64,
+                           eps_vir.data_ptr(), F_occ.data_ptr(),
+                           None if self.cen is None else self.cen.ctypes.data_as(ctypes.c_void_p))
+        self.sel = sel
+        s = sel.c()
+        h = ctypes.c_void_p()
+        self.handle = None
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_build_pairs(ctypes.byref(sysc), ctypes.byref(s), precision,
+                                             _stream(self.device), ctypes.byref(h)))
+        self.handle = h
+        self.precision = precision
+        c = L.OsvCounts()
+        L.check(self.lib.osv_query(self.handle, ctypes.byref(c)), self.handle)
+        self.counts = c.as_dict()
+
+    @classmethod
+    def from_system(cls, s, device="cuda", precision=None, sel: Selection = None):
+        """Copy a synth.System to the device and build it."""
+        dev = torch.device(device)
+        Qt = torch.from_numpy(np.ascontiguousarray(s.Q.T)).to(dev)   # sum(r) x nvir row-major = Q col-major
+        C = torch.from_numpy(np.ascontiguousarray(s.C)).to(dev)
+        eps = torch.from_numpy(np.ascontiguousarray(s.eps_vir)).to(dev)
+        F = torch.from_numpy(np.ascontiguousarray(s.F_occ)).to(dev)
+        prec = s.precision if precision is None else precision
+        sel = sel or Selection(s.sel_mode, s.cut2, s.cut3)
+        return cls(Qt, C, eps, F, s.r, s.centroid, sel, prec)
+
+    def solve(self, tau_R=1e-10, max_sweeps=60, raise_on_error=True):
+        info = L.OsvSolveInfo()
+        with torch.cuda.device(self.device):
+            st = self.lib.osv_solve_clusters(self.handle, tau_R, max_sweeps, _stream(self.device),
+                                             ctypes.byref(info))
+        if raise_on_error:
+            L.check(st, self.handle)
+        return dict(status=st, sweeps=info.sweeps, max_residual=info.max_residual,
+                    converged=bool(info.converged), n_not_converged=info.n_not_converged)
+
+    def energy(self, per_cluster=False):
+        E = ctypes.c_double()
+        orders = (ctypes.c_double * 3)()
+        Ecl = None
+        if per_cluster:
+            Ecl = torch.empty(self.counts["n_clusters"], dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_energy(self.handle, _stream(self.device), ctypes.byref(E), orders,
+                                        _ptr(Ecl)), self.handle)
+        return E.value, np.array(orders[:]), Ecl
+
+    def densities(self, dC=True, dF=True, deps=True, dvir=False):
+        f64 = dict(dtype=torch.float64, device=self.device)
+        out_C = torch.empty(self.nosv, self.naux, **f64) if dC else None
+        out_F = torch.empty(self.nocc, self.nocc, **f64) if dF else None
+        out_e = torch.empty(self.nvir, **f64) if deps else None
+        out_D = torch.empty(self.nvir, self.nvir, **f64) if dvir else None
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_densities(self.handle, _stream(self.device), _ptr(out_C),
+                                           _ptr(out_F), _ptr(out_e), _ptr(out_D)), self.handle)
+        return out_C, out_F, out_e, out_D
+
+    def stage_times(self):
+        ms = (ctypes.c_double * 8)()
+        L.check(self.lib.osv_stage_times(self.handle, ms), self.handle)
+        names = ["sf", "k", "prep", "couplings", "solve", "energy", "adjoint", "backtransform"]
+        return dict(zip(names, ms[:]))
+
+    def close(self):
+        if self.handle is not None:
+            self.lib.osv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

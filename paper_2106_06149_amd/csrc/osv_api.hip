@@ -1,0 +1,908 @@
+// Host side of libosvmbe: argument checks, cluster selection and MBE
+// coefficients, the pair/domain/coupling/term structure that drives the
+// kernels, device memory, stage orchestration and the C ABI of osv.h.
+#include "osv.h"
+#include "osv_internal.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace osv;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+struct Selection {
+  std::vector<int> lmo_ptr, lmo;  // LMOs of each cluster (ascending)
+  std::vector<double> coef;       // c_X
+  std::vector<int> order;         // 1, 2, 3 (0 for the single full cluster)
+  std::vector<int> n2, n3i;       // per LMO: selected pairs / triples holding it
+  std::vector<int> n3ij;          // per selected pair (in 2b order): triples holding it
+  int64_t n1 = 0, n2b = 0, n3b = 0;
+};
+
+// MBE(3) selection (downward closed) and inclusion-exclusion coefficients:
+// c = 1 (3b), 1 - n3(IJ) (2b), 1 - n2(I) + n3(I) (1b).  keep2/keep3 decide.
+template <class K2, class K3>
+void select_mbe(int nocc, K2 keep2, K3 keep3, Selection &s) {
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<std::vector<int>> nbr(nocc);
+  std::vector<char> sel((size_t)nocc * nocc, 0);
+  for (int i = 0; i < nocc; i++)
+    for (int j = i + 1; j < nocc; j++)
+      if (keep2(i, j)) {
+        pairs.push_back({i, j});
+        nbr[i].push_back(j);
+        sel[(size_t)i * nocc + j] = 1;
+      }
+  std::vector<std::array<int, 3>> triples;
+  for (int i = 0; i < nocc; i++)
+    for (int j : nbr[i])
+      for (int k : nbr[j])
+        if (sel[(size_t)i * nocc + k] && keep3(i, j, k)) triples.push_back({i, j, k});
+  // nbr lists are ascending, so triples come out lexicographic
+  s.n2.assign(nocc, 0);
+  s.n3i.assign(nocc, 0);
+  std::unordered_map<long long, int> pidx;
+  for (size_t t = 0; t < pairs.size(); t++) {
+    s.n2[pairs[t].first]++;
+    s.n2[pairs[t].second]++;
+    pidx[(long long)pairs[t].first * nocc + pairs[t].second] = (int)t;
+  }
+  s.n3ij.assign(pairs.size(), 0);
+  for (auto &t : triples) {
+    for (int a = 0; a < 3; a++) s.n3i[t[a]]++;
+    s.n3ij[pidx[(long long)t[0] * nocc + t[1]]]++;
+    s.n3ij[pidx[(long long)t[0] * nocc + t[2]]]++;
+    s.n3ij[pidx[(long long)t[1] * nocc + t[2]]]++;
+  }
+  s.lmo_ptr.assign(1, 0);
+  s.lmo.clear();
+  s.coef.clear();
+  s.order.clear();
+  for (int i = 0; i < nocc; i++) {
+    s.lmo.push_back(i);
+    s.lmo_ptr.push_back((int)s.lmo.size());
+    s.coef.push_back(1.0 - s.n2[i] + s.n3i[i]);
+    s.order.push_back(1);
+  }
+  for (size_t t = 0; t < pairs.size(); t++) {
+    s.lmo.push_back(pairs[t].first);
+    s.lmo.push_back(pairs[t].second);
+    s.lmo_ptr.push_back((int)s.lmo.size());
+    s.coef.push_back(1.0 - s.n3ij[t]);
+    s.order.push_back(2);
+  }
+  for (auto &t : triples) {
+    for (int a = 0; a < 3; a++) s.lmo.push_back(t[a]);
+    s.lmo_ptr.push_back((int)s.lmo.size());
+    s.coef.push_back(1.0);
+    s.order.push_back(3);
+  }
+  s.n1 = nocc;
+  s.n2b = (int64_t)pairs.size();
+  s.n3b = (int64_t)triples.size();
+}
+
+void select_full(int nocc, Selection &s) {
+  s.lmo_ptr = {0, nocc};
+  s.lmo.resize(nocc);
+  std::iota(s.lmo.begin(), s.lmo.end(), 0);
+  s.coef = {1.0};
+  s.order = {0};
+  s.n1 = s.n2b = s.n3b = 0;
+}
+
+double dist(const double *c, int i, int j) {
+  double dx = c[3 * i] - c[3 * j], dy = c[3 * i + 1] - c[3 * j + 1], dz = c[3 * i + 2] - c[3 * j + 2];
+  return std::sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+void select_distance(int nocc, const double *cen, double cut2, double cut3, Selection &s) {
+  select_mbe(
+      nocc, [&](int i, int j) { return dist(cen, i, j) <= cut2; },
+      [&](int i, int j, int k) {
+        return dist(cen, i, j) <= cut3 && dist(cen, i, k) <= cut3 && dist(cen, j, k) <= cut3;
+      },
+      s);
+}
+
+// Structure derived from a selection: domains, couplings, cluster pairs, terms.
+struct Plan {
+  std::vector<Domain> doms;
+  std::vector<int> dom_of;  // nocc*nocc -> domain id (p <= q) or -1
+  std::vector<Coupling> cpls;
+  std::vector<CPair> cps;
+  std::vector<Term> terms;
+  std::vector<Cluster> cls;
+  std::vector<int> queue;
+  long long n_slot = 0;   // sum n^2 over domains
+  long long n_vec = 0;    // sum n over domains
+  long long n_T = 0;      // amplitude doubles
+  long long n_M = 0;      // coupling doubles
+  long long rs_stride = 0;
+  long long n_pl = 0;     // dE/dF inner-product doubles
+  int64_t n_pair_blocks = 0;
+};
+
+// Builds the plan.  r/off may be null (counts only, domain sizes unknown).
+int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan &P,
+               std::string &err) {
+  P.dom_of.assign((size_t)nocc * nocc, -1);
+  const int ncl = (int)s.coef.size();
+  auto rr = [&](int i) { return r ? r[i] : 1; };
+  // domains in (p, q) lexicographic order
+  std::vector<char> need((size_t)nocc * nocc, 0);
+  for (int X = 0; X < ncl; X++)
+    for (int a = s.lmo_ptr[X]; a < s.lmo_ptr[X + 1]; a++)
+      for (int b = a; b < s.lmo_ptr[X + 1]; b++) need[(size_t)s.lmo[a] * nocc + s.lmo[b]] = 1;
+  for (int p = 0; p < nocc; p++)
+    for (int q = p; q < nocc; q++)
+      if (need[(size_t)p * nocc + q]) {
+        Domain D{};
+        D.p = p;
+        D.q = q;
+        D.rp = rr(p);
+        D.rq = (p == q) ? 0 : rr(q);
+        D.n = D.rp + D.rq;
+        D.offp = off ? off[p] : 0;
+        D.offq = off ? off[q] : 0;
+        if (r && D.n > DMAX) {
+          err = "pair domain (" + std::to_string(p) + "," + std::to_string(q) + ") has dimension " +
+                std::to_string(D.n) + " > OSV_MAX_DOMAIN";
+          return OSV_E_ARG;
+        }
+        D.moff = P.n_slot;
+        D.voff = P.n_vec;
+        P.n_slot += (long long)D.n * D.n;
+        P.n_vec += D.n;
+        P.dom_of[(size_t)p * nocc + q] = (int)P.doms.size();
+        P.doms.push_back(D);
+      }
+  auto dom_id = [&](int a, int b) {
+    return a <= b ? P.dom_of[(size_t)a * nocc + b] : P.dom_of[(size_t)b * nocc + a];
+  };
+  std::unordered_map<long long, int> cmap;
+  const long long ND = (long long)P.doms.size();
+  auto coupling = [&](int t, int src, int &flags) {
+    int A = std::min(t, src), B = std::max(t, src);
+    long long key = (long long)A * ND + B;
+    auto it = cmap.find(key);
+    int id;
+    if (it == cmap.end()) {
+      id = (int)P.cpls.size();
+      Coupling c{};
+      c.A = A;
+      c.B = B;
+      c.off = P.n_M;
+      P.n_M += (long long)P.doms[A].n * P.doms[B].n;
+      P.cpls.push_back(c);
+      cmap[key] = id;
+    } else {
+      id = it->second;
+    }
+    if (t != A) flags |= 1;
+    return id;
+  };
+  std::vector<double> cost(ncl, 0.0);
+  for (int X = 0; X < ncl; X++) {
+    Cluster C{};
+    const int l0 = s.lmo_ptr[X], nl = s.lmo_ptr[X + 1] - l0;
+    C.cp0 = (int)P.cps.size();
+    C.nlmo = nl;
+    C.lmo0 = l0;
+    C.toff0 = P.n_T;
+    C.poff = P.n_pl;
+    P.n_pl += (long long)nl * nl;
+    // local pair index table
+    std::vector<int> lpair((size_t)nl * nl, -1);
+    for (int a = 0; a < nl; a++)
+      for (int b = a; b < nl; b++) {
+        CPair cp{};
+        int p = s.lmo[l0 + a], q = s.lmo[l0 + b];
+        cp.dom = dom_id(p, q);
+        cp.la = a;
+        cp.lb = b;
+        cp.w = (a == b) ? 1 : 2;
+        cp.toff = P.n_T;
+        long long n = P.doms[cp.dom].n;
+        P.n_T += n * n;
+        lpair[(size_t)a * nl + b] = lpair[(size_t)b * nl + a] = (int)P.cps.size();
+        P.cps.push_back(cp);
+      }
+    C.ncp = (int)P.cps.size() - C.cp0;
+    // terms of eq:rij for every pair of the cluster
+    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+      CPair &cp = P.cps[c];
+      cp.term0 = (int)P.terms.size();
+      const int a = cp.la, b = cp.lb;
+      const int p = s.lmo[l0 + a], q = s.lmo[l0 + b];
+      const double nt = P.doms[cp.dom].n;
+      cost[X] += nt * nt;
+      // first sum: m != q, source ordered (p, m), coefficient f_mq
+      for (int mm = 0; mm < nl; mm++) {
+        if (mm == b) continue;
+        const int m = s.lmo[l0 + mm];
+        Term t{};
+        t.src = lpair[(size_t)a * nl + mm];
+        int flags = (p > m) ? 2 : 0;
+        t.cpl = coupling(cp.dom, P.cps[t.src].dom, flags);
+        t.flags = flags;
+        t.fa = m;
+        t.fb = q;
+        t.la = mm;
+        t.lb = b;
+        const double ns = P.doms[P.cps[t.src].dom].n;
+        cost[X] += nt * ns * ns + nt * nt * ns;
+        P.terms.push_back(t);
+      }
+      // second sum: m != p, source ordered (m, q), coefficient f_pm
+      for (int mm = 0; mm < nl; mm++) {
+        if (mm == a) continue;
+        const int m = s.lmo[l0 + mm];
+        Term t{};
+        t.src = lpair[(size_t)mm * nl + b];
+        int flags = (m > q) ? 2 : 0;
+        t.cpl = coupling(cp.dom, P.cps[t.src].dom, flags);
+        t.flags = flags;
+        t.fa = p;
+        t.fb = m;
+        t.la = a;
+        t.lb = mm;
+        const double ns = P.doms[P.cps[t.src].dom].n;
+        cost[X] += nt * ns * ns + nt * nt * ns;
+        P.terms.push_back(t);
+      }
+      cp.nterm = (int)P.terms.size() - cp.term0;
+    }
+    P.rs_stride = std::max(P.rs_stride, P.n_T - C.toff0);
+    P.n_pair_blocks += C.ncp;
+    P.cls.push_back(C);
+  }
+  P.queue.resize(ncl);
+  std::iota(P.queue.begin(), P.queue.end(), 0);
+  std::stable_sort(P.queue.begin(), P.queue.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  return OSV_OK;
+}
+
+}  // namespace
+
+struct osv_ctx {
+  int nocc = 0, nvir = 0, naux = 0, nosv = 0, precision = 0, c_dtype = 0, mode = 0;
+  std::vector<int> r, off;
+  const double *Q = nullptr, *eps = nullptr, *F = nullptr;
+  const void *C = nullptr;
+  double tau_S = 1e-8;
+  Selection sel;
+  Plan plan;
+  osv_counts counts{};
+  std::vector<int2> tiles;
+  // device memory
+  std::vector<void *> allocs;
+  double *dS = nullptr, *dF = nullptr, *dK = nullptr, *dW = nullptr, *dY = nullptr, *dKt = nullptr;
+  double *dEpst = nullptr, *dMinev = nullptr, *dM = nullptr, *dT = nullptr, *dRs = nullptr;
+  double *dEcl = nullptr, *dPl = nullptr, *dMaxres = nullptr, *dWts = nullptr, *dEout = nullptr;
+  int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
+  int *dOff = nullptr, *dR = nullptr;
+  Domain *dDom = nullptr;
+  Coupling *dCpl = nullptr;
+  CPair *dCp = nullptr;
+  Term *dTerms = nullptr;
+  Cluster *dCl = nullptr;
+  int2 *dTiles = nullptr;
+  void *dHi = nullptr, *dMid = nullptr, *dLo = nullptr;
+  int nwg = 1;
+  int mixed_terms = 6;
+  // densities (allocated on first use)
+  bool dens_ready = false;
+  double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
+  double *dClcoef = nullptr;
+  long long *dDptr = nullptr, *dDtoff = nullptr, *dBptr = nullptr, *dPptr = nullptr, *dPidx = nullptr;
+  int *dBdom = nullptr, *dBpart = nullptr;
+  int2 *dBlocks = nullptr;
+  int nblocks = 0;
+  // state
+  bool solved = false;
+  std::string err;
+  double stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<int> rank_host;
+  ~osv_ctx() {
+    for (void *p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+int fail(osv_ctx *ctx, int code, const std::string &msg) {
+  g_last_error = msg;
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return fail(ctx, _e == hipErrorOutOfMemory ? OSV_E_NOMEM : OSV_E_HIP,                \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                      \
+  } while (0)
+
+template <class T>
+int dalloc(osv_ctx *ctx, T **p, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess)
+    return fail(ctx, OSV_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  ctx->allocs.push_back(q);
+  *p = (T *)q;
+  return OSV_OK;
+}
+
+template <class T>
+int upload(osv_ctx *ctx, T **p, const std::vector<T> &v, hipStream_t s) {
+  int rc = dalloc(ctx, p, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(ctx, hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return OSV_OK;
+}
+
+struct StageTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit StageTimer(hipStream_t st) : s(st) {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s);
+  }
+  // records the end of the stage; the value is read after the stream is synchronised
+  void stop() { (void)hipEventRecord(b, s); }
+  double ms() {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.0;
+    return t;
+  }
+  ~StageTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// tiles (ti <= tj, 64x64) of the sum(r) x sum(r) index space that hold a domain block
+std::vector<int2> make_tiles(const Plan &P, int nosv, bool all) {
+  const int nt = (nosv + 63) / 64;
+  std::vector<char> mark((size_t)nt * nt, all ? 1 : 0);
+  if (!all)
+    for (const Domain &D : P.doms) {
+      int a0 = D.offp / 64, a1 = (D.offp + D.rp - 1) / 64;
+      int qo = (D.p == D.q) ? D.offp : D.offq, qr = (D.p == D.q) ? D.rp : D.rq;
+      int b0 = qo / 64, b1 = (qo + qr - 1) / 64;
+      for (int a = a0; a <= a1; a++)
+        for (int b = b0; b <= b1; b++) mark[(size_t)std::min(a, b) * nt + std::max(a, b)] = 1;
+    }
+  std::vector<int2> t;
+  for (int a = 0; a < nt; a++)
+    for (int b = a; b < nt; b++)
+      if (mark[(size_t)a * nt + b]) t.push_back(make_int2(a, b));
+  return t;
+}
+
+}  // namespace
+
+static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel, int32_t precision,
+                      hipStream_t stream) {
+  long long nosv = 0;
+  for (int i = 0; i < sys->nocc; i++) nosv += sys->r[i];
+  ctx->nocc = sys->nocc;
+  ctx->nvir = sys->nvir;
+  ctx->naux = sys->naux;
+  ctx->nosv = (int)nosv;
+  ctx->precision = precision;
+  ctx->c_dtype = sys->C_dtype;
+  ctx->mode = sel->mode;
+  ctx->Q = sys->Q;
+  ctx->C = sys->C;
+  ctx->eps = sys->eps_vir;
+  ctx->F = sys->F_occ;
+  ctx->tau_S = sel->tau_S;
+  ctx->r.assign(sys->r, sys->r + sys->nocc);
+  ctx->off.assign(sys->nocc + 1, 0);
+  for (int i = 0; i < sys->nocc; i++) ctx->off[i + 1] = ctx->off[i] + ctx->r[i];
+  hipStream_t s = stream;
+  const int nocc = ctx->nocc, N = ctx->nosv;
+  const long long ld = N;
+  int rc;
+
+  // input checks on the device (NaN / Inf)
+  if ((rc = dalloc(ctx, &ctx->dFlag, 4))) return rc;
+  HIPCHK(ctx, launch_fill_i32(ctx->dFlag, 0, 4, s));
+  HIPCHK(ctx, launch_check_finite(ctx->Q, (long long)ctx->nvir * N, ctx->dFlag, s));
+  if (ctx->c_dtype == OSV_DT_F32)
+    HIPCHK(ctx, launch_check_finite_f32((const float *)ctx->C, (long long)N * ctx->naux, ctx->dFlag, s));
+  else
+    HIPCHK(ctx, launch_check_finite((const double *)ctx->C, (long long)N * ctx->naux, ctx->dFlag, s));
+  HIPCHK(ctx, launch_check_finite(ctx->eps, ctx->nvir, ctx->dFlag, s));
+  HIPCHK(ctx, launch_check_finite(ctx->F, (long long)nocc * nocc, ctx->dFlag, s));
+  int flag = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&flag, ctx->dFlag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (flag) {
+    return fail(ctx, OSV_E_NONFINITE, "NaN or Inf in Q, C, eps_vir or F_occ");
+  }
+
+  if ((rc = dalloc(ctx, &ctx->dS, (size_t)ld * ld))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dF, (size_t)ld * ld))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dK, (size_t)ld * ld))) return rc;
+  if ((rc = upload(ctx, &ctx->dOff, ctx->off, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dR, ctx->r, s))) return rc;
+
+  StageTimer t_sf(s);
+  // cluster selection
+  if (sel->mode == OSV_SEL_DISTANCE) {
+    select_distance(nocc, sys->centroid, sel->cut2, sel->cut3, ctx->sel);
+  } else if (sel->mode == OSV_SEL_FULL) {
+    select_full(nocc, ctx->sel);
+  } else {
+    // overlap metric eq:2bscreen needs every S block: full S first
+    std::vector<int2> all = make_tiles(ctx->plan, N, true);
+    int2 *dAll = nullptr;
+    if ((rc = upload(ctx, &dAll, all, s))) return rc;
+    HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, nullptr, ctx->dS, nullptr, ld, dAll,
+                                (int)all.size(), s));
+    double *dSq = nullptr;
+    if ((rc = dalloc(ctx, &dSq, (size_t)nocc * nocc))) return rc;
+    HIPCHK(ctx, launch_block_sumsq(ctx->dS, ld, ctx->dOff, ctx->dR, nocc, dSq, s));
+    std::vector<double> sq((size_t)nocc * nocc);
+    HIPCHK(ctx, hipMemcpyAsync(sq.data(), dSq, sq.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    auto s2b = [&](int i, int j) { return sq[(size_t)i * nocc + j] / std::sqrt((double)ctx->r[i] * ctx->r[j]); };
+    select_mbe(
+        nocc, [&](int i, int j) { return s2b(i, j) > sel->l2b; },
+        [&](int i, int j, int k) { return (s2b(i, j) + s2b(i, k) + s2b(j, k)) / 3.0 > sel->l3b; },
+        ctx->sel);
+  }
+  {
+    std::string err;
+    rc = build_plan(nocc, ctx->sel, ctx->r.data(), ctx->off.data(), ctx->plan, err);
+    if (rc) return fail(ctx, rc, err);
+  }
+  Plan &P = ctx->plan;
+  const Selection &S = ctx->sel;
+  ctx->counts.n1b = S.n1;
+  ctx->counts.n2b = S.n2b;
+  ctx->counts.n3b = S.n3b;
+  ctx->counts.n_clusters = (int64_t)S.coef.size();
+  ctx->counts.n_pair_blocks = P.n_pair_blocks;
+  ctx->counts.n_domains = (int64_t)P.doms.size();
+  ctx->counts.n_couplings = (int64_t)P.cpls.size();
+  ctx->tiles = make_tiles(P, N, false);
+  const int ndom = (int)P.doms.size();
+  const int ncl = (int)P.cls.size();
+
+  if ((rc = upload(ctx, &ctx->dTiles, ctx->tiles, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dDom, P.doms, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCp, P.cps, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dTerms, P.terms, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
+
+  // S and F blocks: one pass over Q^T (rows = OSVs, k = virtuals)
+  HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, ctx->eps, ctx->dS, ctx->dF, ld,
+                              ctx->dTiles, (int)ctx->tiles.size(), s));
+  t_sf.stop();
+  StageTimer t_k(s);
+  if (precision == OSV_MIXED) {
+    const long long nc = (long long)N * ctx->naux;
+    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dHi, nc))) return rc;
+    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dMid, nc))) return rc;
+    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dLo, nc))) return rc;
+    HIPCHK(ctx, launch_split_bf16((const float *)ctx->C, nc, ctx->dHi, ctx->dMid, ctx->dLo, s));
+    HIPCHK(ctx, launch_syrk_bf16x(ctx->dHi, ctx->dMid, ctx->dLo, ctx->naux, N, ctx->naux, ctx->mixed_terms,
+                                  ctx->dK, ld, ctx->dTiles, (int)ctx->tiles.size(), s));
+  } else {
+    HIPCHK(ctx, launch_syrk_f64(ctx->C, ctx->c_dtype == OSV_DT_F32, ctx->naux, N, ctx->naux, nullptr, ctx->dK,
+                                nullptr, ld, ctx->dTiles, (int)ctx->tiles.size(), s));
+  }
+  t_k.stop();
+
+  // pair-domain preparation
+  StageTimer t_prep(s);
+  if ((rc = dalloc(ctx, &ctx->dW, P.n_slot))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dY, P.n_slot))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dKt, P.n_slot))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dEpst, P.n_vec))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
+  HIPCHK(ctx, launch_domain_prep(ctx->dDom, ndom, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S, ctx->dW, ctx->dY,
+                                 ctx->dKt, ctx->dEpst, ctx->dRank, ctx->dMinev, s));
+  t_prep.stop();
+  StageTimer t_cpl(s);
+  if ((rc = dalloc(ctx, &ctx->dM, P.n_M))) return rc;
+  HIPCHK(ctx, launch_couplings(ctx->dCpl, (int)P.cpls.size(), ctx->dDom, ctx->dRank, ctx->dS, ld, ctx->dW,
+                               ctx->dM, s));
+  t_cpl.stop();
+  ctx->rank_host.resize(ndom);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->rank_host.data(), ctx->dRank, ndom * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  for (int d = 0; d < ndom; d++)
+    if (ctx->rank_host[d] < 1) {
+      return fail(ctx, OSV_E_DOMAIN, "pair domain (" + std::to_string(P.doms[d].p) + "," +
+                                         std::to_string(P.doms[d].q) + ") has rank 0 after the tau_S cut");
+    }
+  ctx->stage_ms[0] = t_sf.ms();
+  ctx->stage_ms[1] = t_k.ms();
+  ctx->stage_ms[2] = t_prep.ms();
+  ctx->stage_ms[3] = t_cpl.ms();
+
+  // solve-time buffers
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  ctx->nwg = std::max(1, std::min(ncl, 2 * ncu));
+  if ((rc = dalloc(ctx, &ctx->dT, P.n_T))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dRs, (size_t)ctx->nwg * P.rs_stride))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dEcl, ncl))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dPl, P.n_pl))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dMaxres, ncl))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dSweeps, ncl))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dCounter, 1))) return rc;
+  // MBE weights: E, E_1b, dE_2b, dE_3b
+  {
+    std::vector<double> w((size_t)4 * ncl, 0.0);
+    int p2 = 0;
+    for (int X = 0; X < ncl; X++) {
+      w[X] = S.coef[X];
+      if (S.order[X] == 1) {
+        int i = S.lmo[S.lmo_ptr[X]];
+        w[(size_t)ncl + X] = 1.0;
+        w[(size_t)2 * ncl + X] = -S.n2[i];
+        w[(size_t)3 * ncl + X] = S.n3i[i];
+      } else if (S.order[X] == 2) {
+        w[(size_t)2 * ncl + X] = 1.0;
+        w[(size_t)3 * ncl + X] = -S.n3ij[p2++];
+      } else if (S.order[X] == 3) {
+        w[(size_t)3 * ncl + X] = 1.0;
+      }
+    }
+    if ((rc = upload(ctx, &ctx->dWts, w, s))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dEout, 4))) return rc;
+  }
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  return OSV_OK;
+}
+
+
+extern "C" {
+
+const char *osv_status_string(int st) {
+  switch (st) {
+    case OSV_OK: return "ok";
+    case OSV_E_ARG: return "invalid argument";
+    case OSV_E_HIP: return "HIP runtime error";
+    case OSV_E_NOMEM: return "out of memory";
+    case OSV_E_NOT_CONVERGED: return "residual iteration did not converge";
+    case OSV_E_NONFINITE: return "non-finite value in input or residual";
+    case OSV_E_STATE: return "called before a converged solve";
+    case OSV_E_DOMAIN: return "pair domain of rank 0";
+    default: return "unknown status";
+  }
+}
+
+const char *osv_last_error(const osv_ctx *ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_last_error.c_str();
+}
+
+int osv_plan_clusters(int32_t nocc, const double *centroid, const osv_select *sel,
+                      osv_counts *counts, int32_t *lmos, double *coef, int64_t cap) {
+  if (nocc < 1 || !sel || !counts) return fail(nullptr, OSV_E_ARG, "osv_plan_clusters: bad arguments");
+  Selection s;
+  if (sel->mode == OSV_SEL_DISTANCE) {
+    if (!centroid) return fail(nullptr, OSV_E_ARG, "DISTANCE selection needs centroids");
+    if (!(sel->cut2 >= 0) || !(sel->cut3 >= 0)) return fail(nullptr, OSV_E_ARG, "negative cutoff");
+    select_distance(nocc, centroid, sel->cut2, sel->cut3, s);
+  } else if (sel->mode == OSV_SEL_FULL) {
+    select_full(nocc, s);
+  } else {
+    return fail(nullptr, OSV_E_ARG, "osv_plan_clusters supports DISTANCE and FULL selection");
+  }
+  Plan P;
+  std::string err;
+  int rc = build_plan(nocc, s, nullptr, nullptr, P, err);
+  if (rc) return fail(nullptr, rc, err);
+  counts->n1b = s.n1;
+  counts->n2b = s.n2b;
+  counts->n3b = s.n3b;
+  counts->n_clusters = (int64_t)s.coef.size();
+  counts->n_pair_blocks = P.n_pair_blocks;
+  counts->n_domains = (int64_t)P.doms.size();
+  counts->n_couplings = (int64_t)P.cpls.size();
+  const int64_t ncl = (int64_t)s.coef.size();
+  if ((lmos || coef) && cap < ncl) return fail(nullptr, OSV_E_ARG, "capacity below the cluster count");
+  if (lmos && sel->mode != OSV_SEL_FULL)
+    for (int64_t X = 0; X < ncl; X++)
+      for (int a = 0; a < 3; a++) {
+        int i = s.lmo_ptr[X] + a;
+        lmos[3 * X + a] = (i < s.lmo_ptr[X + 1]) ? s.lmo[i] : -1;
+      }
+  if (coef)
+    for (int64_t X = 0; X < ncl; X++) coef[X] = s.coef[X];
+  return OSV_OK;
+}
+
+int osv_build_pairs(const osv_system *sys, const osv_select *sel, int32_t precision,
+                    hipStream_t stream, osv_ctx **out) {
+  if (!out) return fail(nullptr, OSV_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sys || !sel) return fail(nullptr, OSV_E_ARG, "sys or sel is NULL");
+  if (sys->nocc < 1 || sys->nvir < 1 || sys->naux < 1)
+    return fail(nullptr, OSV_E_ARG, "nocc, nvir and naux must be >= 1");
+  if (!sys->r || !sys->Q || !sys->C || !sys->eps_vir || !sys->F_occ)
+    return fail(nullptr, OSV_E_ARG, "NULL array in osv_system");
+  if (sys->C_dtype != OSV_DT_F64 && sys->C_dtype != OSV_DT_F32)
+    return fail(nullptr, OSV_E_ARG, "unknown C_dtype");
+  if (precision != OSV_FP64 && precision != OSV_MIXED)
+    return fail(nullptr, OSV_E_ARG, "unknown precision");
+  if (precision == OSV_MIXED && sys->C_dtype != OSV_DT_F32)
+    return fail(nullptr, OSV_E_ARG, "OSV_MIXED needs C in FP32");
+  if (sel->mode != OSV_SEL_DISTANCE && sel->mode != OSV_SEL_OVERLAP && sel->mode != OSV_SEL_FULL)
+    return fail(nullptr, OSV_E_ARG, "unknown selection mode");
+  if (sel->mode == OSV_SEL_DISTANCE && (!sys->centroid || !(sel->cut2 >= 0) || !(sel->cut3 >= 0)))
+    return fail(nullptr, OSV_E_ARG, "DISTANCE selection needs centroids and cutoffs >= 0");
+  if (!(sel->tau_S >= 0.0)) return fail(nullptr, OSV_E_ARG, "tau_S must be >= 0");
+  long long nosv = 0;
+  for (int i = 0; i < sys->nocc; i++) {
+    if (sys->r[i] < 1 || sys->r[i] > sys->nvir || sys->r[i] > OSV_MAX_DOMAIN)
+      return fail(nullptr, OSV_E_ARG, "r[" + std::to_string(i) + "] out of range");
+    nosv += sys->r[i];
+  }
+  if (nosv > (1LL << 30)) return fail(nullptr, OSV_E_ARG, "sum(r) too large");
+
+  osv_ctx *ctx = new (std::nothrow) osv_ctx();
+  if (!ctx) return fail(nullptr, OSV_E_NOMEM, "host allocation");
+  int rc = build_impl(ctx, sys, sel, precision, stream);
+  if (rc != OSV_OK) {
+    g_last_error = ctx->err;
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return OSV_OK;
+}
+
+int osv_query(const osv_ctx *ctx, osv_counts *out) {
+  if (!ctx || !out) return fail(nullptr, OSV_E_ARG, "osv_query: NULL argument");
+  *out = ctx->counts;
+  return OSV_OK;
+}
+
+int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream_t s,
+                       osv_solve_info *info) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!(tau_R > 0.0) || max_sweeps < 1) return fail(ctx, OSV_E_ARG, "tau_R must be > 0 and max_sweeps >= 1");
+  ctx->solved = false;
+  Plan &P = ctx->plan;
+  const int ncl = (int)P.cls.size();
+  SolveArgs a{};
+  a.cl = ctx->dCl;
+  a.cp = ctx->dCp;
+  a.terms = ctx->dTerms;
+  a.dom = ctx->dDom;
+  a.dom_rank = ctx->dRank;
+  a.cpl = ctx->dCpl;
+  a.M = ctx->dM;
+  a.Kt = ctx->dKt;
+  a.epst = ctx->dEpst;
+  a.F_occ = ctx->F;
+  a.nocc = ctx->nocc;
+  a.T = ctx->dT;
+  a.Rs = ctx->dRs;
+  a.rs_stride = P.rs_stride;
+  a.Ecl = ctx->dEcl;
+  a.Pl = ctx->dPl;
+  a.sweeps = ctx->dSweeps;
+  a.maxres = ctx->dMaxres;
+  a.queue = ctx->dQueue;
+  a.counter = ctx->dCounter;
+  a.n_clusters = ncl;
+  a.tau_R = tau_R;
+  a.max_sweeps = max_sweeps;
+  StageTimer t(s);
+  HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 1, s));
+  HIPCHK(ctx, launch_solve(a, ctx->nwg, s));
+  t.stop();
+  std::vector<int> sw(ncl);
+  std::vector<double> mr(ncl);
+  HIPCHK(ctx, hipMemcpyAsync(sw.data(), ctx->dSweeps, ncl * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipMemcpyAsync(mr.data(), ctx->dMaxres, ncl * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  ctx->stage_ms[4] = t.ms();
+  osv_solve_info inf{};
+  inf.converged = 1;
+  bool nonfinite = false;
+  for (int X = 0; X < ncl; X++) {
+    inf.sweeps = std::max(inf.sweeps, sw[X]);
+    if (mr[X] != mr[X]) nonfinite = true;
+    else inf.max_residual = std::max(inf.max_residual, mr[X]);
+    if (!(mr[X] < tau_R)) {
+      inf.converged = 0;
+      inf.n_not_converged++;
+    }
+  }
+  if (info) *info = inf;
+  if (nonfinite) return fail(ctx, OSV_E_NONFINITE, "residual is not finite");
+  if (!inf.converged)
+    return fail(ctx, OSV_E_NOT_CONVERGED, std::to_string(inf.n_not_converged) + " clusters did not converge");
+  ctx->solved = true;
+  return OSV_OK;
+}
+
+int osv_energy(osv_ctx *ctx, hipStream_t s, double *E, double *E_orders, double *E_cluster) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!E) return fail(ctx, OSV_E_ARG, "E is NULL");
+  if (!ctx->solved) return fail(ctx, OSV_E_STATE, "osv_energy before a converged solve");
+  const int ncl = (int)ctx->plan.cls.size();
+  StageTimer t(s);
+  HIPCHK(ctx, launch_wdot(ctx->dEcl, ctx->dWts, ncl, 4, ctx->dEout, s));
+  t.stop();
+  double h[4];
+  HIPCHK(ctx, hipMemcpyAsync(h, ctx->dEout, sizeof(h), hipMemcpyDeviceToHost, s));
+  if (E_cluster)
+    HIPCHK(ctx, hipMemcpyAsync(E_cluster, ctx->dEcl, ncl * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  ctx->stage_ms[5] = t.ms();
+  *E = h[0];
+  if (E_orders) {
+    if (ctx->mode == OSV_SEL_FULL) {
+      E_orders[0] = E_orders[1] = E_orders[2] = std::nan("");
+    } else {
+      E_orders[0] = h[1];
+      E_orders[1] = h[2];
+      E_orders[2] = h[3];
+    }
+  }
+  return OSV_OK;
+}
+
+static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
+  if (ctx->dens_ready) return OSV_OK;
+  Plan &P = ctx->plan;
+  const Selection &S = ctx->sel;
+  const int ndom = (int)P.doms.size(), ncl = (int)P.cls.size(), nocc = ctx->nocc, N = ctx->nosv;
+  int rc;
+  // per domain: (amplitude offset, c_X) over the clusters holding it, cluster order
+  std::vector<std::vector<std::pair<long long, double>>> lists(ndom);
+  for (int X = 0; X < ncl; X++) {
+    if (S.coef[X] == 0.0) continue;
+    const Cluster &C = P.cls[X];
+    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) lists[P.cps[c].dom].push_back({P.cps[c].toff, S.coef[X]});
+  }
+  std::vector<long long> ptr(ndom + 1, 0), toff;
+  std::vector<double> cf;
+  for (int d = 0; d < ndom; d++) {
+    for (auto &e : lists[d]) {
+      toff.push_back(e.first);
+      cf.push_back(e.second);
+    }
+    ptr[d + 1] = (long long)toff.size();
+  }
+  if ((rc = upload(ctx, &ctx->dDptr, ptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dDtoff, toff, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dDcoef, cf, s))) return rc;
+  // G^F orbital blocks
+  std::vector<int2> blocks;
+  std::vector<long long> bptr(1, 0);
+  std::vector<int> bdom, bpart;
+  std::vector<std::vector<std::pair<int, int>>> diag_src(nocc);
+  for (int d = 0; d < ndom; d++) {
+    const Domain &D = P.doms[d];
+    diag_src[D.p].push_back({d, 0});
+    if (D.q != D.p) diag_src[D.q].push_back({d, 1});
+  }
+  for (int d = 0; d < ndom; d++) {
+    const Domain &D = P.doms[d];
+    blocks.push_back(make_int2(D.p, D.q));
+    if (D.p == D.q) {
+      for (auto &e : diag_src[D.p]) {
+        bdom.push_back(e.first);
+        bpart.push_back(e.second);
+      }
+    } else {
+      bdom.push_back(d);
+      bpart.push_back(0);
+    }
+    bptr.push_back((long long)bdom.size());
+  }
+  ctx->nblocks = (int)blocks.size();
+  if ((rc = upload(ctx, &ctx->dBlocks, blocks, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dBptr, bptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dBdom, bdom, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dBpart, bpart, s))) return rc;
+  // dE/dF: per entry (u, v) the (cluster, inner-product index) list
+  std::vector<std::vector<std::pair<long long, long long>>> pl((size_t)nocc * nocc);
+  for (int X = 0; X < ncl; X++) {
+    if (S.coef[X] == 0.0) continue;
+    const Cluster &C = P.cls[X];
+    for (int a = 0; a < C.nlmo; a++)
+      for (int b = 0; b < C.nlmo; b++) {
+        int u = S.lmo[C.lmo0 + a], v = S.lmo[C.lmo0 + b];
+        pl[(size_t)u * nocc + v].push_back({X, C.poff + (long long)a * C.nlmo + b});
+      }
+  }
+  std::vector<long long> pptr((size_t)nocc * nocc + 1, 0), pidx;
+  for (size_t e = 0; e < pl.size(); e++) {
+    for (auto &x : pl[e]) {
+      pidx.push_back(x.first);
+      pidx.push_back(x.second);
+    }
+    pptr[e + 1] = (long long)pidx.size() / 2;
+  }
+  if ((rc = upload(ctx, &ctx->dPptr, pptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dPidx, pidx, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dClcoef, S.coef, s))) return rc;
+  const long long ld = N;
+  if ((rc = dalloc(ctx, &ctx->dGK, (size_t)ld * ld))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dGF, (size_t)ld * ld))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dGd, P.n_slot))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dZt, (size_t)N * ctx->nvir))) return rc;
+  HIPCHK(ctx, launch_fill_f64(ctx->dGK, 0.0, ld * ld, s));
+  HIPCHK(ctx, launch_fill_f64(ctx->dGF, 0.0, ld * ld, s));
+  ctx->dens_ready = true;
+  return OSV_OK;
+}
+
+int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, double *dE_deps,
+                  double *Dvir_full) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!ctx->solved) return fail(ctx, OSV_E_STATE, "osv_densities before a converged solve");
+  int rc = prepare_densities(ctx, s);
+  if (rc) return rc;
+  Plan &P = ctx->plan;
+  const int ndom = (int)P.doms.size(), N = ctx->nosv;
+  const long long ld = N;
+  StageTimer t_adj(s);
+  HIPCHK(ctx, launch_adjoint(ctx->dDom, ndom, ctx->dRank, ctx->dW, ctx->dY, ctx->dT, ctx->dDptr, ctx->dDtoff,
+                             ctx->dDcoef, ctx->dGK, ld, ctx->dGd, s));
+  HIPCHK(ctx, launch_assemble_gf(ctx->dDom, ctx->dBptr, ctx->dBdom, ctx->dBpart, ctx->dBlocks, ctx->nblocks,
+                                 ctx->dOff, ctx->dR, ctx->dGd, ctx->dGF, ld, s));
+  t_adj.stop();
+  StageTimer t_bt(s);
+  if (dE_dC)
+    HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGK, ld, (const double *)ctx->C, ctx->c_dtype == OSV_DT_F32, ctx->naux,
+                                   dE_dC, ctx->naux, N, ctx->naux, N, 2.0, s));
+  if (dE_deps || Dvir_full) {
+    // Z^T = G^F Q^T  (Q^T is row-major sum(r) x nvir)
+    HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGF, ld, ctx->Q, 0, ctx->nvir, ctx->dZt, ctx->nvir, N, ctx->nvir, N,
+                                   1.0, s));
+    if (dE_deps) HIPCHK(ctx, launch_coldot(ctx->Q, ctx->dZt, N, ctx->nvir, dE_deps, s));
+    if (Dvir_full)
+      HIPCHK(ctx, launch_gemm_tn_f64(ctx->Q, ctx->nvir, ctx->dZt, ctx->nvir, Dvir_full, ctx->nvir, ctx->nvir,
+                                     ctx->nvir, N, 1.0, s));
+  }
+  if (dE_dFocc)
+    HIPCHK(ctx, launch_pocc(ctx->dPptr, ctx->dPidx, ctx->dClcoef, ctx->dPl, ctx->nocc, dE_dFocc, s));
+  t_bt.stop();
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  ctx->stage_ms[6] = t_adj.ms();
+  ctx->stage_ms[7] = t_bt.ms();
+  return OSV_OK;
+}
+
+int osv_stage_times(const osv_ctx *ctx, double *ms8) {
+  if (!ctx || !ms8) return fail(nullptr, OSV_E_ARG, "osv_stage_times: NULL argument");
+  for (int i = 0; i < 8; i++) ms8[i] = ctx->stage_ms[i];
+  return OSV_OK;
+}
+
+void osv_destroy(osv_ctx *ctx) { delete ctx; }
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal layout shared by the host orchestration and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osv {
+
+constexpr int DMAX = 100;      // largest pair-domain dimension r_p + r_q
+constexpr int NTHREADS = 256;  // threads of every per-item workgroup (4 wave64)
+
+// One pair domain [Q_p Q_q] (p < q) or Q_p (p == q).  Every per-domain square
+// matrix (W, Y = W^T S, K~, the OSV-basis virtual density) lives in an n x n
+// slot at moff (row-major, ld n); the kept rank dt <= n is written by the
+// preparation kernel into dom_rank[].
+struct Domain {
+  int p, q, rp, rq, n, offp, offq, pad;
+  long long moff;   // n*n slot offset
+  long long voff;   // n slot offset (pseudo-canonical energies)
+};
+
+// Coupling between domains A and B that share an LMO:
+// M(A,B) = W_A^T S_(A,B) W_B  (n_A x n_B slot, ld n_B).
+struct Coupling {
+  int A, B;
+  long long off;
+};
+
+// One residual term of eq:rij in pseudo-canonical coordinates:
+//   R~_tgt += -f[fa][fb] * M op(T~_src) M^T,   M = M(tgt, src)
+// flags bit0: the stored coupling is M(src, tgt) (use its transpose)
+//       bit1: op = transpose (ordered source pair (a,b) with a > b)
+struct Term {
+  int src;    // absolute cluster-pair index of the source amplitudes
+  int cpl;    // coupling index
+  int flags;
+  int fa, fb; // global LMO indices of the coefficient f[fa][fb]
+  int la, lb; // the same LMOs as cluster-local indices (dE/dF bookkeeping)
+  int pad;
+};
+
+// One unordered LMO pair (p <= q) of one cluster.
+struct CPair {
+  int dom;
+  int la, lb;         // cluster-local LMO indices of p and q
+  int term0, nterm;   // range in the term array
+  int w;              // 1 for p == q, 2 for p < q (ordered-pair multiplicity)
+  long long toff;     // offset of the n x n amplitude slot
+};
+
+struct Cluster {
+  int cp0, ncp;       // range of cluster pairs
+  int nlmo, lmo0;     // LMOs: cl_lmo[lmo0 .. lmo0+nlmo)
+  long long toff0;    // amplitude offset of the first pair (scratch base)
+  long long poff;     // offset of the nlmo x nlmo block of dE/dF inner products
+};
+
+struct SolveArgs {
+  const Cluster *cl;
+  const CPair *cp;
+  const Term *terms;
+  const Domain *dom;
+  const int *dom_rank;
+  const Coupling *cpl;
+  const double *M;      // couplings
+  const double *Kt;     // K~ per domain
+  const double *epst;   // pseudo-canonical energies per domain
+  const double *F_occ;  // nocc x nocc
+  int nocc;
+  double *T;            // amplitudes per cluster pair
+  double *Rs;           // per-workgroup residual scratch
+  long long rs_stride;  // doubles per workgroup
+  double *Ecl;          // [n_clusters] Hylleraas energies
+  double *Pl;           // dE/dF inner products per cluster (nlmo x nlmo)
+  int *sweeps;          // [n_clusters]
+  double *maxres;       // [n_clusters]
+  const int *queue;     // cluster order (cost descending)
+  int *counter;         // work-queue head
+  int n_clusters;
+  double tau_R;
+  int max_sweeps;
+};
+
+}  // namespace osv
+
+// ---- launch wrappers (defined next to their kernels) -----------------------
+namespace osv {
+// C[i][j] = sum_k A[i][k] B[j][k] (and C2 with weight w[k]) on the listed 64x64
+// output tiles; A, B row-major.  mirror: also write the transposed tile.
+hipError_t launch_syrk_f64(const void *A, int a_is_f32, long long lda, int M, int K,
+                           const double *w, double *C, double *C2, long long ldc,
+                           const int2 *tiles, int ntiles, hipStream_t s);
+// split-bf16 variant for K in mixed mode (A FP32 row-major)
+hipError_t launch_split_bf16(const float *A, long long n, void *hi, void *mid, void *lo,
+                             hipStream_t s);
+hipError_t launch_syrk_bf16x(const void *hi, const void *mid, const void *lo, long long lda,
+                             int M, int K, int nterms, double *C, long long ldc,
+                             const int2 *tiles, int ntiles, hipStream_t s);
+// C[i][j] = alpha * sum_k A[i][k] B[k][j]  (A row-major M x K, B row-major K x N)
+hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, int b_is_f32,
+                              long long ldb, double *C, long long ldc, int M, int N, int K,
+                              double alpha, hipStream_t s);
+// C[i][j] = alpha * sum_k A[k][i] B[k][j]  (A row-major K x M)
+hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, long long ldb,
+                              double *C, long long ldc, int M, int N, int K, double alpha,
+                              hipStream_t s);
+hipError_t launch_domain_prep(const Domain *dom, int ndom, const double *S, const double *F,
+                              const double *K, long long ld, double tau_S, double *W,
+                              double *Y, double *Kt, double *epst, int *rank, double *minev,
+                              hipStream_t s);
+hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
+                            const int *rank, const double *S, long long ld, const double *W,
+                            double *M, hipStream_t s);
+hipError_t launch_solve(const SolveArgs &a, int nwg, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int v, long long n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, long long n, hipStream_t s);
+hipError_t launch_check_finite(const double *x, long long n, int *flag, hipStream_t s);
+hipError_t launch_check_finite_f32(const float *x, long long n, int *flag, hipStream_t s);
+// fixed-order weighted sums: out[j] = sum_i w[j*n + i] * x[i], j < nw
+hipError_t launch_wdot(const double *x, const double *w, long long n, int nw, double *out,
+                       hipStream_t s);
+// adjoint per domain: G^K blocks into GK (ld), virtual density in OSV basis into Gd
+hipError_t launch_adjoint(const Domain *dom, int ndom, const int *rank, const double *W,
+                          const double *Y, const double *T, const long long *dcp_ptr,
+                          const long long *dcp_toff, const double *dcp_coef, double *GK,
+                          long long ld, double *Gd, hipStream_t s);
+// assemble G^F (nosv x nosv) from per-domain OSV-basis blocks (fixed order)
+hipError_t launch_assemble_gf(const Domain *dom, const long long *blk_ptr,
+                              const int *blk_dom, const int *blk_part, const int2 *blocks,
+                              int nblocks, const int *off, const int *r, const double *Gd,
+                              double *GF, long long ld, hipStream_t s);
+// dE/deps_a = sum_y Qt[y][a] Zt[y][a]
+hipError_t launch_coldot(const double *Qt, const double *Zt, int nosv, int nvir,
+                         double *out, hipStream_t s);
+// dE/dF: out[u][v] = sum over clusters of c_X * Pl (CSR per entry, fixed order)
+hipError_t launch_pocc(const long long *ptr, const long long *idx, const double *coef,
+                       const double *Pl, int nocc, double *out, hipStream_t s);
+}  // namespace osv
+namespace osv {
+hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
+                              int nocc, double *out, hipStream_t s);
+}
