@@ -201,11 +201,18 @@ const char *osv_status_string(int status);
 /* last error message recorded on ctx (or the library-wide one for NULL); never NULL */
 const char *osv_last_error(const osv_ctx *ctx);
 
-/* stage timings of the last build/solve/energy/densities on ctx, milliseconds
- * (HIP events on the caller's stream); host out [8]:
+/* stage timings of the last build/solve/energy/densities on ctx, milliseconds,
+ * from HIP events on the caller's stream (stage 8 is host wall time); host out [9]:
  *   0 S/F blocks, 1 K blocks, 2 domain prep, 3 couplings, 4 solve, 5 energy,
- *   6 adjoint (per domain), 7 back-transforms.  Values of stages not run are 0. */
-int osv_stage_times(const osv_ctx *ctx, double *ms8);
+ *   6 adjoint (per domain), 7 back-transforms, 8 host cluster selection + plan.
+ * Values of stages not run are 0. */
+int osv_stage_times(const osv_ctx *ctx, double *ms9);
+
+/* algorithmic floating-point operations of the same stages (host out [9]):
+ * the flops of the mathematical contractions at the kept (unpadded) sizes,
+ * e.g. 2*r_p*r_q*naux per K_pq block and 2*(n_t*n_s^2 + n_t^2*n_s) per residual
+ * term per sweep; the eigensolvers of stage 2 and the host stage 8 count 0. */
+int osv_stage_flops(const osv_ctx *ctx, double *flops9);
 
 #ifdef __cplusplus
 }

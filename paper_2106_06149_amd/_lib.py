@@ -16,7 +16,7 @@ OSV_MAX_DOMAIN = 100
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_densities",
            "osv_plan_clusters", "osv_destroy", "osv_status_string", "osv_last_error",
-           "osv_stage_times"]
+           "osv_stage_times", "osv_stage_flops"]
 
 
 class OsvSystem(ctypes.Structure):
@@ -85,6 +85,8 @@ def load():
     lib.osv_last_error.restype = ctypes.c_char_p
     lib.osv_stage_times.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.osv_stage_times.restype = ctypes.c_int
+    lib.osv_stage_flops.argtypes = [vp, ctypes.POINTER(dbl)]
+    lib.osv_stage_flops.restype = ctypes.c_int
     _lib = lib
     return lib
 

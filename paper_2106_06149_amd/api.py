@@ -130,11 +130,18 @@ class OSVContext:
                                            _ptr(out_F), _ptr(out_e), _ptr(out_D)), self.handle)
         return out_C, out_F, out_e, out_D
 
+    STAGES = ["sf", "k", "prep", "couplings", "solve", "energy", "adjoint", "backtransform",
+              "host_plan"]
+
     def stage_times(self):
-        ms = (ctypes.c_double * 8)()
+        ms = (ctypes.c_double * 9)()
         L.check(self.lib.osv_stage_times(self.handle, ms), self.handle)
-        names = ["sf", "k", "prep", "couplings", "solve", "energy", "adjoint", "backtransform"]
-        return dict(zip(names, ms[:]))
+        return dict(zip(self.STAGES, ms[:]))
+
+    def stage_flops(self):
+        f = (ctypes.c_double * 9)()
+        L.check(self.lib.osv_stage_flops(self.handle, f), self.handle)
+        return dict(zip(self.STAGES, f[:]))
 
     def close(self):
         if self.handle is not None:

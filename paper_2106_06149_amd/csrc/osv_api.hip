@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -312,7 +313,9 @@ struct osv_ctx {
   // state
   bool solved = false;
   std::string err;
-  double stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double stage_ms[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double stage_flops[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<double> flops_sweep;  // per cluster: residual-term flops of one sweep
   std::vector<int> rank_host;
   ~osv_ctx() {
     for (void *p : allocs) (void)hipFree(p);
@@ -444,7 +447,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = upload(ctx, &ctx->dOff, ctx->off, s))) return rc;
   if ((rc = upload(ctx, &ctx->dR, ctx->r, s))) return rc;
 
-  StageTimer t_sf(s);
+  const auto h0 = std::chrono::steady_clock::now();
   // cluster selection
   if (sel->mode == OSV_SEL_DISTANCE) {
     select_distance(nocc, sys->centroid, sel->cut2, sel->cut3, ctx->sel);
@@ -495,7 +498,9 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
   if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
 
+  ctx->stage_ms[8] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   // S and F blocks: one pass over Q^T (rows = OSVs, k = virtuals)
+  StageTimer t_sf(s);
   HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, ctx->eps, ctx->dS, ctx->dF, ld,
                               ctx->dTiles, (int)ctx->tiles.size(), s));
   t_sf.stop();
@@ -538,6 +543,36 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       return fail(ctx, OSV_E_DOMAIN, "pair domain (" + std::to_string(P.doms[d].p) + "," +
                                          std::to_string(P.doms[d].q) + ") has rank 0 after the tau_S cut");
     }
+  {
+    // algorithmic flops of the build stages and of one sweep per cluster
+    const std::vector<int> &rk = ctx->rank_host;
+    double fsf = 0, fk = 0, fc = 0;
+    for (const Domain &D : P.doms) {
+      double rp = D.rp, rq = (D.p == D.q) ? D.rp : D.rq;
+      fsf += (D.p == D.q ? 2.0 : 4.0) * rp * rq * ctx->nvir;
+      fk += 2.0 * rp * rq * ctx->naux;
+    }
+    for (const Coupling &c : P.cpls) {
+      double nA = P.doms[c.A].n, nB = P.doms[c.B].n, dA = rk[c.A], dB = rk[c.B];
+      fc += 2.0 * (nA * dB * nB + dA * dB * nA);
+    }
+    ctx->stage_flops[0] = fsf;
+    ctx->stage_flops[1] = fk;
+    ctx->stage_flops[3] = fc;
+    ctx->flops_sweep.assign(P.cls.size(), 0.0);
+    for (size_t X = 0; X < P.cls.size(); X++) {
+      const Cluster &C = P.cls[X];
+      double f = 0;
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+        double nt = rk[P.cps[c].dom];
+        for (int t = P.cps[c].term0; t < P.cps[c].term0 + P.cps[c].nterm; t++) {
+          double ns = rk[P.cps[P.terms[t].src].dom];
+          f += 2.0 * (nt * ns * ns + nt * nt * ns);
+        }
+      }
+      ctx->flops_sweep[X] = f;
+    }
+  }
   ctx->stage_ms[0] = t_sf.ms();
   ctx->stage_ms[1] = t_k.ms();
   ctx->stage_ms[2] = t_prep.ms();
@@ -729,6 +764,9 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   osv_solve_info inf{};
   inf.converged = 1;
   bool nonfinite = false;
+  double fs = 0;
+  for (int X = 0; X < ncl; X++) fs += ctx->flops_sweep[X] * sw[X];
+  ctx->stage_flops[4] = fs;
   for (int X = 0; X < ncl; X++) {
     inf.sweeps = std::max(inf.sweeps, sw[X]);
     if (mr[X] != mr[X]) nonfinite = true;
@@ -894,12 +932,40 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
   HIPCHK(ctx, hipStreamSynchronize(s));
   ctx->stage_ms[6] = t_adj.ms();
   ctx->stage_ms[7] = t_bt.ms();
+  {
+    double fa = 0, fb = 0;
+    const Selection &S = ctx->sel;
+    std::vector<int> nent(ndom, 0);
+    for (size_t X = 0; X < P.cls.size(); X++) {
+      if (S.coef[X] == 0.0) continue;
+      for (int c = P.cls[X].cp0; c < P.cls[X].cp0 + P.cls[X].ncp; c++) nent[P.cps[c].dom]++;
+    }
+    for (int d = 0; d < ndom; d++) {
+      const Domain &D = P.doms[d];
+      double dt = ctx->rank_host[d], n = D.n, rp = D.rp, rq = (D.p == D.q) ? D.rp : D.rq;
+      fa += nent[d] * 4.0 * dt * dt * dt + 2.0 * n * dt * dt + 2.0 * n * n * dt + 2.0 * dt * dt * rq +
+            2.0 * rp * dt * rq;
+      double mult = (D.p == D.q) ? 1.0 : 2.0;
+      if (dE_dC) fb += mult * 2.0 * rp * rq * ctx->naux;
+      if (dE_deps || Dvir_full) fb += mult * 2.0 * rp * rq * ctx->nvir;
+    }
+    if (dE_deps) fb += 2.0 * N * ctx->nvir;
+    if (Dvir_full) fb += 2.0 * (double)ctx->nvir * ctx->nvir * N;
+    ctx->stage_flops[6] = fa;
+    ctx->stage_flops[7] = fb;
+  }
   return OSV_OK;
 }
 
-int osv_stage_times(const osv_ctx *ctx, double *ms8) {
-  if (!ctx || !ms8) return fail(nullptr, OSV_E_ARG, "osv_stage_times: NULL argument");
-  for (int i = 0; i < 8; i++) ms8[i] = ctx->stage_ms[i];
+int osv_stage_times(const osv_ctx *ctx, double *ms9) {
+  if (!ctx || !ms9) return fail(nullptr, OSV_E_ARG, "osv_stage_times: NULL argument");
+  for (int i = 0; i < 9; i++) ms9[i] = ctx->stage_ms[i];
+  return OSV_OK;
+}
+
+int osv_stage_flops(const osv_ctx *ctx, double *f9) {
+  if (!ctx || !f9) return fail(nullptr, OSV_E_ARG, "osv_stage_flops: NULL argument");
+  for (int i = 0; i < 9; i++) f9[i] = ctx->stage_flops[i];
   return OSV_OK;
 }
 
