@@ -39,280 +39,380 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Cyclic Jacobi: A (n x n, stride LDM) is diagonalised in place, V receives the
-// eigenvectors (columns).  Pair tables c/s/t/pp/qq have room for DMAX/2 pairs.
-__device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, double *tn,
-                           int *pp, int *qq, double *red) {
+// block-wide sum over NT threads (fixed order); red has room for NT/64 values
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < NT / 64; w++) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// Cyclic Jacobi: A (n x n, stride LD) is diagonalised in place, V receives the
+// eigenvectors (columns).  Round-robin ordering: in step st the n/2 disjoint
+// pairs rotate simultaneously; A <- J^T A J is applied as independent 2x2 block
+// updates; a step is a rotation table, a barrier, the updates, a barrier.
+// Threshold rule: |a_pq| <= 1e-17 sqrt(|a_pp a_qq|) or <= 1e-18 ||A||_F is set
+// to zero without a rotation; the solve ends after a sweep with no rotation.
+template <int LD, int NT, int MAXB, int MAXV>
+__device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, int *pp, int *qq,
+                           int *zz, double *red, int *flag) {
   const int tid = threadIdx.x;
   const int nE = n + (n & 1), h = nE / 2, m = nE - 1;
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    int i = e / n, j = e % n;
-    V[i * LDM + j] = (i == j) ? 1.0 : 0.0;
+  for (int e = tid; e < n * n; e += NT) {
+    int i = e / n, j = e - i * n;
+    V[i * LD + j] = (i == j) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  double f2 = 0.0;
+  for (int e = tid; e < n * n; e += NT) {
+    int i = e / n, j = e - i * n;
+    f2 += A[i * LD + j] * A[i * LD + j];
+  }
+  const double absthr = 1e-18 * sqrt(block_sum<NT>(f2, red));
   if (n == 1) return;
-  // scale for the stopping test
-  double d2 = 0.0;
-  for (int i = tid; i < n; i += NTHREADS) d2 += A[i * LDM + i] * A[i * LDM + i];
-  double off2 = 0.0;
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    int i = e / n, j = e % n;
-    if (i != j) off2 += A[i * LDM + j] * A[i * LDM + j];
-  }
-  d2 = wave_sum(d2);
-  off2 = wave_sum(off2);
-  if ((tid & 63) == 0) { red[tid >> 6] = d2; red[4 + (tid >> 6)] = off2; }
-  __syncthreads();
-  double norm2 = red[0] + red[1] + red[2] + red[3] + red[4] + red[5] + red[6] + red[7];
-  __syncthreads();
-  const double tol2 = 1e-32 * norm2;
-  for (int sweep = 0; sweep < 40; sweep++) {
+  // (I, J) of upper-triangle block b (row-major over I <= J < h) and (i, k) of V
+  // entry e = i*h + k, computed each step without divisions
+  const int nb = h * (h + 1) / 2;
+  const unsigned inv_h = ((1u << 20) + h - 1) / h;   // floor(e * inv_h / 2^20) = e / h for e < 2^20 / h
+  const float twoh1 = 2.0f * h + 1.0f;
+  for (int sweep = 0; sweep < 60; sweep++) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
     for (int st = 0; st < m; st++) {
       if (tid < h) {
         int a, b;
-        if (tid == 0) { a = st % m; b = m; } else { a = (st + tid) % m; b = (st - tid + m) % m; }
+        if (tid == 0) { a = st; b = m; } else { a = st + tid; a -= (a >= m) ? m : 0; b = st - tid; b += (b < 0) ? m : 0; }
         int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, s = 0.0, t = 0.0;
+        double c = 1.0, s = 0.0;
+        int z = 0;
         if (q < n) {
-          double apq = A[p * LDM + q];
+          double apq = A[p * LD + q];
           if (apq != 0.0) {
-            double app = A[p * LDM + p], aqq = A[q * LDM + q];
-            double theta = (aqq - app) / (2.0 * apq);
-            double at = fabs(theta);
-            if (at > 1e150) t = 0.5 / theta;
-            else t = (theta >= 0.0 ? 1.0 : -1.0) / (at + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
+            double app = A[p * LD + p], aqq = A[q * LD + q];
+            z = 1;
+            if (!(fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq)) || fabs(apq) <= absthr)) {
+              double theta = (aqq - app) / (2.0 * apq);
+              double at = fabs(theta), t;
+              if (at > 1e150) t = 0.5 / theta;
+              else t = (theta >= 0.0 ? 1.0 : -1.0) / (at + sqrt(theta * theta + 1.0));
+              c = 1.0 / sqrt(t * t + 1.0);
+              s = t * c;
+              *flag = 1;
+            }
           }
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s; tn[tid] = t;
+        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s; zz[tid] = z;
       }
       __syncthreads();
-      // A <- J^T A J as 2x2 block updates over pairs (I <= J)
-      const int nb = h * (h + 1) / 2;
-      for (int bidx = tid; bidx < nb; bidx += NTHREADS) {
-        // invert bidx -> (I, J) with I <= J, row-major over the upper triangle
-        int I = 0, rem = bidx;
-        while (rem >= h - I) { rem -= h - I; I++; }
-        int J = I + rem;
-        int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
-        double cI = cs[I], sI = sn[I], cJ = cs[J], sJ = sn[J];
+      for (int b = tid; b < nb; b += NT) {
+        int I = (int)((twoh1 - sqrtf(twoh1 * twoh1 - 8.0f * b)) * 0.5f);
+        if (I < 0) I = 0;
+        while (I + 1 < h && (I + 1) * h - ((I + 1) * I) / 2 <= b) I++;
+        while (I > 0 && I * h - (I * (I - 1)) / 2 > b) I--;
+        const int J = I + (b - (I * h - (I * (I - 1)) / 2));
+        const int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
+        const double cI = cs[I], sI = sn[I], cJ = cs[J], sJ = sn[J];
         if (I == J) {
-          if (qI < n && sI != 0.0) {
-            double apq = A[pI * LDM + qI];
-            A[pI * LDM + pI] -= tn[I] * apq;
-            A[qI * LDM + qI] += tn[I] * apq;
-            A[pI * LDM + qI] = 0.0;
-            A[qI * LDM + pI] = 0.0;
+          if (qI < n && zz[I]) {
+            const double apq = A[pI * LD + qI];
+            if (sI != 0.0) {
+              const double tt = sI / cI;
+              A[pI * LD + pI] -= tt * apq;
+              A[qI * LD + qI] += tt * apq;
+            }
+            A[pI * LD + qI] = 0.0;
+            A[qI * LD + pI] = 0.0;
           }
-        } else {
-          bool vqI = qI < n, vqJ = qJ < n;
-          double b00 = A[pI * LDM + pJ];
-          double b01 = vqJ ? A[pI * LDM + qJ] : 0.0;
-          double b10 = vqI ? A[qI * LDM + pJ] : 0.0;
-          double b11 = (vqI && vqJ) ? A[qI * LDM + qJ] : 0.0;
-          // rows: R_I^T B  with R = [[c, s], [-s, c]]
-          double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
-          double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
-          // cols: (.) R_J
-          double n00 = r00 * cJ - r01 * sJ, n01 = r00 * sJ + r01 * cJ;
-          double n10 = r10 * cJ - r11 * sJ, n11 = r10 * sJ + r11 * cJ;
-          A[pI * LDM + pJ] = n00; A[pJ * LDM + pI] = n00;
-          if (vqJ) { A[pI * LDM + qJ] = n01; A[qJ * LDM + pI] = n01; }
-          if (vqI) { A[qI * LDM + pJ] = n10; A[pJ * LDM + qI] = n10; }
-          if (vqI && vqJ) { A[qI * LDM + qJ] = n11; A[qJ * LDM + qI] = n11; }
+        } else if (sI != 0.0 || sJ != 0.0) {
+          const bool vqI = qI < n, vqJ = qJ < n;
+          const double b00 = A[pI * LD + pJ];
+          const double b01 = vqJ ? A[pI * LD + qJ] : 0.0;
+          const double b10 = vqI ? A[qI * LD + pJ] : 0.0;
+          const double b11 = (vqI && vqJ) ? A[qI * LD + qJ] : 0.0;
+          const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
+          const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
+          const double n00 = r00 * cJ - r01 * sJ, n01 = r00 * sJ + r01 * cJ;
+          const double n10 = r10 * cJ - r11 * sJ, n11 = r10 * sJ + r11 * cJ;
+          A[pI * LD + pJ] = n00; A[pJ * LD + pI] = n00;
+          if (vqJ) { A[pI * LD + qJ] = n01; A[qJ * LD + pI] = n01; }
+          if (vqI) { A[qI * LD + pJ] = n10; A[pJ * LD + qI] = n10; }
+          if (vqI && vqJ) { A[qI * LD + qJ] = n11; A[qJ * LD + qI] = n11; }
         }
       }
-      // V <- V J
-      for (int e = tid; e < n * h; e += NTHREADS) {
-        int i = e / h, k = e % h;
-        int p = pp[k], q = qq[k];
-        if (q < n) {
-          double c = cs[k], s = sn[k];
-          double vp = V[i * LDM + p], vq = V[i * LDM + q];
-          V[i * LDM + p] = c * vp - s * vq;
-          V[i * LDM + q] = s * vp + c * vq;
+      for (int e = tid; e < n * h; e += NT) {
+        const int i = (int)(((unsigned long long)e * inv_h) >> 20);
+        const int k = e - i * h;
+        const double s = sn[k];
+        if (s != 0.0) {
+          const int p = pp[k], q = qq[k];
+          const double c = cs[k];
+          const double vp = V[i * LD + p], vq = V[i * LD + q];
+          V[i * LD + p] = c * vp - s * vq;
+          V[i * LD + q] = s * vp + c * vq;
         }
       }
       __syncthreads();
     }
-    off2 = 0.0;
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      if (i != j) off2 += A[i * LDM + j] * A[i * LDM + j];
-    }
-    off2 = wave_sum(off2);
-    if ((tid & 63) == 0) red[tid >> 6] = off2;
+    const int any = *flag;
     __syncthreads();
-    double tot = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
-    if (tot <= tol2) break;
+    if (!any) break;
   }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_domain_prep(const Domain *__restrict__ doms,
-                                                          const double *__restrict__ S,
-                                                          const double *__restrict__ F,
-                                                          const double *__restrict__ K,
-                                                          long long ld, double tau_S, double *W,
-                                                          double *Y, double *Kt, double *epst,
-                                                          int *rank, double *minev) {
-  __shared__ double L1[DMAX * LDM];
-  __shared__ double L2[DMAX * LDM];
-  __shared__ double cs[DMAX / 2], sn[DMAX / 2], tn[DMAX / 2];
-  __shared__ int pp[DMAX / 2], qq[DMAX / 2];
-  __shared__ double red[8];
-  __shared__ int keep_idx[DMAX];
-  __shared__ int s_dt;
-  const Domain D = doms[blockIdx.x];
+// Pair-domain preparation, one workgroup of NT threads per domain of dimension
+// n <= NM (LDS work matrices NM x (NM+1)).
+template <int NM, int NT>
+__global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ doms,
+                                                    const int *__restrict__ ids,
+                                                    const double *__restrict__ S,
+                                                    const double *__restrict__ F,
+                                                    const double *__restrict__ K, long long ld,
+                                                    double tau_S, double *W, double *Y,
+                                                    double *Kt, double *epst, int *rank,
+                                                    double *minev) {
+  constexpr int LD = NM + 1;
+  constexpr int HM = NM / 2;
+  constexpr int MAXB = (HM * (HM + 1) / 2 + NT - 1) / NT;
+  constexpr int MAXV = (NM * HM + NT - 1) / NT;
+  __shared__ double L1[NM * LD];
+  __shared__ double L2[NM * LD];
+  __shared__ double cs[HM], sn[HM];
+  __shared__ int pp[HM], qq[HM], zz[HM];
+  __shared__ double red[NT / 64];
+  __shared__ int keep_idx[NM];
+  __shared__ int s_dt, s_flag;
+  const int dom_id = ids[blockIdx.x];
+  const Domain D = doms[dom_id];
   const int tid = threadIdx.x, n = D.n;
   const bool diag = (D.p == D.q);
   double *Wg = W + D.moff, *Yg = Y + D.moff, *Kg = Kt + D.moff, *eg = epst + D.voff;
   int dt;
   if (!diag) {
-    // 1) S_(pq,pq) = U s U^T ; X = U_kept s_kept^{-1/2}
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      L1[i * LDM + j] = comp_elem(S, ld, D, D, i, j, true);
+    const int rp = D.rp, rq = D.rq;
+    const double *Bg = S + (long long)D.offp * ld + D.offq;   // B = S_pq (rp x rq, ld)
+    // 1) canonical orthogonalisation.  Block Gram-Schmidt: Q_q' = Q_q - Q_p B has
+    //    overlap A = 1 - B^T B = L L^T, so X = [[1, -B L^-T], [0, L^-T]] gives
+    //    X^T S X = 1.  The overlap eigenvalues are 1 +- sigma_k(B) (and 1), so all of
+    //    them exceed tau_S iff lambda_min(A) > tau_S (2 - tau_S); since
+    //    lambda_min(A) >= 1 / trace(A^-1) = 1 / ||L^-1||_F^2, that bound certifies
+    //    that nothing is dropped.  Otherwise the overlap eigenvalues are cut
+    //    explicitly (eigendecomposition of S_(pq,pq)).
+    for (int e = tid; e < rq * rq; e += NT) {
+      int i = e / rq, j = e - i * rq;
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int k = 0; k < rp; k++) s -= Bg[(long long)k * ld + i] * Bg[(long long)k * ld + j];
+      L1[i * LD + j] = s;
     }
     __syncthreads();
-    jacobi_eig(L1, L2, n, cs, sn, tn, pp, qq, red);
-    if (tid == 0) {
-      int c = 0;
-      double mn = 1e300;
-      for (int k = 0; k < n; k++) {
-        double sk = L1[k * LDM + k];
-        if (sk < mn) mn = sk;
-        if (sk > tau_S) keep_idx[c++] = k;
+    // right-looking Cholesky (lower triangle of L1)
+    for (int j = 0; j < rq; j++) {
+      const double d = L1[j * LD + j];
+      __syncthreads();
+      if (!(d > 0.0)) break;  // uniform: every thread read the same d
+      const double sd = sqrt(d);
+      for (int i = j + 1 + tid; i < rq; i += NT) L1[i * LD + j] /= sd;
+      __syncthreads();
+      if (tid == 0) L1[j * LD + j] = sd;
+      for (int e = tid; e < (rq - j - 1) * (rq - j - 1); e += NT) {
+        int i = j + 1 + e / (rq - j - 1), k = j + 1 + e % (rq - j - 1);
+        if (k <= i) L1[i * LD + k] -= L1[i * LD + j] * L1[k * LD + j];
       }
-      s_dt = c;
-      minev[blockIdx.x] = mn;
+      __syncthreads();
     }
-    __syncthreads();
-    dt = s_dt;
-    // X (n x dt) into the Y slot (global scratch)
-    for (int e = tid; e < n * dt; e += NTHREADS) {
-      int i = e / dt, c = e % dt;
-      int k = keep_idx[c];
-      Yg[i * n + c] = L2[i * LDM + k] / sqrt(L1[k * LDM + k]);
+    bool chol_ok = true;
+    for (int j = 0; j < rq; j++) chol_ok = chol_ok && (L1[j * LD + j] > 0.0);
+    // L^-1 by forward substitution, one column per thread (lower triangle of L2)
+    double tr = 0.0;
+    if (chol_ok) {
+      for (int c = tid; c < rq; c += NT) {
+        for (int i = 0; i < rq; i++) {
+          double x;
+          if (i < c) {
+            x = 0.0;
+          } else {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = c; k < i; k++) s -= L1[i * LD + k] * L2[k * LD + c];
+            x = s / L1[i * LD + i];
+          }
+          L2[i * LD + c] = x;
+          tr += x * x;
+        }
+      }
     }
-    __syncthreads();
+    tr = block_sum<NT>(tr, red);
+    const bool gs = chol_ok && (1.0 / tr > tau_S * (2.0 - tau_S));
+    if (gs) {
+      // X = [[1, -B Z], [0, Z]], Z = L^-T (upper): X into the Y slot (global scratch)
+      for (int e = tid; e < n * n; e += NT) {
+        int i = e / n, j = e - i * n;
+        double x;
+        if (j < rp) {
+          x = (i == j) ? 1.0 : 0.0;
+        } else {
+          const int jj = j - rp;
+          if (i < rp) {
+            double s = 0.0;
+            for (int k = 0; k <= jj; k++) s -= Bg[(long long)i * ld + k] * L2[jj * LD + k];
+            x = s;
+          } else {
+            const int ii = i - rp;
+            x = (ii <= jj) ? L2[jj * LD + ii] : 0.0;
+          }
+        }
+        Yg[i * n + j] = x;
+      }
+      if (tid == 0) { s_dt = n; minev[dom_id] = 1.0 / tr; }
+      __syncthreads();
+      dt = n;
+    } else {
+      // eigenvalue cut of S_(pq,pq) = U s U^T: X = U_kept s_kept^{-1/2}
+      for (int e = tid; e < n * n; e += NT) {
+        int i = e / n, j = e - i * n;
+        L1[i * LD + j] = comp_elem(S, ld, D, D, i, j, true);
+      }
+      __syncthreads();
+      jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, cs, sn, pp, qq, zz, red, &s_flag);
+      if (tid == 0) {
+        int c = 0;
+        double mn = 1e300;
+        for (int k = 0; k < n; k++) {
+          double sk = L1[k * LD + k];
+          if (sk < mn) mn = sk;
+          if (sk > tau_S) keep_idx[c++] = k;
+        }
+        s_dt = c;
+        minev[dom_id] = mn;
+      }
+      __syncthreads();
+      dt = s_dt;
+      for (int e = tid; e < n * dt; e += NT) {
+        int i = e / dt, c = e - i * dt;
+        int k = keep_idx[c];
+        Yg[i * n + c] = L2[i * LD + k] / sqrt(L1[k * LD + k]);
+      }
+      __syncthreads();
+    }
     // 2) L1 = F_(pq,pq) X (n x dt)
-    for (int e = tid; e < n * dt; e += NTHREADS) {
-      int i = e / dt, j = e % dt;
+    for (int e = tid; e < n * dt; e += NT) {
+      int i = e / dt, j = e - i * dt;
       double s = 0.0;
       for (int k = 0; k < n; k++) s += comp_elem(F, ld, D, D, i, k, false) * Yg[k * n + j];
-      L1[i * LDM + j] = s;
+      L1[i * LD + j] = s;
     }
     __syncthreads();
-    // H = X^T L1 (dt x dt) into L2
-    for (int e = tid; e < dt * dt; e += NTHREADS) {
-      int i = e / dt, j = e % dt;
+    // H = X^T L1 (dt x dt) into L2, symmetrised into L1
+    for (int e = tid; e < dt * dt; e += NT) {
+      int i = e / dt, j = e - i * dt;
       double s = 0.0;
-      for (int k = 0; k < n; k++) s += Yg[k * n + i] * L1[k * LDM + j];
-      L2[i * LDM + j] = s;
+      for (int k = 0; k < n; k++) s += Yg[k * n + i] * L1[k * LD + j];
+      L2[i * LD + j] = s;
     }
     __syncthreads();
-    for (int e = tid; e < dt * dt; e += NTHREADS) {
-      int i = e / dt, j = e % dt;
-      L1[i * LDM + j] = 0.5 * (L2[i * LDM + j] + L2[j * LDM + i]);
+    for (int e = tid; e < dt * dt; e += NT) {
+      int i = e / dt, j = e - i * dt;
+      L1[i * LD + j] = 0.5 * (L2[i * LD + j] + L2[j * LD + i]);
     }
     __syncthreads();
-    jacobi_eig(L1, L2, dt, cs, sn, tn, pp, qq, red);
-    for (int a = tid; a < dt; a += NTHREADS) eg[a] = L1[a * LDM + a];
+    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, cs, sn, pp, qq, zz, red, &s_flag);
+    for (int a = tid; a < dt; a += NT) eg[a] = L1[a * LD + a];
     __syncthreads();
     // W = X V (n x dt) into L1, then to global
-    for (int e = tid; e < n * dt; e += NTHREADS) {
-      int i = e / dt, j = e % dt;
+    for (int e = tid; e < n * dt; e += NT) {
+      int i = e / dt, j = e - i * dt;
       double s = 0.0;
-      for (int k = 0; k < dt; k++) s += Yg[i * n + k] * L2[k * LDM + j];
-      L1[i * LDM + j] = s;
+      for (int k = 0; k < dt; k++) s += Yg[i * n + k] * L2[k * LD + j];
+      L1[i * LD + j] = s;
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      Wg[i * n + j] = (j < dt) ? L1[i * LDM + j] : 0.0;
+    for (int e = tid; e < n * n; e += NT) {
+      int i = e / n, j = e - i * n;
+      Wg[i * n + j] = (j < dt) ? L1[i * LD + j] : 0.0;
     }
     __syncthreads();
-    // 3) Y = W^T S_(pq,pq) (dt x n) into L2 and global
-    for (int e = tid; e < dt * n; e += NTHREADS) {
-      int a = e / n, j = e % n;
+    // 3) Y = W^T S_(pq,pq) (dt x n) into L2
+    for (int e = tid; e < dt * n; e += NT) {
+      int a = e / n, j = e - a * n;
       double s = 0.0;
-      for (int k = 0; k < n; k++) s += L1[k * LDM + a] * comp_elem(S, ld, D, D, k, j, true);
-      L2[a * LDM + j] = s;
+      for (int k = 0; k < n; k++) s += L1[k * LD + a] * comp_elem(S, ld, D, D, k, j, true);
+      L2[a * LD + j] = s;
     }
     __syncthreads();
   } else {
     // diagonal domain: S = 1, W = eigenvectors of F_pp
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      L1[i * LDM + j] = F[(long long)(D.offp + i) * ld + (D.offp + j)];
+    for (int e = tid; e < n * n; e += NT) {
+      int i = e / n, j = e - i * n;
+      L1[i * LD + j] = 0.5 * (F[(long long)(D.offp + i) * ld + (D.offp + j)] +
+                              F[(long long)(D.offp + j) * ld + (D.offp + i)]);
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      L2[i * LDM + j] = 0.5 * (L1[i * LDM + j] + L1[j * LDM + i]);
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      L1[i * LDM + j] = L2[i * LDM + j];
-    }
-    __syncthreads();
-    jacobi_eig(L1, L2, n, cs, sn, tn, pp, qq, red);
+    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, cs, sn, pp, qq, zz, red, &s_flag);
     dt = n;
-    if (tid == 0) minev[blockIdx.x] = 1.0;
-    for (int a = tid; a < n; a += NTHREADS) eg[a] = L1[a * LDM + a];
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int i = e / n, j = e % n;
-      Wg[i * n + j] = L2[i * LDM + j];
+    if (tid == 0) minev[dom_id] = 1.0;
+    for (int a = tid; a < n; a += NT) eg[a] = L1[a * LD + a];
+    for (int e = tid; e < n * n; e += NT) {
+      int i = e / n, j = e - i * n;
+      Wg[i * n + j] = L2[i * LD + j];
     }
     __syncthreads();
     // Y = W^T
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int a = e / n, j = e % n;
-      L1[a * LDM + j] = L2[j * LDM + a];
+    for (int e = tid; e < n * n; e += NT) {
+      int a = e / n, j = e - a * n;
+      L1[a * LD + j] = L2[j * LD + a];
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += NTHREADS) {
-      int a = e / n, j = e % n;
-      L2[a * LDM + j] = L1[a * LDM + j];
+    for (int e = tid; e < n * n; e += NT) {
+      int a = e / n, j = e - a * n;
+      L2[a * LD + j] = L1[a * LD + j];
     }
     __syncthreads();
   }
   // Y (dt x n) is in L2: store it
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    int a = e / n, j = e % n;
-    Yg[a * n + j] = (a < dt) ? L2[a * LDM + j] : 0.0;
+  for (int e = tid; e < n * n; e += NT) {
+    int a = e / n, j = e - a * n;
+    Yg[a * n + j] = (a < dt) ? L2[a * LD + j] : 0.0;
   }
   // 4) K~ = Y_p K_pq Y_q^T: L1 = Y_p K_pq (dt x rq), then K~ = L1 Y_q^T
   const int rq = diag ? D.rp : D.rq;
   const int offq = diag ? D.offp : D.offq;
   const int qcol = diag ? 0 : D.rp;
-  for (int e = tid; e < dt * rq; e += NTHREADS) {
-    int a = e / rq, j = e % rq;
+  for (int e = tid; e < dt * rq; e += NT) {
+    int a = e / rq, j = e - a * rq;
     double s = 0.0;
-    for (int k = 0; k < D.rp; k++) s += L2[a * LDM + k] * K[(long long)(D.offp + k) * ld + (offq + j)];
-    L1[a * LDM + j] = s;
+    for (int k = 0; k < D.rp; k++) s += L2[a * LD + k] * K[(long long)(D.offp + k) * ld + (offq + j)];
+    L1[a * LD + j] = s;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    int a = e / n, b = e % n;
+  for (int e = tid; e < n * n; e += NT) {
+    int a = e / n, b = e - a * n;
     double s = 0.0;
     if (a < dt && b < dt)
-      for (int k = 0; k < rq; k++) s += L1[a * LDM + k] * L2[b * LDM + qcol + k];
+      for (int k = 0; k < rq; k++) s += L1[a * LD + k] * L2[b * LD + qcol + k];
     Kg[a * n + b] = s;
   }
-  if (tid == 0) rank[blockIdx.x] = dt;
+  if (tid == 0) rank[dom_id] = dt;
 }
 
-hipError_t launch_domain_prep(const Domain *dom, int ndom, const double *S, const double *F,
-                              const double *K, long long ld, double tau_S, double *W,
-                              double *Y, double *Kt, double *epst, int *rank, double *minev,
-                              hipStream_t s) {
-  if (ndom <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_domain_prep, dim3(ndom), dim3(NTHREADS), 0, s, dom, S, F, K, ld, tau_S, W,
-                     Y, Kt, epst, rank, minev);
+hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
+                              const double *S, const double *F, const double *K, long long ld,
+                              double tau_S, double *W, double *Y, double *Kt, double *epst,
+                              int *rank, double *minev, hipStream_t s) {
+  // counts3: number of domains with n <= 32, 32 < n <= 64, 64 < n <= DMAX, in that
+  // order in ids[]
+  int o = 0;
+  if (counts3[0] > 0)
+    hipLaunchKernelGGL((k_domain_prep<32, 256>), dim3(counts3[0]), dim3(256), 0, s, dom, ids + o, S, F,
+                       K, ld, tau_S, W, Y, Kt, epst, rank, minev);
+  o += counts3[0];
+  if (counts3[1] > 0)
+    hipLaunchKernelGGL((k_domain_prep<64, 1024>), dim3(counts3[1]), dim3(1024), 0, s, dom, ids + o, S, F,
+                       K, ld, tau_S, W, Y, Kt, epst, rank, minev);
+  o += counts3[1];
+  if (counts3[2] > 0)
+    hipLaunchKernelGGL((k_domain_prep<DMAX, 1024>), dim3(counts3[2]), dim3(1024), 0, s, dom, ids + o, S, F,
+                       K, ld, tau_S, W, Y, Kt, epst, rank, minev);
   return hipGetLastError();
 }
 

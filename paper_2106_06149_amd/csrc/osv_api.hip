@@ -292,7 +292,7 @@ struct osv_ctx {
   double *dEpst = nullptr, *dMinev = nullptr, *dM = nullptr, *dT = nullptr, *dRs = nullptr;
   double *dEcl = nullptr, *dPl = nullptr, *dMaxres = nullptr, *dWts = nullptr, *dEout = nullptr;
   int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
-  int *dOff = nullptr, *dR = nullptr;
+  int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr;
   Domain *dDom = nullptr;
   Coupling *dCpl = nullptr;
   CPair *dCp = nullptr;
@@ -527,8 +527,22 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = dalloc(ctx, &ctx->dEpst, P.n_vec))) return rc;
   if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
   if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
-  HIPCHK(ctx, launch_domain_prep(ctx->dDom, ndom, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S, ctx->dW, ctx->dY,
-                                 ctx->dKt, ctx->dEpst, ctx->dRank, ctx->dMinev, s));
+  {
+    // domains by LDS size class (n <= 32, <= 64, <= DMAX)
+    std::vector<int> ids;
+    int cnt[3] = {0, 0, 0};
+    for (int c = 0; c < 3; c++)
+      for (int d = 0; d < ndom; d++) {
+        int n = P.doms[d].n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+        if (cls == c) {
+          ids.push_back(d);
+          cnt[c]++;
+        }
+      }
+    if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
+    HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds, cnt, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S,
+                                   ctx->dW, ctx->dY, ctx->dKt, ctx->dEpst, ctx->dRank, ctx->dMinev, s));
+  }
   t_prep.stop();
   StageTimer t_cpl(s);
   if ((rc = dalloc(ctx, &ctx->dM, P.n_M))) return rc;

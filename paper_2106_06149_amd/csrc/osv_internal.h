@@ -103,10 +103,10 @@ hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, i
 hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, long long ldb,
                               double *C, long long ldc, int M, int N, int K, double alpha,
                               hipStream_t s);
-hipError_t launch_domain_prep(const Domain *dom, int ndom, const double *S, const double *F,
-                              const double *K, long long ld, double tau_S, double *W,
-                              double *Y, double *Kt, double *epst, int *rank, double *minev,
-                              hipStream_t s);
+hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
+                              const double *S, const double *F, const double *K, long long ld,
+                              double tau_S, double *W, double *Y, double *Kt, double *epst,
+                              int *rank, double *minev, hipStream_t s);
 hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
                             const int *rank, const double *S, long long ld, const double *W,
                             double *M, hipStream_t s);
