@@ -297,6 +297,7 @@ struct osv_ctx {
   Coupling *dCpl = nullptr;
   CPair *dCp = nullptr;
   Term *dTerms = nullptr;
+  TermFlat *dTflat = nullptr;
   Cluster *dCl = nullptr;
   int2 *dTiles = nullptr;
   void *dHi = nullptr, *dMid = nullptr, *dLo = nullptr;
@@ -597,6 +598,9 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   ctx->nwg = std::max(1, std::min(ncl, 2 * ncu));
+  if ((rc = dalloc(ctx, &ctx->dTflat, P.terms.size()))) return rc;
+  HIPCHK(ctx, launch_term_flat(ctx->dTerms, (long long)P.terms.size(), ctx->dCp, ctx->dCpl, ctx->dDom,
+                               ctx->dRank, ctx->F, nocc, ctx->dTflat, s));
   if ((rc = dalloc(ctx, &ctx->dT, P.n_T))) return rc;
   if ((rc = dalloc(ctx, &ctx->dRs, (size_t)ctx->nwg * P.rs_stride))) return rc;
   if ((rc = dalloc(ctx, &ctx->dEcl, ncl))) return rc;
@@ -745,6 +749,7 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   a.cl = ctx->dCl;
   a.cp = ctx->dCp;
   a.terms = ctx->dTerms;
+  a.tflat = ctx->dTflat;
   a.dom = ctx->dDom;
   a.dom_rank = ctx->dRank;
   a.cpl = ctx->dCpl;

@@ -54,7 +54,19 @@ struct Cluster {
   long long poff;     // offset of the nlmo x nlmo block of dE/dF inner products
 };
 
+// Everything the solve kernel needs about one term, gathered once after the
+// pair domains are prepared (one aligned 48-byte load per term).
+struct TermFlat {
+  long long tsrc;   // amplitude offset of the source pair
+  long long moff;   // coupling offset
+  double coef;      // -f[fa][fb]
+  int ldT, ldM;     // slot leading dimensions of the source amplitudes and of M
+  int ns;           // kept rank of the source domain
+  int flags;        // bit0: use M^T, bit1: use T^T
+};
+
 struct SolveArgs {
+  const TermFlat *tflat;
   const Cluster *cl;
   const CPair *cp;
   const Term *terms;
@@ -111,6 +123,9 @@ hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
                             const int *rank, const double *S, long long ld, const double *W,
                             double *M, hipStream_t s);
 hipError_t launch_solve(const SolveArgs &a, int nwg, hipStream_t s);
+hipError_t launch_term_flat(const Term *terms, long long nterms, const CPair *cp,
+                            const Coupling *cpl, const Domain *dom, const int *rank,
+                            const double *F_occ, int nocc, TermFlat *out, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int v, long long n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, long long n, hipStream_t s);
 hipError_t launch_check_finite(const double *x, long long n, int *flag, hipStream_t s);
