@@ -7,8 +7,8 @@
 // All of them are written as one 64x64-tile MFMA kernel over the full
 // sum(r) x sum(r) (or sum(r) x n) index space; a tile list skips tiles that
 // hold no needed orbital-pair block.  FP64 tiles use v_mfma_f64_16x16x4f64,
-// the mixed-precision K uses v_mfma_f32_16x16x32_bf16 on hi/mid/lo bfloat16
-// splits of the FP32 input, with each 32-long k-chunk flushed into FP64.
+// the mixed-precision K uses v_mfma_f32_16x16x32_bf16 on exact bfloat16 digit
+// splits of the FP32 input with exact FP32 accumulation flushed into FP64.
 #include "osv_internal.h"
 
 namespace osv {
@@ -162,72 +162,119 @@ hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, l
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision K = C C^T.  C (FP32) = hi + mid + lo exactly, each bfloat16
-// (8 significant bits each).  Products of two bfloat16 are exact in FP32; the
-// product set is chosen by nterms: 3 -> hh, hm, mh; 6 -> + hl, lh, mm; 9 -> all.
-// Each 32-long k-chunk is accumulated by MFMA in FP32 and then added in FP64.
+// Mixed precision K = C C^T from exact bfloat16 digits.
+//
+// Each row i of the FP32 input C is scaled by a power of two s_i so that
+// |x| = |C[i][P]| / s_i < 1/2, and x is split into ND signed integer digits
+//   x = sum_k d_k 2^(-8(k+1)) + r,   |d_k| <= 128,   |r| <= 2^(-8 ND - 1)
+// (round to nearest at each level; every step is exact in FP32).  Integers of
+// magnitude <= 128 are exact in bfloat16, products of two digits are integers
+// <= 2^14, and the bf16 MFMA accumulates them in FP32 exactly as long as a
+// partial sum stays below 2^24: one FP32 accumulator per level l = a + b holds
+// at most (l + 1) * 128 products per flush (128 k), i.e. < 2^24.  Levels
+// l <= ND - 1 are kept; each flushed level sum is added into FP64 with weight
+// 2^(-8 l).  K_ij = s_i s_j 2^-16 sum_l 2^(-8l) S_l.  The only error is the
+// truncation r of C (and the dropped levels l >= ND), both below
+// 2^(-8 ND) s_i per element: the method of error-free splitting of a product
+// into exact low-precision products (Ozaki, Ogita, Oishi and Rump, Numer.
+// Algorithms 59 (2012) 95-118), here with per-row power-of-two scaling.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ __bf16 f2bf(float x) { return (__bf16)x; }  // round to nearest even
+constexpr int ND = 5;  // bf16 digits per element
 
-__global__ void k_split_bf16(const float *__restrict__ x, long long n, __bf16 *hi, __bf16 *mid,
-                             __bf16 *lo) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    float v = x[i];
-    __bf16 h = f2bf(v);
-    float r1 = v - (float)h;
-    __bf16 m = f2bf(r1);
-    float r2 = r1 - (float)m;
-    hi[i] = h;
-    mid[i] = m;
-    lo[i] = f2bf(r2);
+// per-row exponent: s_i = 2^e_i with max_P |C[i][P]| < 2^(e_i - 1)
+__global__ __launch_bounds__(256) void k_row_scale(const float *__restrict__ C, long long ld,
+                                                   int ncol, int *exps) {
+  __shared__ float red[4];
+  const int i = blockIdx.x;
+  float m = 0.0f;
+  for (int c = threadIdx.x; c < ncol; c += 256) m = fmaxf(m, fabsf(C[(long long)i * ld + c]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int e = 0;
+    if (t > 0.0f) {
+      int ex;
+      frexpf(t, &ex);  // t = f 2^ex, f in [0.5, 1)  ->  t < 2^ex
+      e = ex + 1;      // |x| = |c| / 2^e < 1/2
+    }
+    exps[i] = e;
   }
 }
 
-hipError_t launch_split_bf16(const float *A, long long n, void *hi, void *mid, void *lo,
-                             hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+__global__ void k_split_digits(const float *__restrict__ C, long long ld, int nrow, int ncol,
+                               const int *__restrict__ exps, __bf16 *dig) {
+  const long long n = (long long)nrow * ncol;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / ncol), c = (int)(t - (long long)i * ncol);
+    float x = ldexpf(C[(long long)i * ld + c], -exps[i]);
+#pragma unroll
+    for (int k = 0; k < ND; k++) {
+      const float y = ldexpf(x, 8 * (k + 1));
+      const float d = rintf(y);
+      x -= ldexpf(d, -8 * (k + 1));
+      dig[(long long)k * n + t] = (__bf16)d;
+    }
+  }
+}
+
+hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
+                               hipStream_t s) {
+  if (nrow <= 0 || ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_scale, dim3(nrow), dim3(256), 0, s, C, (long long)ncol, ncol, exps);
+  const long long n = (long long)nrow * ncol;
   long long nb = (n + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)nb), dim3(256), 0, s, A, n, (__bf16 *)hi,
-                     (__bf16 *)mid, (__bf16 *)lo);
+  hipLaunchKernelGGL(k_split_digits, dim3((unsigned)nb), dim3(256), 0, s, C, (long long)ncol, nrow,
+                     ncol, (const int *)exps, (__bf16 *)dig);
   return hipGetLastError();
 }
 
 constexpr int KB = 32;        // k per bf16 MFMA step
 constexpr int LDB16 = KB + 8; // LDS row stride (bf16 elements): 80 bytes
+constexpr int FLUSH = 4;      // k-steps (of 32) between FP32 -> FP64 flushes
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_syrk_bf16x(const __bf16 *__restrict__ hi,
-                                                    const __bf16 *__restrict__ mid,
-                                                    const __bf16 *__restrict__ lo, long long lda,
-                                                    int M, int K, double *C, long long ldc,
-                                                    const int2 *__restrict__ tiles) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[3][TB * LDB16];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[3][TB * LDB16];
+__global__ __launch_bounds__(256) void k_syrk_digits(const __bf16 *__restrict__ dig, int M,
+                                                     int K, const int *__restrict__ exps,
+                                                     double *C, long long ldc,
+                                                     const int2 *__restrict__ tiles) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[ND][TB * LDB16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[ND][TB * LDB16];
+  const long long plane = (long long)M * K;
   int2 t = tiles[blockIdx.x];
   const int ti = t.x, tj = t.y;
   const int i0 = ti * TB, j0 = tj * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const __bf16 *src[3] = {hi, mid, lo};
   d4 acc[2][2];
+  f4 lev[ND][2][2];
   for (int a = 0; a < 2; a++)
-    for (int b = 0; b < 2; b++) acc[a][b] = (d4){0, 0, 0, 0};
-  constexpr int NL = (NT == 3) ? 2 : 3;  // split levels that take part
+    for (int b = 0; b < 2; b++) {
+      acc[a][b] = (d4){0, 0, 0, 0};
+      for (int l = 0; l < ND; l++) lev[l][a][b] = (f4){0, 0, 0, 0};
+    }
+  int step = 0;
   for (int k0 = 0; k0 < K; k0 += KB) {
-    // stage 64 rows x 32 k of each level for the row tile and the column tile:
-    // 64*32 = 2048 elements = 256 threads x 8
+    // stage 64 rows x 32 k of every digit plane, row tile and column tile
     {
-      int r = tid >> 2, kq = (tid & 3) * 8;
-      for (int lv = 0; lv < NL; lv++) {
+      const int r = tid >> 2, kq = (tid & 3) * 8;
+      const int gi = i0 + r, gj = j0 + r;
+      for (int lv = 0; lv < ND; lv++) {
         bf8 va, vb;
-        for (int e = 0; e < 8; e++) {
-          int gk = k0 + kq + e;
-          int gi = i0 + r, gj = j0 + r;
-          va[e] = (gi < M && gk < K) ? src[lv][(long long)gi * lda + gk] : (__bf16)0.0f;
-          vb[e] = (gj < M && gk < K) ? src[lv][(long long)gj * lda + gk] : (__bf16)0.0f;
+        const __bf16 *src = dig + (long long)lv * plane;
+        if (gi < M && k0 + kq + 8 <= K) {
+          va = *(const bf8 *)&src[(long long)gi * K + k0 + kq];
+        } else {
+          for (int e = 0; e < 8; e++)
+            va[e] = (gi < M && k0 + kq + e < K) ? src[(long long)gi * K + k0 + kq + e] : (__bf16)0.0f;
+        }
+        if (gj < M && k0 + kq + 8 <= K) {
+          vb = *(const bf8 *)&src[(long long)gj * K + k0 + kq];
+        } else {
+          for (int e = 0; e < 8; e++)
+            vb[e] = (gj < M && k0 + kq + e < K) ? src[(long long)gj * K + k0 + kq + e] : (__bf16)0.0f;
         }
         *(bf8 *)&As[lv][r * LDB16 + kq] = va;
         *(bf8 *)&Bs[lv][r * LDB16 + kq] = vb;
@@ -235,62 +282,60 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x(const __bf16 *__restrict__ h
     }
     __syncthreads();
     const int kq = (lane >> 4) * 8;
-    f4 part[2][2];
-    for (int a = 0; a < 2; a++)
-      for (int b = 0; b < 2; b++) part[a][b] = (f4){0, 0, 0, 0};
-    // small products first, the hi*hi product last
+    bf8 af[ND][2], bfv[ND][2];
 #pragma unroll
-    for (int pi = 0; pi < NT; pi++) {
-      // product list ordered from smallest to largest magnitude
-      const int la_tab[9] = {2, 1, 2, 0, 1, 2, 0, 1, 0};
-      const int lb_tab[9] = {2, 2, 1, 2, 1, 0, 1, 0, 0};
-      const int off = 9 - NT;
-      const int la = la_tab[off + pi], lb = lb_tab[off + pi];
-      bf8 af[2], bfv[2];
+    for (int lv = 0; lv < ND; lv++) {
 #pragma unroll
-      for (int a = 0; a < 2; a++) af[a] = *(const bf8 *)&As[la][(wr + a * 16 + (lane & 15)) * LDB16 + kq];
+      for (int a = 0; a < 2; a++) af[lv][a] = *(const bf8 *)&As[lv][(wr + a * 16 + (lane & 15)) * LDB16 + kq];
 #pragma unroll
-      for (int b = 0; b < 2; b++) bfv[b] = *(const bf8 *)&Bs[lb][(wc + b * 16 + (lane & 15)) * LDB16 + kq];
+      for (int b = 0; b < 2; b++) bfv[lv][b] = *(const bf8 *)&Bs[lv][(wc + b * 16 + (lane & 15)) * LDB16 + kq];
+    }
+#pragma unroll
+    for (int la = 0; la < ND; la++)
+#pragma unroll
+      for (int lb = 0; lb < ND - la; lb++)
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+          for (int b = 0; b < 2; b++)
+            lev[la + lb][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[la][a], bfv[lb][b], lev[la + lb][a][b], 0, 0, 0);
+    __syncthreads();
+    if (++step == FLUSH || k0 + KB >= K) {
+      step = 0;
 #pragma unroll
       for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int b = 0; b < 2; b++)
-          part[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], part[a][b], 0, 0, 0);
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = ND - 1; l >= 0; l--) s += ldexp((double)lev[l][a][b][v], -8 * l);
+            acc[a][b][v] += s;
+#pragma unroll
+            for (int l = 0; l < ND; l++) lev[l][a][b][v] = 0.0f;
+          }
     }
-    // f32 layout: lane l, reg v -> row 4(l>>4) + v, col l & 15.  Convert to the
-    // f64 accumulator layout (row (l>>4) + 4v) by keeping the f32 layout and
-    // storing with the f32 map below.
-    for (int a = 0; a < 2; a++)
-      for (int b = 0; b < 2; b++)
-        for (int v = 0; v < 4; v++) acc[a][b][v] += (double)part[a][b][v];
-    __syncthreads();
   }
+  // f32 accumulator layout: lane l, reg v -> row 4(l>>4) + v, col l & 15
   for (int a = 0; a < 2; a++)
     for (int b = 0; b < 2; b++)
       for (int v = 0; v < 4; v++) {
         int i = i0 + wr + a * 16 + 4 * (lane >> 4) + v;
         int j = j0 + wc + b * 16 + (lane & 15);
         if (i < M && j < M) {
-          C[(long long)i * ldc + j] = acc[a][b][v];
-          if (ti != tj) C[(long long)j * ldc + i] = acc[a][b][v];
+          const double val = ldexp(acc[a][b][v], exps[i] + exps[j] - 16);
+          C[(long long)i * ldc + j] = val;
+          if (ti != tj) C[(long long)j * ldc + i] = val;
         }
       }
 }
 
-hipError_t launch_syrk_bf16x(const void *hi, const void *mid, const void *lo, long long lda,
-                             int M, int K, int nterms, double *C, long long ldc,
-                             const int2 *tiles, int ntiles, hipStream_t s) {
+hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, double *C,
+                              long long ldc, const int2 *tiles, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  dim3 grid(ntiles), block(256);
-  const __bf16 *h = (const __bf16 *)hi, *m = (const __bf16 *)mid, *l = (const __bf16 *)lo;
-  if (nterms == 3)
-    hipLaunchKernelGGL(k_syrk_bf16x<3>, grid, block, 0, s, h, m, l, lda, M, K, C, ldc, tiles);
-  else if (nterms == 6)
-    hipLaunchKernelGGL(k_syrk_bf16x<6>, grid, block, 0, s, h, m, l, lda, M, K, C, ldc, tiles);
-  else if (nterms == 9)
-    hipLaunchKernelGGL(k_syrk_bf16x<9>, grid, block, 0, s, h, m, l, lda, M, K, C, ldc, tiles);
-  else
-    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_syrk_digits, dim3(ntiles), dim3(256), 0, s, (const __bf16 *)dig, M, K,
+                     exps, C, ldc, tiles);
   return hipGetLastError();
 }
 

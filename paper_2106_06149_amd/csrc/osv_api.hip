@@ -300,9 +300,9 @@ struct osv_ctx {
   TermFlat *dTflat = nullptr;
   Cluster *dCl = nullptr;
   int2 *dTiles = nullptr;
-  void *dHi = nullptr, *dMid = nullptr, *dLo = nullptr;
+  void *dDig = nullptr;
+  int *dExps = nullptr;
   int nwg = 1;
-  int mixed_terms = 6;
   // densities (allocated on first use)
   bool dens_ready = false;
   double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
@@ -508,12 +508,11 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   StageTimer t_k(s);
   if (precision == OSV_MIXED) {
     const long long nc = (long long)N * ctx->naux;
-    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dHi, nc))) return rc;
-    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dMid, nc))) return rc;
-    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dLo, nc))) return rc;
-    HIPCHK(ctx, launch_split_bf16((const float *)ctx->C, nc, ctx->dHi, ctx->dMid, ctx->dLo, s));
-    HIPCHK(ctx, launch_syrk_bf16x(ctx->dHi, ctx->dMid, ctx->dLo, ctx->naux, N, ctx->naux, ctx->mixed_terms,
-                                  ctx->dK, ld, ctx->dTiles, (int)ctx->tiles.size(), s));
+    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dDig, 5 * nc))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
+    HIPCHK(ctx, launch_split_digits((const float *)ctx->C, N, ctx->naux, ctx->dExps, ctx->dDig, s));
+    HIPCHK(ctx, launch_syrk_digits(ctx->dDig, N, ctx->naux, ctx->dExps, ctx->dK, ld, ctx->dTiles,
+                                   (int)ctx->tiles.size(), s));
   } else {
     HIPCHK(ctx, launch_syrk_f64(ctx->C, ctx->c_dtype == OSV_DT_F32, ctx->naux, N, ctx->naux, nullptr, ctx->dK,
                                 nullptr, ld, ctx->dTiles, (int)ctx->tiles.size(), s));

@@ -101,12 +101,12 @@ namespace osv {
 hipError_t launch_syrk_f64(const void *A, int a_is_f32, long long lda, int M, int K,
                            const double *w, double *C, double *C2, long long ldc,
                            const int2 *tiles, int ntiles, hipStream_t s);
-// split-bf16 variant for K in mixed mode (A FP32 row-major)
-hipError_t launch_split_bf16(const float *A, long long n, void *hi, void *mid, void *lo,
-                             hipStream_t s);
-hipError_t launch_syrk_bf16x(const void *hi, const void *mid, const void *lo, long long lda,
-                             int M, int K, int nterms, double *C, long long ldc,
-                             const int2 *tiles, int ntiles, hipStream_t s);
+// mixed-precision K: exact bf16 digit planes of the FP32 rows (ND = 5 planes,
+// nrow x ncol each) with per-row power-of-two exponents, then the digit SYRK
+hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
+                               hipStream_t s);
+hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, double *C,
+                              long long ldc, const int2 *tiles, int ntiles, hipStream_t s);
 // C[i][j] = alpha * sum_k A[i][k] B[k][j]  (A row-major M x K, B row-major K x N)
 hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, int b_is_f32,
                               long long ldb, double *C, long long ldc, int M, int N, int K,

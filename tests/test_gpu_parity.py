@@ -123,3 +123,36 @@ def test_error_paths():
     with pytest.raises(L.OSVError) as e:
         OSVContext.from_system(s, device="cuda:0")
     assert e.value.status == L.OSV_E_NONFINITE
+
+
+MIXED_TOL = 1e-6   # Eh: the mixed path's energy bar
+
+
+def test_mixed_split_k_vs_oracle():
+    """Mixed precision: FP32 C, K from exact bf16 digits.  The oracle works in
+    FP64 on the same FP32 values, so the only difference is the digit
+    truncation of C (below 2^-40 of each row's largest element); naux = 150 is
+    not a multiple of the 128-long exact-accumulation window nor of 32."""
+    s = synth.make_system(7, 60, 150, (5, 12), seed=15, cut2=6.5, cut3=4.5,
+                          c_dtype=np.float32, precision=1)
+    say("case mixed nocc=7 nvir=60 naux=150 r=5..12")
+    g = run_gpu(s)
+    ref = O.solve(s)
+    assert abs(g["E"] - ref["E"]) <= MIXED_TOL * 1e-2, (g["E"], ref["E"])
+    assert np.max(np.abs(g["Ecl"] - ref["E_cluster"])) <= MIXED_TOL * 1e-2
+    assert rel_err(g["dC"], ref["dE_dC"]) <= 1e-7
+    assert rel_err(g["dF"], ref["dE_dF"]) <= 1e-7
+    assert rel_err(g["de"], ref["dE_deps"]) <= 1e-7
+
+
+def test_mixed_matches_fp64_large_rows():
+    """Mixed against FP64 GPU path on the same FP32 input, with rows spanning
+    many 64-wide K tiles (nosv = 378) and naux = 1000 (ragged last window)."""
+    s = synth.make_system(30, 200, 1000, (9, 17), seed=16, cut2=6.5, cut3=4.5,
+                          c_dtype=np.float32, precision=1)
+    say("case mixed-vs-fp64 nocc=30 nvir=200 naux=1000")
+    gm = run_gpu(s, precision=1)
+    gd = run_gpu(s, precision=0)
+    assert abs(gm["E"] - gd["E"]) <= MIXED_TOL * 1e-2, (gm["E"], gd["E"])
+    assert np.max(np.abs(gm["Ecl"] - gd["Ecl"])) <= MIXED_TOL * 1e-2
+    assert rel_err(gm["dC"], gd["dC"]) <= 1e-7
