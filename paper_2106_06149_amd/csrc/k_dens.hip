@@ -30,7 +30,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const Domain *__restrict__
   __shared__ double L2[DMAX * LDA];
   const int d = blockIdx.x;
   const Domain D = doms[d];
-  const int n = D.n, dt = rank[d];
+  const int n = D.n, np = D.np, dt = rank[d];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool diag = (D.p == D.q);
   for (int e = tid; e < dt * dt; e += NTHREADS) {
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const Domain *__restrict__
     const double *T = Tall + dcp_toff[en];
     for (int e = tid; e < dt * dt; e += NTHREADS) {
       int i = e / dt, j = e % dt;
-      L1[i * LDA + j] += c * (2.0 * T[i * n + j] - T[j * n + i]);
+      L1[i * LDA + j] += c * (2.0 * T[i * np + j] - T[j * np + i]);
     }
     // g tiles: T^T Tbar + Tbar T^T
     for (int tile = wave; tile < tn * tn; tile += 4) {
@@ -56,12 +56,12 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(const Domain *__restrict__
         const int k = k0 + (lane >> 4);
         double a1 = 0, b1 = 0, a2 = 0, b2 = 0;
         if (ia < dt && k < dt) {
-          a1 = T[k * n + ia];                                  // (T^T)(i,k)
-          a2 = 2.0 * T[ia * n + k] - T[k * n + ia];            // Tbar(i,k)
+          a1 = T[k * np + ia];                                 // (T^T)(i,k)
+          a2 = 2.0 * T[ia * np + k] - T[k * np + ia];          // Tbar(i,k)
         }
         if (jb < dt && k < dt) {
-          b1 = 2.0 * T[k * n + jb] - T[jb * n + k];            // Tbar(k,j)
-          b2 = T[jb * n + k];                                  // (T^T)(k,j)
+          b1 = 2.0 * T[k * np + jb] - T[jb * np + k];         // Tbar(k,j)
+          b2 = T[jb * np + k];                                 // (T^T)(k,j)
         }
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc, 0, 0, 0);

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
                                                     const double *__restrict__ F,
                                                     const double *__restrict__ K, long long ld,
                                                     double tau_S, double *W, double *Y,
-                                                    double *Kt, double *epst, int *rank,
+                                                    double *Kep, int *rank,
                                                     double *minev) {
   constexpr int LD = NM + 1;
   constexpr int HM = NM / 2;
@@ -188,7 +188,10 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
   const Domain D = doms[dom_id];
   const int tid = threadIdx.x, n = D.n;
   const bool diag = (D.p == D.q);
-  double *Wg = W + D.moff, *Yg = Y + D.moff, *Kg = Kt + D.moff, *eg = epst + D.voff;
+  // K~^T (np x np, ld np) and the pseudo-canonical energies (np) share one
+  // zero-padded slot at voff
+  const int np = D.np;
+  double *Wg = W + D.moff, *Yg = Y + D.moff, *Kg = Kep + D.voff, *eg = Kg + np * np;
   int dt;
   if (!diag) {
     const int rp = D.rp, rq = D.rq;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     }
     __syncthreads();
     jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, cs, sn, pp, qq, zz, red, &s_flag);
-    for (int a = tid; a < dt; a += NT) eg[a] = L1[a * LD + a];
+    for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
     __syncthreads();
     // W = X V (n x dt) into L1, then to global
     for (int e = tid; e < n * dt; e += NT) {
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, cs, sn, pp, qq, zz, red, &s_flag);
     dt = n;
     if (tid == 0) minev[dom_id] = 1.0;
-    for (int a = tid; a < n; a += NT) eg[a] = L1[a * LD + a];
+    for (int a = tid; a < np; a += NT) eg[a] = (a < n) ? L1[a * LD + a] : 0.0;
     for (int e = tid; e < n * n; e += NT) {
       int i = e / n, j = e - i * n;
       Wg[i * n + j] = L2[i * LD + j];
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     int a = e / n, j = e - a * n;
     Yg[a * n + j] = (a < dt) ? L2[a * LD + j] : 0.0;
   }
-  // 4) K~ = Y_p K_pq Y_q^T: L1 = Y_p K_pq (dt x rq), then K~ = L1 Y_q^T
+  // 4) K~ = Y_p K_pq Y_q^T: L1 = Y_p K_pq (dt x rq), then K~ = L1 Y_q^T (stored as K~^T)
   const int rq = diag ? D.rp : D.rq;
   const int offq = diag ? D.offp : D.offq;
   const int qcol = diag ? 0 : D.rp;
@@ -385,65 +388,103 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     L1[a * LD + j] = s;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += NT) {
-    int a = e / n, b = e - a * n;
+  // stored transposed and zero-padded: Kg[b np + a] = K~(a, b)
+  for (int e = tid; e < np * np; e += NT) {
+    int b = e / np, a = e - b * np;
     double s = 0.0;
     if (a < dt && b < dt)
       for (int k = 0; k < rq; k++) s += L1[a * LD + k] * L2[b * LD + qcol + k];
-    Kg[a * n + b] = s;
+    Kg[b * np + a] = s;
   }
   if (tid == 0) rank[dom_id] = dt;
 }
 
 hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
                               const double *S, const double *F, const double *K, long long ld,
-                              double tau_S, double *W, double *Y, double *Kt, double *epst,
+                              double tau_S, double *W, double *Y, double *Kep,
                               int *rank, double *minev, hipStream_t s) {
   // counts3: number of domains with n <= 32, 32 < n <= 64, 64 < n <= DMAX, in that
   // order in ids[]
   int o = 0;
   if (counts3[0] > 0)
     hipLaunchKernelGGL((k_domain_prep<32, 256>), dim3(counts3[0]), dim3(256), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, W, Y, Kt, epst, rank, minev);
+                       K, ld, tau_S, W, Y, Kep, rank, minev);
   o += counts3[0];
   if (counts3[1] > 0)
     hipLaunchKernelGGL((k_domain_prep<64, 1024>), dim3(counts3[1]), dim3(1024), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, W, Y, Kt, epst, rank, minev);
+                       K, ld, tau_S, W, Y, Kep, rank, minev);
   o += counts3[1];
   if (counts3[2] > 0)
     hipLaunchKernelGGL((k_domain_prep<DMAX, 1024>), dim3(counts3[2]), dim3(1024), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, W, Y, Kt, epst, rank, minev);
+                       K, ld, tau_S, W, Y, Kep, rank, minev);
   return hipGetLastError();
 }
 
-// M(A,B) = W_A^T S_(A,B) W_B   (dt_A x dt_B in an n_A x n_B slot)
-__global__ __launch_bounds__(NTHREADS) void k_couplings(const Coupling *__restrict__ cpl,
-                                                        const Domain *__restrict__ doms,
-                                                        const int *__restrict__ rank,
-                                                        const double *__restrict__ S, long long ld,
-                                                        const double *__restrict__ W,
-                                                        double *M) {
-  __shared__ double G[DMAX * LDM];
+// Couplings M(A,B) = W_A^T S_(A,B) W_B, one workgroup (8 wave64) per coupling,
+// FP64 MFMA 16x16x4.  G = S_(A,B) W_B (n_A x np_B, zero beyond dt_B) is formed in
+// LDS; the product W_A^T G is then taken once per orientation, so that M(A,B)
+// and M(B,A) = M(A,B)^T are both written with row-contiguous stores over their
+// whole zero-padded np x np slots.
+constexpr int CNT = 512;          // threads per coupling workgroup
+constexpr int LDG = 16 * 7 + 1;   // LDS stride of G (columns < np_B <= 112)
+typedef double d4c __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ cpl,
+                                                   const Domain *__restrict__ doms,
+                                                   const int *__restrict__ rank,
+                                                   const double *__restrict__ S, long long ld,
+                                                   const double *__restrict__ W,
+                                                   double *M) {
+  __shared__ double G[DMAX * LDG];
   const Coupling c = cpl[blockIdx.x];
   const Domain A = doms[c.A], B = doms[c.B];
   const int dtA = rank[c.A], dtB = rank[c.B];
   const double *WA = W + A.moff, *WB = W + B.moff;
-  const int tid = threadIdx.x;
-  // G = S_(A,B) W_B  (n_A x dt_B)
-  for (int e = tid; e < A.n * dtB; e += NTHREADS) {
-    int i = e / dtB, j = e % dtB;
-    double s = 0.0;
-    for (int k = 0; k < B.n; k++) s += comp_elem(S, ld, A, B, i, k, true) * WB[k * B.n + j];
-    G[i * LDM + j] = s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l15 = lane & 15, lhi = lane >> 4;
+  constexpr int NWV = CNT / 64;
+  // 1) G(i, j) = sum_k S_(A,B)(i, k) W_B(k, j); S_(A,B)(i, k) is read as S_(B,A)(k, i),
+  //    which is contiguous in i for a fixed k (S holds both orientations of its blocks)
+  const int ti = (A.n + 15) >> 4, tj = B.np >> 4;
+  for (int tile = wave; tile < ti * tj; tile += NWV) {
+    const int i0 = (tile / tj) * 16, j0 = (tile % tj) * 16;
+    const int i = i0 + l15, j = j0 + l15;
+    d4c acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < B.n; k0 += 4) {
+      const int k = k0 + lhi;
+      const double av = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
+      const double bv = (j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
+    for (int v = 0; v < 4; v++) {
+      const int ii = i0 + 4 * v + lhi;
+      if (ii < A.n) G[ii * LDG + j] = acc[v];
+    }
   }
   __syncthreads();
-  double *Mg = M + c.off;
-  for (int e = tid; e < A.n * B.n; e += NTHREADS) {
-    int a = e / B.n, b = e % B.n;
-    double s = 0.0;
-    if (a < dtA && b < dtB)
-      for (int k = 0; k < A.n; k++) s += WA[k * A.n + a] * G[k * LDM + b];
-    Mg[a * B.n + b] = s;
+  // 2) M(A,B)(a, b) = sum_k W_A(k, a) G(k, b) and M(B,A)(b, a) = sum_k G(k, b) W_A(k, a)
+  //    over the padded ranges (W_A columns beyond dt_A and G columns beyond dt_B are 0)
+  const int ta = A.np >> 4, tb = B.np >> 4, nt1 = ta * tb;
+  double *Mab = M + c.offAB, *Mba = M + c.offBA;
+  for (int tile = wave; tile < 2 * nt1; tile += NWV) {
+    const bool tr = tile >= nt1;
+    const int t2 = tr ? tile - nt1 : tile;
+    const int a0 = (t2 / tb) * 16, b0 = (t2 % tb) * 16;
+    const int a = a0 + l15, b = b0 + l15;
+    d4c acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < A.n; k0 += 4) {
+      const int k = k0 + lhi;
+      const double w = (a < dtA && k < A.n) ? WA[k * A.n + a] : 0.0;
+      const double g = (k < A.n) ? G[k * LDG + b] : 0.0;
+      acc = tr ? __builtin_amdgcn_mfma_f64_16x16x4f64(g, w, acc, 0, 0, 0)
+               : __builtin_amdgcn_mfma_f64_16x16x4f64(w, g, acc, 0, 0, 0);
+    }
+    if (!tr) {
+      for (int v = 0; v < 4; v++) Mab[(long long)(a0 + 4 * v + lhi) * B.np + b] = acc[v];
+    } else {
+      for (int v = 0; v < 4; v++) Mba[(long long)(b0 + 4 * v + lhi) * A.np + a] = acc[v];
+    }
   }
 }
 
@@ -451,7 +492,7 @@ hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom, co
                             const double *S, long long ld, const double *W, double *M,
                             hipStream_t s) {
   if (ncpl <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_couplings, dim3(ncpl), dim3(NTHREADS), 0, s, cpl, dom, rank, S, ld, W, M);
+  hipLaunchKernelGGL(k_couplings, dim3(ncpl), dim3(CNT), 0, s, cpl, dom, rank, S, ld, W, M);
   return hipGetLastError();
 }
 

@@ -14,22 +14,32 @@
 // clusters from a cost-sorted queue, zeroes the cluster's amplitudes, and iterates
 //   R~ from the current T~ for every pair; stop if max ||R~||_F < tau_R;
 //   otherwise T~ <- T~ - R~ / (e~_a + e~_b - f_pp - f_qq)
-// to convergence inside the kernel.  At the stopping sweep it records
-//   E^X = sum_pairs w <2 T~ - T~^T, K~ + R~>       (eq:ec; w = 1 for p = q, 2 for p < q)
-// and, in one more pass over the terms at the same amplitudes, the inner
-// products <Tbar~_tgt, M op(T~_src) M^T> that make up dE/df_ab.
+// to convergence inside the kernel.  After the stopping sweep one more pass over
+// the terms at the same amplitudes records, per pair,
+//   E^X = sum_pairs w <Tbar~, K~ + R~>   (eq:ec; w = 1 for p = q, 2 for p < q)
+// split into <Tbar~, 2 K~ + Delta T~> and the terms' <Tbar~, M op(T~_src) M^T>,
+// which are also the inner products that make up dE/df_ab.
 //
 // A term Y = M op(T) M^T runs on FP64 MFMA 16x16x4 tiles.  Wave w owns the
 // 16-wide target blocks i = w and i = w + 4: for each it forms the column block
-// X'(:, i) of X' = op(T)^T M^T in registers, then Y^T(:, i) = M X'(:, i).  The f64
-// MFMA accumulator layout (lane l, register v -> row 4v + (l >> 4), column l & 15)
-// equals the B-operand layout of the k-rows 4v..4v+3, so X' (scaled by the term's
-// coefficient) feeds the second product straight from registers, accumulating
-// into R~ of the target, which stays in MFMA accumulators across its terms.
-// M and op(T) stream through LDS in 16-wide chunks, double-buffered, with the
-// next chunk's global loads issued into registers before the current chunk is
-// multiplied.  Tbar~ of the target sits in LDS.
-// Every reduction has a fixed order, so results are bitwise reproducible.
+// X'(:, i) of X' = coef op(T)^T M^T in registers, then Y^T(:, i) = M X'(:, i).  The
+// f64 MFMA accumulator layout (lane l, register v -> row 4v + (l >> 4), column
+// l & 15) equals the B-operand layout of the k-rows 4v..4v+3, so X' feeds the
+// second product straight from its accumulators, and R~ of the target stays in
+// MFMA accumulators across its terms.
+//
+// Operands are zero-padded row-major slots (leading dimension np = n rounded up
+// to 16): op(T~) is a T~ or T~^T slot and M(tgt, src)^T = M(src, tgt) is stored,
+// so every chunk of 16 k-rows is 16 contiguous rows of two matrices.  After a
+// target's terms its epilogue chunks bring 16 rows of K~^T and of T~^T plus e~, so
+// the residual R~ = terms + K~ + Delta T~, its norm and the Jacobi step
+// -R~ / Delta are formed from LDS and registers only.  The step is written to a
+// per-workgroup scratch in both orientations and added to T~ and T~^T once the
+// sweep's norms are known.  All chunks stream through a 4-stage LDS ring by
+// direct global-to-LDS loads (16 bytes per lane, no registers), issued three
+// chunks ahead of the multiply across term and target boundaries; a chunk is
+// consumed after a partial vmcnt wait and one barrier.  Every reduction has a
+// fixed order, so results are bitwise reproducible.
 #include "osv_internal.h"
 
 namespace osv {
@@ -40,10 +50,58 @@ constexpr int SNT = 256;        // threads per workgroup (4 wave64, one per SIMD
 constexpr int NW = SNT / 64;    // waves
 constexpr int NS = 2;           // 16-wide target blocks per wave (blocks w, w + NW)
 constexpr int MT = 7;           // 16-tiles per dimension covering DMAX = 100
-constexpr int TLD = 16 * MT;    // 112: padded dimension
-constexpr int KC = 16;          // chunk width (k or m)
-constexpr int TPC = KC / 16;    // MFMA tiles per chunk
-constexpr int MLD = KC + 1;     // LDS stride of M chunks (conflict-free column reads)
+constexpr int RS = 130;         // LDS row stride (doubles) of a staged row
+constexpr int NSTG = 4;         // ring stages: loads run three chunks ahead
+constexpr int STG = 33 * RS;    // doubles per stage: rows 0..15, 16..31, and row 32
+constexpr int PLMAX = 64;       // clusters with nlmo^2 <= PLMAX keep dE/df sums in LDS
+constexpr int MAXT = SOLVE_MAXT;        // clusters with <= MAXT pairs and <= MAXTERM terms
+constexpr int MAXTERM = SOLVE_MAXTERM;  //   keep their pair and term descriptors in LDS
+constexpr int NTG = 6;          // P pass: terms per reduction group
+
+// What the sweep needs about one target pair of the current cluster.
+struct TgtDesc {
+  long long toff;    // amplitude slots (T~ then T~^T)
+  long long kslot;   // K~^T / e~ slot
+  double fd;         // f_pp + f_qq
+  int np, nt, term0, nterm, w, la, lb, dom;
+};
+
+// Descriptor source: LDS tables filled at the start of each cluster (DLDS), or
+// the global arrays for clusters too large for the tables.
+template <bool DLDS>
+struct Desc {
+  const SolveArgs *a;
+  const Cluster *cl;
+  const TgtDesc *tg;
+  const TermFlat *tm;
+  __device__ __forceinline__ TgtDesc target(int c) const {
+    if (DLDS) return tg[c];
+    return make_target(*a, *cl, c);
+  }
+  __device__ __forceinline__ TermFlat term(int t) const {
+    if (DLDS) return tm[t - cl->term0];
+    return a->tflat[t];
+  }
+  static __device__ __forceinline__ TgtDesc make_target(const SolveArgs &a, const Cluster &cl, int c) {
+    const CPair P = a.cp[cl.cp0 + c];
+    const Domain D = a.dom[P.dom];
+    TgtDesc g;
+    g.toff = P.toff;
+    g.kslot = D.voff;
+    g.fd = a.F_occ[D.p * a.nocc + D.p] + a.F_occ[D.q * a.nocc + D.q];
+    g.np = D.np;
+    g.nt = a.dom_rank[P.dom];
+    g.term0 = P.term0;
+    g.nterm = P.nterm;
+    g.w = P.w;
+    g.la = P.la;
+    g.lb = P.lb;
+    g.dom = P.dom;
+    return g;
+  }
+};
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 __device__ __forceinline__ double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -73,100 +131,149 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One LDS chunk of a term: pass 1 chunk c (c < nc1 = ceil(ns/KC)) holds
-// op(T)(KC c .. KC c + KC-1, :) in Ts (row = m - KC c) and M(:, KC c ..) in Mc
-// (col = m - KC c); pass 2 chunk c (nc1 <= c) holds M(:, KC(c-nc1) ..) in Mc.
-// Each thread moves PF values of each part: it loads them from global memory
-// into registers (prefetch) and later stores them into the LDS buffer (commit),
-// so the next chunk's loads are in flight while the current one is multiplied.
-// Thread-to-element maps use shifts only and keep KC- or 128-wide runs of
-// threads on consecutive addresses for either storage order.
-constexpr int PF = KC * 128 / SNT;  // values per thread and part
-
-struct TermDesc {
-  const double *T, *M;
-  double coef;
-  int ldT, ldM, trT, trM, ns, nkb, nc1;
+// Producer of the chunk stream of one sweep of a cluster.  For every target pair
+// (in cluster order): the chunks of its terms (term t: nkb pass-1 chunks holding
+// op(T) rows and M(src,tgt) rows 16q.., then nkb pass-2 chunks holding M(src,tgt)
+// rows), then, unless this is the P pass, njb epilogue chunks holding K~^T rows,
+// T~^T rows and e~.  Every field is wave-uniform.
+struct Producer {
+  int c, ncp;           // target pair, pairs in the cluster
+  int t, tend;          // term, end of the target's terms
+  int q, nq;            // chunk within the term (or epilogue), chunks in it
+  int nkb, ldT, ldM;    // current term
+  long long tsrc, moff;
+  int epi;              // 1 while issuing the target's epilogue
+  int np;               // target's padded dimension
+  long long kslot, ttslot;
+  int use_terms, use_epi;
 };
 
-__device__ __forceinline__ TermDesc term_desc(const SolveArgs &a, int t) {
-  const TermFlat f = a.tflat[t];
-  TermDesc d;
-  d.T = a.T + f.tsrc;
-  d.M = a.M + f.moff;
-  d.coef = f.coef;
-  d.ldT = f.ldT;
-  d.ldM = f.ldM;
-  d.trM = f.flags & 1;
-  d.trT = (f.flags >> 1) & 1;
-  d.ns = f.ns;
-  d.nkb = (d.ns + 15) >> 4;
-  d.nc1 = (d.ns + KC - 1) / KC;
-  return d;
+// Load the next target with something to issue (or run off the end).
+template <bool DLDS>
+__device__ __forceinline__ void next_target(const Desc<DLDS> &ds, Producer &p) {
+  for (; p.c < p.ncp; p.c++) {
+    const TgtDesc g = ds.target(p.c);
+    p.np = uni(g.np);
+    p.kslot = g.kslot;
+    p.ttslot = g.toff + (long long)p.np * p.np;
+    p.t = uni(g.term0);
+    p.tend = p.use_terms ? p.t + uni(g.nterm) : p.t;
+    p.q = 0;
+    if (p.t < p.tend) {
+      const TermFlat f = ds.term(p.t);
+      p.nkb = uni((f.ns + 15) >> 4);
+      p.nq = 2 * p.nkb;
+      p.ldT = uni(f.ldT);
+      p.ldM = uni(f.ldM);
+      p.tsrc = f.tsrc;
+      p.moff = f.moff;
+      p.epi = 0;
+      return;
+    }
+    if (p.use_epi) {
+      p.epi = 1;
+      p.nq = uni((g.nt + 15) >> 4);
+      return;
+    }
+  }
 }
 
-// element (row, col) of slot s in a KC x 128 (Ts part: chunk row, column) or
-// 128 x KC (Mc part: matrix row, chunk column) tile; "wide" = 128 consecutive
-// threads along the 128 side, otherwise KC consecutive threads along the KC side
-__device__ __forceinline__ void slot_rc(int tid, int s, bool wide, bool ts_part, int &r, int &c) {
-  constexpr int WS = SNT / 128, NSs = SNT / KC;  // slot strides of the two maps
-  if (ts_part) {
-    if (wide) { c = tid & 127; r = (tid >> 7) + WS * s; }
-    else { r = tid % KC; c = tid / KC + NSs * s; }
+template <bool DLDS>
+__device__ __forceinline__ void advance(const Desc<DLDS> &ds, Producer &p) {
+  if (++p.q < p.nq) return;
+  p.q = 0;
+  if (!p.epi) {
+    if (++p.t < p.tend) {
+      const TermFlat f = ds.term(p.t);
+      p.nkb = uni((f.ns + 15) >> 4);
+      p.nq = 2 * p.nkb;
+      p.ldT = uni(f.ldT);
+      p.ldM = uni(f.ldM);
+      p.tsrc = f.tsrc;
+      p.moff = f.moff;
+      return;
+    }
+    if (p.use_epi) {
+      p.epi = 1;
+      p.nq = uni((ds.target(p.c).nt + 15) >> 4);
+      return;
+    }
+  }
+  p.c++;
+  next_target(ds, p);
+}
+
+// Issue the producer's chunk into a ring stage and advance; returns the number of
+// load instructions each wave issued for it (8 pass 1, 4 pass 2, 9 epilogue,
+// 0 past the end).  Every lane takes part: lane l moves doubles 2l, 2l+1 of a row,
+// clamped to the row's last 16 bytes, so lanes past the row end only fill LDS
+// columns that are never read.  stage_off is the stage's LDS byte offset from the
+// ring base (uniform).
+template <bool DLDS>
+__device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, Producer &p,
+                                     double *ring, int stage_off) {
+  if (p.c >= p.ncp) return 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // LDS byte address of row rr of this stage: uniform, kept in a scalar register
+  const int lbase = uni((int)(size_t)(__attribute__((address_space(3))) void *)ring + stage_off +
+                        wave * RS * 8);
+  int cnt;
+  if (!p.epi) {
+    const bool p1 = p.q < p.nkb;
+    const int c = p1 ? p.q : p.q - p.nkb;
+    const int ldT = p.ldT, ldM = p.ldM;
+    const double *Tg = a.T + p.tsrc + (16 * c + wave) * ldT + min(2 * lane, ldT - 2);
+    const double *Mg = a.M + p.moff + (16 * c + wave) * ldM + min(2 * lane, ldM - 2);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if (p1)
+        __builtin_amdgcn_global_load_lds((const void *)(Tg + u * NW * ldT),
+                                         (__attribute__((address_space(3))) void *)(size_t)(lbase + u * NW * RS * 8),
+                                         16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(Mg + u * NW * ldM),
+                                       (__attribute__((address_space(3))) void *)(size_t)(lbase + (16 + u * NW) * RS * 8),
+                                       16, 0, 0);
+    }
+    cnt = p1 ? 8 : 4;
   } else {
-    if (wide) { r = tid & 127; c = (tid >> 7) + WS * s; }
-    else { c = tid % KC; r = tid / KC + NSs * s; }
+    const int np = p.np;
+    const int col = min(2 * lane, np - 2);
+    const double *Kg = a.Kep + p.kslot + (16 * p.q + wave) * np + col;
+    const double *Tg = a.T + p.ttslot + (16 * p.q + wave) * np + col;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      __builtin_amdgcn_global_load_lds((const void *)(Kg + u * NW * np),
+                                       (__attribute__((address_space(3))) void *)(size_t)(lbase + u * NW * RS * 8),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(Tg + u * NW * np),
+                                       (__attribute__((address_space(3))) void *)(size_t)(lbase + (16 + u * NW) * RS * 8),
+                                       16, 0, 0);
+    }
+    // e~: every wave loads the whole row (same bytes), keeping the count uniform
+    __builtin_amdgcn_global_load_lds((const void *)(a.Kep + p.kslot + (long long)np * np + col),
+                                     (__attribute__((address_space(3))) void *)(size_t)(lbase - wave * RS * 8 + 32 * RS * 8),
+                                     16, 0, 0);
+    cnt = 9;
   }
+  advance(ds, p);
+  return cnt;
 }
 
-__device__ __forceinline__ void prefetch(const TermDesc &d, int c, int nt, double *pt, double *pm) {
-  const int tid = threadIdx.x;
-  const bool p1 = c < d.nc1;
-  const int col0 = KC * (p1 ? c : c - d.nc1);
-  if (p1) {
-    // op(T)(col0 + r, k): trT = 0 -> T[(col0 + r) ldT + k] (wide along k);
-    //                     trT = 1 -> T[k ldT + col0 + r]  (32 along r)
-#pragma unroll
-    for (int s = 0; s < PF; s++) {
-      int r, k;
-      slot_rc(tid, s, !d.trT, true, r, k);
-      const int m = col0 + r;
-      double v = 0.0;
-      if (m < d.ns && k < d.ns) v = d.trT ? d.T[k * d.ldT + m] : d.T[m * d.ldT + k];
-      pt[s] = v;
-    }
-  }
-  // M(i, col0 + cc): trM = 0 -> M[i ldM + col0 + cc] (32 along cc);
-  //                  trM = 1 -> M[(col0 + cc) ldM + i] (wide along i)
-#pragma unroll
-  for (int s = 0; s < PF; s++) {
-    int i, cc;
-    slot_rc(tid, s, d.trM, false, i, cc);
-    const int m = col0 + cc;
-    double v = 0.0;
-    if (i < nt && m < d.ns) v = d.trM ? d.M[m * d.ldM + i] : d.M[i * d.ldM + m];
-    pm[s] = v;
+// Wait until this wave's loads of the oldest outstanding chunk have landed
+// (pending = load instructions issued after them), then barrier: afterwards every
+// wave's loads of that chunk are in LDS and every wave has finished the previous
+// chunk.  Loads complete in issue order; stores issued in between can only make
+// the count larger, so the wait stays sufficient.
+#define OSV_WAIT_CASE(N) \
+  case N: asm volatile("s_waitcnt vmcnt(" #N ") lgkmcnt(0)\n\ts_barrier" ::: "memory"); break;
+__device__ __forceinline__ void stage_wait(int pending) {
+  switch (pending) {
+    OSV_WAIT_CASE(4) OSV_WAIT_CASE(8) OSV_WAIT_CASE(9) OSV_WAIT_CASE(12) OSV_WAIT_CASE(13)
+    OSV_WAIT_CASE(16) OSV_WAIT_CASE(17) OSV_WAIT_CASE(18)
+    default: asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory"); break;
   }
 }
-
-__device__ __forceinline__ void commit(const TermDesc &d, int c, double *Ts, double *Mc,
-                                       const double *pt, const double *pm) {
-  const int tid = threadIdx.x;
-  if (c < d.nc1) {
-#pragma unroll
-    for (int s = 0; s < PF; s++) {
-      int r, k;
-      slot_rc(tid, s, !d.trT, true, r, k);
-      if (k < TLD) Ts[r * TLD + k] = pt[s];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < PF; s++) {
-    int i, cc;
-    slot_rc(tid, s, d.trM, false, i, cc);
-    if (i < TLD) Mc[i * MLD + cc] = pm[s];
-  }
-}
+#undef OSV_WAIT_CASE
 
 __global__ void k_term_flat(const Term *terms, long long nterms, const CPair *cp,
                             const Coupling *cpl, const Domain *dom, const int *rank,
@@ -176,14 +283,16 @@ __global__ void k_term_flat(const Term *terms, long long nterms, const CPair *cp
   const Term tm = terms[t];
   const CPair ps = cp[tm.src];
   const Coupling c = cpl[tm.cpl];
+  const Domain Ds = dom[ps.dom];
+  const bool tgt_is_B = tm.flags & 1;   // then the source is A and M(src,tgt) = M(A,B)
+  const Domain Dt = dom[tgt_is_B ? c.B : c.A];
   TermFlat f;
-  f.tsrc = ps.toff;
-  f.moff = c.off;
+  f.tsrc = ps.toff + ((tm.flags & 2) ? (long long)Ds.np * Ds.np : 0LL);
+  f.moff = tgt_is_B ? c.offAB : c.offBA;
   f.coef = -F_occ[tm.fa * nocc + tm.fb];
-  f.ldT = dom[ps.dom].n;
-  f.ldM = dom[c.B].n;
+  f.ldT = (short)Ds.np;
+  f.ldM = (short)Dt.np;
   f.ns = rank[ps.dom];
-  f.flags = tm.flags;
   out[t] = f;
 }
 
@@ -196,11 +305,33 @@ hipError_t launch_term_flat(const Term *terms, long long nterms, const CPair *cp
   return hipGetLastError();
 }
 
+// The consumer's step to the next chunk: wait for it, issue the chunk three
+// ahead into the stage just freed, and return the chunk's stage.
+struct Ring {
+  double *base;
+  int k1, k2, seq;
+};
+
+template <bool DLDS>
+__device__ __forceinline__ const double *next_chunk(const SolveArgs &a, const Desc<DLDS> &ds,
+                                                    Producer &p, Ring &r) {
+  stage_wait(uni(r.k1 + r.k2));
+  const int k3 = issue(a, ds, p, r.base, ((r.seq + 3) & 3) * STG * 8);
+  const double *st = r.base + (r.seq & 3) * STG;
+  r.k1 = r.k2;
+  r.k2 = uni(k3);
+  r.seq++;
+  return st;
+}
+
+template <bool DLDS>
 __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
-  __shared__ double Ts[2][KC * TLD];
-  __shared__ double Mc[2][TLD * MLD];
-  __shared__ double Tb[TLD * TLD];  // Tbar~^T(j, i) = 2 T~(i,j) - T~(j,i) of the current target
-  __shared__ double red[3 * NW];
+  __shared__ __attribute__((aligned(16))) double ring[NSTG * STG];
+  __shared__ double red[(NTG + 2) * NW];
+  __shared__ double plds[PLMAX];
+  __shared__ double nrm[MAXT * NW];
+  __shared__ TgtDesc tg_l[MAXT];
+  __shared__ TermFlat tm_l[MAXTERM];
   __shared__ int s_cur;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l15 = lane & 15, lhi = lane >> 4;
@@ -214,215 +345,252 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
     const int X = a.queue[qi];
     const Cluster cl = a.cl[X];
     const int nl = cl.nlmo;
-    double *Pl = a.Pl + cl.poff;
+    const bool small = nl * nl <= PLMAX;
+    const bool lds_norms = cl.ncp <= MAXT;
+    double *Pl = small ? plds : a.Pl + cl.poff;
+    const Desc<DLDS> ds{&a, &cl, tg_l, tm_l};
+    if (DLDS) {
+      // the previous cluster's readers of the tables finished at its last barrier
+      for (int c = tid; c < cl.ncp; c += SNT) tg_l[c] = Desc<DLDS>::make_target(a, cl, c);
+      for (int t = tid; t < cl.term1 - cl.term0; t += SNT) tm_l[t] = a.tflat[cl.term0 + t];
+    }
     for (int c = 0; c < cl.ncp; c++) {
       const CPair P = a.cp[cl.cp0 + c];
-      const int n = a.dom[P.dom].n;
+      const int np = a.dom[P.dom].np;
       double *T = a.T + P.toff;
-      for (int e = tid; e < n * n; e += SNT) T[e] = 0.0;
+      for (int e = tid; e < 2 * np * np; e += SNT) T[e] = 0.0;
     }
-    __syncthreads();
-    int sweep = 0, buf = 0;
+    int sweep = 0;
     double maxn = 0.0, E = 0.0;
-    bool pmode = false;  // after convergence: one pass for the dE/df inner products
+    bool pmode = false;  // after convergence: the pass for energies and dE/df
     for (;;) {
-      if (!pmode) {
-        maxn = 0.0;
-        E = 0.0;
-        if (tid == 0)
-          for (int e = 0; e < nl * nl; e++) Pl[e] = 0.0;
-      }
+      __syncthreads();   // amplitudes written, ring and scratch free
+      Producer pr;
+      pr.c = 0;
+      pr.ncp = cl.ncp;
+      pr.use_terms = (sweep > 0 || pmode) ? 1 : 0;
+      pr.use_epi = pmode ? 0 : 1;
+      next_target(ds, pr);
+      Ring rg{ring, 0, 0, 0};
+      issue(a, ds, pr, ring, 0);
+      rg.k1 = uni(issue(a, ds, pr, ring, STG * 8));
+      rg.k2 = uni(issue(a, ds, pr, ring, 2 * STG * 8));
+      double maxn_s = 0.0;   // norms when they do not fit in LDS
       for (int c = 0; c < cl.ncp; c++) {
-        const CPair P = a.cp[cl.cp0 + c];
-        const Domain D = a.dom[P.dom];
-        const int n = D.n, nt = a.dom_rank[P.dom];
-        const double *T = a.T + P.toff;
-        const double *Kt = a.Kt + D.moff;
-        const double *ep = a.epst + D.voff;
-        double *R = Rs + (P.toff - cl.toff0);
-        const double fd = a.F_occ[D.p * a.nocc + D.p] + a.F_occ[D.q * a.nocc + D.q];
+        const TgtDesc P = ds.target(c);
+        const int np = uni(P.np), nt = uni(P.nt);
+        const double fd = P.fd;
         const int njb = (nt + 15) >> 4;
-        const int ipad = njb * 16;
-        // Tbar~^T of the target into LDS (zero in the padding)
-        for (int e = tid; e < ipad * ipad; e += SNT) {
-          const int j = e / ipad, i = e - j * ipad;
-          Tb[j * TLD + i] = (i < nt && j < nt) ? 2.0 * T[i * n + j] - T[j * n + i] : 0.0;
-        }
+        const int nterm = pr.use_terms ? uni(P.nterm) : 0;
         // coupling-term accumulators of R~^T(j, i): slot s holds target block
         // ib = wave + NW s, tile jb covers rows j = 16 jb + lhi + 4v, lane column
-        // i = 16 ib + l15; K~ + Delta T~ is added when R~ is stored
+        // i = 16 ib + l15
         d4 Racc[NS][MT];
 #pragma unroll
         for (int s = 0; s < NS; s++)
 #pragma unroll
           for (int jb = 0; jb < MT; jb++) Racc[s][jb] = (d4){0, 0, 0, 0};
-        __syncthreads();
-        if ((sweep > 0 || pmode) && P.nterm > 0) {
-          double pt[PF], pm[PF];
-          TermDesc d = term_desc(a, P.term0);
-          prefetch(d, 0, nt, pt, pm);
-          for (int t = P.term0; t < P.term0 + P.nterm; t++) {
-            // in the P pass each term is accumulated alone with unit weight
-            const double coef = pmode ? 1.0 : d.coef;
-            const bool has_next = (t + 1 < P.term0 + P.nterm);
-            const TermDesc dn = has_next ? term_desc(a, t + 1) : d;
-            const int nkb = d.nkb;
-            if (pmode) {
-#pragma unroll
-              for (int s = 0; s < NS; s++)
-#pragma unroll
-                for (int jb = 0; jb < MT; jb++) Racc[s][jb] = (d4){0, 0, 0, 0};
-            }
-            // pass 1: X'(:, i-blocks) = op(T)^T M^T over m-chunks of KC
-            d4 Xp[NS][MT];
+        for (int u = 0; u < nterm; u++) {
+          const TermFlat f = ds.term(P.term0 + u);
+          // in the P pass each term is accumulated alone with unit weight
+          const double coef = pmode ? 1.0 : f.coef;
+          const int nkb = uni((f.ns + 15) >> 4);
+          if (pmode) {
 #pragma unroll
             for (int s = 0; s < NS; s++)
 #pragma unroll
-              for (int kb = 0; kb < MT; kb++) Xp[s][kb] = (d4){0, 0, 0, 0};
-            const int nc1 = d.nc1, nc2 = (nkb + TPC - 1) / TPC;
-            for (int c = 0; c < nc1; c++) {
-              commit(d, c, Ts[buf], Mc[buf], pt, pm);
-              __syncthreads();
-              prefetch(d, c + 1, nt, pt, pm);   // next pass-1 chunk or the first pass-2 chunk
-              const double *ts = Ts[buf], *mc = Mc[buf];
-              double bv[NS][KC / 4];
+              for (int jb = 0; jb < MT; jb++) Racc[s][jb] = (d4){0, 0, 0, 0};
+          }
+          // pass 1: X'(:, i-blocks) = coef op(T)^T M^T over chunks of 16 source rows
+          d4 Xp[NS][MT];
 #pragma unroll
-              for (int s = 0; s < NS; s++)
+          for (int s = 0; s < NS; s++)
 #pragma unroll
-                for (int kk = 0; kk < KC / 4; kk++)
-                  bv[s][kk] = mc[((wave + NW * s) * 16 + l15) * MLD + 4 * kk + lhi];
+            for (int kb = 0; kb < MT; kb++) Xp[s][kb] = (d4){0, 0, 0, 0};
+          for (int cc = 0; cc < nkb; cc++) {
+            const double *ts = next_chunk(a, ds, pr, rg), *mc = ts + 16 * RS;
+            double bv[NS][4];
 #pragma unroll
-              for (int kb = 0; kb < MT; kb++) {
-                if (kb < nkb) {
-                  double av[KC / 4];
+            for (int s = 0; s < NS; s++)
 #pragma unroll
-                  for (int kk = 0; kk < KC / 4; kk++) av[kk] = ts[(4 * kk + lhi) * TLD + kb * 16 + l15];
+              for (int kk = 0; kk < 4; kk++)
+                bv[s][kk] = coef * mc[(4 * kk + lhi) * RS + (wave + NW * s) * 16 + l15];
+#pragma unroll
+            for (int kb = 0; kb < MT; kb++) {
+              if (kb < nkb) {
+                double av[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) av[kk] = ts[(4 * kk + lhi) * RS + kb * 16 + l15];
+#pragma unroll
+                for (int s = 0; s < NS; s++)
+                  if (wave + NW * s < njb)
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++) Xp[s][kb] = mfma(av[kk], bv[s][kk], Xp[s][kb]);
+              }
+            }
+          }
+          // pass 2: R~^T(:, i-blocks) += M X'(:, i-blocks), X' tile kc per chunk
+#pragma unroll
+          for (int kc = 0; kc < MT; kc++) {
+            if (kc < nkb) {
+              const double *mc = next_chunk(a, ds, pr, rg) + 16 * RS;
+#pragma unroll
+              for (int jb = 0; jb < MT; jb++) {
+                if (jb < njb) {
+                  double av[4];
+#pragma unroll
+                  for (int kk = 0; kk < 4; kk++) av[kk] = mc[(4 * kk + lhi) * RS + jb * 16 + l15];
 #pragma unroll
                   for (int s = 0; s < NS; s++)
                     if (wave + NW * s < njb)
 #pragma unroll
-                      for (int kk = 0; kk < KC / 4; kk++) Xp[s][kb] = mfma(av[kk], bv[s][kk], Xp[s][kb]);
+                      for (int kk = 0; kk < 4; kk++)
+                        Racc[s][jb] = mfma(av[kk], Xp[s][kc][kk], Racc[s][jb]);
                 }
               }
-              buf ^= 1;
             }
-            // pass 2: R~^T(:, i-blocks) += coef M X'(:, i-blocks), TPC X' tiles per chunk;
-            // the loop consumes Xp[.][0 .. TPC-1] and shifts the register arrays down
-            for (int kc = 0; kc < nc2; kc++) {
-              commit(d, nc1 + kc, Ts[buf], Mc[buf], pt, pm);
-              __syncthreads();
-              if (kc + 1 < nc2) prefetch(d, nc1 + kc + 1, nt, pt, pm);
-              else if (has_next) prefetch(dn, 0, nt, pt, pm);
-              const double *mc = Mc[buf];
-              double bx[NS][KC / 4];
+          }
+          if (pmode) {
+            // Y^T of this term to scratch slot u (read back after the target's terms)
+            double *Y = Rs + (long long)u * np * np;
 #pragma unroll
-              for (int s = 0; s < NS; s++)
+            for (int s = 0; s < NS; s++) {
+              const int ib = wave + NW * s, i = ib * 16 + l15;
+              if (ib < njb) {
 #pragma unroll
-                for (int kk = 0; kk < KC / 4; kk++) bx[s][kk] = coef * Xp[s][kk >> 2][kk & 3];
+                for (int jb = 0; jb < MT; jb++)
+                  if (jb < njb)
 #pragma unroll
-              for (int jb = 0; jb < MT; jb++) {
-                if (jb < njb) {
-                  double av[KC / 4];
-#pragma unroll
-                  for (int kk = 0; kk < KC / 4; kk++) av[kk] = mc[(jb * 16 + l15) * MLD + 4 * kk + lhi];
-#pragma unroll
-                  for (int s = 0; s < NS; s++)
-                    if (wave + NW * s < njb) {
-#pragma unroll
-                      for (int tt = 0; tt < TPC; tt++)
-                        if (TPC * kc + tt < nkb)
-#pragma unroll
-                          for (int kk = 4 * tt; kk < 4 * tt + 4; kk++)
-                            Racc[s][jb] = mfma(av[kk], bx[s][kk], Racc[s][jb]);
-                    }
-                }
-              }
-#pragma unroll
-              for (int s = 0; s < NS; s++)
-#pragma unroll
-                for (int q = 0; q < MT - TPC; q++) Xp[s][q] = Xp[s][q + TPC];
-              buf ^= 1;
-            }
-            if (pmode) {
-              // <Tbar~_tgt, Y> (padded entries of Y and Tb are zero)
-              double vs[1] = {0.0};
-#pragma unroll
-              for (int s = 0; s < NS; s++) {
-                const int i = (wave + NW * s) * 16 + l15;
-#pragma unroll
-                for (int jb = 0; jb < MT; jb++) {
-                  if (jb < njb) {
-#pragma unroll
-                    for (int v = 0; v < 4; v++) vs[0] += Tb[(jb * 16 + lhi + 4 * v) * TLD + i] * Racc[s][jb][v];
-                  }
-                }
-              }
-              block_sums<1>(vs, red);
-              if (tid == 0) {
-                const Term tm = a.terms[t];
-                Pl[tm.la * nl + tm.lb] -= vs[0];
-                if (P.la != P.lb) Pl[tm.lb * nl + tm.la] -= vs[0];
+                    for (int v = 0; v < 4; v++) Y[(jb * 16 + lhi + 4 * v) * np + i] = Racc[s][jb][v];
               }
             }
-            d = dn;
           }
         }
-        if (pmode) continue;
-        // store R~ (transposed: R[j*n + i] = R~(i, j)); norm, energy, same-pair dE/df
-        double sv[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-          const int i = (wave + NW * s) * 16 + l15;
+        if (!pmode) {
+          // epilogue: R~ = terms + K~ + Delta T~ tile row by tile row from the ring;
+          // norm, and the Jacobi step -R~ / Delta into scratch (both orientations)
+          double *dT = Rs + (P.toff - cl.toff0), *dTT = dT + (long long)np * np;
+          double ss = 0.0;
 #pragma unroll
           for (int jb = 0; jb < MT; jb++) {
             if (jb < njb) {
+              const double *st = next_chunk(a, ds, pr, rg);
+              const double *ev = st + 32 * RS;
 #pragma unroll
-              for (int v = 0; v < 4; v++) {
-                const int j = jb * 16 + lhi + 4 * v;
-                if (i < nt && j < nt) {
-                  const double kij = Kt[i * n + j];
-                  const double tij = T[i * n + j];
-                  const double r = Racc[s][jb][v] + kij + (ep[i] + ep[j] - fd) * tij;
-                  const double tb = Tb[j * TLD + i];
-                  R[j * n + i] = r;
-                  sv[0] += r * r;
-                  sv[1] += tb * (kij + r);
-                  sv[2] += tb * tij;
+              for (int s = 0; s < NS; s++) {
+                const int ib = wave + NW * s, i = ib * 16 + l15;
+                if (ib < njb) {
+                  const double ei = ev[i] - fd;
+#pragma unroll
+                  for (int v = 0; v < 4; v++) {
+                    const int jl = lhi + 4 * v, j = jb * 16 + jl;
+                    const double delta = ei + ev[j];
+                    const double r = Racc[s][jb][v] + st[jl * RS + i] + delta * st[(16 + jl) * RS + i];
+                    const bool in = (i < nt) && (j < nt);
+                    const double d = in ? -r / delta : 0.0;
+                    ss += in ? r * r : 0.0;
+                    dTT[j * np + i] = d;
+                    dT[i * np + j] = d;
+                  }
                 }
               }
             }
           }
-        }
-        block_sums<3>(sv, red);
-        const double nrm = sqrt(sv[0]);
-        maxn = (nrm > maxn || nrm != nrm) ? nrm : maxn;
-        E += P.w * sv[1];
-        if (tid == 0) {
-          Pl[P.la * nl + P.la] -= 2.0 * sv[2];
-          if (P.la != P.lb) Pl[P.lb * nl + P.lb] -= 2.0 * sv[2];
+          ss = wsum(ss);
+          if (lds_norms) {
+            if (lane == 0) nrm[c * NW + wave] = ss;
+          } else {
+            double v1[1] = {lane == 0 ? ss : 0.0};   // ss is already the wave's sum
+            block_sums<1>(v1, red);
+            const double nr = sqrt(v1[0]);
+            maxn_s = (nr > maxn_s || nr != nr) ? nr : maxn_s;
+          }
+        } else {
+          // P pass: <Tbar~, 2 K~ + Delta T~>, <Tbar~, T~> and <Tbar~, Y_u> per term
+          __syncthreads();
+          const double *Tt = a.T + P.toff, *TT = Tt + (long long)np * np;
+          const double *Kg = a.Kep + P.kslot, *ev = Kg + (long long)np * np;
+          for (int g0 = 0; g0 == 0 || g0 < P.nterm; g0 += NTG) {
+            double acc[NTG + 2];
+#pragma unroll
+            for (int k = 0; k < NTG + 2; k++) acc[k] = 0.0;
+            for (int e = tid; e < nt * nt; e += SNT) {
+              const int j = e / nt, i = e - j * nt;
+              const double tij = TT[j * np + i], tji = Tt[j * np + i];
+              const double tb = 2.0 * tij - tji;
+              if (g0 == 0) {
+                acc[0] += tb * (2.0 * Kg[j * np + i] + (ev[i] + ev[j] - fd) * tij);
+                acc[1] += tb * tij;
+              }
+#pragma unroll
+              for (int k = 0; k < NTG; k++)
+                if (g0 + k < P.nterm) acc[2 + k] += tb * Rs[(long long)(g0 + k) * np * np + j * np + i];
+            }
+            block_sums<NTG + 2>(acc, red);
+            if (g0 == 0) {
+              E += P.w * acc[0];
+              if (tid == 0) {
+                Pl[P.la * nl + P.la] -= 2.0 * acc[1];
+                if (P.la != P.lb) Pl[P.lb * nl + P.lb] -= 2.0 * acc[1];
+              }
+            }
+            for (int k = 0; k < NTG && g0 + k < P.nterm; k++) {
+              const TermFlat f = ds.term(P.term0 + g0 + k);
+              E += P.w * f.coef * acc[2 + k];
+              if (tid == 0) {
+                const Term tm = a.terms[P.term0 + g0 + k];
+                Pl[tm.la * nl + tm.lb] -= acc[2 + k];
+                if (P.la != P.lb) Pl[tm.lb * nl + tm.la] -= acc[2 + k];
+              }
+            }
+          }
         }
       }
       if (pmode) break;
-      if (maxn < a.tau_R || maxn != maxn || sweep >= a.max_sweeps) {
-        pmode = true;  // amplitudes final: inner products of the terms at this T
-        continue;
-      }
-      // Jacobi update of every pair of the cluster (R holds R~ transposed)
-      for (int c = 0; c < cl.ncp; c++) {
-        const CPair P = a.cp[cl.cp0 + c];
-        const Domain D = a.dom[P.dom];
-        const int n = D.n, nt = a.dom_rank[P.dom];
-        double *T = a.T + P.toff;
-        const double *ep = a.epst + D.voff;
-        const double *R = Rs + (P.toff - cl.toff0);
-        const double fd = a.F_occ[D.p * a.nocc + D.p] + a.F_occ[D.q * a.nocc + D.q];
-        for (int e = tid; e < nt * nt; e += SNT) {
-          const int j = e / nt, ii = e - j * nt;
-          T[ii * n + j] -= R[j * n + ii] / (ep[ii] + ep[j] - fd);
+      __syncthreads();   // steps in scratch, norms in LDS
+      maxn = maxn_s;
+      if (lds_norms) {
+        for (int c = 0; c < cl.ncp; c++) {
+          double t = 0.0;
+          for (int w = 0; w < NW; w++) t += nrm[c * NW + w];
+          const double nr = sqrt(t);
+          maxn = (nr > maxn || nr != nr) ? nr : maxn;
         }
       }
-      __syncthreads();
+      if (maxn < a.tau_R || maxn != maxn || sweep >= a.max_sweeps) {
+        pmode = true;  // amplitudes final: energies and inner products at this T
+        if (tid == 0)
+          for (int e = 0; e < nl * nl; e++) Pl[e] = 0.0;
+        E = 0.0;
+        continue;
+      }
+      // Jacobi update: T~ and T~^T += the steps over each pair's 16 njb square
+      for (int c = 0; c < cl.ncp; c++) {
+        const TgtDesc P = ds.target(c);
+        const int np = uni(P.np), m = uni(((P.nt + 15) >> 4) * 16);
+        double *__restrict__ T = a.T + P.toff;
+        const double *__restrict__ dT = Rs + (P.toff - cl.toff0);
+        for (int e = tid; e < 2 * m * 16; e += SNT) {
+          const int h = e / (m * 16), e2 = e - h * m * 16;
+          const int row = e2 >> 4, col = e2 & 15;
+          const long long base = (long long)h * np * np + (long long)row * np + col;
+          double tv[MT], dv[MT];
+#pragma unroll
+          for (int cb = 0; cb < MT; cb++)
+            if (16 * cb < m) {
+              tv[cb] = T[base + 16 * cb];
+              dv[cb] = dT[base + 16 * cb];
+            }
+#pragma unroll
+          for (int cb = 0; cb < MT; cb++)
+            if (16 * cb < m) T[base + 16 * cb] = tv[cb] + dv[cb];
+        }
+      }
       sweep++;
+    }
+    if (small) {
+      __syncthreads();
+      for (int e = tid; e < nl * nl; e += SNT) a.Pl[cl.poff + e] = plds[e];
     }
     if (tid == 0) {
       a.Ecl[X] = E;
@@ -433,9 +601,24 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
   }
 }
 
-hipError_t launch_solve(const SolveArgs &a, int nwg, hipStream_t s) {
+// Clusters whose descriptors fit the LDS tables run in the DLDS instantiation;
+// the queue holds the others first (cost order puts large clusters there), so
+// a.queue[0 .. n_big) goes to the global-descriptor instantiation with
+// counter[0] and the rest to the LDS one with counter[1].
+hipError_t launch_solve(const SolveArgs &a, int n_big, int nwg, hipStream_t s) {
   if (a.n_clusters <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_solve, dim3(nwg), dim3(SNT), 0, s, a);
+  if (n_big > 0) {
+    SolveArgs b = a;
+    b.n_clusters = n_big;
+    hipLaunchKernelGGL(k_solve<false>, dim3(nwg < n_big ? nwg : n_big), dim3(SNT), 0, s, b);
+  }
+  if (a.n_clusters > n_big) {
+    SolveArgs b = a;
+    b.queue = a.queue + n_big;
+    b.n_clusters = a.n_clusters - n_big;
+    b.counter = a.counter + 1;
+    hipLaunchKernelGGL(k_solve<true>, dim3(nwg < b.n_clusters ? nwg : b.n_clusters), dim3(SNT), 0, s, b);
+  }
   return hipGetLastError();
 }
 

@@ -126,12 +126,13 @@ struct Plan {
   std::vector<Cluster> cls;
   std::vector<int> queue;
   long long n_slot = 0;   // sum n^2 over domains
-  long long n_vec = 0;    // sum n over domains
+  long long n_vec = 0;    // sum (np^2 + np) over domains: K~^T and e~ slots
   long long n_T = 0;      // amplitude doubles
   long long n_M = 0;      // coupling doubles
   long long rs_stride = 0;
   long long n_pl = 0;     // dE/dF inner-product doubles
   int64_t n_pair_blocks = 0;
+  int n_big = 0;          // leading queue entries too large for the LDS tables
 };
 
 // Builds the plan.  r/off may be null (counts only, domain sizes unknown).
@@ -154,6 +155,7 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
         D.rp = rr(p);
         D.rq = (p == q) ? 0 : rr(q);
         D.n = D.rp + D.rq;
+        D.np = (D.n + 15) / 16 * 16;
         D.offp = off ? off[p] : 0;
         D.offq = off ? off[q] : 0;
         if (r && D.n > DMAX) {
@@ -164,7 +166,7 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
         D.moff = P.n_slot;
         D.voff = P.n_vec;
         P.n_slot += (long long)D.n * D.n;
-        P.n_vec += D.n;
+        P.n_vec += (long long)D.np * D.np + D.np;
         P.dom_of[(size_t)p * nocc + q] = (int)P.doms.size();
         P.doms.push_back(D);
       }
@@ -183,8 +185,10 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
       Coupling c{};
       c.A = A;
       c.B = B;
-      c.off = P.n_M;
-      P.n_M += (long long)P.doms[A].n * P.doms[B].n;
+      const long long sz = (long long)P.doms[A].np * P.doms[B].np;
+      c.offAB = P.n_M;
+      c.offBA = P.n_M + sz;
+      P.n_M += 2 * sz;
       P.cpls.push_back(c);
       cmap[key] = id;
     } else {
@@ -214,12 +218,13 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
         cp.lb = b;
         cp.w = (a == b) ? 1 : 2;
         cp.toff = P.n_T;
-        long long n = P.doms[cp.dom].n;
-        P.n_T += n * n;
+        const long long np = P.doms[cp.dom].np;
+        P.n_T += 2 * np * np;
         lpair[(size_t)a * nl + b] = lpair[(size_t)b * nl + a] = (int)P.cps.size();
         P.cps.push_back(cp);
       }
     C.ncp = (int)P.cps.size() - C.cp0;
+    C.term0 = (int)P.terms.size();
     // terms of eq:rij for every pair of the cluster
     for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
       CPair &cp = P.cps[c];
@@ -263,14 +268,29 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
         P.terms.push_back(t);
       }
       cp.nterm = (int)P.terms.size() - cp.term0;
+      // the solve's P pass keeps one np x np product per term of the pair in scratch
+      const long long npt = P.doms[cp.dom].np;
+      P.rs_stride = std::max(P.rs_stride, (long long)cp.nterm * npt * npt);
     }
+    C.term1 = (int)P.terms.size();
     P.rs_stride = std::max(P.rs_stride, P.n_T - C.toff0);
     P.n_pair_blocks += C.ncp;
     P.cls.push_back(C);
   }
+  // Work-queue order: the canonical cluster order, in which neighbouring clusters
+  // share LMOs, so workgroups running at the same time touch the same couplings
+  // (allocated above in order of first use) and nearby amplitude slots.  Cluster
+  // costs vary by less than 2^3 in MBE(3) runs, so there is no long tail to
+  // schedule first.
+  (void)cost;
   P.queue.resize(ncl);
   std::iota(P.queue.begin(), P.queue.end(), 0);
-  std::stable_sort(P.queue.begin(), P.queue.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  // clusters too large for the solve's LDS descriptor tables go first
+  auto big = [&](int x) {
+    return P.cls[x].ncp > SOLVE_MAXT || P.cls[x].term1 - P.cls[x].term0 > SOLVE_MAXTERM;
+  };
+  auto mid = std::stable_partition(P.queue.begin(), P.queue.end(), big);
+  P.n_big = (int)(mid - P.queue.begin());
   return OSV_OK;
 }
 
@@ -523,8 +543,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   StageTimer t_prep(s);
   if ((rc = dalloc(ctx, &ctx->dW, P.n_slot))) return rc;
   if ((rc = dalloc(ctx, &ctx->dY, P.n_slot))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dKt, P.n_slot))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dEpst, P.n_vec))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dKt, P.n_vec))) return rc;
   if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
   if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
   {
@@ -541,7 +560,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       }
     if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
     HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds, cnt, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S,
-                                   ctx->dW, ctx->dY, ctx->dKt, ctx->dEpst, ctx->dRank, ctx->dMinev, s));
+                                   ctx->dW, ctx->dY, ctx->dKt, ctx->dRank, ctx->dMinev, s));
   }
   t_prep.stop();
   StageTimer t_cpl(s);
@@ -606,7 +625,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = dalloc(ctx, &ctx->dPl, P.n_pl))) return rc;
   if ((rc = dalloc(ctx, &ctx->dMaxres, ncl))) return rc;
   if ((rc = dalloc(ctx, &ctx->dSweeps, ncl))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dCounter, 1))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dCounter, 2))) return rc;
   // MBE weights: E, E_1b, dE_2b, dE_3b
   {
     std::vector<double> w((size_t)4 * ncl, 0.0);
@@ -753,8 +772,7 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   a.dom_rank = ctx->dRank;
   a.cpl = ctx->dCpl;
   a.M = ctx->dM;
-  a.Kt = ctx->dKt;
-  a.epst = ctx->dEpst;
+  a.Kep = ctx->dKt;
   a.F_occ = ctx->F;
   a.nocc = ctx->nocc;
   a.T = ctx->dT;
@@ -770,8 +788,8 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   a.tau_R = tau_R;
   a.max_sweeps = max_sweeps;
   StageTimer t(s);
-  HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 1, s));
-  HIPCHK(ctx, launch_solve(a, ctx->nwg, s));
+  HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 2, s));
+  HIPCHK(ctx, launch_solve(a, P.n_big, ctx->nwg, s));
   t.stop();
   std::vector<int> sw(ncl);
   std::vector<double> mr(ncl);

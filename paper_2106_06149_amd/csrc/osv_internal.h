@@ -6,28 +6,37 @@
 namespace osv {
 
 constexpr int DMAX = 100;      // largest pair-domain dimension r_p + r_q
+// clusters with at most SOLVE_MAXT pairs and SOLVE_MAXTERM terms run in the solve
+// kernel that keeps their descriptors in LDS (every MBE(3) cluster does)
+constexpr int SOLVE_MAXT = 64, SOLVE_MAXTERM = 256;
 constexpr int NTHREADS = 256;  // threads of every per-item workgroup (4 wave64)
 
 // One pair domain [Q_p Q_q] (p < q) or Q_p (p == q).  Every per-domain square
-// matrix (W, Y = W^T S, K~, the OSV-basis virtual density) lives in an n x n
-// slot at moff (row-major, ld n); the kept rank dt <= n is written by the
-// preparation kernel into dom_rank[].
+// matrix (W, Y = W^T S, the OSV-basis virtual density) lives in an n x n slot at
+// moff (row-major, ld n); K~ (transposed) and the pseudo-canonical energies e~
+// live in a zero-padded slot at voff (np x np, ld np, then np values).  The
+// kept rank dt <= n is written by the preparation kernel into dom_rank[].
+// np = n rounded up to a multiple of 16: the leading dimension of the zero-padded
+// amplitude and coupling slots used by the solve.
 struct Domain {
-  int p, q, rp, rq, n, offp, offq, pad;
+  int p, q, rp, rq, n, offp, offq, np;
   long long moff;   // n*n slot offset
-  long long voff;   // n slot offset (pseudo-canonical energies)
+  long long voff;   // offset of the zero-padded slot holding K~^T (np x np) then e~ (np)
 };
 
-// Coupling between domains A and B that share an LMO:
-// M(A,B) = W_A^T S_(A,B) W_B  (n_A x n_B slot, ld n_B).
+// Coupling between domains A < B that share an LMO, stored in both orientations
+// as zero-padded row-major slots:
+//   offAB: M(A,B) = W_A^T S_(A,B) W_B   (np_A x np_B, ld np_B)
+//   offBA: M(B,A) = M(A,B)^T            (np_B x np_A, ld np_A)
+// entries beyond the kept ranks are zero.
 struct Coupling {
   int A, B;
-  long long off;
+  long long offAB, offBA;
 };
 
 // One residual term of eq:rij in pseudo-canonical coordinates:
 //   R~_tgt += -f[fa][fb] * M op(T~_src) M^T,   M = M(tgt, src)
-// flags bit0: the stored coupling is M(src, tgt) (use its transpose)
+// flags bit0: the target is the coupling's B domain (the source is A)
 //       bit1: op = transpose (ordered source pair (a,b) with a > b)
 struct Term {
   int src;    // absolute cluster-pair index of the source amplitudes
@@ -44,25 +53,27 @@ struct CPair {
   int la, lb;         // cluster-local LMO indices of p and q
   int term0, nterm;   // range in the term array
   int w;              // 1 for p == q, 2 for p < q (ordered-pair multiplicity)
-  long long toff;     // offset of the n x n amplitude slot
+  long long toff;     // offset of the amplitude slots: T~ (np x np, ld np) at toff,
+                      // T~^T at toff + np*np; zero beyond the kept rank
 };
 
 struct Cluster {
   int cp0, ncp;       // range of cluster pairs
   int nlmo, lmo0;     // LMOs: cl_lmo[lmo0 .. lmo0+nlmo)
   long long toff0;    // amplitude offset of the first pair (scratch base)
+  int term0, term1;   // the cluster's terms (contiguous, in pair order)
   long long poff;     // offset of the nlmo x nlmo block of dE/dF inner products
 };
 
 // Everything the solve kernel needs about one term, gathered once after the
-// pair domains are prepared (one aligned 48-byte load per term).
+// pair domains are prepared (one aligned 32-byte load per term).
 struct TermFlat {
-  long long tsrc;   // amplitude offset of the source pair
-  long long moff;   // coupling offset
+  long long tsrc;   // slot of op(T~_src) as a row-major np_src x np_src matrix
+                    // (the T~ slot, or the T~^T slot when op is a transpose)
+  long long moff;   // slot of M(src, tgt) (np_src x np_tgt, row-major)
   double coef;      // -f[fa][fb]
-  int ldT, ldM;     // slot leading dimensions of the source amplitudes and of M
+  short ldT, ldM;   // np_src, np_tgt
   int ns;           // kept rank of the source domain
-  int flags;        // bit0: use M^T, bit1: use T^T
 };
 
 struct SolveArgs {
@@ -74,8 +85,7 @@ struct SolveArgs {
   const int *dom_rank;
   const Coupling *cpl;
   const double *M;      // couplings
-  const double *Kt;     // K~ per domain
-  const double *epst;   // pseudo-canonical energies per domain
+  const double *Kep;    // per domain: K~^T (np x np) then e~ (np), zero-padded
   const double *F_occ;  // nocc x nocc
   int nocc;
   double *T;            // amplitudes per cluster pair
@@ -86,7 +96,7 @@ struct SolveArgs {
   int *sweeps;          // [n_clusters]
   double *maxres;       // [n_clusters]
   const int *queue;     // cluster order (cost descending)
-  int *counter;         // work-queue head
+  int *counter;         // work-queue heads (two: large clusters, then the rest)
   int n_clusters;
   double tau_R;
   int max_sweeps;
@@ -117,12 +127,13 @@ hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, l
                               hipStream_t s);
 hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
                               const double *S, const double *F, const double *K, long long ld,
-                              double tau_S, double *W, double *Y, double *Kt, double *epst,
-                              int *rank, double *minev, hipStream_t s);
+                              double tau_S, double *W, double *Y, double *Kep, int *rank,
+                              double *minev, hipStream_t s);
+// both orientations of every coupling, zero-padded (FP64 MFMA)
 hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
                             const int *rank, const double *S, long long ld, const double *W,
                             double *M, hipStream_t s);
-hipError_t launch_solve(const SolveArgs &a, int nwg, hipStream_t s);
+hipError_t launch_solve(const SolveArgs &a, int n_big, int nwg, hipStream_t s);
 hipError_t launch_term_flat(const Term *terms, long long nterms, const CPair *cp,
                             const Coupling *cpl, const Domain *dom, const int *rank,
                             const double *F_occ, int nocc, TermFlat *out, hipStream_t s);
