@@ -135,9 +135,10 @@ struct Plan {
   int n_big = 0;          // leading queue entries too large for the LDS tables
 };
 
-// Builds the plan.  r/off may be null (counts only, domain sizes unknown).
-int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan &P,
-               std::string &err) {
+// Builds the pair domains of the plan (all the S/F/K blocks and the domain
+// preparation need).  r/off may be null (counts only, domain sizes unknown).
+int build_domains(int nocc, const Selection &s, const int *r, const int *off, Plan &P,
+                  std::string &err) {
   P.dom_of.assign((size_t)nocc * nocc, -1);
   const int ncl = (int)s.coef.size();
   auto rr = [&](int i) { return r ? r[i] : 1; };
@@ -170,17 +171,49 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
         P.dom_of[(size_t)p * nocc + q] = (int)P.doms.size();
         P.doms.push_back(D);
       }
+  return OSV_OK;
+}
+
+// Builds the clusters' pairs, terms and couplings and the work queue (after
+// build_domains; runs on the host while the device forms S, F, K and the domains).
+void build_clusters(int nocc, const Selection &s, Plan &P) {
+  const int ncl = (int)s.coef.size();
   auto dom_id = [&](int a, int b) {
     return a <= b ? P.dom_of[(size_t)a * nocc + b] : P.dom_of[(size_t)b * nocc + a];
   };
-  std::unordered_map<long long, int> cmap;
+  // couplings keyed by (A, B), A < B: open addressing with linear probing
   const long long ND = (long long)P.doms.size();
+  size_t cap = 1024;
+  while ((long long)cap < 32 * ND) cap <<= 1;   // grown below at half load
+  std::vector<long long> hkey(cap, -1);
+  std::vector<int> hval(cap);
+  auto slot = [&](long long key) {
+    size_t h = (size_t)((unsigned long long)key * 0x9E3779B97F4A7C15ull >> 17) & (cap - 1);
+    while (hkey[h] != -1 && hkey[h] != key) h = (h + 1) & (cap - 1);
+    return h;
+  };
   auto coupling = [&](int t, int src, int &flags) {
-    int A = std::min(t, src), B = std::max(t, src);
-    long long key = (long long)A * ND + B;
-    auto it = cmap.find(key);
+    const int A = std::min(t, src), B = std::max(t, src);
+    const long long key = (long long)A * ND + B;
+    size_t h = slot(key);
     int id;
-    if (it == cmap.end()) {
+    if (hkey[h] == -1) {
+      if (2 * (P.cpls.size() + 1) > cap) {   // rehash at half load
+        std::vector<long long> ok;
+        std::vector<int> ov;
+        ok.swap(hkey);
+        ov.swap(hval);
+        cap <<= 1;
+        hkey.assign(cap, -1);
+        hval.resize(cap);
+        for (size_t e = 0; e < ok.size(); e++)
+          if (ok[e] != -1) {
+            const size_t g = slot(ok[e]);
+            hkey[g] = ok[e];
+            hval[g] = ov[e];
+          }
+        h = slot(key);
+      }
       id = (int)P.cpls.size();
       Coupling c{};
       c.A = A;
@@ -190,14 +223,27 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
       c.offBA = P.n_M + sz;
       P.n_M += 2 * sz;
       P.cpls.push_back(c);
-      cmap[key] = id;
+      hkey[h] = key;
+      hval[h] = id;
     } else {
-      id = it->second;
+      id = hval[h];
     }
     if (t != A) flags |= 1;
     return id;
   };
+  {
+    long long npairs = 0, nterms = 0;
+    for (int X = 0; X < ncl; X++) {
+      const long long nl = s.lmo_ptr[X + 1] - s.lmo_ptr[X];
+      npairs += nl * (nl + 1) / 2;
+      nterms += nl * (nl + 1) / 2 * 2 * (nl - 1);
+    }
+    P.cps.reserve(npairs);
+    P.terms.reserve(nterms);
+    P.cls.reserve(ncl);
+  }
   std::vector<double> cost(ncl, 0.0);
+  std::vector<int> lpair;
   for (int X = 0; X < ncl; X++) {
     Cluster C{};
     const int l0 = s.lmo_ptr[X], nl = s.lmo_ptr[X + 1] - l0;
@@ -208,7 +254,7 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
     C.poff = P.n_pl;
     P.n_pl += (long long)nl * nl;
     // local pair index table
-    std::vector<int> lpair((size_t)nl * nl, -1);
+    lpair.assign((size_t)nl * nl, -1);
     for (int a = 0; a < nl; a++)
       for (int b = a; b < nl; b++) {
         CPair cp{};
@@ -291,6 +337,13 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
   };
   auto mid = std::stable_partition(P.queue.begin(), P.queue.end(), big);
   P.n_big = (int)(mid - P.queue.begin());
+}
+
+int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan &P,
+               std::string &err) {
+  const int rc = build_domains(nocc, s, r, off, P, err);
+  if (rc) return rc;
+  build_clusters(nocc, s, P);
   return OSV_OK;
 }
 
@@ -495,31 +548,43 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   }
   {
     std::string err;
-    rc = build_plan(nocc, ctx->sel, ctx->r.data(), ctx->off.data(), ctx->plan, err);
+    rc = build_domains(nocc, ctx->sel, ctx->r.data(), ctx->off.data(), ctx->plan, err);
     if (rc) return fail(ctx, rc, err);
   }
   Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
-  ctx->counts.n1b = S.n1;
-  ctx->counts.n2b = S.n2b;
-  ctx->counts.n3b = S.n3b;
-  ctx->counts.n_clusters = (int64_t)S.coef.size();
-  ctx->counts.n_pair_blocks = P.n_pair_blocks;
-  ctx->counts.n_domains = (int64_t)P.doms.size();
-  ctx->counts.n_couplings = (int64_t)P.cpls.size();
   ctx->tiles = make_tiles(P, N, false);
   const int ndom = (int)P.doms.size();
-  const int ncl = (int)P.cls.size();
-
+  // everything the device stages before the couplings need is allocated and
+  // uploaded first: uploads from pageable host memory wait for the stream
   if ((rc = upload(ctx, &ctx->dTiles, ctx->tiles, s))) return rc;
   if ((rc = upload(ctx, &ctx->dDom, P.doms, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCp, P.cps, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dTerms, P.terms, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dW, P.n_slot))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dY, P.n_slot))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dKt, P.n_vec))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
+  int prep_cnt[3] = {0, 0, 0};
+  {
+    // domains by LDS size class (n <= 32, <= 64, <= DMAX)
+    std::vector<int> ids;
+    for (int c = 0; c < 3; c++)
+      for (int d = 0; d < ndom; d++) {
+        int n = P.doms[d].n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+        if (cls == c) {
+          ids.push_back(d);
+          prep_cnt[c]++;
+        }
+      }
+    if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
+  }
+  if (precision == OSV_MIXED) {
+    const long long nc = (long long)N * ctx->naux;
+    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dDig, 5 * nc))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
+  }
+  double host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
 
-  ctx->stage_ms[8] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   // S and F blocks: one pass over Q^T (rows = OSVs, k = virtuals)
   StageTimer t_sf(s);
   HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, ctx->eps, ctx->dS, ctx->dF, ld,
@@ -527,9 +592,6 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   t_sf.stop();
   StageTimer t_k(s);
   if (precision == OSV_MIXED) {
-    const long long nc = (long long)N * ctx->naux;
-    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dDig, 5 * nc))) return rc;
-    if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
     HIPCHK(ctx, launch_split_digits((const float *)ctx->C, N, ctx->naux, ctx->dExps, ctx->dDig, s));
     HIPCHK(ctx, launch_syrk_digits(ctx->dDig, N, ctx->naux, ctx->dExps, ctx->dK, ld, ctx->dTiles,
                                    (int)ctx->tiles.size(), s));
@@ -538,31 +600,30 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
                                 nullptr, ld, ctx->dTiles, (int)ctx->tiles.size(), s));
   }
   t_k.stop();
-
   // pair-domain preparation
   StageTimer t_prep(s);
-  if ((rc = dalloc(ctx, &ctx->dW, P.n_slot))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dY, P.n_slot))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dKt, P.n_vec))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
-  {
-    // domains by LDS size class (n <= 32, <= 64, <= DMAX)
-    std::vector<int> ids;
-    int cnt[3] = {0, 0, 0};
-    for (int c = 0; c < 3; c++)
-      for (int d = 0; d < ndom; d++) {
-        int n = P.doms[d].n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
-        if (cls == c) {
-          ids.push_back(d);
-          cnt[c]++;
-        }
-      }
-    if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
-    HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds, cnt, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S,
-                                   ctx->dW, ctx->dY, ctx->dKt, ctx->dRank, ctx->dMinev, s));
-  }
+  HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds, prep_cnt, ctx->dS, ctx->dF, ctx->dK, ld,
+                                 ctx->tau_S, ctx->dW, ctx->dY, ctx->dKt, ctx->dRank, ctx->dMinev, s));
   t_prep.stop();
+
+  // clusters, terms and couplings on the host while the device works
+  const auto h1 = std::chrono::steady_clock::now();
+  build_clusters(nocc, ctx->sel, P);
+  host_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h1).count();
+  ctx->counts.n1b = S.n1;
+  ctx->counts.n2b = S.n2b;
+  ctx->counts.n3b = S.n3b;
+  ctx->counts.n_clusters = (int64_t)S.coef.size();
+  ctx->counts.n_pair_blocks = P.n_pair_blocks;
+  ctx->counts.n_domains = (int64_t)P.doms.size();
+  ctx->counts.n_couplings = (int64_t)P.cpls.size();
+  const int ncl = (int)P.cls.size();
+  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCp, P.cps, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dTerms, P.terms, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
+  ctx->stage_ms[8] = host_ms;
   StageTimer t_cpl(s);
   if ((rc = dalloc(ctx, &ctx->dM, P.n_M))) return rc;
   HIPCHK(ctx, launch_couplings(ctx->dCpl, (int)P.cpls.size(), ctx->dDom, ctx->dRank, ctx->dS, ld, ctx->dW,
