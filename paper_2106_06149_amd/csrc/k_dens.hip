@@ -9,123 +9,307 @@
 //   G^K_pq = Y_p^T (2 A_d) Y_q        (dE/dK_pq; dE/dC_p = sum_q (G^K_pq + G^K_qp^T) C_q)
 //   G^F_d  = W (g_d + g_d^T) W^T      (p < q; W g_d W^T for p = q): the domain's part of
 //            the virtual density in its composite OSV basis (cf. eq:dv, D_(ij,kl)).
-// Every term is written by one workgroup in a fixed order: no atomics.
+// Every term is written by one workgroup in a fixed order: no atomics.  The
+// cluster amplitudes stream through LDS by direct global-to-LDS loads and all
+// products run on FP64 MFMA 16x16x4.
 #include "osv_internal.h"
 
 namespace osv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int LDA = DMAX + 1;
 
-__global__ __launch_bounds__(NTHREADS) void k_adjoint(const Domain *__restrict__ doms,
-                                                      const int *__restrict__ rank,
-                                                      const double *__restrict__ W,
-                                                      const double *__restrict__ Y,
-                                                      const double *__restrict__ Tall,
-                                                      const long long *__restrict__ dcp_ptr,
-                                                      const long long *__restrict__ dcp_toff,
-                                                      const double *__restrict__ dcp_coef,
-                                                      double *GK, long long ld, double *Gd) {
-  __shared__ double L1[DMAX * LDA];
-  __shared__ double L2[DMAX * LDA];
+constexpr int ANT = 256;             // threads per domain (4 wave64)
+constexpr int ANW = ANT / 64;
+constexpr int ALD = DMAX + 1;        // odd LDS stride of the transform matrices
+constexpr int ARS = 130;             // LDS row stride of a staged amplitude row (>= 128)
+constexpr int ASTG = 32 * ARS;       // stage: T~ rows 0..15, T~^T rows 16..31
+constexpr int ANSTG = 3;             // ring stages (loads run two chunks ahead)
+constexpr int MAXTW = 13;            // 16x16 output tiles per wave (7 x 7 over 4 waves)
+static_assert(ANSTG * ASTG <= 2 * DMAX * ALD, "the ring overlays the transform buffers");
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// 16 rows of T~ and of T~^T (rows 16q..16q+15 of the slot pair at toff, np wide) into
+// a ring stage: 8 direct global-to-LDS loads per wave; lanes past the row end are
+// clamped onto its last 16 bytes and fill LDS columns that are never read.
+__device__ __forceinline__ void adj_issue(const double *T, long long toff, int np, int q,
+                                          double *ring, int stage) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = min(2 * lane, np - 2);
+  const double *Ts = T + toff + (long long)(16 * q + wave) * np + col;
+  const double *Tt = Ts + (long long)np * np;
+  const int lbase = __builtin_amdgcn_readfirstlane(
+      (int)(size_t)(__attribute__((address_space(3))) void *)ring + (stage * ASTG + wave * ARS) * 8);
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    __builtin_amdgcn_global_load_lds((const void *)(Ts + u * ANW * np),
+                                     (__attribute__((address_space(3))) void *)(size_t)(lbase + u * ANW * ARS * 8),
+                                     16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void *)(Tt + u * ANW * np),
+                                     (__attribute__((address_space(3))) void *)(size_t)(lbase + (16 + u * ANW) * ARS * 8),
+                                     16, 0, 0);
+  }
+}
+
+// Per pair domain d = [pq], over every cluster X that holds the pair (fixed order),
+// with c_X the MBE coefficient and T~ the cluster amplitudes (T~ and T~^T slots):
+//   A_d = sum_X c_X Tbar~,      Tbar~ = 2 T~ - T~^T
+//   g_d = sum_X c_X (T~^T Tbar~ + Tbar~ T~^T) = sum_X 2 c_X (Ts^T (Ts - Tt) + Tt^T Tt)
+// with Ts = T~ and Tt = T~^T as row-major slots, so every product is X^T Y of two
+// row-major matrices and both MFMA operands are read along rows.  Then
+//   G^F_d = W g' W^T   (g' = g + g^T for p < q, g for p = q)  -> Gd slot
+//   G^K_pq = Y_p^T (2 A_d) Y_q                                  -> GK block (and transpose)
+__global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms,
+                                                 const int *__restrict__ rank,
+                                                 const double *__restrict__ W,
+                                                 const double *__restrict__ Y,
+                                                 const double *__restrict__ Tall,
+                                                 const long long *__restrict__ dcp_ptr,
+                                                 const long long *__restrict__ dcp_toff,
+                                                 const double *__restrict__ dcp_coef,
+                                                 double *GK, long long ld, double *Gd) {
+  __shared__ __attribute__((aligned(16))) double buf[2 * DMAX * ALD];
+  double *L1 = buf, *L2 = buf + DMAX * ALD;
   const int d = blockIdx.x;
   const Domain D = doms[d];
   const int n = D.n, np = D.np, dt = rank[d];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l15 = lane & 15, lhi = lane >> 4;
   const bool diag = (D.p == D.q);
-  for (int e = tid; e < dt * dt; e += NTHREADS) {
-    int i = e / dt, j = e % dt;
-    L1[i * LDA + j] = 0.0;
-    L2[i * LDA + j] = 0.0;
+  const int tn = (dt + 15) >> 4, nt2 = tn * tn;
+
+  // ---- phase 1: accumulate g and A over the domain's cluster entries -------------
+  d4 g[MAXTW], A[MAXTW];
+#pragma unroll
+  for (int u = 0; u < MAXTW; u++) {
+    g[u] = (d4){0, 0, 0, 0};
+    A[u] = (d4){0, 0, 0, 0};
   }
-  __syncthreads();
-  const int tn = (dt + 15) >> 4;
-  for (long long en = dcp_ptr[d]; en < dcp_ptr[d + 1]; en++) {
-    const double c = dcp_coef[en];
-    const double *T = Tall + dcp_toff[en];
-    for (int e = tid; e < dt * dt; e += NTHREADS) {
-      int i = e / dt, j = e % dt;
-      L1[i * LDA + j] += c * (2.0 * T[i * np + j] - T[j * np + i]);
-    }
-    // g tiles: T^T Tbar + Tbar T^T
-    for (int tile = wave; tile < tn * tn; tile += 4) {
-      const int i0 = (tile / tn) * 16, j0 = (tile % tn) * 16;
-      const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
-      d4 acc = {0, 0, 0, 0};
-      for (int k0 = 0; k0 < dt; k0 += 4) {
-        const int k = k0 + (lane >> 4);
-        double a1 = 0, b1 = 0, a2 = 0, b2 = 0;
-        if (ia < dt && k < dt) {
-          a1 = T[k * np + ia];                                 // (T^T)(i,k)
-          a2 = 2.0 * T[ia * np + k] - T[k * np + ia];          // Tbar(i,k)
+  const long long e0 = dcp_ptr[d], e1 = dcp_ptr[d + 1];
+  const long long nchunk = (e1 - e0) * tn;
+  // producer: chunk k = (entry e0 + k / tn, rows 16 (k % tn) ..)
+  auto issue_k = [&](long long k) {
+    const long long en = e0 + k / tn;
+    adj_issue(Tall, dcp_toff[en], np, (int)(k % tn), buf, (int)(k % ANSTG));
+  };
+  if (nchunk > 0) issue_k(0);
+  if (nchunk > 1) issue_k(1);
+  for (long long k = 0; k < nchunk; k++) {
+    // this wave's loads of chunk k are done once at most the next chunk's 8 remain
+    if (k + 1 < nchunk)
+      asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (k + 2 < nchunk) issue_k(k + 2);
+    const long long en = e0 + k / tn;
+    const int q = (int)(k % tn);
+    const double c = dcp_coef[en], c2 = 2.0 * c;
+    const double *Ts = buf + (k % ANSTG) * ASTG, *Tt = Ts + 16 * ARS;
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      const int tau = wave + ANW * u;
+      if (tau < nt2) {
+        const int ib = tau / tn, jb = tau - ib * tn;
+        const int ci = 16 * ib + l15, cj = 16 * jb + l15;
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int rr = (4 * kk + lhi) * ARS;
+          const double tsj = Ts[rr + cj], ttj = Tt[rr + cj];
+          g[u] = mfma64(Ts[rr + ci], c2 * (tsj - ttj), g[u]);
+          g[u] = mfma64(Tt[rr + ci], c2 * ttj, g[u]);
         }
-        if (jb < dt && k < dt) {
-          b1 = 2.0 * T[k * np + jb] - T[jb * np + k];         // Tbar(k,j)
-          b2 = T[jb * np + k];                                 // (T^T)(k,j)
+        if (ib == q) {
+          // A tile rows 16 ib + 4v + lhi are rows 4v + lhi of this chunk
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            const int rr = (4 * v + lhi) * ARS;
+            A[u][v] += c * (2.0 * Ts[rr + cj] - Tt[rr + cj]);
+          }
         }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc, 0, 0, 0);
       }
+    }
+  }
+  __syncthreads();   // ring free: buf becomes L1 / L2
+
+  // ---- phase 2: g' -> L1 (dt x dt), W -> L2 (n x n) --------------------------------
+#pragma unroll
+  for (int u = 0; u < MAXTW; u++) {
+    const int tau = wave + ANW * u;
+    if (tau < nt2) {
+      const int ib = tau / tn, jb = tau - ib * tn;
+#pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int i = i0 + (lane >> 4) + 4 * v, j = j0 + (lane & 15);
-        if (i < dt && j < dt) L2[i * LDA + j] += c * acc[v];
+        const int i = 16 * ib + 4 * v + lhi, j = 16 * jb + l15;
+        if (i < dt && j < dt) L1[i * ALD + j] = g[u][v];
       }
     }
-    __syncthreads();
   }
-  // symmetrise g for p < q (both orderings of the pair contribute)
+  for (int e = tid; e < n * n; e += ANT) {
+    const int i = e / n, a = e - i * n;
+    L2[i * ALD + a] = W[D.moff + e];
+  }
+  __syncthreads();
   if (!diag) {
-    for (int e = tid; e < dt * dt; e += NTHREADS) {
-      int i = e / dt, j = e % dt;
-      if (i < j) {
-        double s = L2[i * LDA + j] + L2[j * LDA + i];
-        L2[i * LDA + j] = s;
-        L2[j * LDA + i] = s;
-      } else if (i == j) {
-        L2[i * LDA + i] *= 2.0;
+    // g' = g + g^T, through registers
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      const int tau = wave + ANW * u;
+      if (tau < nt2) {
+        const int ib = tau / tn, jb = tau - ib * tn;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int i = 16 * ib + 4 * v + lhi, j = 16 * jb + l15;
+          g[u][v] = (i < dt && j < dt) ? L1[i * ALD + j] + L1[j * ALD + i] : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      const int tau = wave + ANW * u;
+      if (tau < nt2) {
+        const int ib = tau / tn, jb = tau - ib * tn;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int i = 16 * ib + 4 * v + lhi, j = 16 * jb + l15;
+          if (i < dt && j < dt) L1[i * ALD + j] = g[u][v];
+        }
       }
     }
     __syncthreads();
   }
-  // T2 = W g' (n x dt) -> global Gd slot
-  const double *Wd = W + D.moff;
-  double *G = Gd + D.moff;
-  for (int e = tid; e < n * dt; e += NTHREADS) {
-    int i = e / dt, j = e % dt;
-    double s = 0.0;
-    for (int k = 0; k < dt; k++) s += Wd[i * n + k] * L2[k * LDA + j];
-    G[i * n + j] = s;
+
+  // ---- phase 3: Z = W g' (n x dt) -> L1, then G^F = Z W^T (n x n) -> Gd -----------
+  const int tnn = (n + 15) >> 4;
+  {
+    d4 Z[MAXTW];
+    const int nz = tnn * tn;
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      Z[u] = (d4){0, 0, 0, 0};
+      const int tau = wave + ANW * u;
+      if (tau < nz) {
+        const int ib = tau / tn, jb = tau - ib * tn;
+        const int i = 16 * ib + l15, b = 16 * jb + l15;
+        for (int a0 = 0; a0 < dt; a0 += 4) {
+          const int a = a0 + lhi;
+          const double w = (i < n && a < dt) ? L2[i * ALD + a] : 0.0;
+          const double gv = (a < dt && b < dt) ? L1[a * ALD + b] : 0.0;
+          Z[u] = mfma64(w, gv, Z[u]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      const int tau = wave + ANW * u;
+      if (tau < nz) {
+        const int ib = tau / tn, jb = tau - ib * tn;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int i = 16 * ib + 4 * v + lhi, b = 16 * jb + l15;
+          if (i < n && b < dt) L1[i * ALD + b] = Z[u][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  {
+    double *G = Gd + D.moff;
+    for (int tau = wave; tau < tnn * tnn; tau += ANW) {
+      const int ib = tau / tnn, jb = tau - ib * tnn;
+      const int i = 16 * ib + l15, j = 16 * jb + l15;
+      d4 acc = {0, 0, 0, 0};
+      for (int b0 = 0; b0 < dt; b0 += 4) {
+        const int b = b0 + lhi;
+        const double z = (i < n && b < dt) ? L1[i * ALD + b] : 0.0;
+        const double w = (j < n && b < dt) ? L2[j * ALD + b] : 0.0;
+        acc = mfma64(z, w, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int r = 16 * ib + 4 * v + lhi;
+        if (r < n && j < n) G[r * n + j] = acc[v];
+      }
+    }
   }
   __syncthreads();
-  // Gd = T2 W^T (n x n) -> L2, then global
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    int i = e / n, j = e % n;
-    double s = 0.0;
-    for (int k = 0; k < dt; k++) s += G[i * n + k] * Wd[j * n + k];
-    L2[i * LDA + j] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    int i = e / n, j = e % n;
-    G[i * n + j] = L2[i * LDA + j];
-  }
-  __syncthreads();
-  // G^K block: T1 = 2 A Y_q (dt x rq) -> L2 ; Gamma = Y_p^T T1 (rp x rq)
-  const double *Yd = Y + D.moff;
+
+  // ---- phase 4: G^K_pq = Y_p^T (2A) Y_q -------------------------------------------
   const int rq = diag ? D.rp : D.rq, qcol = diag ? 0 : D.rp, offq = diag ? D.offp : D.offq;
-  for (int e = tid; e < dt * rq; e += NTHREADS) {
-    int a = e / rq, j = e % rq;
-    double s = 0.0;
-    for (int k = 0; k < dt; k++) s += L1[a * LDA + k] * Yd[k * n + qcol + j];
-    L2[a * LDA + j] = 2.0 * s;
+#pragma unroll
+  for (int u = 0; u < MAXTW; u++) {
+    const int tau = wave + ANW * u;
+    if (tau < nt2) {
+      const int ib = tau / tn, jb = tau - ib * tn;
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = 16 * ib + 4 * v + lhi, j = 16 * jb + l15;
+        if (i < dt && j < dt) L1[i * ALD + j] = 2.0 * A[u][v];
+      }
+    }
+  }
+  for (int e = tid; e < dt * n; e += ANT) {
+    const int a = e / n, j = e - a * n;
+    L2[a * ALD + j] = Y[D.moff + e];
   }
   __syncthreads();
-  for (int e = tid; e < D.rp * rq; e += NTHREADS) {
-    int i = e / rq, j = e % rq;
-    double s = 0.0;
-    for (int k = 0; k < dt; k++) s += Yd[k * n + i] * L2[k * LDA + j];
-    GK[(long long)(D.offp + i) * ld + (offq + j)] = s;
-    if (!diag) GK[(long long)(offq + j) * ld + (D.offp + i)] = s;
+  const int tq = (rq + 15) >> 4, tp = (D.rp + 15) >> 4;
+  {
+    // T1 = (2A) Y_q (dt x rq) -> L1
+    d4 T1[MAXTW];
+    const int n1 = tn * tq;
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      T1[u] = (d4){0, 0, 0, 0};
+      const int tau = wave + ANW * u;
+      if (tau < n1) {
+        const int ib = tau / tq, jb = tau - ib * tq;
+        const int a = 16 * ib + l15, j = 16 * jb + l15;
+        for (int b0 = 0; b0 < dt; b0 += 4) {
+          const int b = b0 + lhi;
+          const double x = (a < dt && b < dt) ? L1[a * ALD + b] : 0.0;
+          const double y = (b < dt && j < rq) ? L2[b * ALD + qcol + j] : 0.0;
+          T1[u] = mfma64(x, y, T1[u]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXTW; u++) {
+      const int tau = wave + ANW * u;
+      if (tau < n1) {
+        const int ib = tau / tq, jb = tau - ib * tq;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int a = 16 * ib + 4 * v + lhi, j = 16 * jb + l15;
+          if (a < dt && j < rq) L1[a * ALD + j] = T1[u][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Gamma = Y_p^T T1 (rp x rq) -> GK at (offp, offq), and its transpose for p < q
+  for (int tau = wave; tau < tp * tq; tau += ANW) {
+    const int ib = tau / tq, jb = tau - ib * tq;
+    const int i = 16 * ib + l15, j = 16 * jb + l15;
+    d4 acc = {0, 0, 0, 0};
+    for (int a0 = 0; a0 < dt; a0 += 4) {
+      const int a = a0 + lhi;
+      const double y = (a < dt && i < D.rp) ? L2[a * ALD + i] : 0.0;
+      const double t = (a < dt && j < rq) ? L1[a * ALD + j] : 0.0;
+      acc = mfma64(y, t, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int r = 16 * ib + 4 * v + lhi;
+      if (r < D.rp && j < rq) {
+        GK[(long long)(D.offp + r) * ld + (offq + j)] = acc[v];
+        if (!diag) GK[(long long)(offq + j) * ld + (D.offp + r)] = acc[v];
+      }
+    }
   }
 }
 
@@ -134,7 +318,7 @@ hipError_t launch_adjoint(const Domain *dom, int ndom, const int *rank, const do
                           const long long *dcp_toff, const double *dcp_coef, double *GK,
                           long long ld, double *Gd, hipStream_t s) {
   if (ndom <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adjoint, dim3(ndom), dim3(NTHREADS), 0, s, dom, rank, W, Y, T, dcp_ptr,
+  hipLaunchKernelGGL(k_adjoint, dim3(ndom), dim3(ANT), 0, s, dom, rank, W, Y, T, dcp_ptr,
                      dcp_toff, dcp_coef, GK, ld, Gd);
   return hipGetLastError();
 }
