@@ -73,11 +73,27 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
   }
   const double absthr = 1e-18 * sqrt(block_sum<NT>(f2, red));
   if (n == 1) return;
-  // (I, J) of upper-triangle block b (row-major over I <= J < h) and (i, k) of V
-  // entry e = i*h + k, computed each step without divisions
+  // Each thread owns the same 2x2 blocks (I, J), I <= J < h, and the same V
+  // entries (i, k) in every step (only the pair tables change), so both sets
+  // are found once: block b = tid + NT u (row-major over the upper triangle),
+  // V entry e = tid + NT u = i h + k.
   const int nb = h * (h + 1) / 2;
-  const unsigned inv_h = ((1u << 20) + h - 1) / h;   // floor(e * inv_h / 2^20) = e / h for e < 2^20 / h
-  const float twoh1 = 2.0f * h + 1.0f;
+  int bI[MAXB], bJ[MAXB];
+#pragma unroll
+  for (int u = 0; u < MAXB; u++) {
+    const int b = tid + NT * u;
+    int I = 0, rem = b;
+    while (I < h && rem >= h - I) { rem -= h - I; I++; }
+    bI[u] = (b < nb) ? I : -1;
+    bJ[u] = I + rem;
+  }
+  int vI[MAXV], vK[MAXV];
+#pragma unroll
+  for (int u = 0; u < MAXV; u++) {
+    const int e = tid + NT * u;
+    vI[u] = (e < n * h) ? e / h : -1;
+    vK[u] = e - (e / h) * h;
+  }
   for (int sweep = 0; sweep < 60; sweep++) {
     if (tid == 0) *flag = 0;
     __syncthreads();
@@ -107,19 +123,17 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
         pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s; zz[tid] = z;
       }
       __syncthreads();
-      for (int b = tid; b < nb; b += NT) {
-        int I = (int)((twoh1 - sqrtf(twoh1 * twoh1 - 8.0f * b)) * 0.5f);
-        if (I < 0) I = 0;
-        while (I + 1 < h && (I + 1) * h - ((I + 1) * I) / 2 <= b) I++;
-        while (I > 0 && I * h - (I * (I - 1)) / 2 > b) I--;
-        const int J = I + (b - (I * h - (I * (I - 1)) / 2));
-        const int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
-        const double cI = cs[I], sI = sn[I], cJ = cs[J], sJ = sn[J];
+#pragma unroll
+      for (int u = 0; u < MAXB; u++) {
+        const int I = bI[u], J = bJ[u];
+        if (I < 0) continue;
+        const double sI = sn[I], sJ = sn[J];
         if (I == J) {
+          const int pI = pp[I], qI = qq[I];
           if (qI < n && zz[I]) {
             const double apq = A[pI * LD + qI];
             if (sI != 0.0) {
-              const double tt = sI / cI;
+              const double tt = sI / cs[I];
               A[pI * LD + pI] -= tt * apq;
               A[qI * LD + qI] += tt * apq;
             }
@@ -127,6 +141,8 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
             A[qI * LD + pI] = 0.0;
           }
         } else if (sI != 0.0 || sJ != 0.0) {
+          const int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
+          const double cI = cs[I], cJ = cs[J];
           const bool vqI = qI < n, vqJ = qJ < n;
           const double b00 = A[pI * LD + pJ];
           const double b01 = vqJ ? A[pI * LD + qJ] : 0.0;
@@ -142,9 +158,10 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
           if (vqI && vqJ) { A[qI * LD + qJ] = n11; A[qJ * LD + qI] = n11; }
         }
       }
-      for (int e = tid; e < n * h; e += NT) {
-        const int i = (int)(((unsigned long long)e * inv_h) >> 20);
-        const int k = e - i * h;
+#pragma unroll
+      for (int u = 0; u < MAXV; u++) {
+        const int i = vI[u], k = vK[u];
+        if (i < 0) continue;
         const double s = sn[k];
         if (s != 0.0) {
           const int p = pp[k], q = qq[k];

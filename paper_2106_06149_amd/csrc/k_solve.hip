@@ -333,7 +333,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
   __shared__ TgtDesc tg_l[MAXT];
   __shared__ TermFlat tm_l[MAXTERM];
   __shared__ int s_cur;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int l15 = lane & 15, lhi = lane >> 4;
   double *Rs = a.Rs + (long long)blockIdx.x * a.rs_stride;
   for (;;) {
