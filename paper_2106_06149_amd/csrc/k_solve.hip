@@ -415,17 +415,25 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
 #pragma unroll
               for (int kk = 0; kk < 4; kk++)
                 bv[s][kk] = coef * mc[(4 * kk + lhi) * RS + (wave + NW * s) * 16 + l15];
+            // operands of tile kb + 1 are read from LDS before the MFMAs of tile kb
+            double av[2][4];
+#pragma unroll
+            for (int kk = 0; kk < 4; kk++) av[0][kk] = ts[(4 * kk + lhi) * RS + l15];
 #pragma unroll
             for (int kb = 0; kb < MT; kb++) {
               if (kb < nkb) {
-                double av[4];
+                // unconditional (columns up to 127 of a 130-wide row): a uniform number
+                // of LDS reads in flight lets the wait cover only the older tile
+                if (kb + 1 < MT) {
 #pragma unroll
-                for (int kk = 0; kk < 4; kk++) av[kk] = ts[(4 * kk + lhi) * RS + kb * 16 + l15];
+                  for (int kk = 0; kk < 4; kk++)
+                    av[(kb + 1) & 1][kk] = ts[(4 * kk + lhi) * RS + (kb + 1) * 16 + l15];
+                }
 #pragma unroll
                 for (int s = 0; s < NS; s++)
                   if (wave + NW * s < njb)
 #pragma unroll
-                    for (int kk = 0; kk < 4; kk++) Xp[s][kb] = mfma(av[kk], bv[s][kk], Xp[s][kb]);
+                    for (int kk = 0; kk < 4; kk++) Xp[s][kb] = mfma(av[kb & 1][kk], bv[s][kk], Xp[s][kb]);
               }
             }
           }
@@ -434,18 +442,24 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
           for (int kc = 0; kc < MT; kc++) {
             if (kc < nkb) {
               const double *mc = next_chunk(a, ds, pr, rg) + 16 * RS;
+              // operands of tile jb + 1 are read from LDS before the MFMAs of tile jb
+              double av[2][4];
+#pragma unroll
+              for (int kk = 0; kk < 4; kk++) av[0][kk] = mc[(4 * kk + lhi) * RS + l15];
 #pragma unroll
               for (int jb = 0; jb < MT; jb++) {
                 if (jb < njb) {
-                  double av[4];
+                  if (jb + 1 < MT) {
 #pragma unroll
-                  for (int kk = 0; kk < 4; kk++) av[kk] = mc[(4 * kk + lhi) * RS + jb * 16 + l15];
+                    for (int kk = 0; kk < 4; kk++)
+                      av[(jb + 1) & 1][kk] = mc[(4 * kk + lhi) * RS + (jb + 1) * 16 + l15];
+                  }
 #pragma unroll
                   for (int s = 0; s < NS; s++)
                     if (wave + NW * s < njb)
 #pragma unroll
                       for (int kk = 0; kk < 4; kk++)
-                        Racc[s][jb] = mfma(av[kk], Xp[s][kc][kk], Racc[s][jb]);
+                        Racc[s][jb] = mfma(av[jb & 1][kk], Xp[s][kc][kk], Racc[s][jb]);
                 }
               }
             }
