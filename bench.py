@@ -33,7 +33,45 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=300,
                     help="clusters of the workload timed on the CPU oracle (0 = skip)")
     ap.add_argument("--tau-R", type=float, default=1e-10)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB once (device to "
+                         "device) so that a counter run can calibrate its byte counters")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_solve_mbe3-lattice-nocc400.md")
+SOLVE_SOURCES = ["paper_2106_06149_amd/csrc/k_solve.hip", "paper_2106_06149_amd/csrc/osv_internal.h"]
+
+
+def solve_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOLVE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_solve launch from the committed counter summary, or None
+    when there is none for this workload or the solve kernel has changed since
+    the counters were taken (the summary records a hash of its sources)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("- ") and ":" in ln:
+            k, v = ln[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("source_hash") != solve_source_hash() or kv.get("workload") != str(workload):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(s, n_sample, seed=7):
@@ -88,13 +126,22 @@ def main():
     F = torch.from_numpy(s.F_occ).to(dev)
     sel = Selection(s.sel_mode, s.cut2, s.cut3)
     torch.cuda.synchronize()
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)                 # reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr)
+        del src, dst
 
     def step(prec):
         oc = OSVContext(Qt, C, eps, F, s.r, s.centroid, sel, prec)
-        oc.solve(tau_R=args.tau_R)
+        info = oc.solve(tau_R=args.tau_R)
         E, orders, _ = oc.energy()
         oc.densities(dC=True, dF=True, deps=True)
-        out = (E, orders, oc.stage_times(), oc.stage_flops(), oc.counts)
+        counts = dict(oc.counts, sweeps=info["sweeps"])
+        out = (E, orders, oc.stage_times(), oc.stage_flops(), counts)
         oc.close()
         return out
 
@@ -142,9 +189,16 @@ def main():
                    "pair_blocks": npb, "precision": "mixed" if main_prec == 1 else "fp64"},
         "roofline": {"kernel": "k_solve", "bound": "mfma", "achieved": achieved,
                      "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64_mfma_tflops"], "traffic": None},
+                     "frac": achieved / PEAK["fp64_mfma_tflops"],
+                     "traffic": measured_traffic(args.workload)},
         "stages_ms": {k: round(float(np.mean([st[k] for st in r["stages"]])), 2) for k in r["stages"][0]},
         "E": r["E"],
+        # the path without the build stages (S/F, K, domain preparation, couplings)
+        "pair_blocks_per_s_solve_energy_densities": npb / (1e-3 * sum(
+            float(np.mean([st[k] for st in r["stages"]]))
+            for k in ("solve", "energy", "adjoint", "backtransform"))),
+        # sweeps = the largest number any cluster took (every cluster runs to its own bar)
+        "pair_block_sweeps_per_s": npb * r["counts"]["sweeps"] / (solve_ms * 1e-3),
     }
     if 0 in res and 1 in res:
         out["fp64_value"] = npb / res[0]["dt"]

@@ -192,8 +192,27 @@ int osv_densities(osv_ctx *ctx, hipStream_t stream, double *dE_dC, double *dE_dF
 int osv_plan_clusters(int32_t nocc, const double *centroid, const osv_select *sel,
                       osv_counts *counts, int32_t *lmos, double *coef, int64_t cap);
 
-/* osv_destroy -- free a context and its device memory; NULL is a no-op. */
+/* osv_destroy -- free a context; NULL is a no-op.  Waits for the device to finish
+ * queued work, then returns the context's device blocks to the library's cache. */
 void osv_destroy(osv_ctx *ctx);
+
+/*
+ * Device memory cache.  Every context takes its device buffers from a
+ * process-wide cache (one per device): blocks freed by osv_destroy are kept and
+ * handed to later contexts that ask for the same size class (requests round up
+ * to 512 B below 1 MiB, to 2 MiB above; a cached block may be up to 1/8 larger),
+ * so a caller that builds one context per geometry step allocates only in its
+ * first step.  A failed allocation releases the device's cache and retries.
+ * Reused blocks are not cleared; the environment variable OSV_POOL_POISON=1
+ * fills every block handed out with 0xFF bytes (a debugging aid).
+ *   osv_release_cached_memory(device)  hipFree the cached blocks of device
+ *                                      (-1: of every device).  Blocks held by
+ *                                      live contexts are not touched.  Returns
+ *                                      OSV_OK, or OSV_E_ARG for device < -1.
+ *   osv_cached_bytes(device)           bytes held in the cache (-1: all devices).
+ */
+int osv_release_cached_memory(int32_t device);
+int64_t osv_cached_bytes(int32_t device);
 
 /* message of a status code (static string) */
 const char *osv_status_string(int status);

@@ -16,7 +16,7 @@ OSV_MAX_DOMAIN = 100
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_densities",
            "osv_plan_clusters", "osv_destroy", "osv_status_string", "osv_last_error",
-           "osv_stage_times", "osv_stage_flops"]
+           "osv_stage_times", "osv_stage_flops", "osv_release_cached_memory", "osv_cached_bytes"]
 
 
 class OsvSystem(ctypes.Structure):
@@ -87,6 +87,10 @@ def load():
     lib.osv_stage_times.restype = ctypes.c_int
     lib.osv_stage_flops.argtypes = [vp, ctypes.POINTER(dbl)]
     lib.osv_stage_flops.restype = ctypes.c_int
+    lib.osv_release_cached_memory.argtypes = [i32]
+    lib.osv_release_cached_memory.restype = ctypes.c_int
+    lib.osv_cached_bytes.argtypes = [i32]
+    lib.osv_cached_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 

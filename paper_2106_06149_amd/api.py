@@ -28,6 +28,17 @@ class Selection:
         return L.OsvSelect(self.mode, self.cut2, self.cut3, self.l2b, self.l3b, self.tau_S)
 
 
+def release_cached_memory(device: int = -1):
+    """Free the device blocks that the library keeps for reuse by later contexts
+    (device -1: every device).  Blocks of live contexts are not touched."""
+    L.check(L.load().osv_release_cached_memory(device))
+
+
+def cached_bytes(device: int = -1) -> int:
+    """Bytes of device memory held in the library's block cache."""
+    return int(L.load().osv_cached_bytes(device))
+
+
 def plan_clusters(centroid: np.ndarray, sel: Selection):
     """Host-only cluster selection (no GPU): counts, LMO triples (-1 padded), c_X."""
     lib = L.load()

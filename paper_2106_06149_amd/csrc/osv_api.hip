@@ -392,7 +392,10 @@ struct osv_ctx {
   std::vector<double> flops_sweep;  // per cluster: residual-term flops of one sweep
   std::vector<int> rank_host;
   ~osv_ctx() {
-    for (void *p : allocs) (void)hipFree(p);
+    // work still queued on the caller's stream may use these blocks: finish it
+    // before they go back to the cache and a later context reuses them
+    if (!allocs.empty()) (void)hipDeviceSynchronize();
+    for (void *p : allocs) pool_free(p);
   }
 };
 
@@ -416,9 +419,10 @@ template <class T>
 int dalloc(osv_ctx *ctx, T **p, size_t count) {
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   void *q = nullptr;
-  hipError_t e = hipMalloc(&q, bytes);
+  hipError_t e = pool_alloc(&q, bytes);
   if (e != hipSuccess)
-    return fail(ctx, OSV_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    return fail(ctx, e == hipErrorOutOfMemory ? OSV_E_NOMEM : OSV_E_HIP,
+                "device allocation of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
   ctx->allocs.push_back(q);
   *p = (T *)q;
   return OSV_OK;
@@ -1067,5 +1071,13 @@ int osv_stage_flops(const osv_ctx *ctx, double *f9) {
 }
 
 void osv_destroy(osv_ctx *ctx) { delete ctx; }
+
+int osv_release_cached_memory(int32_t device) {
+  if (device < -1) return fail(nullptr, OSV_E_ARG, "device must be >= -1");
+  pool_release(device);
+  return OSV_OK;
+}
+
+int64_t osv_cached_bytes(int32_t device) { return (int64_t)pool_cached_bytes(device); }
 
 }  // extern "C"

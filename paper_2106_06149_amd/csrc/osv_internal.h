@@ -162,6 +162,11 @@ hipError_t launch_pocc(const long long *ptr, const long long *idx, const double 
                        const double *Pl, int nocc, double *out, hipStream_t s);
 }  // namespace osv
 namespace osv {
+// process-wide cache of device allocations (one free list per device); see devpool.hip
+hipError_t pool_alloc(void **p, size_t bytes);  // on the current device
+void pool_free(void *p);                         // back to its device's cache
+void pool_release(int device);                   // hipFree the cached blocks (-1: every device)
+size_t pool_cached_bytes(int device);
 hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
                               int nocc, double *out, hipStream_t s);
 }
