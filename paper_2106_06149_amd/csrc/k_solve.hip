@@ -33,9 +33,11 @@
 // so every chunk of 16 k-rows is 16 contiguous rows of two matrices.  After a
 // target's terms its epilogue chunks bring 16 rows of K~^T and of T~^T plus e~, so
 // the residual R~ = terms + K~ + Delta T~, its norm and the Jacobi step
-// -R~ / Delta are formed from LDS and registers only.  The step is written to a
-// per-workgroup scratch in both orientations and added to T~ and T~^T once the
-// sweep's norms are known.  All chunks stream through a 4-stage LDS ring by
+// -R~ / Delta are formed from LDS and registers only.  Sweeps alternate between
+// two amplitude buffers: a sweep reads T~ and T~^T from one and writes the
+// stepped amplitudes, in both orientations, to the other, so no step goes
+// through scratch; after the last sweep the final amplitudes are moved to T if
+// they are in the second buffer.  All chunks stream through a 4-stage LDS ring by
 // direct global-to-LDS loads (16 bytes per lane, no registers), issued three
 // chunks ahead of the multiply across term and target boundaries; a chunk is
 // consumed after a partial vmcnt wait and one barrier.  Every reduction has a
@@ -146,6 +148,7 @@ struct Producer {
   int np;               // target's padded dimension
   long long kslot, ttslot;
   int use_terms, use_epi;
+  const double *Tb;     // amplitude buffer this sweep reads
 };
 
 // Load the next target with something to issue (or run off the end).
@@ -222,7 +225,7 @@ __device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, P
     const bool p1 = p.q < p.nkb;
     const int c = p1 ? p.q : p.q - p.nkb;
     const int ldT = p.ldT, ldM = p.ldM;
-    const double *Tg = a.T + p.tsrc + (16 * c + wave) * ldT + min(2 * lane, ldT - 2);
+    const double *Tg = p.Tb + p.tsrc + (16 * c + wave) * ldT + min(2 * lane, ldT - 2);
     const double *Mg = a.M + p.moff + (16 * c + wave) * ldM + min(2 * lane, ldM - 2);
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -239,7 +242,7 @@ __device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, P
     const int np = p.np;
     const int col = min(2 * lane, np - 2);
     const double *Kg = a.Kep + p.kslot + (16 * p.q + wave) * np + col;
-    const double *Tg = a.T + p.ttslot + (16 * p.q + wave) * np + col;
+    const double *Tg = p.Tb + p.ttslot + (16 * p.q + wave) * np + col;
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       __builtin_amdgcn_global_load_lds((const void *)(Kg + u * NW * np),
@@ -354,13 +357,18 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       for (int c = tid; c < cl.ncp; c += SNT) tg_l[c] = Desc<DLDS>::make_target(a, cl, c);
       for (int t = tid; t < cl.term1 - cl.term0; t += SNT) tm_l[t] = a.tflat[cl.term0 + t];
     }
+    // both buffers start at zero: entries beyond the 16-rounded kept rank are
+    // never written by a sweep and stay zero in both
     for (int c = 0; c < cl.ncp; c++) {
       const CPair P = a.cp[cl.cp0 + c];
       const int np = a.dom[P.dom].np;
-      double *T = a.T + P.toff;
-      for (int e = tid; e < 2 * np * np; e += SNT) T[e] = 0.0;
+      double *T = a.T + P.toff, *T2 = a.T2 + P.toff;
+      for (int e = tid; e < 2 * np * np; e += SNT) {
+        T[e] = 0.0;
+        T2[e] = 0.0;
+      }
     }
-    int sweep = 0;
+    int sweep = 0, cur = 0;   // cur: the buffer holding the current amplitudes
     double maxn = 0.0, E = 0.0;
     bool pmode = false;  // after convergence: the pass for energies and dE/df
     for (;;) {
@@ -370,6 +378,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       pr.ncp = cl.ncp;
       pr.use_terms = (sweep > 0 || pmode) ? 1 : 0;
       pr.use_epi = pmode ? 0 : 1;
+      double *const Tcur = cur ? a.T2 : a.T, *const Tnext = cur ? a.T : a.T2;
+      pr.Tb = Tcur;
       next_target(ds, pr);
       Ring rg{ring, 0, 0, 0};
       issue(a, ds, pr, ring, 0);
@@ -482,8 +492,9 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         }
         if (!pmode) {
           // epilogue: R~ = terms + K~ + Delta T~ tile row by tile row from the ring;
-          // norm, and the Jacobi step -R~ / Delta into scratch (both orientations)
-          double *dT = Rs + (P.toff - cl.toff0), *dTT = dT + (long long)np * np;
+          // norm, and the stepped amplitudes T~ - R~ / Delta into the other buffer
+          // (both orientations); a converged sweep's step is never read
+          double *Tn = Tnext + P.toff, *TnT = Tn + (long long)np * np;
           double ss = 0.0;
 #pragma unroll
           for (int jb = 0; jb < MT; jb++) {
@@ -499,12 +510,13 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
                   for (int v = 0; v < 4; v++) {
                     const int jl = lhi + 4 * v, j = jb * 16 + jl;
                     const double delta = ei + ev[j];
-                    const double r = Racc[s][jb][v] + st[jl * RS + i] + delta * st[(16 + jl) * RS + i];
+                    const double tij = st[(16 + jl) * RS + i];   // T~(i, j) from the T~^T row j
+                    const double r = Racc[s][jb][v] + st[jl * RS + i] + delta * tij;
                     const bool in = (i < nt) && (j < nt);
-                    const double d = in ? -r / delta : 0.0;
+                    const double tn = in ? tij - r / delta : 0.0;
                     ss += in ? r * r : 0.0;
-                    dTT[j * np + i] = d;
-                    dT[i * np + j] = d;
+                    TnT[j * np + i] = tn;
+                    Tn[i * np + j] = tn;
                   }
                 }
               }
@@ -522,7 +534,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         } else {
           // P pass: <Tbar~, 2 K~ + Delta T~>, <Tbar~, T~> and <Tbar~, Y_u> per term
           __syncthreads();
-          const double *Tt = a.T + P.toff, *TT = Tt + (long long)np * np;
+          const double *Tt = Tcur + P.toff, *TT = Tt + (long long)np * np;
           const double *Kg = a.Kep + P.kslot, *ev = Kg + (long long)np * np;
           for (int g0 = 0; g0 == 0 || g0 < P.nterm; g0 += NTG) {
             double acc[NTG + 2];
@@ -578,29 +590,19 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         E = 0.0;
         continue;
       }
-      // Jacobi update: T~ and T~^T += the steps over each pair's 16 njb square
-      for (int c = 0; c < cl.ncp; c++) {
-        const TgtDesc P = ds.target(c);
-        const int np = uni(P.np), m = uni(((P.nt + 15) >> 4) * 16);
-        double *__restrict__ T = a.T + P.toff;
-        const double *__restrict__ dT = Rs + (P.toff - cl.toff0);
-        for (int e = tid; e < 2 * m * 16; e += SNT) {
-          const int h = e / (m * 16), e2 = e - h * m * 16;
-          const int row = e2 >> 4, col = e2 & 15;
-          const long long base = (long long)h * np * np + (long long)row * np + col;
-          double tv[MT], dv[MT];
-#pragma unroll
-          for (int cb = 0; cb < MT; cb++)
-            if (16 * cb < m) {
-              tv[cb] = T[base + 16 * cb];
-              dv[cb] = dT[base + 16 * cb];
-            }
-#pragma unroll
-          for (int cb = 0; cb < MT; cb++)
-            if (16 * cb < m) T[base + 16 * cb] = tv[cb] + dv[cb];
-        }
-      }
+      cur ^= 1;   // the stepped amplitudes become current
       sweep++;
+    }
+    if (cur) {
+      // the final amplitudes are in the second buffer: move them to T
+      __syncthreads();
+      for (int c = 0; c < cl.ncp; c++) {
+        const CPair P = a.cp[cl.cp0 + c];
+        const int np = a.dom[P.dom].np;
+        const double *__restrict__ src = a.T2 + P.toff;
+        double *__restrict__ dst = a.T + P.toff;
+        for (int e = tid; e < 2 * np * np; e += SNT) dst[e] = src[e];
+      }
     }
     if (small) {
       __syncthreads();

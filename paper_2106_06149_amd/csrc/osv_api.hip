@@ -319,7 +319,6 @@ void build_clusters(int nocc, const Selection &s, Plan &P) {
       P.rs_stride = std::max(P.rs_stride, (long long)cp.nterm * npt * npt);
     }
     C.term1 = (int)P.terms.size();
-    P.rs_stride = std::max(P.rs_stride, P.n_T - C.toff0);
     P.n_pair_blocks += C.ncp;
     P.cls.push_back(C);
   }
@@ -363,6 +362,7 @@ struct osv_ctx {
   std::vector<void *> allocs;
   double *dS = nullptr, *dF = nullptr, *dK = nullptr, *dW = nullptr, *dY = nullptr, *dKt = nullptr;
   double *dEpst = nullptr, *dMinev = nullptr, *dM = nullptr, *dT = nullptr, *dRs = nullptr;
+  double *dT2 = nullptr;  // second amplitude buffer of the solve (Jacobi ping-pong)
   double *dEcl = nullptr, *dPl = nullptr, *dMaxres = nullptr, *dWts = nullptr, *dEout = nullptr;
   int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
   int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr;
@@ -685,6 +685,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   HIPCHK(ctx, launch_term_flat(ctx->dTerms, (long long)P.terms.size(), ctx->dCp, ctx->dCpl, ctx->dDom,
                                ctx->dRank, ctx->F, nocc, ctx->dTflat, s));
   if ((rc = dalloc(ctx, &ctx->dT, P.n_T))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dT2, P.n_T))) return rc;
   if ((rc = dalloc(ctx, &ctx->dRs, (size_t)ctx->nwg * P.rs_stride))) return rc;
   if ((rc = dalloc(ctx, &ctx->dEcl, ncl))) return rc;
   if ((rc = dalloc(ctx, &ctx->dPl, P.n_pl))) return rc;
@@ -841,6 +842,7 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   a.F_occ = ctx->F;
   a.nocc = ctx->nocc;
   a.T = ctx->dT;
+  a.T2 = ctx->dT2;
   a.Rs = ctx->dRs;
   a.rs_stride = P.rs_stride;
   a.Ecl = ctx->dEcl;

@@ -88,8 +88,9 @@ struct SolveArgs {
   const double *Kep;    // per domain: K~^T (np x np) then e~ (np), zero-padded
   const double *F_occ;  // nocc x nocc
   int nocc;
-  double *T;            // amplitudes per cluster pair
-  double *Rs;           // per-workgroup residual scratch
+  double *T;            // amplitudes per cluster pair (final values)
+  double *T2;           // second buffer of the same layout: sweeps alternate T -> T2 -> T
+  double *Rs;           // per-workgroup scratch (the P pass's per-term products)
   long long rs_stride;  // doubles per workgroup
   double *Ecl;          // [n_clusters] Hylleraas energies
   double *Pl;           // dE/dF inner products per cluster (nlmo x nlmo)
