@@ -192,6 +192,9 @@ def main():
                      "frac": achieved / PEAK["fp64_mfma_tflops"],
                      "traffic": measured_traffic(args.workload)},
         "stages_ms": {k: round(float(np.mean([st[k] for st in r["stages"]])), 2) for k in r["stages"][0]},
+        # algorithmic TFLOP/s per stage (kept ranks, selected blocks only) over its device time
+        "stage_tflops": {k: round(r["flops"][k] / (1e-3 * float(np.mean([st[k] for st in r["stages"]]))) / 1e12, 2)
+                         for k in r["flops"] if r["flops"][k] > 0 and k != "host_plan"},
         "E": r["E"],
         # the path without the build stages (S/F, K, domain preparation, couplings)
         "pair_blocks_per_s_solve_energy_densities": npb / (1e-3 * sum(
