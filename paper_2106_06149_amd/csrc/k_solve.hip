@@ -14,11 +14,12 @@
 // clusters from a cost-sorted queue, zeroes the cluster's amplitudes, and iterates
 //   R~ from the current T~ for every pair; stop if max ||R~||_F < tau_R;
 //   otherwise T~ <- T~ - R~ / (e~_a + e~_b - f_pp - f_qq)
-// to convergence inside the kernel.  After the stopping sweep one more pass over
-// the terms at the same amplitudes records, per pair,
+// to convergence inside the kernel.  At the final amplitudes the kernel records
 //   E^X = sum_pairs w <Tbar~, K~ + R~>   (eq:ec; w = 1 for p = q, 2 for p < q)
 // split into <Tbar~, 2 K~ + Delta T~> and the terms' <Tbar~, M op(T~_src) M^T>,
-// which are also the inner products that make up dE/df_ab.
+// which are also the inner products that make up dE/df_ab.  They come from the
+// stopping sweep itself when its convergence was predicted from the two previous
+// norms (geometric rate), else from one more pass over the terms (P pass).
 //
 // A term Y = M op(T) M^T runs on FP64 MFMA 16x16x4 tiles.  Wave w owns the
 // 16-wide target blocks i = w and i = w + 4: for each it forms the column block
@@ -59,6 +60,8 @@ constexpr int PLMAX = 64;       // clusters with nlmo^2 <= PLMAX keep dE/df sums
 constexpr int MAXT = SOLVE_MAXT;        // clusters with <= MAXT pairs and <= MAXTERM terms
 constexpr int MAXTERM = SOLVE_MAXTERM;  //   keep their pair and term descriptors in LDS
 constexpr int NTG = 6;          // P pass: terms per reduction group
+constexpr int FMAXTERM = 128;   // clusters with at most this many terms may take the
+                                // energy and dE/df products in their last sweep
 
 // What the sweep needs about one target pair of the current cluster.
 struct TgtDesc {
@@ -335,6 +338,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
   __shared__ double nrm[MAXT * NW];
   __shared__ TgtDesc tg_l[MAXT];
   __shared__ TermFlat tm_l[MAXTERM];
+  __shared__ double fpart[FMAXTERM];   // predicted last sweep: <Tbar~, Z_u> per term
+  __shared__ double fe[MAXT * 2];      //   and <Tbar~, 2K~ + Delta T~>, <Tbar~, T~> per target
   __shared__ int s_cur;
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int l15 = lane & 15, lhi = lane >> 4;
@@ -371,6 +376,31 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
     int sweep = 0, cur = 0;   // cur: the buffer holding the current amplitudes
     double maxn = 0.0, E = 0.0;
     bool pmode = false;  // after convergence: the pass for energies and dE/df
+    // A sweep predicted to be the last one (fmode) also stores, after each term,
+    // the target's residual terms so far Z_u = sum_{v <= u} coef_v Y_v, and after
+    // the target's epilogue takes <Tbar~, Z_u>, <Tbar~, 2K~ + Delta T~> and
+    // <Tbar~, T~>; if it converges, the energy and the dE/df products follow from
+    // these and the P pass is skipped.  A term's own product is the difference
+    // of two consecutive partial sums divided by its coefficient, so a cluster
+    // qualifies only if every term's |coef| is at least 2^-10 of the largest one
+    // of its target (no cancellation worse than 2^10 ulp), and if its terms and
+    // pairs fit the LDS tables.
+    bool fm_ok = false;
+    if (DLDS) {
+      int ok = (cl.term1 - cl.term0 <= FMAXTERM && cl.ncp <= MAXT) ? 1 : 0;
+      __syncthreads();   // tables written
+      if (ok && tid < cl.ncp) {
+        const TgtDesc P = tg_l[tid];
+        double cmax = 0.0;
+        for (int u = 0; u < P.nterm; u++) cmax = fmax(cmax, fabs(tm_l[P.term0 - cl.term0 + u].coef));
+        for (int u = 0; u < P.nterm; u++) {
+          const double cu = tm_l[P.term0 - cl.term0 + u].coef;
+          if (!(cu != 0.0 && fabs(cu) >= 0x1p-10 * cmax)) ok = 0;
+        }
+      }
+      fm_ok = __syncthreads_and(ok) != 0;
+    }
+    double n1 = 0.0, n2 = 0.0;   // norms of the previous two sweeps
     for (;;) {
       __syncthreads();   // amplitudes written, ring and scratch free
       Producer pr;
@@ -380,6 +410,9 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       pr.use_epi = pmode ? 0 : 1;
       double *const Tcur = cur ? a.T2 : a.T, *const Tnext = cur ? a.T : a.T2;
       pr.Tb = Tcur;
+      // geometric prediction of this sweep's norm: n1^2 / n2 below tau_R (a wrong
+      // guess costs the products' stores and sums, a missed one the whole P pass)
+      const bool fmode = fm_ok && !pmode && sweep >= 2 && n1 * n1 < a.tau_R * n2;
       next_target(ds, pr);
       Ring rg{ring, 0, 0, 0};
       issue(a, ds, pr, ring, 0);
@@ -474,8 +507,9 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
               }
             }
           }
-          if (pmode) {
-            // Y^T of this term to scratch slot u (read back after the target's terms)
+          if (pmode || fmode) {
+            // Y^T of this term (P pass), or R~^T of the terms so far (predicted last
+            // sweep), to scratch slot u, read back after the target's epilogue
             double *Y = Rs + (long long)u * np * np;
 #pragma unroll
             for (int s = 0; s < NS; s++) {
@@ -531,8 +565,10 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
             const double nr = sqrt(v1[0]);
             maxn_s = (nr > maxn_s || nr != nr) ? nr : maxn_s;
           }
-        } else {
+        }
+        if (pmode || fmode) {
           // P pass: <Tbar~, 2 K~ + Delta T~>, <Tbar~, T~> and <Tbar~, Y_u> per term
+          // (predicted last sweep: <Tbar~, Z_u> of the partial sums Z_u, kept in LDS)
           __syncthreads();
           const double *Tt = Tcur + P.toff, *TT = Tt + (long long)np * np;
           const double *Kg = a.Kep + P.kslot, *ev = Kg + (long long)np * np;
@@ -553,6 +589,17 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
                 if (g0 + k < P.nterm) acc[2 + k] += tb * Rs[(long long)(g0 + k) * np * np + j * np + i];
             }
             block_sums<NTG + 2>(acc, red);
+            if (fmode) {
+              if (tid == 0) {
+                if (g0 == 0) {
+                  fe[c * 2] = acc[0];
+                  fe[c * 2 + 1] = acc[1];
+                }
+                for (int k = 0; k < NTG && g0 + k < P.nterm; k++)
+                  fpart[P.term0 - cl.term0 + g0 + k] = acc[2 + k];
+              }
+              continue;
+            }
             if (g0 == 0) {
               E += P.w * acc[0];
               if (tid == 0) {
@@ -583,6 +630,37 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
           maxn = (nr > maxn || nr != nr) ? nr : maxn;
         }
       }
+      if (fmode && maxn < a.tau_R) {
+        // the predicted last sweep converged: energy and dE/df from its partial
+        // sums, in the fixed order of the P pass (targets, then their terms)
+        if (tid == 0)
+          for (int e = 0; e < nl * nl; e++) Pl[e] = 0.0;
+        E = 0.0;
+        for (int c = 0; c < cl.ncp; c++) {
+          const TgtDesc P = tg_l[c];
+          const double ek = fe[c * 2], et = fe[c * 2 + 1];
+          E += P.w * ek;
+          if (tid == 0) {
+            Pl[P.la * nl + P.la] -= 2.0 * et;
+            if (P.la != P.lb) Pl[P.lb * nl + P.lb] -= 2.0 * et;
+          }
+          double prev = 0.0;
+          for (int u = 0; u < P.nterm; u++) {
+            const int t = P.term0 - cl.term0 + u;
+            const double pu = fpart[t];
+            const double d = pu - prev;   // coef_u <Tbar~, Y_u>
+            prev = pu;
+            E += P.w * d;
+            if (tid == 0) {
+              const double y = d / tm_l[t].coef;
+              const Term tm = a.terms[P.term0 + u];
+              Pl[tm.la * nl + tm.lb] -= y;
+              if (P.la != P.lb) Pl[tm.lb * nl + tm.la] -= y;
+            }
+          }
+        }
+        break;
+      }
       if (maxn < a.tau_R || maxn != maxn || sweep >= a.max_sweeps) {
         pmode = true;  // amplitudes final: energies and inner products at this T
         if (tid == 0)
@@ -591,6 +669,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         continue;
       }
       cur ^= 1;   // the stepped amplitudes become current
+      n2 = n1;
+      n1 = maxn;
       sweep++;
     }
     if (cur) {

@@ -156,3 +156,25 @@ def test_mixed_matches_fp64_large_rows():
     assert abs(gm["E"] - gd["E"]) <= MIXED_TOL * 1e-2, (gm["E"], gd["E"])
     assert np.max(np.abs(gm["Ecl"] - gd["Ecl"])) <= MIXED_TOL * 1e-2
     assert rel_err(gm["dC"], gd["dC"]) <= 1e-7
+
+
+@pytest.mark.parametrize("case", ["diagonal_F", "tiny_couplings"])
+def test_energy_pass_fallbacks(case):
+    """The solve takes the energy and dE/df products in the sweep it predicts to
+    be the last one, unless a target's coupling coefficients -f_ab span more than
+    2^10 (or one is zero); those clusters run the separate pass at the final
+    amplitudes.  Diagonal F_occ (canonical occupied orbitals) sends every cluster
+    there; off-diagonal f scaled by 1e-5 for LMO 0 sends only the clusters that
+    contain LMO 0."""
+    s = synth.make_system(8, 50, 40, (4, 9), seed=17, cut2=6.5, cut3=4.5)
+    F = s.F_occ.copy()
+    if case == "diagonal_F":
+        F = np.diag(np.diag(F))
+    else:
+        F[0, 1:] *= 1e-5
+        F[1:, 0] *= 1e-5
+    s.F_occ = F
+    say(f"case energy-pass fallback {case} nocc=8")
+    g = run_gpu(s)
+    ref = O.solve(s)
+    compare(s, g, ref)
