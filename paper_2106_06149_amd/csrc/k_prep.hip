@@ -51,15 +51,34 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return t;
 }
 
+// One rotation of a Jacobi step: (p, q) with p < q, cosine and sine; z = 1 when
+// a_pq is set to zero in this step (with or without a rotation).  32 bytes, read
+// with two 16-byte LDS loads.
+struct __attribute__((aligned(16))) Rot {
+  double c, s;
+  int p, q, z, pad;
+};
+
+// index of element (a, b) of a symmetric matrix of which only the upper triangle
+// is kept
+template <int LD>
+__device__ __forceinline__ int up(int a, int b) {
+  return a < b ? a * LD + b : b * LD + a;
+}
+
 // Cyclic Jacobi: A (n x n, stride LD) is diagonalised in place, V receives the
 // eigenvectors (columns).  Round-robin ordering: in step st the n/2 disjoint
 // pairs rotate simultaneously; A <- J^T A J is applied as independent 2x2 block
 // updates; a step is a rotation table, a barrier, the updates, a barrier.
+// A is read in full on entry; during the sweeps only its upper triangle is kept
+// (each 2x2 block is read and written once), so on return only the diagonal
+// (the eigenvalues) and the upper triangle are meaningful.  The step is bound by
+// LDS bandwidth: every thread reads the rotation table once per step (its V
+// entries share one rotation) and each block touches four elements.
 // Threshold rule: |a_pq| <= 1e-17 sqrt(|a_pp a_qq|) or <= 1e-18 ||A||_F is set
 // to zero without a rotation; the solve ends after a sweep with no rotation.
 template <int LD, int NT, int MAXB, int MAXV>
-__device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, int *pp, int *qq,
-                           int *zz, double *red, int *flag) {
+__device__ void jacobi_eig(double *A, double *V, int n, Rot *rt, double *red, int *flag) {
   const int tid = threadIdx.x;
   const int nE = n + (n & 1), h = nE / 2, m = nE - 1;
   for (int e = tid; e < n * n; e += NT) {
@@ -73,10 +92,9 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
   }
   const double absthr = 1e-18 * sqrt(block_sum<NT>(f2, red));
   if (n == 1) return;
-  // Each thread owns the same 2x2 blocks (I, J), I <= J < h, and the same V
-  // entries (i, k) in every step (only the pair tables change), so both sets
-  // are found once: block b = tid + NT u (row-major over the upper triangle),
-  // V entry e = tid + NT u = i h + k.
+  // Each thread owns the same 2x2 blocks (I, J), I <= J < h, in every step (only
+  // the rotation table changes): block b = tid + NT u, row-major over the upper
+  // triangle of the h x h block grid.
   const int nb = h * (h + 1) / 2;
   int bI[MAXB], bJ[MAXB];
 #pragma unroll
@@ -87,13 +105,11 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
     bI[u] = (b < nb) ? I : -1;
     bJ[u] = I + rem;
   }
-  int vI[MAXV], vK[MAXV];
-#pragma unroll
-  for (int u = 0; u < MAXV; u++) {
-    const int e = tid + NT * u;
-    vI[u] = (e < n * h) ? e / h : -1;
-    vK[u] = e - (e / h) * h;
-  }
+  // V entries: thread tid applies rotation k = tid mod h to rows r0 + R u,
+  // r0 = tid / h, R = NT / h (threads tid >= R h have none)
+  const int R = NT / h;
+  const int vk = (tid < R * h) ? tid % h : -1;
+  const int r0 = tid / h;
   for (int sweep = 0; sweep < 60; sweep++) {
     if (tid == 0) *flag = 0;
     __syncthreads();
@@ -101,74 +117,79 @@ __device__ void jacobi_eig(double *A, double *V, int n, double *cs, double *sn, 
       if (tid < h) {
         int a, b;
         if (tid == 0) { a = st; b = m; } else { a = st + tid; a -= (a >= m) ? m : 0; b = st - tid; b += (b < 0) ? m : 0; }
-        int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, s = 0.0;
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, sv = 0.0;
         int z = 0;
         if (q < n) {
-          double apq = A[p * LD + q];
+          const double apq = A[p * LD + q];
           if (apq != 0.0) {
-            double app = A[p * LD + p], aqq = A[q * LD + q];
+            const double app = A[p * LD + p], aqq = A[q * LD + q];
             z = 1;
             if (!(fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq)) || fabs(apq) <= absthr)) {
-              double theta = (aqq - app) / (2.0 * apq);
-              double at = fabs(theta), t;
+              const double theta = (aqq - app) / (2.0 * apq);
+              const double at = fabs(theta);
+              double t;
               if (at > 1e150) t = 0.5 / theta;
               else t = (theta >= 0.0 ? 1.0 : -1.0) / (at + sqrt(theta * theta + 1.0));
               c = 1.0 / sqrt(t * t + 1.0);
-              s = t * c;
+              sv = t * c;
               *flag = 1;
             }
           }
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s; zz[tid] = z;
+        Rot r;
+        r.c = c; r.s = sv; r.p = p; r.q = q; r.z = z; r.pad = 0;
+        rt[tid] = r;
       }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < MAXB; u++) {
         const int I = bI[u], J = bJ[u];
         if (I < 0) continue;
-        const double sI = sn[I], sJ = sn[J];
+        const Rot rI = rt[I];
         if (I == J) {
-          const int pI = pp[I], qI = qq[I];
-          if (qI < n && zz[I]) {
-            const double apq = A[pI * LD + qI];
-            if (sI != 0.0) {
-              const double tt = sI / cs[I];
-              A[pI * LD + pI] -= tt * apq;
-              A[qI * LD + qI] += tt * apq;
+          if (rI.q < n && rI.z) {
+            const double apq = A[rI.p * LD + rI.q];
+            if (rI.s != 0.0) {
+              const double tt = rI.s / rI.c;
+              A[rI.p * LD + rI.p] -= tt * apq;
+              A[rI.q * LD + rI.q] += tt * apq;
             }
-            A[pI * LD + qI] = 0.0;
-            A[qI * LD + pI] = 0.0;
+            A[rI.p * LD + rI.q] = 0.0;
           }
-        } else if (sI != 0.0 || sJ != 0.0) {
-          const int pI = pp[I], qI = qq[I], pJ = pp[J], qJ = qq[J];
-          const double cI = cs[I], cJ = cs[J];
-          const bool vqI = qI < n, vqJ = qJ < n;
-          const double b00 = A[pI * LD + pJ];
-          const double b01 = vqJ ? A[pI * LD + qJ] : 0.0;
-          const double b10 = vqI ? A[qI * LD + pJ] : 0.0;
-          const double b11 = (vqI && vqJ) ? A[qI * LD + qJ] : 0.0;
-          const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
-          const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
-          const double n00 = r00 * cJ - r01 * sJ, n01 = r00 * sJ + r01 * cJ;
-          const double n10 = r10 * cJ - r11 * sJ, n11 = r10 * sJ + r11 * cJ;
-          A[pI * LD + pJ] = n00; A[pJ * LD + pI] = n00;
-          if (vqJ) { A[pI * LD + qJ] = n01; A[qJ * LD + pI] = n01; }
-          if (vqI) { A[qI * LD + pJ] = n10; A[pJ * LD + qI] = n10; }
-          if (vqI && vqJ) { A[qI * LD + qJ] = n11; A[qJ * LD + qI] = n11; }
+        } else {
+          const Rot rJ = rt[J];
+          if (rI.s != 0.0 || rJ.s != 0.0) {
+            const int pI = rI.p, qI = rI.q, pJ = rJ.p, qJ = rJ.q;
+            const double cI = rI.c, sI = rI.s, cJ = rJ.c, sJ = rJ.s;
+            const bool vqI = qI < n, vqJ = qJ < n;
+            const int i00 = up<LD>(pI, pJ), i01 = up<LD>(pI, qJ), i10 = up<LD>(qI, pJ),
+                      i11 = up<LD>(qI, qJ);
+            const double b00 = A[i00];
+            const double b01 = vqJ ? A[i01] : 0.0;
+            const double b10 = vqI ? A[i10] : 0.0;
+            const double b11 = (vqI && vqJ) ? A[i11] : 0.0;
+            const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
+            const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
+            A[i00] = r00 * cJ - r01 * sJ;
+            if (vqJ) A[i01] = r00 * sJ + r01 * cJ;
+            if (vqI) A[i10] = r10 * cJ - r11 * sJ;
+            if (vqI && vqJ) A[i11] = r10 * sJ + r11 * cJ;
+          }
         }
       }
+      if (vk >= 0) {
+        const Rot r = rt[vk];
+        if (r.s != 0.0) {   // a rotation implies q < n
 #pragma unroll
-      for (int u = 0; u < MAXV; u++) {
-        const int i = vI[u], k = vK[u];
-        if (i < 0) continue;
-        const double s = sn[k];
-        if (s != 0.0) {
-          const int p = pp[k], q = qq[k];
-          const double c = cs[k];
-          const double vp = V[i * LD + p], vq = V[i * LD + q];
-          V[i * LD + p] = c * vp - s * vq;
-          V[i * LD + q] = s * vp + c * vq;
+          for (int u = 0; u < MAXV; u++) {
+            const int i = r0 + R * u;
+            if (i < n) {
+              const double vp = V[i * LD + r.p], vq = V[i * LD + r.q];
+              V[i * LD + r.p] = r.c * vp - r.s * vq;
+              V[i * LD + r.q] = r.s * vp + r.c * vq;
+            }
+          }
         }
       }
       __syncthreads();
@@ -193,11 +214,10 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
   constexpr int LD = NM + 1;
   constexpr int HM = NM / 2;
   constexpr int MAXB = (HM * (HM + 1) / 2 + NT - 1) / NT;
-  constexpr int MAXV = (NM * HM + NT - 1) / NT;
+  constexpr int MAXV = (NM + NT / HM - 1) / (NT / HM);   // V rows per thread
   __shared__ double L1[NM * LD];
   __shared__ double L2[NM * LD];
-  __shared__ double cs[HM], sn[HM];
-  __shared__ int pp[HM], qq[HM], zz[HM];
+  __shared__ Rot rt[HM];
   __shared__ double red[NT / 64];
   __shared__ int keep_idx[NM];
   __shared__ int s_dt, s_flag;
@@ -294,7 +314,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
         L1[i * LD + j] = comp_elem(S, ld, D, D, i, j, true);
       }
       __syncthreads();
-      jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, cs, sn, pp, qq, zz, red, &s_flag);
+      jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, rt, red, &s_flag);
       if (tid == 0) {
         int c = 0;
         double mn = 1e300;
@@ -336,7 +356,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       L1[i * LD + j] = 0.5 * (L2[i * LD + j] + L2[j * LD + i]);
     }
     __syncthreads();
-    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, cs, sn, pp, qq, zz, red, &s_flag);
+    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, rt, red, &s_flag);
     for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
     __syncthreads();
     // W = X V (n x dt) into L1, then to global
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
                               F[(long long)(D.offp + j) * ld + (D.offp + i)]);
     }
     __syncthreads();
-    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, cs, sn, pp, qq, zz, red, &s_flag);
+    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, rt, red, &s_flag);
     dt = n;
     if (tid == 0) minev[dom_id] = 1.0;
     for (int a = tid; a < np; a += NT) eg[a] = (a < n) ? L1[a * LD + a] : 0.0;
