@@ -362,15 +362,22 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       for (int c = tid; c < cl.ncp; c += SNT) tg_l[c] = Desc<DLDS>::make_target(a, cl, c);
       for (int t = tid; t < cl.term1 - cl.term0; t += SNT) tm_l[t] = a.tflat[cl.term0 + t];
     }
-    // both buffers start at zero: entries beyond the 16-rounded kept rank are
-    // never written by a sweep and stay zero in both
+    // Every sweep's epilogue writes the whole m x m corner (m = kept rank rounded
+    // up to 16) of the stepped slots, zeros included; the band of rows and columns
+    // m .. np-1 is never written by a sweep, so it is cleared here in both buffers.
+    // Sweep 0 takes the current amplitudes as zero without reading them.
     for (int c = 0; c < cl.ncp; c++) {
       const CPair P = a.cp[cl.cp0 + c];
-      const int np = a.dom[P.dom].np;
-      double *T = a.T + P.toff, *T2 = a.T2 + P.toff;
-      for (int e = tid; e < 2 * np * np; e += SNT) {
-        T[e] = 0.0;
-        T2[e] = 0.0;
+      const int np = a.dom[P.dom].np, m = ((a.dom_rank[P.dom] + 15) >> 4) * 16;
+      if (m < np) {
+        double *T = a.T + P.toff, *T2 = a.T2 + P.toff;
+        for (int e = tid; e < 2 * np * np; e += SNT) {
+          const int r = (e / np) % np, col = e % np;
+          if (r >= m || col >= m) {
+            T[e] = 0.0;
+            T2[e] = 0.0;
+          }
+        }
       }
     }
     int sweep = 0, cur = 0;   // cur: the buffer holding the current amplitudes
@@ -544,7 +551,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
                   for (int v = 0; v < 4; v++) {
                     const int jl = lhi + 4 * v, j = jb * 16 + jl;
                     const double delta = ei + ev[j];
-                    const double tij = st[(16 + jl) * RS + i];   // T~(i, j) from the T~^T row j
+                    // T~(i, j) from the T~^T row j (zero in sweep 0)
+                    const double tij = sweep > 0 ? st[(16 + jl) * RS + i] : 0.0;
                     const double r = Racc[s][jb][v] + st[jl * RS + i] + delta * tij;
                     const bool in = (i < nt) && (j < nt);
                     const double tn = in ? tij - r / delta : 0.0;
@@ -662,6 +670,15 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         break;
       }
       if (maxn < a.tau_R || maxn != maxn || sweep >= a.max_sweeps) {
+        if (sweep == 0) {
+          // stopped before any step: the final amplitudes are zero
+          for (int c = 0; c < cl.ncp; c++) {
+            const TgtDesc P = ds.target(c);
+            double *T = a.T + P.toff;
+            for (int e = tid; e < 2 * P.np * P.np; e += SNT) T[e] = 0.0;
+          }
+          __syncthreads();
+        }
         pmode = true;  // amplitudes final: energies and inner products at this T
         if (tid == 0)
           for (int e = 0; e < nl * nl; e++) Pl[e] = 0.0;
