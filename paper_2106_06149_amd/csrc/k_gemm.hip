@@ -114,11 +114,186 @@ __global__ __launch_bounds__(256) void k_tile_f64(const TA *__restrict__ A, long
       }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 128x128-tile kernel fed by direct global-to-LDS loads.
+//   A(i,k) = A[i*lda + k] (rows i, k contiguous)
+//   BK == 0: B(k,j) = B[j*ldb + k] (rows j, k contiguous)   -- C = A B^T (SYRK form)
+//   BK == 1: B(k,j) = B[k*ldb + j] (rows k, j contiguous)   -- C = A B
+//   C[i][j] = alpha sum_k A(i,k) B(k,j), or with WGT alpha sum_k A(i,k) w[k] B(k,j)
+// Eight waves (two per SIMD: one wave alone cannot keep the FP64 MFMA pipe busy),
+// each a 32x64 part of the tile as 2x4 MFMA 16x16x4 accumulators.
+// k advances in stages of 16 through a ring of three LDS buffers: the loads of
+// stage s+2 (global_load_lds_dwordx4, 16 bytes per lane, no registers) are
+// issued before the MFMAs of stage s.  A [row][k] stage keeps a row's 16 doubles as eight
+// 16-byte slots, slot index XOR (row mod 8), so that the 16 rows of an operand
+// fragment spread over the LDS banks; a [k][j] stage pads its rows to 130 doubles.
+// Rows and columns past M, N are clamped to the last valid one (they only feed
+// outputs that are not stored); k past K is clamped on load and zeroed in LDS.
+// Requirements (checked by the launchers): lda, ldb, K even, 16-byte aligned
+// A and B, and for BK == 1 also N even.
+// ---------------------------------------------------------------------------
+constexpr int G = 128;             // output tile edge
+constexpr int GKS = 16;            // k per stage (doubles)
+constexpr int GRS = 130;           // LDS row stride of a [k][j] stage (doubles)
+constexpr int GA = G * GKS;        // doubles of a [row][k] stage
+constexpr int GB1 = GKS * GRS;     // doubles of a [k][j] stage
+constexpr int GNS = 3;             // ring stages
+constexpr int GNT = 512;           // threads (8 waves)
+
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
+// issue the loads of stage k0 into buffer (As_b, Bs_b): 16 blocks of 1 KB per
+// operand, two per wave
+template <int BK>
+__device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long long lda,
+                                           const double *__restrict__ B, long long ldb, int i0,
+                                           int j0, int k0, int M, int N, int K, double *As_b,
+                                           double *Bs_b) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < 2; v++) {
+    const int u = wave + 8 * v;                 // 1 KB block of the stage
+    const int p = u * 64 + lane;                // 16-byte slot in the stage
+    const int row = p >> 3, kp = (p & 7) ^ (row & 7);
+    const int gk = min(k0 + 2 * kp, K - 2);
+    const int gi = min(i0 + row, M - 1);
+    __builtin_amdgcn_global_load_lds((const void *)(A + (long long)gi * lda + gk),
+                                     (lds_ptr)(As_b + u * 128), 16, 0, 0);
+    if (BK == 0) {
+      const int gj = min(j0 + row, N - 1);
+      __builtin_amdgcn_global_load_lds((const void *)(B + (long long)gj * ldb + gk),
+                                       (lds_ptr)(Bs_b + u * 128), 16, 0, 0);
+    } else {
+      const int kr = u;                          // k-row of the stage
+      const int gkr = min(k0 + kr, K - 1);
+      const int gj = min(j0 + 2 * lane, N - 2);
+      __builtin_amdgcn_global_load_lds((const void *)(B + (long long)gkr * ldb + gj),
+                                       (lds_ptr)(Bs_b + kr * GRS), 16, 0, 0);
+    }
+  }
+}
+
+template <int BK, bool WGT>
+__global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, long long lda,
+                                                  const double *__restrict__ B, long long ldb,
+                                                  const double *__restrict__ w, double *C,
+                                                  long long ldc, int M, int N, int K,
+                                                  double alpha, const int2 *__restrict__ tiles,
+                                                  int mirror) {
+  constexpr int GBS = BK == 0 ? GA : GB1;
+  __shared__ __attribute__((aligned(16))) double As[GNS * GA];
+  __shared__ __attribute__((aligned(16))) double Bs[GNS * GBS];
+  int ti, tj;
+  if (tiles) {
+    const int2 t = tiles[blockIdx.x];
+    ti = t.x;
+    tj = t.y;
+  } else {
+    ti = blockIdx.y;
+    tj = blockIdx.x;
+  }
+  const int i0 = ti * G, j0 = tj * G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l15 = lane & 15, lhi = lane >> 4;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
+  d4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = (d4){0, 0, 0, 0};
+  const int nst = (K + GKS - 1) / GKS;
+  gemm_issue<BK>(A, lda, B, ldb, i0, j0, 0, M, N, K, As, Bs);
+  if (nst > 1) gemm_issue<BK>(A, lda, B, ldb, i0, j0, GKS, M, N, K, As + GA, Bs + GBS);
+  for (int st = 0; st < nst; st++) {
+    const int k0 = st * GKS, sb = st % GNS;
+    double *Ab = As + sb * GA, *Bb = Bs + sb * GBS;
+    // this stage's loads have landed (the 4 load instructions of the next stage,
+    // if issued, may still be in flight; loads complete in order) and every wave
+    // is done with the stage that the loads issued next will overwrite
+    if (st + 1 < nst) asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (st + 2 < nst) {
+      const int nb = (st + 2) % GNS;
+      gemm_issue<BK>(A, lda, B, ldb, i0, j0, k0 + 2 * GKS, M, N, K, As + nb * GA, Bs + nb * GBS);
+    }
+    if (k0 + GKS > K) {
+      // last, partial stage: zero k >= K
+      const int kv = K - k0;
+      for (int e = tid; e < G * GKS; e += GNT) {
+        const int row = e >> 4, k = e & 15;
+        if (k >= kv) {
+          const int idx = row * GKS + ((((k >> 1) ^ (row & 7))) << 1) + (k & 1);
+          Ab[idx] = 0.0;
+          if (BK == 0) Bb[idx] = 0.0;
+          else Bb[k * GRS + row] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int ks = 0; ks < GKS; ks += 4) {
+      const int kk = ks + lhi;
+      double af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; a++) {
+        const int row = wr + a * 16 + l15;
+        af[a] = Ab[row * GKS + ((((kk >> 1) ^ (row & 7))) << 1) + (kk & 1)];
+      }
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int col = wc + b * 16 + l15;
+        bf[b] = BK == 0 ? Bb[col * GKS + ((((kk >> 1) ^ (col & 7))) << 1) + (kk & 1)]
+                        : Bb[kk * GRS + col];
+      }
+      if (WGT) {
+        const double wk = (k0 + kk < K) ? w[k0 + kk] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 2; a++) af[a] *= wk;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  }
+  // accumulator layout: lane l, register v -> row 4v + (l >> 4), column l & 15
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = i0 + wr + a * 16 + lhi + 4 * v;
+        const int j = j0 + wc + b * 16 + l15;
+        if (i < M && j < N) {
+          C[(long long)i * ldc + j] = alpha * acc[a][b][v];
+          if (mirror && ti != tj) C[(long long)j * ldc + i] = alpha * acc[a][b][v];
+        }
+      }
+}
+
+static bool dma_ok(const void *p, long long ld) {
+  return ((size_t)p & 15) == 0 && (ld & 1) == 0;
+}
+
 hipError_t launch_syrk_f64(const void *A, int a_is_f32, long long lda, int M, int K,
                            const double *w, double *C, double *C2, long long ldc,
-                           const int2 *tiles, int ntiles, hipStream_t s) {
+                           const int2 *tiles, int ntiles, const int2 *tiles128, int ntiles128,
+                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  dim3 grid(ntiles), block(256);
+  dim3 block(256);
+  if (!a_is_f32 && tiles128 && ntiles128 > 0 && dma_ok(A, lda) && (K & 1) == 0 && K >= 2) {
+    // with a weight: C = A A^T and C2 = A diag(w) A^T as two passes over A
+    dim3 grid(ntiles128), blk(GNT);
+    hipLaunchKernelGGL((k_gemm_dma<0, false>), grid, blk, 0, s, (const double *)A, lda,
+                       (const double *)A, lda, nullptr, C, ldc, M, M, K, 1.0, tiles128, 1);
+    if (w)
+      hipLaunchKernelGGL((k_gemm_dma<0, true>), grid, blk, 0, s, (const double *)A, lda,
+                         (const double *)A, lda, w, C2, ldc, M, M, K, 1.0, tiles128, 1);
+    return hipGetLastError();
+  }
+  dim3 grid(ntiles);
   if (w) {
     if (a_is_f32) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tile_f64<0, 0, double, double, true>), grid, block, 0, s,
@@ -140,6 +315,12 @@ hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, i
                               long long ldb, double *C, long long ldc, int M, int N, int K,
                               double alpha, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (!b_is_f32 && dma_ok(A, lda) && dma_ok(B, ldb) && (K & 1) == 0 && K >= 2 && (N & 1) == 0) {
+    dim3 grid((N + G - 1) / G, (M + G - 1) / G), block(GNT);
+    hipLaunchKernelGGL((k_gemm_dma<1, false>), grid, block, 0, s, A, lda, B, ldb, nullptr, C,
+                       ldc, M, N, K, alpha, nullptr, 0);
+    return hipGetLastError();
+  }
   dim3 grid((N + TB - 1) / TB, (M + TB - 1) / TB), block(256);
   if (b_is_f32)
     hipLaunchKernelGGL((k_tile_f64<0, 1, double, float, false>), grid, block, 0, s, A, lda,
@@ -342,6 +523,19 @@ hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, do
 // ---------------------------------------------------------------------------
 // small utility kernels
 // ---------------------------------------------------------------------------
+__global__ void k_f32_to_f64(const float *__restrict__ x, double *__restrict__ y, long long n) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x)
+    y[t] = (double)x[t];
+}
+
+hipError_t launch_f32_to_f64(const float *x, double *y, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)nb), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
 __global__ void k_fill_i32(int *p, int v, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;

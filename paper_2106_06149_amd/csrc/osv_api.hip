@@ -363,6 +363,9 @@ struct osv_ctx {
   double *dS = nullptr, *dF = nullptr, *dK = nullptr, *dW = nullptr, *dY = nullptr, *dKt = nullptr;
   double *dEpst = nullptr, *dMinev = nullptr, *dM = nullptr, *dT = nullptr, *dRs = nullptr;
   double *dT2 = nullptr;  // second amplitude buffer of the solve (Jacobi ping-pong)
+  double *dC64 = nullptr; // FP64 copy of an FP32 C (made when an FP64 product needs it)
+  std::vector<int2> tiles128;
+  int2 *dTiles128 = nullptr;
   double *dEcl = nullptr, *dPl = nullptr, *dMaxres = nullptr, *dWts = nullptr, *dEout = nullptr;
   int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
   int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr;
@@ -436,6 +439,16 @@ int upload(osv_ctx *ctx, T **p, const std::vector<T> &v, hipStream_t s) {
   return OSV_OK;
 }
 
+// the FP64 copy of an FP32 C, made once per context
+int c64(osv_ctx *ctx, hipStream_t s) {
+  if (ctx->dC64) return OSV_OK;
+  const long long n = (long long)ctx->nosv * ctx->naux;
+  int rc = dalloc(ctx, &ctx->dC64, (size_t)n);
+  if (rc) return rc;
+  HIPCHK(ctx, launch_f32_to_f64((const float *)ctx->C, ctx->dC64, n, s));
+  return OSV_OK;
+}
+
 struct StageTimer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s;
@@ -457,15 +470,15 @@ struct StageTimer {
   }
 };
 
-// tiles (ti <= tj, 64x64) of the sum(r) x sum(r) index space that hold a domain block
-std::vector<int2> make_tiles(const Plan &P, int nosv, bool all) {
-  const int nt = (nosv + 63) / 64;
+// tiles (ti <= tj, tsz x tsz) of the sum(r) x sum(r) index space that hold a domain block
+std::vector<int2> make_tiles(const Plan &P, int nosv, bool all, int tsz) {
+  const int nt = (nosv + tsz - 1) / tsz;
   std::vector<char> mark((size_t)nt * nt, all ? 1 : 0);
   if (!all)
     for (const Domain &D : P.doms) {
-      int a0 = D.offp / 64, a1 = (D.offp + D.rp - 1) / 64;
+      int a0 = D.offp / tsz, a1 = (D.offp + D.rp - 1) / tsz;
       int qo = (D.p == D.q) ? D.offp : D.offq, qr = (D.p == D.q) ? D.rp : D.rq;
-      int b0 = qo / 64, b1 = (qo + qr - 1) / 64;
+      int b0 = qo / tsz, b1 = (qo + qr - 1) / tsz;
       for (int a = a0; a <= a1; a++)
         for (int b = b0; b <= b1; b++) mark[(size_t)std::min(a, b) * nt + std::max(a, b)] = 1;
     }
@@ -533,11 +546,12 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     select_full(nocc, ctx->sel);
   } else {
     // overlap metric eq:2bscreen needs every S block: full S first
-    std::vector<int2> all = make_tiles(ctx->plan, N, true);
-    int2 *dAll = nullptr;
+    std::vector<int2> all = make_tiles(ctx->plan, N, true, 64), all128 = make_tiles(ctx->plan, N, true, 128);
+    int2 *dAll = nullptr, *dAll128 = nullptr;
     if ((rc = upload(ctx, &dAll, all, s))) return rc;
+    if ((rc = upload(ctx, &dAll128, all128, s))) return rc;
     HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, nullptr, ctx->dS, nullptr, ld, dAll,
-                                (int)all.size(), s));
+                                (int)all.size(), dAll128, (int)all128.size(), s));
     double *dSq = nullptr;
     if ((rc = dalloc(ctx, &dSq, (size_t)nocc * nocc))) return rc;
     HIPCHK(ctx, launch_block_sumsq(ctx->dS, ld, ctx->dOff, ctx->dR, nocc, dSq, s));
@@ -557,11 +571,13 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   }
   Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
-  ctx->tiles = make_tiles(P, N, false);
+  ctx->tiles = make_tiles(P, N, false, 64);
+  ctx->tiles128 = make_tiles(P, N, false, 128);
   const int ndom = (int)P.doms.size();
   // everything the device stages before the couplings need is allocated and
   // uploaded first: uploads from pageable host memory wait for the stream
   if ((rc = upload(ctx, &ctx->dTiles, ctx->tiles, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dTiles128, ctx->tiles128, s))) return rc;
   if ((rc = upload(ctx, &ctx->dDom, P.doms, s))) return rc;
   if ((rc = dalloc(ctx, &ctx->dW, P.n_slot))) return rc;
   if ((rc = dalloc(ctx, &ctx->dY, P.n_slot))) return rc;
@@ -592,7 +608,8 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   // S and F blocks: one pass over Q^T (rows = OSVs, k = virtuals)
   StageTimer t_sf(s);
   HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, ctx->eps, ctx->dS, ctx->dF, ld,
-                              ctx->dTiles, (int)ctx->tiles.size(), s));
+                              ctx->dTiles, (int)ctx->tiles.size(), ctx->dTiles128,
+                              (int)ctx->tiles128.size(), s));
   t_sf.stop();
   StageTimer t_k(s);
   if (precision == OSV_MIXED) {
@@ -600,8 +617,15 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     HIPCHK(ctx, launch_syrk_digits(ctx->dDig, N, ctx->naux, ctx->dExps, ctx->dK, ld, ctx->dTiles,
                                    (int)ctx->tiles.size(), s));
   } else {
-    HIPCHK(ctx, launch_syrk_f64(ctx->C, ctx->c_dtype == OSV_DT_F32, ctx->naux, N, ctx->naux, nullptr, ctx->dK,
-                                nullptr, ld, ctx->dTiles, (int)ctx->tiles.size(), s));
+    const void *Cd = ctx->C;
+    if (ctx->c_dtype == OSV_DT_F32) {
+      // FP64 copy of the FP32 input for the FP64 tile kernel (also used by dE/dC)
+      if ((rc = c64(ctx, s))) return rc;
+      Cd = ctx->dC64;
+    }
+    HIPCHK(ctx, launch_syrk_f64(Cd, 0, ctx->naux, N, ctx->naux, nullptr, ctx->dK, nullptr, ld,
+                                ctx->dTiles, (int)ctx->tiles.size(), ctx->dTiles128,
+                                (int)ctx->tiles128.size(), s));
   }
   t_k.stop();
   // pair-domain preparation
@@ -1017,9 +1041,14 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
                                  ctx->dOff, ctx->dR, ctx->dGd, ctx->dGF, ld, s));
   t_adj.stop();
   StageTimer t_bt(s);
-  if (dE_dC)
-    HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGK, ld, (const double *)ctx->C, ctx->c_dtype == OSV_DT_F32, ctx->naux,
-                                   dE_dC, ctx->naux, N, ctx->naux, N, 2.0, s));
+  if (dE_dC) {
+    const double *Cd = (const double *)ctx->C;
+    if (ctx->c_dtype == OSV_DT_F32) {
+      if ((rc = c64(ctx, s))) return rc;
+      Cd = ctx->dC64;
+    }
+    HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGK, ld, Cd, 0, ctx->naux, dE_dC, ctx->naux, N, ctx->naux, N, 2.0, s));
+  }
   if (dE_deps || Dvir_full) {
     // Z^T = G^F Q^T  (Q^T is row-major sum(r) x nvir)
     HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGF, ld, ctx->Q, 0, ctx->nvir, ctx->dZt, ctx->nvir, N, ctx->nvir, N,

@@ -107,11 +107,15 @@ struct SolveArgs {
 
 // ---- launch wrappers (defined next to their kernels) -----------------------
 namespace osv {
-// C[i][j] = sum_k A[i][k] B[j][k] (and C2 with weight w[k]) on the listed 64x64
-// output tiles; A, B row-major.  mirror: also write the transposed tile.
+// C[i][j] = sum_k A[i][k] A[j][k] (and C2 with weight w[k]) on the listed output
+// tiles (ti <= tj; the transposed tile is written too); A row-major.  FP64 A with
+// even lda and K runs on the 128x128 tiles of tiles128, anything else on the
+// 64x64 tiles of tiles.
 hipError_t launch_syrk_f64(const void *A, int a_is_f32, long long lda, int M, int K,
                            const double *w, double *C, double *C2, long long ldc,
-                           const int2 *tiles, int ntiles, hipStream_t s);
+                           const int2 *tiles, int ntiles, const int2 *tiles128, int ntiles128,
+                           hipStream_t s);
+hipError_t launch_f32_to_f64(const float *x, double *y, long long n, hipStream_t s);
 // mixed-precision K: exact bf16 digit planes of the FP32 rows (ND = 5 planes,
 // nrow x ncol each) with per-row power-of-two exponents, then the digit SYRK
 hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
