@@ -181,7 +181,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+bf16-split-K" if main_prec == 1 else "f64",
+        "dtype": "f64+int8-digit-K" if main_prec == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": spec["name"], "nocc": s.nocc, "nvir": s.nvir, "naux": s.naux,
                    "r_range": list(spec["r"]) if isinstance(spec["r"], tuple) else spec["r"],

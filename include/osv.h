@@ -50,8 +50,10 @@ enum {
 /* arithmetic of the fitted-integral contraction K_ij = C_i C_j^T */
 enum {
   OSV_FP64 = 0,   /* every step in FP64 (FP64 MFMA)                                      */
-  OSV_MIXED = 1   /* K_ij from C split into bfloat16 terms on bf16 MFMA with FP32        */
-                  /* accumulation of short k-chunks summed in FP64; FP64 elsewhere       */
+  OSV_MIXED = 1   /* K_ij from FP32 C split into exact int8 digits (per-row power-of-two */
+                  /* scale) on int8 MFMA with exact int32 accumulation, combined in      */
+                  /* FP64; FP64 elsewhere.  Needs C_dtype = FP32; above naux = 87000   */
+                  /* (int32 range) K is computed in FP64.                                */
 };
 
 /* cluster selection */

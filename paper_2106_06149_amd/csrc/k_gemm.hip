@@ -7,15 +7,14 @@
 // All of them are written as one 64x64-tile MFMA kernel over the full
 // sum(r) x sum(r) (or sum(r) x n) index space; a tile list skips tiles that
 // hold no needed orbital-pair block.  FP64 tiles use v_mfma_f64_16x16x4f64,
-// the mixed-precision K uses v_mfma_f32_16x16x32_bf16 on exact bfloat16 digit
-// splits of the FP32 input with exact FP32 accumulation flushed into FP64.
+// the mixed-precision K uses v_mfma_i32_16x16x64_i8 on exact int8 digit splits of
+// the FP32 input with exact int32 accumulation, combined in FP64 at the end.
 #include "osv_internal.h"
 
 namespace osv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int TB = 64;      // output tile edge
 constexpr int KC = 16;      // k-chunk staged in LDS (FP64 kernel)
@@ -343,24 +342,27 @@ hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, l
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision K = C C^T from exact bfloat16 digits.
+// Mixed precision K = C C^T from exact int8 digits.
 //
 // Each row i of the FP32 input C is scaled by a power of two s_i so that
 // |x| = |C[i][P]| / s_i < 1/2, and x is split into ND signed integer digits
-//   x = sum_k d_k 2^(-8(k+1)) + r,   |d_k| <= 128,   |r| <= 2^(-8 ND - 1)
-// (round to nearest at each level; every step is exact in FP32).  Integers of
-// magnitude <= 128 are exact in bfloat16, products of two digits are integers
-// <= 2^14, and the bf16 MFMA accumulates them in FP32 exactly as long as a
-// partial sum stays below 2^24: one FP32 accumulator per level l = a + b holds
-// at most (l + 1) * 128 products per flush (128 k), i.e. < 2^24.  Levels
-// l <= ND - 1 are kept; each flushed level sum is added into FP64 with weight
-// 2^(-8 l).  K_ij = s_i s_j 2^-16 sum_l 2^(-8l) S_l.  The only error is the
-// truncation r of C (and the dropped levels l >= ND), both below
-// 2^(-8 ND) s_i per element: the method of error-free splitting of a product
-// into exact low-precision products (Ozaki, Ogita, Oishi and Rump, Numer.
-// Algorithms 59 (2012) 95-118), here with per-row power-of-two scaling.
+//   x = sum_k d_k 2^(-7(k+1)) + r,   |d_k| <= 64,   |r| <= 2^(-7 ND - 1)
+// (round to nearest at each level; every step is exact in FP32).  The digits are
+// int8, the int8 MFMA multiplies digit planes and accumulates in int32, exactly:
+// one accumulator per level l = a + b <= NL - 1 = ND holds at most ND products of
+// at most 2^12 per k, below 2^31 for up to 87,000 k (the launcher refuses more).
+// At the end K_ij = s_i s_j 2^-14 sum_l 2^(-7 l) S_l in FP64.  Level ND is kept
+// because an FP32 element at the top of its row fills four 7-bit digits and the
+// square of its last digit lands there (dropping it biases K_ii by ~1e-11); the
+// errors left are the truncation r of C and the levels l > ND, below 2^(-49) of
+// the row scales: error-free splitting of a product into exact low-precision products
+// (Ozaki, Ogita, Oishi and Rump, Numer. Algorithms 59 (2012) 95-118), here with
+// per-row power-of-two scaling and integer arithmetic.
 // ---------------------------------------------------------------------------
-constexpr int ND = 5;  // bf16 digits per element
+constexpr int ND = 6;       // int8 digits per element
+constexpr int NL = ND + 1;  // levels a + b kept
+constexpr int DKS = 64;     // k per stage (bytes of a digit row)
+constexpr int DMAXK = 87000;
 
 // per-row exponent: s_i = 2^e_i with max_P |C[i][P]| < 2^(e_i - 1)
 __global__ __launch_bounds__(256) void k_row_scale(const float *__restrict__ C, long long ld,
@@ -384,130 +386,140 @@ __global__ __launch_bounds__(256) void k_row_scale(const float *__restrict__ C, 
   }
 }
 
-__global__ void k_split_digits(const float *__restrict__ C, long long ld, int nrow, int ncol,
-                               const int *__restrict__ exps, __bf16 *dig) {
-  const long long n = (long long)nrow * ncol;
+// digit planes [ND][nrow][kp] (kp = ncol rounded up to DKS, zero beyond ncol);
+// one thread per 4 consecutive elements of a row, stored as one 4-byte word per plane
+__global__ void k_split_i8(const float *__restrict__ C, long long ld, int nrow, int ncol, int kp,
+                           const int *__restrict__ exps, signed char *dig) {
+  const long long plane = (long long)nrow * kp;
+  const int q = kp / 4;
+  const long long n = (long long)nrow * q;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t / ncol), c = (int)(t - (long long)i * ncol);
-    float x = ldexpf(C[(long long)i * ld + c], -exps[i]);
+    const int i = (int)(t / q), c0 = (int)(t - (long long)i * q) * 4;
+    float x[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+      x[e] = (c0 + e < ncol) ? ldexpf(C[(long long)i * ld + c0 + e], -exps[i]) : 0.0f;
 #pragma unroll
     for (int k = 0; k < ND; k++) {
-      const float y = ldexpf(x, 8 * (k + 1));
-      const float d = rintf(y);
-      x -= ldexpf(d, -8 * (k + 1));
-      dig[(long long)k * n + t] = (__bf16)d;
+      unsigned w = 0;
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const float d = rintf(ldexpf(x[e], 7 * (k + 1)));
+        x[e] -= ldexpf(d, -7 * (k + 1));
+        w |= ((unsigned)(int)d & 0xffu) << (8 * e);
+      }
+      *(unsigned *)(dig + k * plane + (long long)i * kp + c0) = w;
     }
   }
 }
+
+int digit_kp(int ncol) { return (ncol + DKS - 1) / DKS * DKS; }
+size_t digit_bytes(int nrow, int ncol) { return (size_t)ND * nrow * digit_kp(ncol); }
+int digit_max_k() { return DMAXK; }
 
 hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
                                hipStream_t s) {
   if (nrow <= 0 || ncol <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_scale, dim3(nrow), dim3(256), 0, s, C, (long long)ncol, ncol, exps);
-  const long long n = (long long)nrow * ncol;
+  const int kp = digit_kp(ncol);
+  const long long n = (long long)nrow * (kp / 4);
   long long nb = (n + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_split_digits, dim3((unsigned)nb), dim3(256), 0, s, C, (long long)ncol, nrow,
-                     ncol, (const int *)exps, (__bf16 *)dig);
+  hipLaunchKernelGGL(k_split_i8, dim3((unsigned)nb), dim3(256), 0, s, C, (long long)ncol, nrow,
+                     ncol, kp, (const int *)exps, (signed char *)dig);
   return hipGetLastError();
 }
 
-constexpr int KB = 32;        // k per bf16 MFMA step
-constexpr int LDB16 = KB + 8; // LDS row stride (bf16 elements): 80 bytes
-constexpr int FLUSH = 4;      // k-steps (of 32) between FP32 -> FP64 flushes
+// SYRK of the digit planes on 128 x 64 output tiles (rows 128 ti.., columns 64 tj..)
+// with eight waves of 32 x 32 (2 x 2 MFMA 16x16x64 tiles, NL level accumulators
+// each).  Stages of 64 k move all planes of the tile's 192 rows (72 KB) into LDS
+// by direct global-to-LDS loads, double-buffered: the next stage is in flight
+// while the current one is multiplied.  A stage is [plane][12 blocks][16 rows][64 B];
+// blocks 0-7 hold the 128 A rows, 8-11 the 64 B rows.  Every element is written
+// at (i, j) and at (j, i): K is symmetric, so tiles that cross the diagonal or
+// repeat a block only store the same values again.
+constexpr int DNT = 512;
+constexpr int DSTG = ND * 12 * 1024;   // bytes per stage
+typedef int i4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_syrk_digits(const __bf16 *__restrict__ dig, int M,
-                                                     int K, const int *__restrict__ exps,
-                                                     double *C, long long ldc,
-                                                     const int2 *__restrict__ tiles) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[ND][TB * LDB16];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[ND][TB * LDB16];
-  const long long plane = (long long)M * K;
-  int2 t = tiles[blockIdx.x];
-  const int ti = t.x, tj = t.y;
-  const int i0 = ti * TB, j0 = tj * TB;
+__device__ __forceinline__ void dig_issue(const signed char *__restrict__ dig, long long plane,
+                                          int kp, int M, int i0, int j0, int k0,
+                                          signed char *stage) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < 9; v++) {
+    const int u = wave + 8 * v;            // 1 KB block: plane u / 12, block u % 12
+    const int d = u / 12, rb = u - d * 12;
+    const int r = (rb < 8 ? i0 + 16 * rb : j0 + 16 * (rb - 8)) + (lane >> 2);
+    const signed char *src = dig + d * plane + (long long)min(r, M - 1) * kp + k0 + 16 * (lane & 3);
+    __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr)(stage + u * 1024), 16, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(DNT) void k_syrk_i8(const signed char *__restrict__ dig, int M,
+                                                 int kp, const int *__restrict__ exps,
+                                                 double *C, long long ldc,
+                                                 const int2 *__restrict__ tiles) {
+  __shared__ __attribute__((aligned(16))) signed char st_l[2 * DSTG];
+  const long long plane = (long long)M * kp;
+  const int2 t = tiles[blockIdx.x];
+  const int i0 = t.x * 128, j0 = t.y * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l15 = lane & 15, lhi = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  d4 acc[2][2];
-  f4 lev[ND][2][2];
-  for (int a = 0; a < 2; a++)
-    for (int b = 0; b < 2; b++) {
-      acc[a][b] = (d4){0, 0, 0, 0};
-      for (int l = 0; l < ND; l++) lev[l][a][b] = (f4){0, 0, 0, 0};
-    }
-  int step = 0;
-  for (int k0 = 0; k0 < K; k0 += KB) {
-    // stage 64 rows x 32 k of every digit plane, row tile and column tile
-    {
-      const int r = tid >> 2, kq = (tid & 3) * 8;
-      const int gi = i0 + r, gj = j0 + r;
-      for (int lv = 0; lv < ND; lv++) {
-        bf8 va, vb;
-        const __bf16 *src = dig + (long long)lv * plane;
-        if (gi < M && k0 + kq + 8 <= K) {
-          va = *(const bf8 *)&src[(long long)gi * K + k0 + kq];
-        } else {
-          for (int e = 0; e < 8; e++)
-            va[e] = (gi < M && k0 + kq + e < K) ? src[(long long)gi * K + k0 + kq + e] : (__bf16)0.0f;
-        }
-        if (gj < M && k0 + kq + 8 <= K) {
-          vb = *(const bf8 *)&src[(long long)gj * K + k0 + kq];
-        } else {
-          for (int e = 0; e < 8; e++)
-            vb[e] = (gj < M && k0 + kq + e < K) ? src[(long long)gj * K + k0 + kq + e] : (__bf16)0.0f;
-        }
-        *(bf8 *)&As[lv][r * LDB16 + kq] = va;
-        *(bf8 *)&Bs[lv][r * LDB16 + kq] = vb;
-      }
-    }
-    __syncthreads();
-    const int kq = (lane >> 4) * 8;
-    bf8 af[ND][2], bfv[ND][2];
+  i4 lev[NL][2][2];
 #pragma unroll
-    for (int lv = 0; lv < ND; lv++) {
+  for (int l = 0; l < NL; l++)
 #pragma unroll
-      for (int a = 0; a < 2; a++) af[lv][a] = *(const bf8 *)&As[lv][(wr + a * 16 + (lane & 15)) * LDB16 + kq];
+    for (int a = 0; a < 2; a++)
 #pragma unroll
-      for (int b = 0; b < 2; b++) bfv[lv][b] = *(const bf8 *)&Bs[lv][(wc + b * 16 + (lane & 15)) * LDB16 + kq];
+      for (int b = 0; b < 2; b++) lev[l][a][b] = (i4){0, 0, 0, 0};
+  const int nst = kp / DKS;
+  dig_issue(dig, plane, kp, M, i0, j0, 0, st_l);
+  for (int st = 0; st < nst; st++) {
+    const signed char *S = st_l + (st & 1) * DSTG;
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (st + 1 < nst) dig_issue(dig, plane, kp, M, i0, j0, (st + 1) * DKS, st_l + ((st + 1) & 1) * DSTG);
+    // fragment of 16 rows x 64 k: lane l reads row l & 15, bytes 16 (l >> 4) ..
+    i4 af[ND][2], bf[ND][2];
+#pragma unroll
+    for (int d = 0; d < ND; d++) {
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+        af[d][a] = *(const i4 *)(S + (d * 12 + (wr >> 4) + a) * 1024 + l15 * 64 + lhi * 16);
+#pragma unroll
+      for (int b = 0; b < 2; b++)
+        bf[d][b] = *(const i4 *)(S + (d * 12 + 8 + (wc >> 4) + b) * 1024 + l15 * 64 + lhi * 16);
     }
 #pragma unroll
     for (int la = 0; la < ND; la++)
 #pragma unroll
-      for (int lb = 0; lb < ND - la; lb++)
+      for (int lb = 0; lb < ND; lb++)
+        if (la + lb < NL)
 #pragma unroll
-        for (int a = 0; a < 2; a++)
+          for (int a = 0; a < 2; a++)
 #pragma unroll
-          for (int b = 0; b < 2; b++)
-            lev[la + lb][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[la][a], bfv[lb][b], lev[la + lb][a][b], 0, 0, 0);
-    __syncthreads();
-    if (++step == FLUSH || k0 + KB >= K) {
-      step = 0;
-#pragma unroll
-      for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int b = 0; b < 2; b++)
-#pragma unroll
-          for (int v = 0; v < 4; v++) {
-            double s = 0.0;
-#pragma unroll
-            for (int l = ND - 1; l >= 0; l--) s += ldexp((double)lev[l][a][b][v], -8 * l);
-            acc[a][b][v] += s;
-#pragma unroll
-            for (int l = 0; l < ND; l++) lev[l][a][b][v] = 0.0f;
-          }
-    }
+            for (int b = 0; b < 2; b++)
+              lev[la + lb][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[la][a], bf[lb][b],
+                                                                          lev[la + lb][a][b], 0, 0, 0);
   }
-  // f32 accumulator layout: lane l, reg v -> row 4(l>>4) + v, col l & 15
+  // int32 accumulator layout: lane l, register v -> row 4 (l >> 4) + v, column l & 15
+#pragma unroll
   for (int a = 0; a < 2; a++)
+#pragma unroll
     for (int b = 0; b < 2; b++)
+#pragma unroll
       for (int v = 0; v < 4; v++) {
-        int i = i0 + wr + a * 16 + 4 * (lane >> 4) + v;
-        int j = j0 + wc + b * 16 + (lane & 15);
+        const int i = i0 + wr + a * 16 + 4 * lhi + v;
+        const int j = j0 + wc + b * 16 + l15;
         if (i < M && j < M) {
-          const double val = ldexp(acc[a][b][v], exps[i] + exps[j] - 16);
+          double sum = 0.0;
+#pragma unroll
+          for (int l = NL - 1; l >= 0; l--) sum += ldexp((double)lev[l][a][b][v], -7 * l);
+          const double val = ldexp(sum, exps[i] + exps[j] - 14);
           C[(long long)i * ldc + j] = val;
-          if (ti != tj) C[(long long)j * ldc + i] = val;
+          C[(long long)j * ldc + i] = val;
         }
       }
 }
@@ -515,8 +527,9 @@ __global__ __launch_bounds__(256) void k_syrk_digits(const __bf16 *__restrict__ 
 hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, double *C,
                               long long ldc, const int2 *tiles, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_syrk_digits, dim3(ntiles), dim3(256), 0, s, (const __bf16 *)dig, M, K,
-                     exps, C, ldc, tiles);
+  if (K > DMAXK) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_syrk_i8, dim3(ntiles), dim3(DNT), 0, s, (const signed char *)dig, M,
+                     digit_kp(K), exps, C, ldc, tiles);
   return hipGetLastError();
 }
 

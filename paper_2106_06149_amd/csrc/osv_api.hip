@@ -378,6 +378,8 @@ struct osv_ctx {
   int2 *dTiles = nullptr;
   void *dDig = nullptr;
   int *dExps = nullptr;
+  int2 *dDigTiles = nullptr;
+  int ndig_tiles = 0;
   int nwg = 1;
   // densities (allocated on first use)
   bool dens_ready = false;
@@ -598,10 +600,23 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       }
     if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
   }
-  if (precision == OSV_MIXED) {
-    const long long nc = (long long)N * ctx->naux;
-    if ((rc = dalloc(ctx, (uint16_t **)&ctx->dDig, 5 * nc))) return rc;
+  const bool digits = precision == OSV_MIXED && ctx->naux <= digit_max_k();
+  if (digits) {
+    if ((rc = dalloc(ctx, (unsigned char **)&ctx->dDig, digit_bytes(N, ctx->naux)))) return rc;
     if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
+    // 128 x 64 tiles of the digit SYRK: pairs of 64-row tiles of the tile list
+    const int nt = (N + 63) / 64;
+    std::vector<char> mark((size_t)((nt + 1) / 2) * nt, 0);
+    std::vector<int2> dt;
+    for (const int2 &t : ctx->tiles) {
+      const size_t k = (size_t)(t.x / 2) * nt + t.y;
+      if (!mark[k]) {
+        mark[k] = 1;
+        dt.push_back(make_int2(t.x / 2, t.y));
+      }
+    }
+    ctx->ndig_tiles = (int)dt.size();
+    if ((rc = upload(ctx, &ctx->dDigTiles, dt, s))) return rc;
   }
   double host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
 
@@ -612,10 +627,10 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
                               (int)ctx->tiles128.size(), s));
   t_sf.stop();
   StageTimer t_k(s);
-  if (precision == OSV_MIXED) {
+  if (digits) {
     HIPCHK(ctx, launch_split_digits((const float *)ctx->C, N, ctx->naux, ctx->dExps, ctx->dDig, s));
-    HIPCHK(ctx, launch_syrk_digits(ctx->dDig, N, ctx->naux, ctx->dExps, ctx->dK, ld, ctx->dTiles,
-                                   (int)ctx->tiles.size(), s));
+    HIPCHK(ctx, launch_syrk_digits(ctx->dDig, N, ctx->naux, ctx->dExps, ctx->dK, ld, ctx->dDigTiles,
+                                   ctx->ndig_tiles, s));
   } else {
     const void *Cd = ctx->C;
     if (ctx->c_dtype == OSV_DT_F32) {

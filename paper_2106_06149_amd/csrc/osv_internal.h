@@ -116,8 +116,12 @@ hipError_t launch_syrk_f64(const void *A, int a_is_f32, long long lda, int M, in
                            const int2 *tiles, int ntiles, const int2 *tiles128, int ntiles128,
                            hipStream_t s);
 hipError_t launch_f32_to_f64(const float *x, double *y, long long n, hipStream_t s);
-// mixed-precision K: exact bf16 digit planes of the FP32 rows (ND = 5 planes,
-// nrow x ncol each) with per-row power-of-two exponents, then the digit SYRK
+// mixed-precision K: exact int8 digit planes of the FP32 rows with per-row
+// power-of-two exponents (digit_bytes(nrow, ncol) bytes), then the digit SYRK on
+// 128 x 64 output tiles (tile row ti covers rows 128 ti.., column tj columns 64 tj..);
+// K (ncol) at most digit_max_k()
+size_t digit_bytes(int nrow, int ncol);
+int digit_max_k();
 hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
                                hipStream_t s);
 hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, double *C,

@@ -129,10 +129,10 @@ MIXED_TOL = 1e-6   # Eh: the mixed path's energy bar
 
 
 def test_mixed_split_k_vs_oracle():
-    """Mixed precision: FP32 C, K from exact bf16 digits.  The oracle works in
+    """Mixed precision: FP32 C, K from exact int8 digits.  The oracle works in
     FP64 on the same FP32 values, so the only difference is the digit
-    truncation of C (below 2^-40 of each row's largest element); naux = 150 is
-    not a multiple of the 128-long exact-accumulation window nor of 32."""
+    truncation of C (below 2^-43 of each row's scale) and the dropped digit
+    levels; naux = 150 is not a multiple of the 64-wide digit stage."""
     s = synth.make_system(7, 60, 150, (5, 12), seed=15, cut2=6.5, cut3=4.5,
                           c_dtype=np.float32, precision=1)
     say("case mixed nocc=7 nvir=60 naux=150 r=5..12")
