@@ -481,18 +481,25 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
   const int l15 = lane & 15, lhi = lane >> 4;
   constexpr int NWV = CNT / 64;
   // 1) G(i, j) = sum_k S_(A,B)(i, k) W_B(k, j); S_(A,B)(i, k) is read as S_(B,A)(k, i),
-  //    which is contiguous in i for a fixed k (S holds both orientations of its blocks)
+  //    which is contiguous in i for a fixed k (S holds both orientations of its blocks).
+  //    Every operand of a tile's whole k range is loaded before its MFMAs, so the
+  //    global loads are in flight together instead of one k-step at a time.
+  constexpr int KST = (DMAX + 3) / 4;   // k-steps of 4 covering DMAX
   const int ti = (A.n + 15) >> 4, tj = B.np >> 4;
   for (int tile = wave; tile < ti * tj; tile += NWV) {
     const int i0 = (tile / tj) * 16, j0 = (tile % tj) * 16;
     const int i = i0 + l15, j = j0 + l15;
-    d4c acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < B.n; k0 += 4) {
-      const int k = k0 + lhi;
-      const double av = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
-      const double bv = (j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    double av[KST], bv[KST];
+#pragma unroll
+    for (int st = 0; st < KST; st++) {
+      const int k = 4 * st + lhi;
+      av[st] = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
+      bv[st] = (j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
     }
+    d4c acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < KST; st++)
+      if (4 * st < B.n) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
     // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
     for (int v = 0; v < 4; v++) {
       const int ii = i0 + 4 * v + lhi;
@@ -509,13 +516,21 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
     const int t2 = tr ? tile - nt1 : tile;
     const int a0 = (t2 / tb) * 16, b0 = (t2 % tb) * 16;
     const int a = a0 + l15, b = b0 + l15;
+    double wv[KST];
+#pragma unroll
+    for (int st = 0; st < KST; st++) {
+      const int k = 4 * st + lhi;
+      wv[st] = (a < dtA && k < A.n) ? WA[k * A.n + a] : 0.0;
+    }
     d4c acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < A.n; k0 += 4) {
-      const int k = k0 + lhi;
-      const double w = (a < dtA && k < A.n) ? WA[k * A.n + a] : 0.0;
-      const double g = (k < A.n) ? G[k * LDG + b] : 0.0;
-      acc = tr ? __builtin_amdgcn_mfma_f64_16x16x4f64(g, w, acc, 0, 0, 0)
-               : __builtin_amdgcn_mfma_f64_16x16x4f64(w, g, acc, 0, 0, 0);
+#pragma unroll
+    for (int st = 0; st < KST; st++) {
+      if (4 * st < A.n) {
+        const int k = 4 * st + lhi;
+        const double g = (k < A.n) ? G[k * LDG + b] : 0.0;
+        acc = tr ? __builtin_amdgcn_mfma_f64_16x16x4f64(g, wv[st], acc, 0, 0, 0)
+                 : __builtin_amdgcn_mfma_f64_16x16x4f64(wv[st], g, acc, 0, 0, 0);
+      }
     }
     if (!tr) {
       for (int v = 0; v < 4; v++) Mab[(long long)(a0 + 4 * v + lhi) * B.np + b] = acc[v];
