@@ -51,6 +51,45 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return t;
 }
 
+typedef double d4p __attribute__((ext_vector_type(4)));
+
+// C(i, j) = sum_{k < K} A(i, k) B(k, j) for i < M, j < N (all <= DMAX) on FP64
+// MFMA 16x16x4: the 16x16 output tiles are spread over the block's waves, and the
+// operands of 8 k-steps are loaded before their MFMAs, so that global loads are
+// in flight together.  a(i, k), b(k, j) are called for in-range indices only;
+// c(i, j, value) stores.  No barrier inside: the caller orders producers and
+// consumers.
+template <int NT, class FA, class FB, class FC>
+__device__ __forceinline__ void mma_tiles(int M, int N, int K, FA a, FB b, FC c) {
+  constexpr int KB = 8;    // k-steps of 4 per batch
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l15 = lane & 15, lhi = lane >> 4;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  for (int t = wave; t < tm * tn; t += NT / 64) {
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+    const int i = i0 + l15, j = j0 + l15;
+    d4p acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4 * KB) {
+      double av[KB], bv[KB];
+#pragma unroll
+      for (int st = 0; st < KB; st++) {
+        const int k = k0 + 4 * st + lhi;
+        av[st] = (i < M && k < K) ? a(i, k) : 0.0;
+        bv[st] = (j < N && k < K) ? b(k, j) : 0.0;
+      }
+#pragma unroll
+      for (int st = 0; st < KB; st++)
+        if (k0 + 4 * st < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
+    }
+    // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int ii = i0 + 4 * v + lhi;
+      if (ii < M && j < N) c(ii, j, acc[v]);
+    }
+  }
+}
+
 // One rotation of a Jacobi step: (p, q) with p < q, cosine and sine; z = 1 when
 // a_pq is set to zero in this step (with or without a rotation).  32 bytes, read
 // with two 16-byte LDS loads.
@@ -240,12 +279,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     //    lambda_min(A) >= 1 / trace(A^-1) = 1 / ||L^-1||_F^2, that bound certifies
     //    that nothing is dropped.  Otherwise the overlap eigenvalues are cut
     //    explicitly (eigendecomposition of S_(pq,pq)).
-    for (int e = tid; e < rq * rq; e += NT) {
-      int i = e / rq, j = e - i * rq;
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int k = 0; k < rp; k++) s -= Bg[(long long)k * ld + i] * Bg[(long long)k * ld + j];
-      L1[i * LD + j] = s;
-    }
+    mma_tiles<NT>(rq, rq, rp, [&](int i, int k) { return Bg[(long long)k * ld + i]; },
+                  [&](int k, int j) { return Bg[(long long)k * ld + j]; },
+                  [&](int i, int j, double v) { L1[i * LD + j] = ((i == j) ? 1.0 : 0.0) - v; });
     __syncthreads();
     // right-looking Cholesky (lower triangle of L1)
     for (int j = 0; j < rq; j++) {
@@ -336,20 +372,14 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       __syncthreads();
     }
     // 2) L1 = F_(pq,pq) X (n x dt)
-    for (int e = tid; e < n * dt; e += NT) {
-      int i = e / dt, j = e - i * dt;
-      double s = 0.0;
-      for (int k = 0; k < n; k++) s += comp_elem(F, ld, D, D, i, k, false) * Yg[k * n + j];
-      L1[i * LD + j] = s;
-    }
+    mma_tiles<NT>(n, dt, n, [&](int i, int k) { return comp_elem(F, ld, D, D, i, k, false); },
+                  [&](int k, int j) { return Yg[k * n + j]; },
+                  [&](int i, int j, double v) { L1[i * LD + j] = v; });
     __syncthreads();
     // H = X^T L1 (dt x dt) into L2, symmetrised into L1
-    for (int e = tid; e < dt * dt; e += NT) {
-      int i = e / dt, j = e - i * dt;
-      double s = 0.0;
-      for (int k = 0; k < n; k++) s += Yg[k * n + i] * L1[k * LD + j];
-      L2[i * LD + j] = s;
-    }
+    mma_tiles<NT>(dt, dt, n, [&](int i, int k) { return Yg[k * n + i]; },
+                  [&](int k, int j) { return L1[k * LD + j]; },
+                  [&](int i, int j, double v) { L2[i * LD + j] = v; });
     __syncthreads();
     for (int e = tid; e < dt * dt; e += NT) {
       int i = e / dt, j = e - i * dt;
@@ -360,12 +390,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
     __syncthreads();
     // W = X V (n x dt) into L1, then to global
-    for (int e = tid; e < n * dt; e += NT) {
-      int i = e / dt, j = e - i * dt;
-      double s = 0.0;
-      for (int k = 0; k < dt; k++) s += Yg[i * n + k] * L2[k * LD + j];
-      L1[i * LD + j] = s;
-    }
+    mma_tiles<NT>(n, dt, dt, [&](int i, int k) { return Yg[i * n + k]; },
+                  [&](int k, int j) { return L2[k * LD + j]; },
+                  [&](int i, int j, double v) { L1[i * LD + j] = v; });
     __syncthreads();
     for (int e = tid; e < n * n; e += NT) {
       int i = e / n, j = e - i * n;
@@ -373,12 +400,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     }
     __syncthreads();
     // 3) Y = W^T S_(pq,pq) (dt x n) into L2
-    for (int e = tid; e < dt * n; e += NT) {
-      int a = e / n, j = e - a * n;
-      double s = 0.0;
-      for (int k = 0; k < n; k++) s += L1[k * LD + a] * comp_elem(S, ld, D, D, k, j, true);
-      L2[a * LD + j] = s;
-    }
+    mma_tiles<NT>(dt, n, n, [&](int a, int k) { return L1[k * LD + a]; },
+                  [&](int k, int j) { return comp_elem(S, ld, D, D, k, j, true); },
+                  [&](int a, int j, double v) { L2[a * LD + j] = v; });
     __syncthreads();
   } else {
     // diagonal domain: S = 1, W = eigenvectors of F_pp
@@ -418,21 +442,18 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
   const int rq = diag ? D.rp : D.rq;
   const int offq = diag ? D.offp : D.offq;
   const int qcol = diag ? 0 : D.rp;
-  for (int e = tid; e < dt * rq; e += NT) {
-    int a = e / rq, j = e - a * rq;
-    double s = 0.0;
-    for (int k = 0; k < D.rp; k++) s += L2[a * LD + k] * K[(long long)(D.offp + k) * ld + (offq + j)];
-    L1[a * LD + j] = s;
-  }
+  mma_tiles<NT>(dt, rq, D.rp, [&](int a, int k) { return L2[a * LD + k]; },
+                [&](int k, int j) { return K[(long long)(D.offp + k) * ld + (offq + j)]; },
+                [&](int a, int j, double v) { L1[a * LD + j] = v; });
   __syncthreads();
   // stored transposed and zero-padded: Kg[b np + a] = K~(a, b)
   for (int e = tid; e < np * np; e += NT) {
-    int b = e / np, a = e - b * np;
-    double s = 0.0;
-    if (a < dt && b < dt)
-      for (int k = 0; k < rq; k++) s += L1[a * LD + k] * L2[b * LD + qcol + k];
-    Kg[b * np + a] = s;
+    const int b = e / np, a = e - b * np;
+    if (a >= dt || b >= dt) Kg[b * np + a] = 0.0;
   }
+  mma_tiles<NT>(dt, dt, rq, [&](int a, int k) { return L1[a * LD + k]; },
+                [&](int k, int b) { return L2[b * LD + qcol + k]; },
+                [&](int a, int b, double v) { Kg[b * np + a] = v; });
   if (tid == 0) rank[dom_id] = dt;
 }
 
