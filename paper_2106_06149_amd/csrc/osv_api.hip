@@ -348,6 +348,15 @@ int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan 
 
 }  // namespace
 
+// host-side index lists of the densities (built once per context)
+struct DensHost {
+  bool ready = false;
+  std::vector<long long> ptr, toff, bptr, pptr, pidx;
+  std::vector<double> cf;
+  std::vector<int2> blocks;
+  std::vector<int> bdom, bpart;
+};
+
 struct osv_ctx {
   int nocc = 0, nvir = 0, naux = 0, nosv = 0, precision = 0, c_dtype = 0, mode = 0;
   std::vector<int> r, off;
@@ -383,6 +392,7 @@ struct osv_ctx {
   int nwg = 1;
   // densities (allocated on first use)
   bool dens_ready = false;
+  DensHost dh;
   double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
   double *dClcoef = nullptr;
   long long *dDptr = nullptr, *dDtoff = nullptr, *dBptr = nullptr, *dPptr = nullptr, *dPidx = nullptr;
@@ -680,36 +690,6 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       return fail(ctx, OSV_E_DOMAIN, "pair domain (" + std::to_string(P.doms[d].p) + "," +
                                          std::to_string(P.doms[d].q) + ") has rank 0 after the tau_S cut");
     }
-  {
-    // algorithmic flops of the build stages and of one sweep per cluster
-    const std::vector<int> &rk = ctx->rank_host;
-    double fsf = 0, fk = 0, fc = 0;
-    for (const Domain &D : P.doms) {
-      double rp = D.rp, rq = (D.p == D.q) ? D.rp : D.rq;
-      fsf += (D.p == D.q ? 2.0 : 4.0) * rp * rq * ctx->nvir;
-      fk += 2.0 * rp * rq * ctx->naux;
-    }
-    for (const Coupling &c : P.cpls) {
-      double nA = P.doms[c.A].n, nB = P.doms[c.B].n, dA = rk[c.A], dB = rk[c.B];
-      fc += 2.0 * (nA * dB * nB + dA * dB * nA);
-    }
-    ctx->stage_flops[0] = fsf;
-    ctx->stage_flops[1] = fk;
-    ctx->stage_flops[3] = fc;
-    ctx->flops_sweep.assign(P.cls.size(), 0.0);
-    for (size_t X = 0; X < P.cls.size(); X++) {
-      const Cluster &C = P.cls[X];
-      double f = 0;
-      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
-        double nt = rk[P.cps[c].dom];
-        for (int t = P.cps[c].term0; t < P.cps[c].term0 + P.cps[c].nterm; t++) {
-          double ns = rk[P.cps[P.terms[t].src].dom];
-          f += 2.0 * (nt * ns * ns + nt * nt * ns);
-        }
-      }
-      ctx->flops_sweep[X] = f;
-    }
-  }
   ctx->stage_ms[0] = t_sf.ms();
   ctx->stage_ms[1] = t_k.ms();
   ctx->stage_ms[2] = t_prep.ms();
@@ -861,6 +841,42 @@ int osv_query(const osv_ctx *ctx, osv_counts *out) {
   return OSV_OK;
 }
 
+// algorithmic flops of the build stages and of one sweep per cluster (host; the
+// solve runs it while its kernel occupies the GPU)
+static void count_flops(osv_ctx *ctx) {
+  if (!ctx->flops_sweep.empty() || ctx->plan.cls.empty()) return;
+  Plan &P = ctx->plan;
+    const std::vector<int> &rk = ctx->rank_host;
+    double fsf = 0, fk = 0, fc = 0;
+    for (const Domain &D : P.doms) {
+      double rp = D.rp, rq = (D.p == D.q) ? D.rp : D.rq;
+      fsf += (D.p == D.q ? 2.0 : 4.0) * rp * rq * ctx->nvir;
+      fk += 2.0 * rp * rq * ctx->naux;
+    }
+    for (const Coupling &c : P.cpls) {
+      double nA = P.doms[c.A].n, nB = P.doms[c.B].n, dA = rk[c.A], dB = rk[c.B];
+      fc += 2.0 * (nA * dB * nB + dA * dB * nA);
+    }
+    ctx->stage_flops[0] = fsf;
+    ctx->stage_flops[1] = fk;
+    ctx->stage_flops[3] = fc;
+    ctx->flops_sweep.assign(P.cls.size(), 0.0);
+    for (size_t X = 0; X < P.cls.size(); X++) {
+      const Cluster &C = P.cls[X];
+      double f = 0;
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+        double nt = rk[P.cps[c].dom];
+        for (int t = P.cps[c].term0; t < P.cps[c].term0 + P.cps[c].nterm; t++) {
+          double ns = rk[P.cps[P.terms[t].src].dom];
+          f += 2.0 * (nt * ns * ns + nt * nt * ns);
+        }
+      }
+      ctx->flops_sweep[X] = f;
+    }
+  }
+
+static void densities_host(osv_ctx *ctx);
+
 int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream_t s,
                        osv_solve_info *info) {
   if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
@@ -897,6 +913,9 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 2, s));
   HIPCHK(ctx, launch_solve(a, P.n_big, ctx->nwg, s));
   t.stop();
+  // host bookkeeping while the kernel runs
+  count_flops(ctx);
+  densities_host(ctx);
   std::vector<int> sw(ncl);
   std::vector<double> mr(ncl);
   HIPCHK(ctx, hipMemcpyAsync(sw.data(), ctx->dSweeps, ncl * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -953,35 +972,42 @@ int osv_energy(osv_ctx *ctx, hipStream_t s, double *E, double *E_orders, double 
   return OSV_OK;
 }
 
-static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
-  if (ctx->dens_ready) return OSV_OK;
+// Host part of the densities' bookkeeping (it depends on the plan only, so the
+// solve runs it while its kernel occupies the GPU).
+static void densities_host(osv_ctx *ctx) {
+  DensHost &H = ctx->dh;
+  if (H.ready) return;
   Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
-  const int ndom = (int)P.doms.size(), ncl = (int)P.cls.size(), nocc = ctx->nocc, N = ctx->nosv;
-  int rc;
+  const int ndom = (int)P.doms.size(), ncl = (int)P.cls.size(), nocc = ctx->nocc;
   // per domain: (amplitude offset, c_X) over the clusters holding it, cluster order
-  std::vector<std::vector<std::pair<long long, double>>> lists(ndom);
+  // (counting sort by domain)
+  H.ptr.assign(ndom + 1, 0);
   for (int X = 0; X < ncl; X++) {
     if (S.coef[X] == 0.0) continue;
     const Cluster &C = P.cls[X];
-    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) lists[P.cps[c].dom].push_back({P.cps[c].toff, S.coef[X]});
+    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) H.ptr[P.cps[c].dom + 1]++;
   }
-  std::vector<long long> ptr(ndom + 1, 0), toff;
-  std::vector<double> cf;
-  for (int d = 0; d < ndom; d++) {
-    for (auto &e : lists[d]) {
-      toff.push_back(e.first);
-      cf.push_back(e.second);
+  for (int d = 0; d < ndom; d++) H.ptr[d + 1] += H.ptr[d];
+  H.toff.assign(H.ptr[ndom], 0);
+  H.cf.assign(H.ptr[ndom], 0.0);
+  {
+    std::vector<long long> fill(H.ptr.begin(), H.ptr.end() - 1);
+    for (int X = 0; X < ncl; X++) {
+      if (S.coef[X] == 0.0) continue;
+      const Cluster &C = P.cls[X];
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+        const long long k = fill[P.cps[c].dom]++;
+        H.toff[k] = P.cps[c].toff;
+        H.cf[k] = S.coef[X];
+      }
     }
-    ptr[d + 1] = (long long)toff.size();
   }
-  if ((rc = upload(ctx, &ctx->dDptr, ptr, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dDtoff, toff, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dDcoef, cf, s))) return rc;
   // G^F orbital blocks
-  std::vector<int2> blocks;
-  std::vector<long long> bptr(1, 0);
-  std::vector<int> bdom, bpart;
+  H.blocks.clear();
+  H.bptr.assign(1, 0);
+  H.bdom.clear();
+  H.bpart.clear();
   std::vector<std::vector<std::pair<int, int>>> diag_src(nocc);
   for (int d = 0; d < ndom; d++) {
     const Domain &D = P.doms[d];
@@ -990,44 +1016,66 @@ static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
   }
   for (int d = 0; d < ndom; d++) {
     const Domain &D = P.doms[d];
-    blocks.push_back(make_int2(D.p, D.q));
+    H.blocks.push_back(make_int2(D.p, D.q));
     if (D.p == D.q) {
       for (auto &e : diag_src[D.p]) {
-        bdom.push_back(e.first);
-        bpart.push_back(e.second);
+        H.bdom.push_back(e.first);
+        H.bpart.push_back(e.second);
       }
     } else {
-      bdom.push_back(d);
-      bpart.push_back(0);
+      H.bdom.push_back(d);
+      H.bpart.push_back(0);
     }
-    bptr.push_back((long long)bdom.size());
+    H.bptr.push_back((long long)H.bdom.size());
   }
-  ctx->nblocks = (int)blocks.size();
-  if ((rc = upload(ctx, &ctx->dBlocks, blocks, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dBptr, bptr, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dBdom, bdom, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dBpart, bpart, s))) return rc;
-  // dE/dF: per entry (u, v) the (cluster, inner-product index) list
-  std::vector<std::vector<std::pair<long long, long long>>> pl((size_t)nocc * nocc);
+  // dE/dF: per entry (u, v) the (cluster, inner-product index) list, cluster order
+  // (counting sort by entry)
+  const size_t ne = (size_t)nocc * nocc;
+  H.pptr.assign(ne + 1, 0);
   for (int X = 0; X < ncl; X++) {
     if (S.coef[X] == 0.0) continue;
     const Cluster &C = P.cls[X];
     for (int a = 0; a < C.nlmo; a++)
-      for (int b = 0; b < C.nlmo; b++) {
-        int u = S.lmo[C.lmo0 + a], v = S.lmo[C.lmo0 + b];
-        pl[(size_t)u * nocc + v].push_back({X, C.poff + (long long)a * C.nlmo + b});
-      }
+      for (int b = 0; b < C.nlmo; b++)
+        H.pptr[(size_t)S.lmo[C.lmo0 + a] * nocc + S.lmo[C.lmo0 + b] + 1]++;
   }
-  std::vector<long long> pptr((size_t)nocc * nocc + 1, 0), pidx;
-  for (size_t e = 0; e < pl.size(); e++) {
-    for (auto &x : pl[e]) {
-      pidx.push_back(x.first);
-      pidx.push_back(x.second);
+  for (size_t e = 0; e < ne; e++) H.pptr[e + 1] += H.pptr[e];
+  H.pidx.assign(2 * H.pptr[ne], 0);
+  {
+    std::vector<long long> fill(H.pptr.begin(), H.pptr.end() - 1);
+    for (int X = 0; X < ncl; X++) {
+      if (S.coef[X] == 0.0) continue;
+      const Cluster &C = P.cls[X];
+      for (int a = 0; a < C.nlmo; a++)
+        for (int b = 0; b < C.nlmo; b++) {
+          const size_t e = (size_t)S.lmo[C.lmo0 + a] * nocc + S.lmo[C.lmo0 + b];
+          const long long k = fill[e]++;
+          H.pidx[2 * k] = X;
+          H.pidx[2 * k + 1] = C.poff + (long long)a * C.nlmo + b;
+        }
     }
-    pptr[e + 1] = (long long)pidx.size() / 2;
   }
-  if ((rc = upload(ctx, &ctx->dPptr, pptr, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dPidx, pidx, s))) return rc;
+  H.ready = true;
+}
+
+static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
+  if (ctx->dens_ready) return OSV_OK;
+  densities_host(ctx);
+  DensHost &H = ctx->dh;
+  Plan &P = ctx->plan;
+  const Selection &S = ctx->sel;
+  const int N = ctx->nosv;
+  int rc;
+  if ((rc = upload(ctx, &ctx->dDptr, H.ptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dDtoff, H.toff, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dDcoef, H.cf, s))) return rc;
+  ctx->nblocks = (int)H.blocks.size();
+  if ((rc = upload(ctx, &ctx->dBlocks, H.blocks, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dBptr, H.bptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dBdom, H.bdom, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dBpart, H.bpart, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dPptr, H.pptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dPidx, H.pidx, s))) return rc;
   if ((rc = upload(ctx, &ctx->dClcoef, S.coef, s))) return rc;
   const long long ld = N;
   if ((rc = dalloc(ctx, &ctx->dGK, (size_t)ld * ld))) return rc;
@@ -1112,6 +1160,7 @@ int osv_stage_times(const osv_ctx *ctx, double *ms9) {
 
 int osv_stage_flops(const osv_ctx *ctx, double *f9) {
   if (!ctx || !f9) return fail(nullptr, OSV_E_ARG, "osv_stage_flops: NULL argument");
+  count_flops(const_cast<osv_ctx *>(ctx));   // build-stage counts if no solve has run yet
   for (int i = 0; i < 9; i++) f9[i] = ctx->stage_flops[i];
   return OSV_OK;
 }
