@@ -4,10 +4,12 @@
 //   K_ij    = C_i C_j^T                                    (pair tasks of Algorithm 1)
 //   dE/dC   = 2 G^K C,  Z^T = G^F Q^T, D^v = Q Z^T          (back-transforms of the densities)
 //
-// All of them are written as one 64x64-tile MFMA kernel over the full
-// sum(r) x sum(r) (or sum(r) x n) index space; a tile list skips tiles that
-// hold no needed orbital-pair block.  FP64 tiles use v_mfma_f64_16x16x4f64,
-// the mixed-precision K uses v_mfma_i32_16x16x64_i8 on exact int8 digit splits of
+// FP64 products run on a 128x128-tile MFMA kernel fed by direct global-to-LDS
+// loads (k_gemm_dma) whenever the leading dimensions and k are even and the
+// operands 16-byte aligned, else on a 64x64-tile kernel that stages through
+// registers (k_tile_f64); for the symmetric products a tile list skips tiles that
+// hold no needed orbital-pair block.  FP64 tiles use v_mfma_f64_16x16x4f64; the
+// mixed-precision K uses v_mfma_i32_16x16x64_i8 on exact int8 digit splits of
 // the FP32 input with exact int32 accumulation, combined in FP64 at the end.
 #include "osv_internal.h"
 
