@@ -178,3 +178,29 @@ def test_energy_pass_fallbacks(case):
     g = run_gpu(s)
     ref = O.solve(s)
     compare(s, g, ref)
+
+
+def test_overlap_selection_mbe3():
+    """Cluster selection by the OSV overlap metric (eq:2bscreen, eq:3bscreen)
+    instead of centroid distance: thresholds put about half of the pairs and a
+    mix of triples in, so the MBE coefficients differ from the distance rule."""
+    s = synth.make_system(10, 60, 50, (4, 9), seed=19, sel_mode=synth.SEL_OVERLAP)
+    s2b = O.s2b_metric(s)
+    # thresholds halfway between neighbouring values, so that rounding differences
+    # between the two computations of the metric cannot flip a decision
+    off = np.sort(s2b[np.triu_indices(s.nocc, 1)])
+    h = len(off) // 2
+    l2b = float(0.5 * (off[h - 1] + off[h]))
+    n = s.nocc
+    m3 = np.sort([(s2b[i, j] + s2b[i, k] + s2b[j, k]) / 3.0
+                  for i in range(n) for j in range(i + 1, n) for k in range(j + 1, n)])
+    q = int(0.8 * len(m3))
+    l3b = float(0.5 * (m3[q - 1] + m3[q]))
+    say(f"case overlap selection nocc=10 l2b={l2b:.3g} l3b={l3b:.3g}")
+    sel = Selection(L.OSV_SEL_OVERLAP, l2b=l2b, l3b=l3b)
+    g = run_gpu(s, sel=sel)
+    ref = O.solve(s, mode=synth.SEL_OVERLAP, l2b=l2b, l3b=l3b)
+    assert 0 < g["counts"]["n2b"] < s.nocc * (s.nocc - 1) // 2
+    assert g["counts"]["n3b"] > 0
+    assert len(ref["E_cluster"]) == g["counts"]["n_clusters"]
+    compare(s, g, ref)
