@@ -204,3 +204,15 @@ def test_overlap_selection_mbe3():
     assert g["counts"]["n3b"] > 0
     assert len(ref["E_cluster"]) == g["counts"]["n_clusters"]
     compare(s, g, ref)
+
+
+def test_full_cluster_beyond_lds_tables():
+    """One cluster holding every LMO (full OSV-MP2 on nocc = 12: 78 pairs, more
+    than the solve keeps in its LDS descriptor tables), so the solve runs the
+    instantiation that reads pair and term descriptors from global memory."""
+    s = synth.make_system(12, 50, 40, (3, 6), seed=23, sel_mode=synth.SEL_FULL)
+    say("case full cluster nocc=12 (78 pairs, global descriptors)")
+    g = run_gpu(s)
+    assert g["counts"]["n_pair_blocks"] == 78
+    ref = O.solve(s)
+    compare(s, g, ref)
