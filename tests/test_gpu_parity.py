@@ -216,3 +216,14 @@ def test_full_cluster_beyond_lds_tables():
     assert g["counts"]["n_pair_blocks"] == 78
     ref = O.solve(s)
     compare(s, g, ref)
+
+
+def test_mixed_beyond_int32_range_uses_fp64_k():
+    """naux above the int32 range of the exact digit accumulation: the mixed mode
+    computes K in FP64 instead (same result as the oracle to the FP64 bar)."""
+    s = synth.make_system(3, 20, 87100, 4, seed=29, c_dtype=np.float32, precision=1,
+                          sel_mode=synth.SEL_FULL, b_scale=0.01)
+    say("case mixed with naux=87100 (FP64 K fallback)")
+    g = run_gpu(s)
+    ref = O.solve(s)
+    compare(s, g, ref)
