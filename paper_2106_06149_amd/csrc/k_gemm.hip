@@ -123,10 +123,10 @@ __global__ __launch_bounds__(256) void k_tile_f64(const TA *__restrict__ A, long
 //   C[i][j] = alpha sum_k A(i,k) B(k,j), or with WGT alpha sum_k A(i,k) w[k] B(k,j)
 // Eight waves (two per SIMD: one wave alone cannot keep the FP64 MFMA pipe busy),
 // each a 32x64 part of the tile as 2x4 MFMA 16x16x4 accumulators.
-// k advances in stages of 16 through a ring of three LDS buffers: the loads of
-// stage s+2 (global_load_lds_dwordx4, 16 bytes per lane, no registers) are
-// issued before the MFMAs of stage s.  A [row][k] stage keeps a row's 16 doubles as eight
-// 16-byte slots, slot index XOR (row mod 8), so that the 16 rows of an operand
+// k advances in stages of 32 through two LDS buffers: the loads of stage s+1
+// (global_load_lds_dwordx4, 16 bytes per lane, no registers) are issued before
+// the MFMAs of stage s.  A [row][k] stage keeps a row's 32 doubles as sixteen
+// 16-byte slots, slot index XOR (row mod 16), so that the 16 rows of an operand
 // fragment spread over the LDS banks; a [k][j] stage pads its rows to 130 doubles.
 // Rows and columns past M, N are clamped to the last valid one (they only feed
 // outputs that are not stored); k past K is clamped on load and zeroed in LDS.
@@ -134,17 +134,17 @@ __global__ __launch_bounds__(256) void k_tile_f64(const TA *__restrict__ A, long
 // A and B, and for BK == 1 also N even.
 // ---------------------------------------------------------------------------
 constexpr int G = 128;             // output tile edge
-constexpr int GKS = 16;            // k per stage (doubles)
+constexpr int GKS = 32;            // k per stage (doubles)
 constexpr int GRS = 130;           // LDS row stride of a [k][j] stage (doubles)
 constexpr int GA = G * GKS;        // doubles of a [row][k] stage
 constexpr int GB1 = GKS * GRS;     // doubles of a [k][j] stage
-constexpr int GNS = 3;             // ring stages
+constexpr int GNS = 2;             // stages: the next one loads while this one is multiplied
 constexpr int GNT = 512;           // threads (8 waves)
 
 typedef __attribute__((address_space(3))) void *lds_ptr;
 
-// issue the loads of stage k0 into buffer (As_b, Bs_b): 16 blocks of 1 KB per
-// operand, two per wave
+// issue the loads of stage k0 into buffer (As_b, Bs_b): 32 blocks of 1 KB per
+// operand, four per wave
 template <int BK>
 __device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long long lda,
                                            const double *__restrict__ B, long long ldb, int i0,
@@ -152,10 +152,10 @@ __device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long lo
                                            double *Bs_b) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int v = 0; v < 2; v++) {
+  for (int v = 0; v < 4; v++) {
     const int u = wave + 8 * v;                 // 1 KB block of the stage
     const int p = u * 64 + lane;                // 16-byte slot in the stage
-    const int row = p >> 3, kp = (p & 7) ^ (row & 7);
+    const int row = p >> 4, kp = (p & 15) ^ (row & 15);
     const int gk = min(k0 + 2 * kp, K - 2);
     const int gi = min(i0 + row, M - 1);
     __builtin_amdgcn_global_load_lds((const void *)(A + (long long)gi * lda + gk),
@@ -204,26 +204,21 @@ __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, 
     for (int b = 0; b < 4; b++) acc[a][b] = (d4){0, 0, 0, 0};
   const int nst = (K + GKS - 1) / GKS;
   gemm_issue<BK>(A, lda, B, ldb, i0, j0, 0, M, N, K, As, Bs);
-  if (nst > 1) gemm_issue<BK>(A, lda, B, ldb, i0, j0, GKS, M, N, K, As + GA, Bs + GBS);
   for (int st = 0; st < nst; st++) {
-    const int k0 = st * GKS, sb = st % GNS;
+    const int k0 = st * GKS, sb = st & 1;
     double *Ab = As + sb * GA, *Bb = Bs + sb * GBS;
-    // this stage's loads have landed (the 4 load instructions of the next stage,
-    // if issued, may still be in flight; loads complete in order) and every wave
-    // is done with the stage that the loads issued next will overwrite
-    if (st + 1 < nst) asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (st + 2 < nst) {
-      const int nb = (st + 2) % GNS;
-      gemm_issue<BK>(A, lda, B, ldb, i0, j0, k0 + 2 * GKS, M, N, K, As + nb * GA, Bs + nb * GBS);
-    }
+    // this stage's loads have landed and every wave is done with the other buffer
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (st + 1 < nst)
+      gemm_issue<BK>(A, lda, B, ldb, i0, j0, k0 + GKS, M, N, K, As + (sb ^ 1) * GA,
+                     Bs + (sb ^ 1) * GBS);
     if (k0 + GKS > K) {
       // last, partial stage: zero k >= K
       const int kv = K - k0;
       for (int e = tid; e < G * GKS; e += GNT) {
-        const int row = e >> 4, k = e & 15;
+        const int row = e >> 5, k = e & 31;
         if (k >= kv) {
-          const int idx = row * GKS + ((((k >> 1) ^ (row & 7))) << 1) + (k & 1);
+          const int idx = row * GKS + ((((k >> 1) ^ (row & 15))) << 1) + (k & 1);
           Ab[idx] = 0.0;
           if (BK == 0) Bb[idx] = 0.0;
           else Bb[k * GRS + row] = 0.0;
@@ -238,12 +233,12 @@ __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, 
 #pragma unroll
       for (int a = 0; a < 2; a++) {
         const int row = wr + a * 16 + l15;
-        af[a] = Ab[row * GKS + ((((kk >> 1) ^ (row & 7))) << 1) + (kk & 1)];
+        af[a] = Ab[row * GKS + ((((kk >> 1) ^ (row & 15))) << 1) + (kk & 1)];
       }
 #pragma unroll
       for (int b = 0; b < 4; b++) {
         const int col = wc + b * 16 + l15;
-        bf[b] = BK == 0 ? Bb[col * GKS + ((((kk >> 1) ^ (col & 7))) << 1) + (kk & 1)]
+        bf[b] = BK == 0 ? Bb[col * GKS + ((((kk >> 1) ^ (col & 15))) << 1) + (kk & 1)]
                         : Bb[kk * GRS + col];
       }
       if (WGT) {
