@@ -90,13 +90,22 @@ __device__ __forceinline__ void mma_tiles(int M, int N, int K, FA a, FB b, FC c)
   }
 }
 
-// One rotation of a Jacobi step: (p, q) with p < q, cosine and sine; z = 1 when
-// a_pq is set to zero in this step (with or without a rotation).  32 bytes, read
-// with two 16-byte LDS loads.
-struct __attribute__((aligned(16))) Rot {
-  double c, s;
-  int p, q, z, pad;
-};
+// Rotation t of step st of a round-robin sweep over m + 1 indices (m odd): the
+// pair (p, q), p < q; index m is a dummy when n is odd.
+__device__ __forceinline__ void rr_pair(int st, int t, int m, int &p, int &q) {
+  int a, b;
+  if (t == 0) {
+    a = st;
+    b = m;
+  } else {
+    a = st + t;
+    a -= (a >= m) ? m : 0;
+    b = st - t;
+    b += (b < 0) ? m : 0;
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
 
 // index of element (a, b) of a symmetric matrix of which only the upper triangle
 // is kept
@@ -108,16 +117,20 @@ __device__ __forceinline__ int up(int a, int b) {
 // Cyclic Jacobi: A (n x n, stride LD) is diagonalised in place, V receives the
 // eigenvectors (columns).  Round-robin ordering: in step st the n/2 disjoint
 // pairs rotate simultaneously; A <- J^T A J is applied as independent 2x2 block
-// updates; a step is a rotation table, a barrier, the updates, a barrier.
+// updates.  A step has two phases separated by barriers: (1) wave 0 forms the
+// step's rotation table while the other waves apply the previous step's
+// rotations to the rows of V (V is not read by the A updates), (2) every thread
+// updates its 2x2 blocks of A.
 // A is read in full on entry; during the sweeps only its upper triangle is kept
 // (each 2x2 block is read and written once), so on return only the diagonal
-// (the eigenvalues) and the upper triangle are meaningful.  The step is bound by
-// LDS bandwidth: every thread reads the rotation table once per step (its V
-// entries share one rotation) and each block touches four elements.
+// (the eigenvalues) and the upper triangle are meaningful.
 // Threshold rule: |a_pq| <= 1e-17 sqrt(|a_pp a_qq|) or <= 1e-18 ||A||_F is set
-// to zero without a rotation; the solve ends after a sweep with no rotation.
+// to zero without a rotation.  After a sweep with rotations every pair is tested
+// against that rule; the solve ends when no pair would rotate (a further sweep
+// would change no diagonal element and no element of V).
+// Requires NT >= 128 and n/2 <= 64; rt holds n/2 entries.
 template <int LD, int NT, int MAXB, int MAXV>
-__device__ void jacobi_eig(double *A, double *V, int n, Rot *rt, double *red, int *flag) {
+__device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red, int *flag) {
   const int tid = threadIdx.x;
   const int nE = n + (n & 1), h = nE / 2, m = nE - 1;
   for (int e = tid; e < n * n; e += NT) {
@@ -144,26 +157,45 @@ __device__ void jacobi_eig(double *A, double *V, int n, Rot *rt, double *red, in
     bI[u] = (b < nb) ? I : -1;
     bJ[u] = I + rem;
   }
-  // V entries: thread tid applies rotation k = tid mod h to rows r0 + R u,
-  // r0 = tid / h, R = NT / h (threads tid >= R h have none)
-  const int R = NT / h;
-  const int vk = (tid < R * h) ? tid % h : -1;
-  const int r0 = tid / h;
+  // V entries: thread vt = tid - 64 of waves 1.. applies rotation k = vt mod h to
+  // rows r0 + R u, r0 = vt / h, R = (NT - 64) / h (threads vt >= R h have none)
+  const int vt = tid - 64;
+  const int R = (NT - 64) / h;
+  const int vk = (vt >= 0 && vt < R * h) ? vt % h : -1;
+  const int r0 = vt >= 0 ? vt / h : 0;
+  // table entries: (cosine, sine); (1, 0) where no rotation takes place.  A V
+  // thread copies its entry of step st to registers during the A updates of
+  // that step and applies it while the table of the next step is formed.
+  auto v_update = [&](const double2 r, int st) {
+    if (vk < 0) return;
+    if (r.y == 0.0) return;   // a rotation implies q < n
+    int p, q;
+    rr_pair(st, vk, m, p, q);
+#pragma unroll
+    for (int u = 0; u < MAXV; u++) {
+      const int i = r0 + R * u;
+      if (i < n) {
+        const double vp = V[i * LD + p], vq = V[i * LD + q];
+        V[i * LD + p] = r.x * vp - r.y * vq;
+        V[i * LD + q] = r.y * vp + r.x * vq;
+      }
+    }
+  };
+  double2 vr = make_double2(1.0, 0.0);   // this thread's pending V rotation, of step vst
+  int vst = 0;
   for (int sweep = 0; sweep < 60; sweep++) {
     if (tid == 0) *flag = 0;
     __syncthreads();
     for (int st = 0; st < m; st++) {
+      double2 *tab = rt;
       if (tid < h) {
-        int a, b;
-        if (tid == 0) { a = st; b = m; } else { a = st + tid; a -= (a >= m) ? m : 0; b = st - tid; b += (b < 0) ? m : 0; }
-        const int p = a < b ? a : b, q = a < b ? b : a;
+        int p, q;
+        rr_pair(st, tid, m, p, q);
         double c = 1.0, sv = 0.0;
-        int z = 0;
         if (q < n) {
           const double apq = A[p * LD + q];
           if (apq != 0.0) {
             const double app = A[p * LD + p], aqq = A[q * LD + q];
-            z = 1;
             if (!(fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq)) || fabs(apq) <= absthr)) {
               const double theta = (aqq - app) / (2.0 * apq);
               const double at = fabs(theta);
@@ -176,31 +208,39 @@ __device__ void jacobi_eig(double *A, double *V, int n, Rot *rt, double *red, in
             }
           }
         }
-        Rot r;
-        r.c = c; r.s = sv; r.p = p; r.q = q; r.z = z; r.pad = 0;
-        rt[tid] = r;
+        tab[tid] = make_double2(c, sv);
+      } else {
+        v_update(vr, vst);
       }
       __syncthreads();
+      if (vk >= 0) {
+        vr = tab[vk];
+        vst = st;
+      }
 #pragma unroll
       for (int u = 0; u < MAXB; u++) {
         const int I = bI[u], J = bJ[u];
         if (I < 0) continue;
-        const Rot rI = rt[I];
+        const double2 rI = tab[I];
+        int pI, qI;
+        rr_pair(st, I, m, pI, qI);
         if (I == J) {
-          if (rI.q < n && rI.z) {
-            const double apq = A[rI.p * LD + rI.q];
-            if (rI.s != 0.0) {
-              const double tt = rI.s / rI.c;
-              A[rI.p * LD + rI.p] -= tt * apq;
-              A[rI.q * LD + rI.q] += tt * apq;
+          // a_pq is zeroed (it is below the threshold when there is no rotation)
+          if (qI < n) {
+            if (rI.y != 0.0) {
+              const double apq = A[pI * LD + qI];
+              const double tt = rI.y / rI.x;
+              A[pI * LD + pI] -= tt * apq;
+              A[qI * LD + qI] += tt * apq;
             }
-            A[rI.p * LD + rI.q] = 0.0;
+            A[pI * LD + qI] = 0.0;
           }
         } else {
-          const Rot rJ = rt[J];
-          if (rI.s != 0.0 || rJ.s != 0.0) {
-            const int pI = rI.p, qI = rI.q, pJ = rJ.p, qJ = rJ.q;
-            const double cI = rI.c, sI = rI.s, cJ = rJ.c, sJ = rJ.s;
+          const double2 rJ = tab[J];
+          if (rI.y != 0.0 || rJ.y != 0.0) {
+            int pJ, qJ;
+            rr_pair(st, J, m, pJ, qJ);
+            const double cI = rI.x, sI = rI.y, cJ = rJ.x, sJ = rJ.y;
             const bool vqI = qI < n, vqJ = qJ < n;
             const int i00 = up<LD>(pI, pJ), i01 = up<LD>(pI, qJ), i10 = up<LD>(qI, pJ),
                       i11 = up<LD>(qI, qJ);
@@ -217,26 +257,26 @@ __device__ void jacobi_eig(double *A, double *V, int n, Rot *rt, double *red, in
           }
         }
       }
-      if (vk >= 0) {
-        const Rot r = rt[vk];
-        if (r.s != 0.0) {   // a rotation implies q < n
-#pragma unroll
-          for (int u = 0; u < MAXV; u++) {
-            const int i = r0 + R * u;
-            if (i < n) {
-              const double vp = V[i * LD + r.p], vq = V[i * LD + r.q];
-              V[i * LD + r.p] = r.c * vp - r.s * vq;
-              V[i * LD + r.q] = r.s * vp + r.c * vq;
-            }
-          }
-        }
-      }
       __syncthreads();
     }
-    const int any = *flag;
-    __syncthreads();
-    if (!any) break;
+    // would any pair rotate in another sweep?  (none did in this one: done)
+    bool more = false;
+    if (*flag) {
+      for (int e = tid; e < n * n; e += NT) {
+        const int p = e / n, q = e - p * n;
+        if (p < q) {
+          const double apq = A[p * LD + q];
+          if (apq != 0.0 &&
+              !(fabs(apq) <= 1e-17 * sqrt(fabs(A[p * LD + p] * A[q * LD + q])) ||
+                fabs(apq) <= absthr))
+            more = true;
+        }
+      }
+    }
+    if (!__syncthreads_or(more)) break;
   }
+  v_update(vr, vst);
+  __syncthreads();
 }
 
 // Pair-domain preparation, one workgroup of NT threads per domain of dimension
@@ -253,10 +293,11 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
   constexpr int LD = NM + 1;
   constexpr int HM = NM / 2;
   constexpr int MAXB = (HM * (HM + 1) / 2 + NT - 1) / NT;
-  constexpr int MAXV = (NM + NT / HM - 1) / (NT / HM);   // V rows per thread
+  constexpr int MAXV = (NM + (NT - 64) / HM - 1) / ((NT - 64) / HM);   // V rows per thread
+  static_assert(NT >= 128 && HM <= 64, "jacobi_eig needs a rotation wave and V waves");
   __shared__ double L1[NM * LD];
   __shared__ double L2[NM * LD];
-  __shared__ Rot rt[HM];
+  __shared__ double2 rt[HM];
   __shared__ double red[NT / 64];
   __shared__ int keep_idx[NM];
   __shared__ int s_dt, s_flag;
