@@ -287,7 +287,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
                                                     const double *__restrict__ S,
                                                     const double *__restrict__ F,
                                                     const double *__restrict__ K, long long ld,
-                                                    double tau_S, double *W, double *Y,
+                                                    double tau_S,
+                                                    const long long *__restrict__ dmoff,
+                                                    double *W, double *Y,
                                                     double *Kep, int *rank,
                                                     double *minev) {
   constexpr int LD = NM + 1;
@@ -384,6 +386,25 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       if (tid == 0) { s_dt = n; minev[dom_id] = 1.0 / tr; }
       __syncthreads();
       dt = n;
+      // warm start of the Fock eigensolve: X <- X diag(V_p, V_q) with the
+      // eigenvectors of the prepared diagonal domains, so that the p block of
+      // X^T F X is already diagonal and the q block nearly so (X^T S X = 1 still)
+      const long long mp = dmoff ? dmoff[D.p] : -1, mq = dmoff ? dmoff[D.q] : -1;
+      if (mp >= 0 && mq >= 0) {
+        const double *Vp = W + mp, *Vq = W + mq;
+        mma_tiles<NT>(n, n, n, [&](int i, int k) { return Yg[i * n + k]; },
+                      [&](int k, int j) {
+                        return k < rp ? (j < rp ? Vp[k * rp + j] : 0.0)
+                                      : (j >= rp ? Vq[(k - rp) * rq + (j - rp)] : 0.0);
+                      },
+                      [&](int i, int j, double v) { L1[i * LD + j] = v; });
+        __syncthreads();
+        for (int e = tid; e < n * n; e += NT) {
+          int i = e / n, j = e - i * n;
+          Yg[i * n + j] = L1[i * LD + j];
+        }
+        __syncthreads();
+      }
     } else {
       // eigenvalue cut of S_(pq,pq) = U s U^T: X = U_kept s_kept^{-1/2}
       for (int e = tid; e < n * n; e += NT) {
@@ -500,22 +521,22 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
 
 hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
                               const double *S, const double *F, const double *K, long long ld,
-                              double tau_S, double *W, double *Y, double *Kep,
-                              int *rank, double *minev, hipStream_t s) {
+                              double tau_S, const long long *diag_moff, double *W, double *Y,
+                              double *Kep, int *rank, double *minev, hipStream_t s) {
   // counts3: number of domains with n <= 32, 32 < n <= 64, 64 < n <= DMAX, in that
   // order in ids[]
   int o = 0;
   if (counts3[0] > 0)
     hipLaunchKernelGGL((k_domain_prep<32, 256>), dim3(counts3[0]), dim3(256), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, W, Y, Kep, rank, minev);
+                       K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
   o += counts3[0];
   if (counts3[1] > 0)
     hipLaunchKernelGGL((k_domain_prep<64, 1024>), dim3(counts3[1]), dim3(1024), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, W, Y, Kep, rank, minev);
+                       K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
   o += counts3[1];
   if (counts3[2] > 0)
     hipLaunchKernelGGL((k_domain_prep<DMAX, 1024>), dim3(counts3[2]), dim3(1024), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, W, Y, Kep, rank, minev);
+                       K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
   return hipGetLastError();
 }
 

@@ -378,6 +378,7 @@ struct osv_ctx {
   double *dEcl = nullptr, *dPl = nullptr, *dMaxres = nullptr, *dWts = nullptr, *dEout = nullptr;
   int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
   int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr;
+  long long *dDiagMoff = nullptr;  // per LMO p: W slot of domain (p, p), or -1
   Domain *dDom = nullptr;
   Coupling *dCpl = nullptr;
   CPair *dCp = nullptr;
@@ -596,19 +597,26 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = dalloc(ctx, &ctx->dKt, P.n_vec))) return rc;
   if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
   if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
-  int prep_cnt[3] = {0, 0, 0};
+  // prep order: diagonal domains (p, p), then the others, each by LDS size class
+  // (n <= 32, <= 64, <= DMAX); a domain (p, q) starts its eigensolve from the
+  // eigenvectors of (p, p) and (q, q)
+  int prep_cnt[6] = {0, 0, 0, 0, 0, 0};
   {
-    // domains by LDS size class (n <= 32, <= 64, <= DMAX)
     std::vector<int> ids;
-    for (int c = 0; c < 3; c++)
-      for (int d = 0; d < ndom; d++) {
-        int n = P.doms[d].n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
-        if (cls == c) {
-          ids.push_back(d);
-          prep_cnt[c]++;
+    std::vector<long long> dmoff((size_t)nocc, -1);
+    for (int g = 0; g < 2; g++)
+      for (int c = 0; c < 3; c++)
+        for (int d = 0; d < ndom; d++) {
+          const Domain &D = P.doms[d];
+          const int n = D.n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+          if (cls == c && (D.p == D.q) == (g == 0)) {
+            ids.push_back(d);
+            prep_cnt[3 * g + c]++;
+            if (g == 0) dmoff[D.p] = D.moff;
+          }
         }
-      }
     if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
+    if ((rc = upload(ctx, &ctx->dDiagMoff, dmoff, s))) return rc;
   }
   const bool digits = precision == OSV_MIXED && ctx->naux <= digit_max_k();
   if (digits) {
@@ -656,7 +664,12 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   // pair-domain preparation
   StageTimer t_prep(s);
   HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds, prep_cnt, ctx->dS, ctx->dF, ctx->dK, ld,
-                                 ctx->tau_S, ctx->dW, ctx->dY, ctx->dKt, ctx->dRank, ctx->dMinev, s));
+                                 ctx->tau_S, nullptr, ctx->dW, ctx->dY, ctx->dKt, ctx->dRank,
+                                 ctx->dMinev, s));
+  HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds + (prep_cnt[0] + prep_cnt[1] + prep_cnt[2]),
+                                 prep_cnt + 3, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S,
+                                 ctx->dDiagMoff, ctx->dW, ctx->dY, ctx->dKt, ctx->dRank,
+                                 ctx->dMinev, s));
   t_prep.stop();
 
   // clusters, terms and couplings on the host while the device works

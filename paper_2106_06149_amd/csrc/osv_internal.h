@@ -134,10 +134,13 @@ hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, i
 hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, long long ldb,
                               double *C, long long ldc, int M, int N, int K, double alpha,
                               hipStream_t s);
+// diag_moff (may be null): per LMO p the W slot of the prepared domain (p, p) or
+// -1; off-diagonal domains then start their Fock eigensolve from those
+// eigenvectors
 hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
                               const double *S, const double *F, const double *K, long long ld,
-                              double tau_S, double *W, double *Y, double *Kep, int *rank,
-                              double *minev, hipStream_t s);
+                              double tau_S, const long long *diag_moff, double *W, double *Y,
+                              double *Kep, int *rank, double *minev, hipStream_t s);
 // both orientations of every coupling, zero-padded (FP64 MFMA)
 hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
                             const int *rank, const double *S, long long ld, const double *W,
