@@ -565,60 +565,74 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
   constexpr int NWV = CNT / 64;
   // 1) G(i, j) = sum_k S_(A,B)(i, k) W_B(k, j); S_(A,B)(i, k) is read as S_(B,A)(k, i),
   //    which is contiguous in i for a fixed k (S holds both orientations of its blocks).
-  //    Every operand of a tile's whole k range is loaded before its MFMAs, so the
-  //    global loads are in flight together instead of one k-step at a time.
+  //    A wave keeps one column tile of W_B in registers for its whole k range and
+  //    walks down row tiles, loading each tile's S operands (its whole k range)
+  //    before their MFMAs.
   constexpr int KST = (DMAX + 3) / 4;   // k-steps of 4 covering DMAX
   const int ti = (A.n + 15) >> 4, tj = B.np >> 4;
-  for (int tile = wave; tile < ti * tj; tile += NWV) {
-    const int i0 = (tile / tj) * 16, j0 = (tile % tj) * 16;
-    const int i = i0 + l15, j = j0 + l15;
-    double av[KST], bv[KST];
+  {
+    const int grp = NWV / tj, jt = wave % tj, g = wave / tj;
+    if (g < grp) {
+      const int j = jt * 16 + l15;
+      double bv[KST];
 #pragma unroll
-    for (int st = 0; st < KST; st++) {
-      const int k = 4 * st + lhi;
-      av[st] = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
-      bv[st] = (j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
-    }
-    d4c acc = {0, 0, 0, 0};
+      for (int st = 0; st < KST; st++) {
+        const int k = 4 * st + lhi;
+        bv[st] = (j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
+      }
+      for (int it = g; it < ti; it += grp) {
+        double av[KST];
 #pragma unroll
-    for (int st = 0; st < KST; st++)
-      if (4 * st < B.n) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
-    // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
-    for (int v = 0; v < 4; v++) {
-      const int ii = i0 + 4 * v + lhi;
-      if (ii < A.n) G[ii * LDG + j] = acc[v];
+        for (int st = 0; st < KST; st++) {
+          const int k = 4 * st + lhi, i = it * 16 + l15;
+          av[st] = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
+        }
+        d4c acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < KST; st++)
+          if (4 * st < B.n) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
+        // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
+        for (int v = 0; v < 4; v++) {
+          const int ii = it * 16 + 4 * v + lhi;
+          if (ii < A.n) G[ii * LDG + j] = acc[v];
+        }
+      }
     }
   }
   __syncthreads();
   // 2) M(A,B)(a, b) = sum_k W_A(k, a) G(k, b) and M(B,A)(b, a) = sum_k G(k, b) W_A(k, a)
-  //    over the padded ranges (W_A columns beyond dt_A and G columns beyond dt_B are 0)
-  const int ta = A.np >> 4, tb = B.np >> 4, nt1 = ta * tb;
+  //    over the padded ranges (W_A columns beyond dt_A and G columns beyond dt_B are 0).
+  //    A wave keeps one column tile of W_A in registers and walks over column tiles
+  //    of G; each G fragment read from LDS feeds both orientations.
+  const int ta = A.np >> 4, tb = B.np >> 4;
   double *Mab = M + c.offAB, *Mba = M + c.offBA;
-  for (int tile = wave; tile < 2 * nt1; tile += NWV) {
-    const bool tr = tile >= nt1;
-    const int t2 = tr ? tile - nt1 : tile;
-    const int a0 = (t2 / tb) * 16, b0 = (t2 % tb) * 16;
-    const int a = a0 + l15, b = b0 + l15;
-    double wv[KST];
+  {
+    const int grp = NWV / ta, at = wave % ta, g = wave / ta;
+    if (g < grp) {
+      const int a0 = at * 16, a = a0 + l15;
+      double wv[KST];
 #pragma unroll
-    for (int st = 0; st < KST; st++) {
-      const int k = 4 * st + lhi;
-      wv[st] = (a < dtA && k < A.n) ? WA[k * A.n + a] : 0.0;
-    }
-    d4c acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int st = 0; st < KST; st++) {
-      if (4 * st < A.n) {
+      for (int st = 0; st < KST; st++) {
         const int k = 4 * st + lhi;
-        const double g = (k < A.n) ? G[k * LDG + b] : 0.0;
-        acc = tr ? __builtin_amdgcn_mfma_f64_16x16x4f64(g, wv[st], acc, 0, 0, 0)
-                 : __builtin_amdgcn_mfma_f64_16x16x4f64(wv[st], g, acc, 0, 0, 0);
+        wv[st] = (a < dtA && k < A.n) ? WA[k * A.n + a] : 0.0;
       }
-    }
-    if (!tr) {
-      for (int v = 0; v < 4; v++) Mab[(long long)(a0 + 4 * v + lhi) * B.np + b] = acc[v];
-    } else {
-      for (int v = 0; v < 4; v++) Mba[(long long)(b0 + 4 * v + lhi) * A.np + a] = acc[v];
+      for (int bt = g; bt < tb; bt += grp) {
+        const int b0 = bt * 16, b = b0 + l15;
+        d4c acc = {0, 0, 0, 0}, acct = {0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < KST; st++) {
+          if (4 * st < A.n) {
+            const int k = 4 * st + lhi;
+            const double gv = (k < A.n) ? G[k * LDG + b] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[st], gv, acc, 0, 0, 0);
+            acct = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, wv[st], acct, 0, 0, 0);
+          }
+        }
+        for (int v = 0; v < 4; v++) {
+          Mab[(long long)(a0 + 4 * v + lhi) * B.np + b] = acc[v];
+          Mba[(long long)(b0 + 4 * v + lhi) * A.np + a] = acct[v];
+        }
+      }
     }
   }
 }
