@@ -380,6 +380,24 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         }
       }
     }
+    // Warm start: pairs with init >= 0 take the final amplitudes of the same pair
+    // from a cluster of an earlier launch, the others start from zero; the
+    // sweeps then take the terms from sweep 0 on.
+    bool warm = false;
+    for (int c = 0; c < cl.ncp; c++) warm = warm || a.cp[cl.cp0 + c].init >= 0;
+    if (warm) {
+      for (int c = 0; c < cl.ncp; c++) {
+        const CPair P = a.cp[cl.cp0 + c];
+        const int np = a.dom[P.dom].np;
+        double *T = a.T + P.toff;
+        if (P.init >= 0) {
+          const double *S0 = a.T + P.init;
+          for (int e = tid; e < 2 * np * np; e += SNT) T[e] = S0[e];
+        } else {
+          for (int e = tid; e < 2 * np * np; e += SNT) T[e] = 0.0;
+        }
+      }
+    }
     int sweep = 0, cur = 0;   // cur: the buffer holding the current amplitudes
     double maxn = 0.0, E = 0.0;
     bool pmode = false;  // after convergence: the pass for energies and dE/df
@@ -413,7 +431,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       Producer pr;
       pr.c = 0;
       pr.ncp = cl.ncp;
-      pr.use_terms = (sweep > 0 || pmode) ? 1 : 0;
+      pr.use_terms = (sweep > 0 || pmode || warm) ? 1 : 0;
       pr.use_epi = pmode ? 0 : 1;
       double *const Tcur = cur ? a.T2 : a.T, *const Tnext = cur ? a.T : a.T2;
       pr.Tb = Tcur;
@@ -551,8 +569,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
                   for (int v = 0; v < 4; v++) {
                     const int jl = lhi + 4 * v, j = jb * 16 + jl;
                     const double delta = ei + ev[j];
-                    // T~(i, j) from the T~^T row j (zero in sweep 0)
-                    const double tij = sweep > 0 ? st[(16 + jl) * RS + i] : 0.0;
+                    // T~(i, j) from the T~^T row j (zero in a cold sweep 0)
+                    const double tij = (sweep > 0 || warm) ? st[(16 + jl) * RS + i] : 0.0;
                     const double r = Racc[s][jb][v] + st[jl * RS + i] + delta * tij;
                     const bool in = (i < nt) && (j < nt);
                     const double tn = in ? tij - r / delta : 0.0;
@@ -670,7 +688,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         break;
       }
       if (maxn < a.tau_R || maxn != maxn || sweep >= a.max_sweeps) {
-        if (sweep == 0) {
+        if (sweep == 0 && !warm) {
           // stopped before any step: the final amplitudes are zero
           for (int c = 0; c < cl.ncp; c++) {
             const TgtDesc P = ds.target(c);
@@ -717,19 +735,23 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
 // Clusters whose descriptors fit the LDS tables run in the DLDS instantiation;
 // the queue holds the others first (cost order puts large clusters there), so
 // a.queue[0 .. n_big) goes to the global-descriptor instantiation with
-// counter[0] and the rest to the LDS one with counter[1].
-hipError_t launch_solve(const SolveArgs &a, int n_big, int nwg, hipStream_t s) {
+// counter[0] and the rest to the LDS one in two launches, [n_big, n_first) with
+// counter[1] and [n_first, n) with counter[2]: clusters of the second launch may
+// start from amplitudes the first one wrote.
+hipError_t launch_solve(const SolveArgs &a, int n_big, int n_first, int nwg, hipStream_t s) {
   if (a.n_clusters <= 0) return hipSuccess;
   if (n_big > 0) {
     SolveArgs b = a;
     b.n_clusters = n_big;
     hipLaunchKernelGGL(k_solve<false>, dim3(nwg < n_big ? nwg : n_big), dim3(SNT), 0, s, b);
   }
-  if (a.n_clusters > n_big) {
+  const int bounds[3] = {n_big, n_first, a.n_clusters};
+  for (int g = 0; g < 2; g++) {
+    if (bounds[g + 1] <= bounds[g]) continue;
     SolveArgs b = a;
-    b.queue = a.queue + n_big;
-    b.n_clusters = a.n_clusters - n_big;
-    b.counter = a.counter + 1;
+    b.queue = a.queue + bounds[g];
+    b.n_clusters = bounds[g + 1] - bounds[g];
+    b.counter = a.counter + 1 + g;
     hipLaunchKernelGGL(k_solve<true>, dim3(nwg < b.n_clusters ? nwg : b.n_clusters), dim3(SNT), 0, s, b);
   }
   return hipGetLastError();

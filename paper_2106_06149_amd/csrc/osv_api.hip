@@ -13,6 +13,7 @@
 #include <numeric>
 #include <string>
 #include <unordered_map>
+#include <unordered_map>
 #include <vector>
 
 using namespace osv;
@@ -133,6 +134,7 @@ struct Plan {
   long long n_pl = 0;     // dE/dF inner-product doubles
   int64_t n_pair_blocks = 0;
   int n_big = 0;          // leading queue entries too large for the LDS tables
+  int n_first = 0;        // end of the queue's first LDS launch (clusters of <= 2 LMOs)
 };
 
 // Builds the pair domains of the plan (all the S/F/K blocks and the domain
@@ -264,6 +266,7 @@ void build_clusters(int nocc, const Selection &s, Plan &P) {
         cp.lb = b;
         cp.w = (a == b) ? 1 : 2;
         cp.toff = P.n_T;
+        cp.init = -1;
         const long long np = P.doms[cp.dom].np;
         P.n_T += 2 * np * np;
         lpair[(size_t)a * nl + b] = lpair[(size_t)b * nl + a] = (int)P.cps.size();
@@ -336,6 +339,49 @@ void build_clusters(int nocc, const Selection &s, Plan &P) {
   };
   auto mid = std::stable_partition(P.queue.begin(), P.queue.end(), big);
   P.n_big = (int)(mid - P.queue.begin());
+  // Warm start of the 3-LMO clusters: they run after the 1- and 2-LMO clusters
+  // (a second launch), and each of their pairs starts from the final amplitudes of
+  // the same pair in a 2-LMO cluster of the same LMOs (p < q: the cluster {p, q};
+  // p = q: the cluster of p with the next LMO of the triple), which live in the
+  // same pair-domain basis.  The fixed point, and so the converged result, does
+  // not depend on the start.
+  {
+    std::unordered_map<long long, int> two;   // (p, q), p < q -> 2-LMO cluster
+    for (int X = 0; X < ncl; X++)
+      if (P.cls[X].nlmo == 2) {
+        const int p = s.lmo[P.cls[X].lmo0], q = s.lmo[P.cls[X].lmo0 + 1];
+        two[(long long)std::min(p, q) * nocc + std::max(p, q)] = X;
+      }
+    // slot of pair (p, q) in the 2-LMO cluster {u, v} (-1 if that cluster is absent)
+    auto slot = [&](int u, int v, int p, int q) -> long long {
+      auto it = two.find((long long)std::min(u, v) * nocc + std::max(u, v));
+      if (it == two.end()) return -1;
+      const Cluster &C = P.cls[it->second];
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+        const int a = s.lmo[C.lmo0 + P.cps[c].la], b = s.lmo[C.lmo0 + P.cps[c].lb];
+        if ((a == p && b == q) || (a == q && b == p)) return P.cps[c].toff;
+      }
+      return -1;
+    };
+    for (int X = 0; X < ncl; X++) {
+      const Cluster &C = P.cls[X];
+      if (C.nlmo != 3 || C.ncp > SOLVE_MAXT || C.term1 - C.term0 > SOLVE_MAXTERM) continue;
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+        CPair &cp = P.cps[c];
+        const int p = s.lmo[C.lmo0 + cp.la], q = s.lmo[C.lmo0 + cp.lb];
+        if (p != q) {
+          cp.init = slot(p, q, p, q);
+        } else {
+          const int o1 = s.lmo[C.lmo0 + (cp.la + 1) % 3], o2 = s.lmo[C.lmo0 + (cp.la + 2) % 3];
+          cp.init = slot(p, o1, p, p);
+          if (cp.init < 0) cp.init = slot(p, o2, p, p);
+        }
+      }
+    }
+    auto first = [&](int x) { return P.cls[x].nlmo <= 2; };
+    auto mid2 = std::stable_partition(P.queue.begin() + P.n_big, P.queue.end(), first);
+    P.n_first = (int)(mid2 - P.queue.begin());
+  }
 }
 
 int build_plan(int nocc, const Selection &s, const int *r, const int *off, Plan &P,
@@ -723,7 +769,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = dalloc(ctx, &ctx->dPl, P.n_pl))) return rc;
   if ((rc = dalloc(ctx, &ctx->dMaxres, ncl))) return rc;
   if ((rc = dalloc(ctx, &ctx->dSweeps, ncl))) return rc;
-  if ((rc = dalloc(ctx, &ctx->dCounter, 2))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dCounter, 3))) return rc;
   // MBE weights: E, E_1b, dE_2b, dE_3b
   {
     std::vector<double> w((size_t)4 * ncl, 0.0);
@@ -923,8 +969,8 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   a.tau_R = tau_R;
   a.max_sweeps = max_sweeps;
   StageTimer t(s);
-  HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 2, s));
-  HIPCHK(ctx, launch_solve(a, P.n_big, ctx->nwg, s));
+  HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 3, s));
+  HIPCHK(ctx, launch_solve(a, P.n_big, P.n_first, ctx->nwg, s));
   t.stop();
   // host bookkeeping while the kernel runs
   count_flops(ctx);
@@ -939,7 +985,14 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   inf.converged = 1;
   bool nonfinite = false;
   double fs = 0;
-  for (int X = 0; X < ncl; X++) fs += ctx->flops_sweep[X] * sw[X];
+  // a cluster that stops at sweep s has taken the terms in sweeps 1..s, and also
+  // in sweep 0 when it started from amplitudes of an earlier launch
+  for (int X = 0; X < ncl; X++) {
+    const Cluster &C = P.cls[X];
+    bool warm = false;
+    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) warm = warm || P.cps[c].init >= 0;
+    fs += ctx->flops_sweep[X] * (sw[X] + (warm ? 1 : 0));
+  }
   ctx->stage_flops[4] = fs;
   for (int X = 0; X < ncl; X++) {
     inf.sweeps = std::max(inf.sweeps, sw[X]);

@@ -55,6 +55,9 @@ struct CPair {
   int w;              // 1 for p == q, 2 for p < q (ordered-pair multiplicity)
   long long toff;     // offset of the amplitude slots: T~ (np x np, ld np) at toff,
                       // T~^T at toff + np*np; zero beyond the kept rank
+  long long init;     // amplitude slots of the same pair in a cluster solved by an
+                      // earlier launch (its final amplitudes start this pair's
+                      // sweeps), or -1: the sweeps start from zero
 };
 
 struct Cluster {
@@ -97,7 +100,8 @@ struct SolveArgs {
   int *sweeps;          // [n_clusters]
   double *maxres;       // [n_clusters]
   const int *queue;     // cluster order (cost descending)
-  int *counter;         // work-queue heads (two: large clusters, then the rest)
+  int *counter;         // work-queue heads (three: large clusters, clusters of <= 2
+                        // LMOs, the rest)
   int n_clusters;
   double tau_R;
   int max_sweeps;
@@ -145,7 +149,10 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
 hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
                             const int *rank, const double *S, long long ld, const double *W,
                             double *M, hipStream_t s);
-hipError_t launch_solve(const SolveArgs &a, int n_big, int nwg, hipStream_t s);
+// queue: [0, n_big) global descriptors; [n_big, n_first) and [n_first, n) LDS
+// descriptors in two launches (the second one's clusters may start from amplitudes
+// of the first one's)
+hipError_t launch_solve(const SolveArgs &a, int n_big, int n_first, int nwg, hipStream_t s);
 hipError_t launch_term_flat(const Term *terms, long long nterms, const CPair *cp,
                             const Coupling *cpl, const Domain *dom, const int *rank,
                             const double *F_occ, int nocc, TermFlat *out, hipStream_t s);

@@ -65,6 +65,17 @@ def test_ragged_tiles_fp64():
     compare(s, g, ref)
 
 
+def test_five_and_six_block_targets_fp64():
+    """Pair domains of 65-96 functions (5 and 6 column blocks of 16): the solve
+    shares the blocks past the fourth between waves in its plain sweeps."""
+    s = synth.make_system(5, 220, 120, [45, 48, 40, 47, 30], seed=33, cut2=4.5, cut3=4.5)
+    say("case 5/6-block targets nocc=5 nvir=220 naux=120 r=[45,48,40,47,30]")
+    g = run_gpu(s)
+    assert g["info"]["sweeps"] >= 3
+    ref = O.solve(s)
+    compare(s, g, ref)
+
+
 def test_workload0_full_osv_mp2():
     s = synth.workload(0)
     say("case workload 0: full OSV-MP2 nocc=6 nvir=60 naux=150 r=8")
