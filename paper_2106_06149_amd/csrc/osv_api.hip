@@ -32,9 +32,11 @@ struct Selection {
 };
 
 // MBE(3) selection (downward closed) and inclusion-exclusion coefficients:
-// c = 1 (3b), 1 - n3(IJ) (2b), 1 - n2(I) + n3(I) (1b).  keep2/keep3 decide.
-template <class K2, class K3>
-void select_mbe(int nocc, K2 keep2, K3 keep3, Selection &s) {
+// c = 1 (3b), 1 - n3(IJ) (2b), 1 - n2(I) + n3(I) (1b).  keep2/keep3 decide;
+// near3(i, j) must hold for every pair of a kept triple (a pre-filter: the
+// triples are searched over the selected pairs that pass it).
+template <class K2, class K3, class N3>
+void select_mbe(int nocc, K2 keep2, K3 keep3, N3 near3, Selection &s) {
   std::vector<std::pair<int, int>> pairs;
   std::vector<std::vector<int>> nbr(nocc);
   std::vector<char> sel((size_t)nocc * nocc, 0);
@@ -42,14 +44,14 @@ void select_mbe(int nocc, K2 keep2, K3 keep3, Selection &s) {
     for (int j = i + 1; j < nocc; j++)
       if (keep2(i, j)) {
         pairs.push_back({i, j});
-        nbr[i].push_back(j);
+        if (near3(i, j)) nbr[i].push_back(j);
         sel[(size_t)i * nocc + j] = 1;
       }
   std::vector<std::array<int, 3>> triples;
   for (int i = 0; i < nocc; i++)
     for (int j : nbr[i])
       for (int k : nbr[j])
-        if (sel[(size_t)i * nocc + k] && keep3(i, j, k)) triples.push_back({i, j, k});
+        if (sel[(size_t)i * nocc + k] && near3(i, k) && keep3(i, j, k)) triples.push_back({i, j, k});
   // nbr lists are ascending, so triples come out lexicographic
   s.n2.assign(nocc, 0);
   s.n3i.assign(nocc, 0);
@@ -114,7 +116,7 @@ void select_distance(int nocc, const double *cen, double cut2, double cut3, Sele
       [&](int i, int j, int k) {
         return dist(cen, i, j) <= cut3 && dist(cen, i, k) <= cut3 && dist(cen, j, k) <= cut3;
       },
-      s);
+      [&](int i, int j) { return dist(cen, i, j) <= cut3; }, s);
 }
 
 // Structure derived from a selection: domains, couplings, cluster pairs, terms.
@@ -621,7 +623,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     select_mbe(
         nocc, [&](int i, int j) { return s2b(i, j) > sel->l2b; },
         [&](int i, int j, int k) { return (s2b(i, j) + s2b(i, k) + s2b(j, k)) / 3.0 > sel->l3b; },
-        ctx->sel);
+        [](int, int) { return true; }, ctx->sel);
   }
   {
     std::string err;
