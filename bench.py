@@ -53,7 +53,8 @@ def solve_source_hash():
 
 
 def measured_traffic(workload):
-    """HBM bytes per k_solve launch from the committed counter summary, or None
+    """HBM bytes of the solve stage (its k_solve launches) from the committed
+    counter summary, or None
     when there is none for this workload or the solve kernel has changed since
     the counters were taken (the summary records a hash of its sources)."""
     try:
@@ -69,7 +70,7 @@ def measured_traffic(workload):
     if kv.get("source_hash") != solve_source_hash() or kv.get("workload") != str(workload):
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_stage"])
     except (KeyError, ValueError):
         return None
 
