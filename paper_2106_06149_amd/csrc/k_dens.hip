@@ -18,13 +18,15 @@ namespace osv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int ANT = 256;             // threads per domain (4 wave64)
+constexpr int ANT = 512;             // threads per domain (8 wave64, two per SIMD)
 constexpr int ANW = ANT / 64;
 constexpr int ALD = DMAX + 1;        // odd LDS stride of the transform matrices
 constexpr int ARS = 130;             // LDS row stride of a staged amplitude row (>= 128)
 constexpr int ASTG = 32 * ARS;       // stage: T~ rows 0..15, T~^T rows 16..31
 constexpr int ANSTG = 3;             // ring stages (loads run two chunks ahead)
-constexpr int MAXTW = 13;            // 16x16 output tiles per wave (7 x 7 over 4 waves)
+constexpr int MAXTW = (49 + ANW - 1) / ANW;   // 16x16 output tiles per wave (7 x 7)
+constexpr int AROWS = 16 / ANW;      // rows of T~ (and of T~^T) each wave loads per chunk
+static_assert(ANW == 8, "the chunk wait below counts 2 * AROWS loads per wave");
 static_assert(ANSTG * ASTG <= 2 * DMAX * ALD, "the ring overlays the transform buffers");
 
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
@@ -32,7 +34,7 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 }
 
 // 16 rows of T~ and of T~^T (rows 16q..16q+15 of the slot pair at toff, np wide) into
-// a ring stage: 8 direct global-to-LDS loads per wave; lanes past the row end are
+// a ring stage: 2 AROWS direct global-to-LDS loads per wave; lanes past the row end are
 // clamped onto its last 16 bytes and fill LDS columns that are never read.
 __device__ __forceinline__ void adj_issue(const double *T, long long toff, int np, int q,
                                           double *ring, int stage) {
@@ -43,7 +45,7 @@ __device__ __forceinline__ void adj_issue(const double *T, long long toff, int n
   const int lbase = __builtin_amdgcn_readfirstlane(
       (int)(size_t)(__attribute__((address_space(3))) void *)ring + (stage * ASTG + wave * ARS) * 8);
 #pragma unroll
-  for (int u = 0; u < 4; u++) {
+  for (int u = 0; u < AROWS; u++) {
     __builtin_amdgcn_global_load_lds((const void *)(Ts + u * ANW * np),
                                      (__attribute__((address_space(3))) void *)(size_t)(lbase + u * ANW * ARS * 8),
                                      16, 0, 0);
@@ -97,9 +99,9 @@ __global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms
   if (nchunk > 0) issue_k(0);
   if (nchunk > 1) issue_k(1);
   for (long long k = 0; k < nchunk; k++) {
-    // this wave's loads of chunk k are done once at most the next chunk's 8 remain
+    // this wave's loads of chunk k are done once at most the next chunk's 4 remain
     if (k + 1 < nchunk)
-      asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     else
       asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (k + 2 < nchunk) issue_k(k + 2);
