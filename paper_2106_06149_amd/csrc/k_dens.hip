@@ -18,7 +18,7 @@ namespace osv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int ANT = 512;             // threads per domain (8 wave64, two per SIMD)
+constexpr int ANT = 1024;            // threads per domain (16 wave64, four per SIMD)
 constexpr int ANW = ANT / 64;
 constexpr int ALD = DMAX + 1;        // odd LDS stride of the transform matrices
 constexpr int ARS = 130;             // LDS row stride of a staged amplitude row (>= 128)
@@ -26,7 +26,7 @@ constexpr int ASTG = 32 * ARS;       // stage: T~ rows 0..15, T~^T rows 16..31
 constexpr int ANSTG = 3;             // ring stages (loads run two chunks ahead)
 constexpr int MAXTW = (49 + ANW - 1) / ANW;   // 16x16 output tiles per wave (7 x 7)
 constexpr int AROWS = 16 / ANW;      // rows of T~ (and of T~^T) each wave loads per chunk
-static_assert(ANW == 8, "the chunk wait below counts 2 * AROWS loads per wave");
+static_assert(ANW == 16, "the chunk wait below counts 2 * AROWS loads per wave");
 static_assert(ANSTG * ASTG <= 2 * DMAX * ALD, "the ring overlays the transform buffers");
 
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
@@ -99,9 +99,9 @@ __global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms
   if (nchunk > 0) issue_k(0);
   if (nchunk > 1) issue_k(1);
   for (long long k = 0; k < nchunk; k++) {
-    // this wave's loads of chunk k are done once at most the next chunk's 4 remain
+    // this wave's loads of chunk k are done once at most the next chunk's 2 remain
     if (k + 1 < nchunk)
-      asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      asm volatile("s_waitcnt vmcnt(2) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     else
       asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (k + 2 < nchunk) issue_k(k + 2);
