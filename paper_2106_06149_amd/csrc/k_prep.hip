@@ -540,12 +540,12 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
   return hipGetLastError();
 }
 
-// Couplings M(A,B) = W_A^T S_(A,B) W_B, one workgroup (8 wave64) per coupling,
+// Couplings M(A,B) = W_A^T S_(A,B) W_B, one workgroup (16 wave64) per coupling,
 // FP64 MFMA 16x16x4.  G = S_(A,B) W_B (n_A x np_B, zero beyond dt_B) is formed in
 // LDS; the product W_A^T G is then taken once per orientation, so that M(A,B)
 // and M(B,A) = M(A,B)^T are both written with row-contiguous stores over their
 // whole zero-padded np x np slots.
-constexpr int CNT = 512;          // threads per coupling workgroup
+constexpr int CNT = 1024;         // threads per coupling workgroup (16 waves)
 constexpr int LDG = 16 * 7 + 1;   // LDS stride of G (columns < np_B <= 112)
 typedef double d4c __attribute__((ext_vector_type(4)));
 
@@ -565,32 +565,39 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
   constexpr int NWV = CNT / 64;
   // 1) G(i, j) = sum_k S_(A,B)(i, k) W_B(k, j); S_(A,B)(i, k) is read as S_(B,A)(k, i),
   //    which is contiguous in i for a fixed k (S holds both orientations of its blocks).
-  //    A wave keeps one column tile of W_B in registers for its whole k range and
-  //    walks down row tiles, loading each tile's S operands (its whole k range)
-  //    before their MFMAs.
+  //    A wave keeps one row tile of S_(A,B) in registers for its whole k range and
+  //    walks over column tiles of W_B, loading each one's k range in two batches.
   constexpr int KST = (DMAX + 3) / 4;   // k-steps of 4 covering DMAX
+  constexpr int KH = (KST + 1) / 2;
   const int ti = (A.n + 15) >> 4, tj = B.np >> 4;
   {
-    const int grp = NWV / tj, jt = wave % tj, g = wave / tj;
+    const int grp = NWV / ti, it = wave % ti, g = wave / ti;
     if (g < grp) {
-      const int j = jt * 16 + l15;
-      double bv[KST];
+      const int i = it * 16 + l15;
+      double av[KST];
 #pragma unroll
       for (int st = 0; st < KST; st++) {
         const int k = 4 * st + lhi;
-        bv[st] = (j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
+        av[st] = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
       }
-      for (int it = g; it < ti; it += grp) {
-        double av[KST];
-#pragma unroll
-        for (int st = 0; st < KST; st++) {
-          const int k = 4 * st + lhi, i = it * 16 + l15;
-          av[st] = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
-        }
+      for (int jt = g; jt < tj; jt += grp) {
+        const int j = jt * 16 + l15;
         d4c acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int st = 0; st < KST; st++)
-          if (4 * st < B.n) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
+        for (int h = 0; h < 2; h++) {
+          double bv[KH];
+#pragma unroll
+          for (int u = 0; u < KH; u++) {
+            const int st = h * KH + u, k = 4 * st + lhi;
+            bv[u] = (st < KST && j < dtB && k < B.n) ? WB[k * B.n + j] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < KH; u++) {
+            const int st = h * KH + u;
+            if (st < KST && 4 * st < B.n)
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[u], acc, 0, 0, 0);
+          }
+        }
         // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
         for (int v = 0; v < 4; v++) {
           const int ii = it * 16 + 4 * v + lhi;
