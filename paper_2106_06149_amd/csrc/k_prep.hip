@@ -531,7 +531,7 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
                        K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
   o += counts3[0];
   if (counts3[1] > 0)
-    hipLaunchKernelGGL((k_domain_prep<64, 1024>), dim3(counts3[1]), dim3(1024), 0, s, dom, ids + o, S, F,
+    hipLaunchKernelGGL((k_domain_prep<64, 512>), dim3(counts3[1]), dim3(512), 0, s, dom, ids + o, S, F,
                        K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
   o += counts3[1];
   if (counts3[2] > 0)
