@@ -123,18 +123,20 @@ __global__ __launch_bounds__(256) void k_tile_f64(const TA *__restrict__ A, long
 //   C[i][j] = alpha sum_k A(i,k) B(k,j), or with WGT alpha sum_k A(i,k) w[k] B(k,j)
 // Eight waves (two per SIMD: one wave alone cannot keep the FP64 MFMA pipe busy),
 // each a 32x64 part of the tile as 2x4 MFMA 16x16x4 accumulators.
-// k advances in stages of 32 through two LDS buffers: the loads of stage s+1
-// (global_load_lds_dwordx4, 16 bytes per lane, no registers) are issued before
-// the MFMAs of stage s.  A [row][k] stage keeps a row's 32 doubles as sixteen
-// 16-byte slots, slot index XOR (row mod 16), so that the 16 rows of an operand
-// fragment spread over the LDS banks; a [k][j] stage pads its rows to 130 doubles.
+// k advances in stages of 16 through two LDS buffers (64 KB, so that two
+// workgroups share a CU): the loads of stage s+1 (global_load_lds_dwordx4, 16
+// bytes per lane, no registers) are issued before the MFMAs of stage s.  A
+// [row][k] stage keeps a row's 16 doubles as eight 16-byte slots, slot index XOR
+// (row mod 8), so that the 16 rows of an operand fragment spread over the LDS
+// banks; a [k][j] stage pads its rows to 130 doubles.
 // Rows and columns past M, N are clamped to the last valid one (they only feed
 // outputs that are not stored); k past K is clamped on load and zeroed in LDS.
 // Requirements (checked by the launchers): lda, ldb, K even, 16-byte aligned
 // A and B, and for BK == 1 also N even.
 // ---------------------------------------------------------------------------
 constexpr int G = 128;             // output tile edge
-constexpr int GKS = 32;            // k per stage (doubles)
+constexpr int GKS = 16;            // k per stage (doubles)
+constexpr int GSL = GKS / 2;       // 16-byte slots per row of a [row][k] stage
 constexpr int GRS = 130;           // LDS row stride of a [k][j] stage (doubles)
 constexpr int GA = G * GKS;        // doubles of a [row][k] stage
 constexpr int GB1 = GKS * GRS;     // doubles of a [k][j] stage
@@ -143,8 +145,8 @@ constexpr int GNT = 512;           // threads (8 waves)
 
 typedef __attribute__((address_space(3))) void *lds_ptr;
 
-// issue the loads of stage k0 into buffer (As_b, Bs_b): 32 blocks of 1 KB per
-// operand, four per wave
+// issue the loads of stage k0 into buffer (As_b, Bs_b): GKS blocks of 1 KB per
+// operand, GKS / 8 per wave
 template <int BK>
 __device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long long lda,
                                            const double *__restrict__ B, long long ldb, int i0,
@@ -152,10 +154,10 @@ __device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long lo
                                            double *Bs_b) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int v = 0; v < 4; v++) {
+  for (int v = 0; v < GKS / 8; v++) {
     const int u = wave + 8 * v;                 // 1 KB block of the stage
     const int p = u * 64 + lane;                // 16-byte slot in the stage
-    const int row = p >> 4, kp = (p & 15) ^ (row & 15);
+    const int row = p / GSL, kp = (p % GSL) ^ (row % GSL);
     const int gk = min(k0 + 2 * kp, K - 2);
     const int gi = min(i0 + row, M - 1);
     __builtin_amdgcn_global_load_lds((const void *)(A + (long long)gi * lda + gk),
@@ -216,9 +218,9 @@ __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, 
       // last, partial stage: zero k >= K
       const int kv = K - k0;
       for (int e = tid; e < G * GKS; e += GNT) {
-        const int row = e >> 5, k = e & 31;
+        const int row = e / GKS, k = e % GKS;
         if (k >= kv) {
-          const int idx = row * GKS + ((((k >> 1) ^ (row & 15))) << 1) + (k & 1);
+          const int idx = row * GKS + ((((k >> 1) ^ (row % GSL))) << 1) + (k & 1);
           Ab[idx] = 0.0;
           if (BK == 0) Bb[idx] = 0.0;
           else Bb[k * GRS + row] = 0.0;
@@ -233,12 +235,12 @@ __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, 
 #pragma unroll
       for (int a = 0; a < 2; a++) {
         const int row = wr + a * 16 + l15;
-        af[a] = Ab[row * GKS + ((((kk >> 1) ^ (row & 15))) << 1) + (kk & 1)];
+        af[a] = Ab[row * GKS + ((((kk >> 1) ^ (row % GSL))) << 1) + (kk & 1)];
       }
 #pragma unroll
       for (int b = 0; b < 4; b++) {
         const int col = wc + b * 16 + l15;
-        bf[b] = BK == 0 ? Bb[col * GKS + ((((kk >> 1) ^ (col & 15))) << 1) + (kk & 1)]
+        bf[b] = BK == 0 ? Bb[col * GKS + ((((kk >> 1) ^ (col % GSL))) << 1) + (kk & 1)]
                         : Bb[kk * GRS + col];
       }
       if (WGT) {
