@@ -617,19 +617,33 @@ hipError_t launch_wdot(const double *x, const double *w, long long n, int nw, do
   return hipGetLastError();
 }
 
-// out[a] = sum_y Qt[y][a] * Zt[y][a]  (column dot over nosv rows; one thread per a,
-// rows in order -> deterministic)
-__global__ void k_coldot(const double *Qt, const double *Zt, int nosv, int nvir, double *out) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
+// out[a] = sum_y Qt[y][a] * Zt[y][a] (column dot over nosv rows) in two passes:
+// part[c][a] sums the rows of chunk c (COLDOT_ROWS rows, in order), then out[a]
+// sums the chunks in order: deterministic.
+__global__ void k_coldot(const double *Qt, const double *Zt, int nosv, int nvir, double *part) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (a >= nvir) return;
+  const int y1 = min(nosv, (c + 1) * COLDOT_ROWS);
+  double s = 0.0;
+  for (int y = c * COLDOT_ROWS; y < y1; y++)
+    s += Qt[(long long)y * nvir + a] * Zt[(long long)y * nvir + a];
+  part[(long long)c * nvir + a] = s;
+}
+__global__ void k_coldot_sum(const double *part, int nchunk, int nvir, double *out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= nvir) return;
   double s = 0.0;
-  for (int y = 0; y < nosv; y++) s += Qt[(long long)y * nvir + a] * Zt[(long long)y * nvir + a];
+  for (int c = 0; c < nchunk; c++) s += part[(long long)c * nvir + a];
   out[a] = s;
 }
-hipError_t launch_coldot(const double *Qt, const double *Zt, int nosv, int nvir, double *out,
-                         hipStream_t s) {
+hipError_t launch_coldot(const double *Qt, const double *Zt, int nosv, int nvir, double *part,
+                         double *out, hipStream_t s) {
   if (nvir <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coldot, dim3((nvir + 255) / 256), dim3(256), 0, s, Qt, Zt, nosv, nvir,
+  const int nchunk = (nosv + COLDOT_ROWS - 1) / COLDOT_ROWS;
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_coldot, dim3((nvir + 255) / 256, nchunk), dim3(256), 0, s, Qt, Zt, nosv,
+                       nvir, part);
+  hipLaunchKernelGGL(k_coldot_sum, dim3((nvir + 255) / 256), dim3(256), 0, s, part, nchunk, nvir,
                      out);
   return hipGetLastError();
 }

@@ -443,6 +443,7 @@ struct osv_ctx {
   bool dens_ready = false;
   DensHost dh;
   double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
+  double *dColPart = nullptr;  // partial column sums of dE/deps
   double *dClcoef = nullptr;
   long long *dDptr = nullptr, *dDtoff = nullptr, *dBptr = nullptr, *dPptr = nullptr, *dPidx = nullptr;
   int *dBdom = nullptr, *dBpart = nullptr;
@@ -1150,6 +1151,9 @@ static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
   if ((rc = dalloc(ctx, &ctx->dGF, (size_t)ld * ld))) return rc;
   if ((rc = dalloc(ctx, &ctx->dGd, P.n_slot))) return rc;
   if ((rc = dalloc(ctx, &ctx->dZt, (size_t)N * ctx->nvir))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dColPart,
+                   (size_t)((N + COLDOT_ROWS - 1) / COLDOT_ROWS) * ctx->nvir)))
+    return rc;
   HIPCHK(ctx, launch_fill_f64(ctx->dGK, 0.0, ld * ld, s));
   HIPCHK(ctx, launch_fill_f64(ctx->dGF, 0.0, ld * ld, s));
   ctx->dens_ready = true;
@@ -1184,7 +1188,7 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
     // Z^T = G^F Q^T  (Q^T is row-major sum(r) x nvir)
     HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGF, ld, ctx->Q, 0, ctx->nvir, ctx->dZt, ctx->nvir, N, ctx->nvir, N,
                                    1.0, s));
-    if (dE_deps) HIPCHK(ctx, launch_coldot(ctx->Q, ctx->dZt, N, ctx->nvir, dE_deps, s));
+    if (dE_deps) HIPCHK(ctx, launch_coldot(ctx->Q, ctx->dZt, N, ctx->nvir, ctx->dColPart, dE_deps, s));
     if (Dvir_full)
       HIPCHK(ctx, launch_gemm_tn_f64(ctx->Q, ctx->nvir, ctx->dZt, ctx->nvir, Dvir_full, ctx->nvir, ctx->nvir,
                                      ctx->nvir, N, 1.0, s));

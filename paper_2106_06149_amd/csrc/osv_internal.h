@@ -174,7 +174,9 @@ hipError_t launch_assemble_gf(const Domain *dom, const long long *blk_ptr,
                               int nblocks, const int *off, const int *r, const double *Gd,
                               double *GF, long long ld, hipStream_t s);
 // dE/deps_a = sum_y Qt[y][a] Zt[y][a]
-hipError_t launch_coldot(const double *Qt, const double *Zt, int nosv, int nvir,
+// part: scratch of ceil(nosv / COLDOT_ROWS) * nvir doubles
+constexpr int COLDOT_ROWS = 64;
+hipError_t launch_coldot(const double *Qt, const double *Zt, int nosv, int nvir, double *part,
                          double *out, hipStream_t s);
 // dE/dF: out[u][v] = sum over clusters of c_X * Pl (CSR per entry, fixed order)
 hipError_t launch_pocc(const long long *ptr, const long long *idx, const double *coef,
