@@ -39,34 +39,47 @@ template <class K2, class K3, class N3>
 void select_mbe(int nocc, K2 keep2, K3 keep3, N3 near3, Selection &s) {
   std::vector<std::pair<int, int>> pairs;
   std::vector<std::vector<int>> nbr(nocc);
-  std::vector<char> sel((size_t)nocc * nocc, 0);
+  // near[i * nocc + j], i < j: the pair is selected and passes near3
+  std::vector<char> near((size_t)nocc * nocc, 0);
   for (int i = 0; i < nocc; i++)
     for (int j = i + 1; j < nocc; j++)
       if (keep2(i, j)) {
         pairs.push_back({i, j});
-        if (near3(i, j)) nbr[i].push_back(j);
-        sel[(size_t)i * nocc + j] = 1;
+        if (near3(i, j)) {
+          nbr[i].push_back(j);
+          near[(size_t)i * nocc + j] = 1;
+        }
       }
   std::vector<std::array<int, 3>> triples;
   for (int i = 0; i < nocc; i++)
     for (int j : nbr[i])
       for (int k : nbr[j])
-        if (sel[(size_t)i * nocc + k] && near3(i, k) && keep3(i, j, k)) triples.push_back({i, j, k});
+        if (near[(size_t)i * nocc + k] && keep3(i, j, k)) triples.push_back({i, j, k});
   // nbr lists are ascending, so triples come out lexicographic
   s.n2.assign(nocc, 0);
   s.n3i.assign(nocc, 0);
+  // pair index of (i, j), i < j: a dense table beside near (which is nocc^2
+  // bytes) while it stays small, else a hash map
+  const bool dense = (long long)nocc * nocc <= (1LL << 26);
+  std::vector<int> pdense(dense ? (size_t)nocc * nocc : 0, -1);
   std::unordered_map<long long, int> pidx;
   for (size_t t = 0; t < pairs.size(); t++) {
     s.n2[pairs[t].first]++;
     s.n2[pairs[t].second]++;
-    pidx[(long long)pairs[t].first * nocc + pairs[t].second] = (int)t;
+    const long long key = (long long)pairs[t].first * nocc + pairs[t].second;
+    if (dense) pdense[(size_t)key] = (int)t;
+    else pidx[key] = (int)t;
   }
+  auto pair_index = [&](int i, int j) {
+    const long long key = (long long)i * nocc + j;
+    return dense ? pdense[(size_t)key] : pidx[key];
+  };
   s.n3ij.assign(pairs.size(), 0);
   for (auto &t : triples) {
     for (int a = 0; a < 3; a++) s.n3i[t[a]]++;
-    s.n3ij[pidx[(long long)t[0] * nocc + t[1]]]++;
-    s.n3ij[pidx[(long long)t[0] * nocc + t[2]]]++;
-    s.n3ij[pidx[(long long)t[1] * nocc + t[2]]]++;
+    s.n3ij[pair_index(t[0], t[1])]++;
+    s.n3ij[pair_index(t[0], t[2])]++;
+    s.n3ij[pair_index(t[1], t[2])]++;
   }
   s.lmo_ptr.assign(1, 0);
   s.lmo.clear();
