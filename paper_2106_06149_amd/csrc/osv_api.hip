@@ -468,6 +468,7 @@ struct osv_ctx {
   double stage_ms[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double stage_flops[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<double> flops_sweep;  // per cluster: residual-term flops of one sweep
+  double flops_warm0 = 0.0;         // sum of flops_sweep over warm-started clusters
   std::vector<int> rank_host;
   ~osv_ctx() {
     // work still queued on the caller's stream may use these blocks: finish it
@@ -757,19 +758,6 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   HIPCHK(ctx, launch_couplings(ctx->dCpl, (int)P.cpls.size(), ctx->dDom, ctx->dRank, ctx->dS, ld, ctx->dW,
                                ctx->dM, s));
   t_cpl.stop();
-  ctx->rank_host.resize(ndom);
-  HIPCHK(ctx, hipMemcpyAsync(ctx->rank_host.data(), ctx->dRank, ndom * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  for (int d = 0; d < ndom; d++)
-    if (ctx->rank_host[d] < 1) {
-      return fail(ctx, OSV_E_DOMAIN, "pair domain (" + std::to_string(P.doms[d].p) + "," +
-                                         std::to_string(P.doms[d].q) + ") has rank 0 after the tau_S cut");
-    }
-  ctx->stage_ms[0] = t_sf.ms();
-  ctx->stage_ms[1] = t_k.ms();
-  ctx->stage_ms[2] = t_prep.ms();
-  ctx->stage_ms[3] = t_cpl.ms();
-
   // solve-time buffers
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
@@ -807,7 +795,20 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     if ((rc = upload(ctx, &ctx->dWts, w, s))) return rc;
     if ((rc = dalloc(ctx, &ctx->dEout, 4))) return rc;
   }
+  // the ranks (and the stage times) once the couplings and the term table are done;
+  // the host work above ran while they did
+  ctx->rank_host.resize(ndom);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->rank_host.data(), ctx->dRank, ndom * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  for (int d = 0; d < ndom; d++)
+    if (ctx->rank_host[d] < 1) {
+      return fail(ctx, OSV_E_DOMAIN, "pair domain (" + std::to_string(P.doms[d].p) + "," +
+                                         std::to_string(P.doms[d].q) + ") has rank 0 after the tau_S cut");
+    }
+  ctx->stage_ms[0] = t_sf.ms();
+  ctx->stage_ms[1] = t_k.ms();
+  ctx->stage_ms[2] = t_prep.ms();
+  ctx->stage_ms[3] = t_cpl.ms();
   return OSV_OK;
 }
 
@@ -947,6 +948,11 @@ static void count_flops(osv_ctx *ctx) {
         }
       }
       ctx->flops_sweep[X] = f;
+      // a cluster that starts from amplitudes of an earlier launch also takes the
+      // terms in its sweep 0
+      bool warm = false;
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) warm = warm || P.cps[c].init >= 0;
+      if (warm) ctx->flops_warm0 += f;
     }
   }
 
@@ -1000,15 +1006,10 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   osv_solve_info inf{};
   inf.converged = 1;
   bool nonfinite = false;
-  double fs = 0;
   // a cluster that stops at sweep s has taken the terms in sweeps 1..s, and also
   // in sweep 0 when it started from amplitudes of an earlier launch
-  for (int X = 0; X < ncl; X++) {
-    const Cluster &C = P.cls[X];
-    bool warm = false;
-    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) warm = warm || P.cps[c].init >= 0;
-    fs += ctx->flops_sweep[X] * (sw[X] + (warm ? 1 : 0));
-  }
+  double fs = ctx->flops_warm0;
+  for (int X = 0; X < ncl; X++) fs += ctx->flops_sweep[X] * sw[X];
   ctx->stage_flops[4] = fs;
   for (int X = 0; X < ncl; X++) {
     inf.sweeps = std::max(inf.sweeps, sw[X]);
