@@ -118,9 +118,10 @@ __device__ __forceinline__ int up(int a, int b) {
 // eigenvectors (columns).  Round-robin ordering: in step st the n/2 disjoint
 // pairs rotate simultaneously; A <- J^T A J is applied as independent 2x2 block
 // updates.  A step has two phases separated by barriers: (1) wave 0 forms the
-// step's rotation table while the other waves apply the previous step's
-// rotations to the rows of V (V is not read by the A updates), (2) every thread
-// updates its 2x2 blocks of A.
+// step's rotation table and applies each rotation to its own diagonal 2x2 block
+// while the other waves apply the previous step's rotations to the rows of V (V
+// is not read by the A updates), (2) every thread updates its off-diagonal 2x2
+// blocks of A.
 // A is read in full on entry; during the sweeps only its upper triangle is kept
 // (each 2x2 block is read and written once), so on return only the diagonal
 // (the eigenvalues) and the upper triangle are meaningful.
@@ -144,18 +145,19 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
   }
   const double absthr = 1e-18 * sqrt(block_sum<NT>(f2, red));
   if (n == 1) return;
-  // Each thread owns the same 2x2 blocks (I, J), I <= J < h, in every step (only
-  // the rotation table changes): block b = tid + NT u, row-major over the upper
-  // triangle of the h x h block grid.
-  const int nb = h * (h + 1) / 2;
+  // Each thread owns the same off-diagonal 2x2 blocks (I, J), I < J < h, in every
+  // step (only the rotation table changes): block b = tid + NT u, row-major over
+  // the strict upper triangle of the h x h block grid.  The diagonal blocks are
+  // updated by the rotation threads themselves.
+  const int nb = h * (h - 1) / 2;
   int bI[MAXB], bJ[MAXB];
 #pragma unroll
   for (int u = 0; u < MAXB; u++) {
     const int b = tid + NT * u;
     int I = 0, rem = b;
-    while (I < h && rem >= h - I) { rem -= h - I; I++; }
+    while (I < h && rem >= h - 1 - I) { rem -= h - 1 - I; I++; }
     bI[u] = (b < nb) ? I : -1;
-    bJ[u] = I + rem;
+    bJ[u] = I + 1 + rem;
   }
   // V entries: thread vt = tid - 64 of waves 1.. applies rotation k = vt mod h to
   // rows r0 + R u, r0 = vt / h, R = (NT - 64) / h (threads vt >= R h have none)
@@ -205,7 +207,13 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
               c = 1.0 / sqrt(t * t + 1.0);
               sv = t * c;
               *flag = 1;
+              // this pair's diagonal block: a_pp, a_qq take the rotation, and a_pq
+              // (zeroed below) is below the threshold when there is none
+              const double tt = sv / c;
+              A[p * LD + p] = app - tt * apq;
+              A[q * LD + q] = aqq + tt * apq;
             }
+            A[p * LD + q] = 0.0;
           }
         }
         tab[tid] = make_double2(c, sv);
@@ -224,37 +232,24 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
         const double2 rI = tab[I];
         int pI, qI;
         rr_pair(st, I, m, pI, qI);
-        if (I == J) {
-          // a_pq is zeroed (it is below the threshold when there is no rotation)
-          if (qI < n) {
-            if (rI.y != 0.0) {
-              const double apq = A[pI * LD + qI];
-              const double tt = rI.y / rI.x;
-              A[pI * LD + pI] -= tt * apq;
-              A[qI * LD + qI] += tt * apq;
-            }
-            A[pI * LD + qI] = 0.0;
-          }
-        } else {
-          const double2 rJ = tab[J];
-          if (rI.y != 0.0 || rJ.y != 0.0) {
-            int pJ, qJ;
-            rr_pair(st, J, m, pJ, qJ);
-            const double cI = rI.x, sI = rI.y, cJ = rJ.x, sJ = rJ.y;
-            const bool vqI = qI < n, vqJ = qJ < n;
-            const int i00 = up<LD>(pI, pJ), i01 = up<LD>(pI, qJ), i10 = up<LD>(qI, pJ),
-                      i11 = up<LD>(qI, qJ);
-            const double b00 = A[i00];
-            const double b01 = vqJ ? A[i01] : 0.0;
-            const double b10 = vqI ? A[i10] : 0.0;
-            const double b11 = (vqI && vqJ) ? A[i11] : 0.0;
-            const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
-            const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
-            A[i00] = r00 * cJ - r01 * sJ;
-            if (vqJ) A[i01] = r00 * sJ + r01 * cJ;
-            if (vqI) A[i10] = r10 * cJ - r11 * sJ;
-            if (vqI && vqJ) A[i11] = r10 * sJ + r11 * cJ;
-          }
+        const double2 rJ = tab[J];
+        if (rI.y != 0.0 || rJ.y != 0.0) {
+          int pJ, qJ;
+          rr_pair(st, J, m, pJ, qJ);
+          const double cI = rI.x, sI = rI.y, cJ = rJ.x, sJ = rJ.y;
+          const bool vqI = qI < n, vqJ = qJ < n;
+          const int i00 = up<LD>(pI, pJ), i01 = up<LD>(pI, qJ), i10 = up<LD>(qI, pJ),
+                    i11 = up<LD>(qI, qJ);
+          const double b00 = A[i00];
+          const double b01 = vqJ ? A[i01] : 0.0;
+          const double b10 = vqI ? A[i10] : 0.0;
+          const double b11 = (vqI && vqJ) ? A[i11] : 0.0;
+          const double r00 = cI * b00 - sI * b10, r01 = cI * b01 - sI * b11;
+          const double r10 = sI * b00 + cI * b10, r11 = sI * b01 + cI * b11;
+          A[i00] = r00 * cJ - r01 * sJ;
+          if (vqJ) A[i01] = r00 * sJ + r01 * cJ;
+          if (vqI) A[i10] = r10 * cJ - r11 * sJ;
+          if (vqI && vqJ) A[i11] = r10 * sJ + r11 * cJ;
         }
       }
       __syncthreads();
@@ -294,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
                                                     double *minev) {
   constexpr int LD = NM + 1;
   constexpr int HM = NM / 2;
-  constexpr int MAXB = (HM * (HM + 1) / 2 + NT - 1) / NT;
+  constexpr int MAXB = (HM * (HM - 1) / 2 + NT - 1) / NT;   // off-diagonal blocks per thread
   constexpr int MAXV = (NM + (NT - 64) / HM - 1) / ((NT - 64) / HM);   // V rows per thread
   static_assert(NT >= 128 && HM <= 64, "jacobi_eig needs a rotation wave and V waves");
   __shared__ double L1[NM * LD];
