@@ -338,21 +338,27 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     }
     bool chol_ok = true;
     for (int j = 0; j < rq; j++) chol_ok = chol_ok && (L1[j * LD + j] > 0.0);
-    // L^-1 by forward substitution, one column per thread (lower triangle of L2)
+    // L^-1 by forward substitution (lower triangle of L2): one column per team of
+    // 16 lanes of a wave, each row's dot product split over the team and summed
+    // by shuffles (fixed order); the team's first lane stores the element, which
+    // the team reads back in later rows (one wave: LDS operations stay in order)
     double tr = 0.0;
     if (chol_ok) {
-      for (int c = tid; c < rq; c += NT) {
+      const int team = tid >> 4, tl = tid & 15;
+      for (int c = team; c < rq; c += NT / 16) {
         for (int i = 0; i < rq; i++) {
-          double x;
-          if (i < c) {
-            x = 0.0;
-          } else {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int k = c; k < i; k++) s -= L1[i * LD + k] * L2[k * LD + c];
-            x = s / L1[i * LD + i];
+          double x = 0.0;
+          if (i >= c) {
+            double sd = 0.0;
+            for (int k = c + tl; k < i; k += 16) sd += L1[i * LD + k] * L2[k * LD + c];
+            for (int o = 8; o > 0; o >>= 1) sd += __shfl_xor(sd, o, 16);
+            x = ((i == c) ? 1.0 : 0.0) - sd;
+            x = x / L1[i * LD + i];
           }
-          L2[i * LD + c] = x;
-          tr += x * x;
+          if (tl == 0) {
+            L2[i * LD + c] = x;
+            tr += x * x;
+          }
         }
       }
     }
