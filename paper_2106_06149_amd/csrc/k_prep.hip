@@ -365,25 +365,23 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     tr = block_sum<NT>(tr, red);
     const bool gs = chol_ok && (1.0 / tr > tau_S * (2.0 - tau_S));
     if (gs) {
-      // X = [[1, -B Z], [0, Z]], Z = L^-T (upper): X into the Y slot (global scratch)
+      // X = [[1, -B Z], [0, Z]], Z = L^-T (upper): X into the Y slot (global scratch);
+      // the block -B Z (rp x rq) as FP64 MFMA tiles, the rest elementwise
       for (int e = tid; e < n * n; e += NT) {
         int i = e / n, j = e - i * n;
+        if (j >= rp && i < rp) continue;
         double x;
         if (j < rp) {
           x = (i == j) ? 1.0 : 0.0;
         } else {
-          const int jj = j - rp;
-          if (i < rp) {
-            double s = 0.0;
-            for (int k = 0; k <= jj; k++) s -= Bg[(long long)i * ld + k] * L2[jj * LD + k];
-            x = s;
-          } else {
-            const int ii = i - rp;
-            x = (ii <= jj) ? L2[jj * LD + ii] : 0.0;
-          }
+          const int jj = j - rp, ii = i - rp;
+          x = (ii <= jj) ? L2[jj * LD + ii] : 0.0;
         }
         Yg[i * n + j] = x;
       }
+      mma_tiles<NT>(rp, rq, rq, [&](int i, int k) { return Bg[(long long)i * ld + k]; },
+                    [&](int k, int jj) { return k <= jj ? L2[jj * LD + k] : 0.0; },
+                    [&](int i, int jj, double v) { Yg[i * n + rp + jj] = -v; });
       if (tid == 0) { s_dt = n; minev[dom_id] = 1.0 / tr; }
       __syncthreads();
       dt = n;
