@@ -125,7 +125,7 @@ __device__ __forceinline__ int up(int a, int b) {
 // A is read in full on entry; during the sweeps only its upper triangle is kept
 // (each 2x2 block is read and written once), so on return only the diagonal
 // (the eigenvalues) and the upper triangle are meaningful.
-// Threshold rule: |a_pq| <= 1e-17 sqrt(|a_pp a_qq|) or <= 1e-18 ||A||_F is set
+// Threshold rule: a_pq^2 <= 1e-34 |a_pp a_qq| or |a_pq| <= 1e-18 ||A||_F is set
 // to zero without a rotation.  After a sweep with rotations every pair is tested
 // against that rule; the solve ends when no pair would rotate (a further sweep
 // would change no diagonal element and no element of V).
@@ -198,7 +198,7 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
           const double apq = A[p * LD + q];
           if (apq != 0.0) {
             const double app = A[p * LD + p], aqq = A[q * LD + q];
-            if (!(fabs(apq) <= 1e-17 * sqrt(fabs(app * aqq)) || fabs(apq) <= absthr)) {
+            if (!(apq * apq <= 1e-34 * fabs(app * aqq) || fabs(apq) <= absthr)) {
               const double theta = (aqq - app) / (2.0 * apq);
               const double at = fabs(theta);
               double t;
@@ -209,9 +209,8 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
               *flag = 1;
               // this pair's diagonal block: a_pp, a_qq take the rotation, and a_pq
               // (zeroed below) is below the threshold when there is none
-              const double tt = sv / c;
-              A[p * LD + p] = app - tt * apq;
-              A[q * LD + q] = aqq + tt * apq;
+              A[p * LD + p] = app - t * apq;
+              A[q * LD + q] = aqq + t * apq;
             }
             A[p * LD + q] = 0.0;
           }
@@ -262,8 +261,7 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
         if (p < q) {
           const double apq = A[p * LD + q];
           if (apq != 0.0 &&
-              !(fabs(apq) <= 1e-17 * sqrt(fabs(A[p * LD + p] * A[q * LD + q])) ||
-                fabs(apq) <= absthr))
+              !(apq * apq <= 1e-34 * fabs(A[p * LD + p] * A[q * LD + q]) || fabs(apq) <= absthr))
             more = true;
         }
       }
