@@ -23,7 +23,7 @@ constexpr int ANW = ANT / 64;
 constexpr int ALD = DMAX + 1;        // odd LDS stride of the transform matrices
 constexpr int ARS = 130;             // LDS row stride of a staged amplitude row (>= 128)
 constexpr int ASTG = 32 * ARS;       // stage: T~ rows 0..15, T~^T rows 16..31
-constexpr int ANSTG = 3;             // ring stages (loads run two chunks ahead)
+constexpr int ANSTG = 4;             // ring stages (loads run three chunks ahead)
 constexpr int MAXTW = (49 + ANW - 1) / ANW;   // 16x16 output tiles per wave (7 x 7)
 constexpr int AROWS = 16 / ANW;      // rows of T~ (and of T~^T) each wave loads per chunk
 static_assert(ANW == 16, "the chunk wait below counts 2 * AROWS loads per wave");
@@ -96,15 +96,20 @@ __global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms
     const long long en = e0 + k / tn;
     adj_issue(Tall, dcp_toff[en], np, (int)(k % tn), buf, (int)(k % ANSTG));
   };
-  if (nchunk > 0) issue_k(0);
-  if (nchunk > 1) issue_k(1);
+  for (int k = 0; k < ANSTG - 1; k++)
+    if (k < nchunk) issue_k(k);
   for (long long k = 0; k < nchunk; k++) {
-    // this wave's loads of chunk k are done once at most the next chunk's 2 remain
-    if (k + 1 < nchunk)
+    // this wave's loads of chunk k are done once at most those of the chunks issued
+    // after it (2 loads each, up to two chunks) remain; then every wave is done
+    // with the stage the next issue overwrites
+    const long long later = nchunk - 1 - k;
+    if (later >= 2)
+      asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else if (later == 1)
       asm volatile("s_waitcnt vmcnt(2) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     else
       asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (k + 2 < nchunk) issue_k(k + 2);
+    if (k + ANSTG - 1 < nchunk) issue_k(k + ANSTG - 1);
     const long long en = e0 + k / tn;
     const int q = (int)(k % tn);
     const double c = dcp_coef[en], c2 = 2.0 * c;
