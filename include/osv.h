@@ -114,7 +114,7 @@ typedef struct {
 } osv_counts;
 
 typedef struct {
-  int32_t sweeps;            /* largest number of Jacobi sweeps of any cluster          */
+  int32_t sweeps;            /* largest number of Jacobi steps of any cluster           */
   double max_residual;       /* largest final max_pairs ||W^T R W||_F of any cluster    */
   int32_t converged;         /* 1 if every cluster met tau_R                             */
   int64_t n_not_converged;   /* clusters that hit max_sweeps                             */
@@ -144,9 +144,12 @@ int osv_query(const osv_ctx *ctx, osv_counts *out);
 /*
  * osv_solve_clusters -- solve eq:rij for every cluster (k restricted to the
  * cluster's LMOs) by Jacobi sweeps preconditioned in each domain's
- * pseudo-canonical basis, starting from T = 0.  A cluster stops when the
+ * pseudo-canonical basis.  Clusters of one or two LMOs start from T = 0; each
+ * pair of a three-LMO cluster starts from the converged amplitudes of the same
+ * pair in one of its two-LMO clusters (solved first).  A cluster stops when the
  * largest ||W^T R W||_F over its pairs is below tau_R; its amplitudes are those
- * at which that residual was evaluated.  Also evaluates each cluster's
+ * at which that residual was evaluated, and info->sweeps counts the Jacobi steps
+ * taken (the largest over the clusters).  Also evaluates each cluster's
  * Hylleraas energy (eq:ec) and the inner products that dE/dF_occ needs.
  *   tau_R       convergence threshold (e.g. 1e-10); max_sweeps >= 1.
  *   info        host, may be NULL.
