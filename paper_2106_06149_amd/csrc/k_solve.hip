@@ -138,8 +138,8 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 // Producer of the chunk stream of one sweep of a cluster.  For every target pair
 // (in cluster order): the chunks of its terms (term t: nkb pass-1 chunks holding
-// op(T) rows and M(src,tgt) rows 16q.., then nkb pass-2 chunks holding M(src,tgt)
-// rows), then, unless this is the P pass, njb epilogue chunks holding K~^T rows,
+// op(T) rows and M(src,tgt) rows 16q.., then ceil(nkb / 2) pass-2 chunks holding
+// the M(src,tgt) rows of two 16-row tiles), then, unless this is the P pass, njb epilogue chunks holding K~^T rows,
 // T~^T rows and e~.  Every field is wave-uniform.
 struct Producer {
   int c, ncp;           // target pair, pairs in the cluster
@@ -168,7 +168,7 @@ __device__ __forceinline__ void next_target(const Desc<DLDS> &ds, Producer &p) {
     if (p.t < p.tend) {
       const TermFlat f = ds.term(p.t);
       p.nkb = uni((f.ns + 15) >> 4);
-      p.nq = 2 * p.nkb;
+      p.nq = p.nkb + ((p.nkb + 1) >> 1);
       p.ldT = uni(f.ldT);
       p.ldM = uni(f.ldM);
       p.tsrc = f.tsrc;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void advance(const Desc<DLDS> &ds, Producer &p) {
     if (++p.t < p.tend) {
       const TermFlat f = ds.term(p.t);
       p.nkb = uni((f.ns + 15) >> 4);
-      p.nq = 2 * p.nkb;
+      p.nq = p.nkb + ((p.nkb + 1) >> 1);
       p.ldT = uni(f.ldT);
       p.ldM = uni(f.ldM);
       p.tsrc = f.tsrc;
@@ -210,7 +210,7 @@ __device__ __forceinline__ void advance(const Desc<DLDS> &ds, Producer &p) {
 }
 
 // Issue the producer's chunk into a ring stage and advance; returns the number of
-// load instructions each wave issued for it (8 pass 1, 4 pass 2, 9 epilogue,
+// load instructions each wave issued for it (8 pass 1, 8 or 4 pass 2, 9 epilogue,
 // 0 past the end).  Every lane takes part: lane l moves doubles 2l, 2l+1 of a row,
 // clamped to the row's last 16 bytes, so lanes past the row end only fill LDS
 // columns that are never read.  stage_off is the stage's LDS byte offset from the
@@ -225,22 +225,42 @@ __device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, P
                         wave * RS * 8);
   int cnt;
   if (!p.epi) {
-    const bool p1 = p.q < p.nkb;
-    const int c = p1 ? p.q : p.q - p.nkb;
     const int ldT = p.ldT, ldM = p.ldM;
-    const double *Tg = p.Tb + p.tsrc + (16 * c + wave) * ldT + min(2 * lane, ldT - 2);
-    const double *Mg = a.M + p.moff + (16 * c + wave) * ldM + min(2 * lane, ldM - 2);
+    if (p.q < p.nkb) {
+      // pass 1: rows 16q.. of op(T) into stage rows 0..15, of M into rows 16..31
+      const int c = p.q;
+      const double *Tg = p.Tb + p.tsrc + (16 * c + wave) * ldT + min(2 * lane, ldT - 2);
+      const double *Mg = a.M + p.moff + (16 * c + wave) * ldM + min(2 * lane, ldM - 2);
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-      if (p1)
+      for (int u = 0; u < 4; u++) {
         __builtin_amdgcn_global_load_lds((const void *)(Tg + u * NW * ldT),
                                          (__attribute__((address_space(3))) void *)(size_t)(lbase + u * NW * RS * 8),
                                          16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void *)(Mg + u * NW * ldM),
-                                       (__attribute__((address_space(3))) void *)(size_t)(lbase + (16 + u * NW) * RS * 8),
-                                       16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(Mg + u * NW * ldM),
+                                         (__attribute__((address_space(3))) void *)(size_t)(lbase + (16 + u * NW) * RS * 8),
+                                         16, 0, 0);
+      }
+      cnt = 8;
+    } else {
+      // pass 2: M rows of tiles 2c and 2c + 1 (if there is one) into stage rows
+      // 0..15 and 16..31
+      const int c = p.q - p.nkb;
+      const bool two = 2 * c + 1 < p.nkb;
+      const double *Mg = a.M + p.moff + (32 * c + wave) * ldM + min(2 * lane, ldM - 2);
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        __builtin_amdgcn_global_load_lds((const void *)(Mg + u * NW * ldM),
+                                         (__attribute__((address_space(3))) void *)(size_t)(lbase + u * NW * RS * 8),
+                                         16, 0, 0);
+      if (two) {
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          __builtin_amdgcn_global_load_lds((const void *)(Mg + (16 + u * NW) * ldM),
+                                           (__attribute__((address_space(3))) void *)(size_t)(lbase + (16 + u * NW) * RS * 8),
+                                           16, 0, 0);
+      }
+      cnt = two ? 8 : 4;
     }
-    cnt = p1 ? 8 : 4;
   } else {
     const int np = p.np;
     const int col = min(2 * lane, np - 2);
@@ -505,11 +525,14 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
               }
             }
           }
-          // pass 2: R~^T(:, i-blocks) += M X'(:, i-blocks), X' tile kc per chunk
+          // pass 2: R~^T(:, i-blocks) += M X'(:, i-blocks), X' tile kc; a chunk
+          // holds the M rows of two tiles
+          const double *mst = nullptr;
 #pragma unroll
           for (int kc = 0; kc < MT; kc++) {
             if (kc < nkb) {
-              const double *mc = next_chunk(a, ds, pr, rg) + 16 * RS;
+              if ((kc & 1) == 0) mst = next_chunk(a, ds, pr, rg);
+              const double *mc = mst + (kc & 1) * 16 * RS;
               // operands of tile jb + 1 are read from LDS before the MFMAs of tile jb
               double av[2][4];
 #pragma unroll
