@@ -130,7 +130,10 @@ typedef struct {
  * pseudo-canonical basis, K in that basis, and the domain-to-domain couplings
  * that eq:rij needs.
  *   sys, sel   problem and selection (see above); precision = OSV_FP64 / OSV_MIXED.
- *   stream     HIP stream for all work.
+ *   stream     HIP stream for all kernels.  The cluster tables built on the host
+ *              are copied to the device on a stream the call creates and
+ *              destroys itself (default priority), ordered before the kernels
+ *              that read them by an event.
  *   out        host: receives a new context (NULL on failure).  Free with osv_destroy.
  * Errors: OSV_E_ARG, OSV_E_NONFINITE (NaN/Inf in Q, C, eps_vir or F_occ),
  * OSV_E_DOMAIN, OSV_E_NOMEM, OSV_E_HIP.  Synchronises the stream.

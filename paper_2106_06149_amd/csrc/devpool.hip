@@ -15,7 +15,7 @@
 // Blocks keep whatever the last user wrote; no kernel of the library may rely on
 // fresh memory being zero.  With OSV_POOL_POISON set in the environment every
 // block handed out is filled with 0xFF bytes (NaN as FP64) to show any such
-// reliance.
+// reliance; the fill has completed on the device when the block is handed out.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -101,7 +101,11 @@ hipError_t pool_alloc(void **p, size_t bytes) {
     g_live[q] = Block{got, dev};
   }
   if (poison()) {
+    // hipMemset runs on the null stream and may return before the fill is done;
+    // the block can next be written from any stream (the library uploads on a
+    // non-blocking stream of its own), so the fill completes before it is handed out
     e = hipMemset(q, 0xFF, got);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
   }
   *p = q;

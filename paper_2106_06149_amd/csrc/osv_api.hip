@@ -515,6 +515,26 @@ int upload(osv_ctx *ctx, T **p, const std::vector<T> &v, hipStream_t s) {
   return OSV_OK;
 }
 
+// A stream of the library's own (default priority) for host-to-device copies
+// that run beside the kernels of the caller's stream, and an event that orders
+// the caller's stream after them.  Waits for its copies before it is released.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  hipError_t create() {
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    return e;
+  }
+  ~SideStream() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
 // the FP64 copy of an FP32 C, made once per context
 int c64(osv_ctx *ctx, hipStream_t s) {
   if (ctx->dC64) return OSV_OK;
@@ -747,11 +767,17 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   ctx->counts.n_domains = (int64_t)P.doms.size();
   ctx->counts.n_couplings = (int64_t)P.cpls.size();
   const int ncl = (int)P.cls.size();
-  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCp, P.cps, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dTerms, P.terms, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
+  // the plan tables (about 150 MB at nocc = 400, from pageable memory) go up on a
+  // side stream while the preparation kernels still run; the couplings wait for them
+  SideStream up;
+  HIPCHK(ctx, up.create());
+  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, up.s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCp, P.cps, up.s))) return rc;
+  if ((rc = upload(ctx, &ctx->dTerms, P.terms, up.s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCl, P.cls, up.s))) return rc;
+  if ((rc = upload(ctx, &ctx->dQueue, P.queue, up.s))) return rc;
+  HIPCHK(ctx, hipEventRecord(up.done, up.s));
+  HIPCHK(ctx, hipStreamWaitEvent(s, up.done, 0));
   ctx->stage_ms[8] = host_ms;
   StageTimer t_cpl(s);
   if ((rc = dalloc(ctx, &ctx->dM, P.n_M))) return rc;
