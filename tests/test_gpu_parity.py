@@ -76,6 +76,29 @@ def test_five_and_six_block_targets_fp64():
     compare(s, g, ref)
 
 
+def test_single_lmo_no_pairs_fp64():
+    """nocc = 1: one 1-LMO cluster, no orbital pairs, no couplings and no residual
+    terms (every pair-level table is empty)."""
+    s = synth.make_system(1, 20, 16, 7, seed=41)
+    say("case single LMO nocc=1 nvir=20 naux=16 r=7")
+    g = run_gpu(s)
+    assert g["counts"]["n_pair_blocks"] == 1 and g["counts"]["n_couplings"] == 0
+    ref = O.solve(s)
+    compare(s, g, ref)
+
+
+def test_largest_domain_dimension_fp64():
+    """Two LMOs of 50 OSVs: the pair domain has the largest dimension the kernels
+    take (100: the largest preparation class, targets of seven 16-wide blocks, so
+    three waves of the solve own two blocks each)."""
+    s = synth.make_system(2, 120, 80, 50, seed=43, cut2=4.5, cut3=4.5)
+    say("case largest domain nocc=2 nvir=120 naux=80 r=50 (n = 100)")
+    g = run_gpu(s)
+    assert g["counts"]["n_clusters"] == 3
+    ref = O.solve(s)
+    compare(s, g, ref)
+
+
 def test_workload0_full_osv_mp2():
     s = synth.workload(0)
     say("case workload 0: full OSV-MP2 nocc=6 nvir=60 naux=150 r=8")
