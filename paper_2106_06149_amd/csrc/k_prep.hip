@@ -537,23 +537,28 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
   return hipGetLastError();
 }
 
-// Couplings M(A,B) = W_A^T S_(A,B) W_B, one workgroup (16 wave64) per coupling,
-// FP64 MFMA 16x16x4.  G = S_(A,B) W_B (n_A x np_B, zero beyond dt_B) is formed in
-// LDS; the product W_A^T G is then taken once per orientation, so that M(A,B)
-// and M(B,A) = M(A,B)^T are both written with row-contiguous stores over their
-// whole zero-padded np x np slots.
-constexpr int CNT = 1024;         // threads per coupling workgroup (16 waves)
-constexpr int LDG = 16 * 7 + 1;   // LDS stride of G (columns < np_B <= 112)
+// Couplings M(A,B) = W_A^T S_(A,B) W_B, one workgroup (8 wave64) per coupling,
+// FP64 MFMA 16x16x4.  G = S_(A,B) W_B (n_A x dt_B) is formed in LDS; the product
+// W_A^T G is then taken once per orientation, so that M(A,B) and M(B,A) =
+// M(A,B)^T are both written with row-contiguous stores over their whole
+// zero-padded np x np slots.  G keeps only the dt_B columns that can be nonzero,
+// so that several workgroups share a CU and one coupling's loads overlap another's
+// products.  Two size classes by the larger of the two domain dimensions: up to
+// 64 (4 waves, G 33 KB, four workgroups per CU) and up to DMAX (8 waves, G
+// 80.8 KB, two per CU); ids lists the couplings of the class.
 typedef double d4c __attribute__((ext_vector_type(4)));
 
+template <int NM, int CNT>
 __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ cpl,
+                                                   const int *__restrict__ ids,
                                                    const Domain *__restrict__ doms,
                                                    const int *__restrict__ rank,
                                                    const double *__restrict__ S, long long ld,
                                                    const double *__restrict__ W,
                                                    double *M) {
-  __shared__ double G[DMAX * LDG];
-  const Coupling c = cpl[blockIdx.x];
+  constexpr int LDG = NM + 1;   // LDS stride of G (columns < dt_B <= NM)
+  __shared__ double G[NM * LDG];
+  const Coupling c = cpl[ids[blockIdx.x]];
   const Domain A = doms[c.A], B = doms[c.B];
   const int dtA = rank[c.A], dtB = rank[c.B];
   const double *WA = W + A.moff, *WB = W + B.moff;
@@ -564,9 +569,9 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
   //    which is contiguous in i for a fixed k (S holds both orientations of its blocks).
   //    A wave keeps one row tile of S_(A,B) in registers for its whole k range and
   //    walks over column tiles of W_B, loading each one's k range in two batches.
-  constexpr int KST = (DMAX + 3) / 4;   // k-steps of 4 covering DMAX
+  constexpr int KST = (NM + 3) / 4;   // k-steps of 4 covering the class's dimensions
   constexpr int KH = (KST + 1) / 2;
-  const int ti = (A.n + 15) >> 4, tj = B.np >> 4;
+  const int ti = (A.n + 15) >> 4, tjn = (dtB + 15) >> 4;   // column tiles holding G's dt_B columns
   {
     const int grp = NWV / ti, it = wave % ti, g = wave / ti;
     if (g < grp) {
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
         const int k = 4 * st + lhi;
         av[st] = (i < A.n && k < B.n) ? comp_elem(S, ld, B, A, k, i, true) : 0.0;
       }
-      for (int jt = g; jt < tj; jt += grp) {
+      for (int jt = g; jt < tjn; jt += grp) {
         const int j = jt * 16 + l15;
         d4c acc = {0, 0, 0, 0};
 #pragma unroll
@@ -598,14 +603,15 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
         // accumulator: lane l, register v -> row 4v + (l >> 4), column l & 15
         for (int v = 0; v < 4; v++) {
           const int ii = it * 16 + 4 * v + lhi;
-          if (ii < A.n) G[ii * LDG + j] = acc[v];
+          if (ii < A.n && j < dtB) G[ii * LDG + j] = acc[v];
         }
       }
     }
   }
   __syncthreads();
   // 2) M(A,B)(a, b) = sum_k W_A(k, a) G(k, b) and M(B,A)(b, a) = sum_k G(k, b) W_A(k, a)
-  //    over the padded ranges (W_A columns beyond dt_A and G columns beyond dt_B are 0).
+  //    over the padded ranges (W_A columns beyond dt_A and G columns beyond dt_B are
+  //    taken as 0).
   //    A wave keeps one column tile of W_A in registers and walks over column tiles
   //    of G; each G fragment read from LDS feeds both orientations.
   const int ta = A.np >> 4, tb = B.np >> 4;
@@ -627,7 +633,7 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
         for (int st = 0; st < KST; st++) {
           if (4 * st < A.n) {
             const int k = 4 * st + lhi;
-            const double gv = (k < A.n) ? G[k * LDG + b] : 0.0;
+            const double gv = (k < A.n && b < dtB) ? G[k * LDG + b] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[st], gv, acc, 0, 0, 0);
             acct = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, wv[st], acct, 0, 0, 0);
           }
@@ -641,11 +647,15 @@ __global__ __launch_bounds__(CNT) void k_couplings(const Coupling *__restrict__ 
   }
 }
 
-hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom, const int *rank,
-                            const double *S, long long ld, const double *W, double *M,
-                            hipStream_t s) {
-  if (ncpl <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_couplings, dim3(ncpl), dim3(CNT), 0, s, cpl, dom, rank, S, ld, W, M);
+hipError_t launch_couplings(const Coupling *cpl, const int *ids, int n64, int nbig,
+                            const Domain *dom, const int *rank, const double *S, long long ld,
+                            const double *W, double *M, hipStream_t s) {
+  if (n64 > 0)
+    hipLaunchKernelGGL((k_couplings<64, 256>), dim3(n64), dim3(256), 0, s, cpl, ids, dom, rank, S, ld,
+                       W, M);
+  if (nbig > 0)
+    hipLaunchKernelGGL((k_couplings<DMAX, 512>), dim3(nbig), dim3(512), 0, s, cpl, ids + n64, dom,
+                       rank, S, ld, W, M);
   return hipGetLastError();
 }
 

@@ -438,7 +438,8 @@ struct osv_ctx {
   int2 *dTiles128 = nullptr;
   double *dEcl = nullptr, *dPl = nullptr, *dMaxres = nullptr, *dWts = nullptr, *dEout = nullptr;
   int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
-  int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr;
+  int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr, *dCplIds = nullptr;
+  std::vector<int> cpl_ids;   // couplings by size class (host copy of dCplIds)
   long long *dDiagMoff = nullptr;  // per LMO p: W slot of domain (p, p), or -1
   Domain *dDom = nullptr;
   Coupling *dCpl = nullptr;
@@ -776,12 +777,28 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = upload(ctx, &ctx->dTerms, P.terms, up.s))) return rc;
   if ((rc = upload(ctx, &ctx->dCl, P.cls, up.s))) return rc;
   if ((rc = upload(ctx, &ctx->dQueue, P.queue, up.s))) return rc;
+  // couplings by size class: both domains with n <= 64, then the others
+  int n64 = 0;
+  {
+    std::vector<int> &ids = ctx->cpl_ids;
+    ids.clear();
+    ids.reserve(P.cpls.size());
+    for (int pass = 0; pass < 2; pass++) {
+      for (int c = 0; c < (int)P.cpls.size(); c++) {
+        const bool small = std::max(P.doms[P.cpls[c].A].n, P.doms[P.cpls[c].B].n) <= 64;
+        if (small == (pass == 0)) ids.push_back(c);
+      }
+      if (pass == 0) n64 = (int)ids.size();
+    }
+    if ((rc = upload(ctx, &ctx->dCplIds, ids, up.s))) return rc;
+  }
   HIPCHK(ctx, hipEventRecord(up.done, up.s));
   HIPCHK(ctx, hipStreamWaitEvent(s, up.done, 0));
   ctx->stage_ms[8] = host_ms;
   StageTimer t_cpl(s);
   if ((rc = dalloc(ctx, &ctx->dM, P.n_M))) return rc;
-  HIPCHK(ctx, launch_couplings(ctx->dCpl, (int)P.cpls.size(), ctx->dDom, ctx->dRank, ctx->dS, ld, ctx->dW,
+  HIPCHK(ctx, launch_couplings(ctx->dCpl, ctx->dCplIds, n64, (int)P.cpls.size() - n64, ctx->dDom,
+                               ctx->dRank, ctx->dS, ld, ctx->dW,
                                ctx->dM, s));
   t_cpl.stop();
   // solve-time buffers

@@ -145,10 +145,11 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
                               const double *S, const double *F, const double *K, long long ld,
                               double tau_S, const long long *diag_moff, double *W, double *Y,
                               double *Kep, int *rank, double *minev, hipStream_t s);
-// both orientations of every coupling, zero-padded (FP64 MFMA)
-hipError_t launch_couplings(const Coupling *cpl, int ncpl, const Domain *dom,
-                            const int *rank, const double *S, long long ld, const double *W,
-                            double *M, hipStream_t s);
+// both orientations of every coupling, zero-padded (FP64 MFMA); ids: the n64
+// couplings whose domains both have n <= 64, then the nbig others
+hipError_t launch_couplings(const Coupling *cpl, const int *ids, int n64, int nbig,
+                            const Domain *dom, const int *rank, const double *S, long long ld,
+                            const double *W, double *M, hipStream_t s);
 // queue: [0, n_big) global descriptors; [n_big, n_first) and [n_first, n) LDS
 // descriptors in two launches (the second one's clusters may start from amplitudes
 // of the first one's)
