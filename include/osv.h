@@ -131,9 +131,9 @@ typedef struct {
  * that eq:rij needs.
  *   sys, sel   problem and selection (see above); precision = OSV_FP64 / OSV_MIXED.
  *   stream     HIP stream for all kernels.  The cluster tables built on the host
- *              are copied to the device on a stream the call creates and
- *              destroys itself (default priority), ordered before the kernels
- *              that read them by an event.
+ *              are copied to the device on the library's own non-blocking stream
+ *              (one per device, default priority, kept until the process ends),
+ *              ordered before the kernels that read them by an event.
  *   out        host: receives a new context (NULL on failure).  Free with osv_destroy.
  * Errors: OSV_E_ARG, OSV_E_NONFINITE (NaN/Inf in Q, C, eps_vir or F_occ),
  * OSV_E_DOMAIN, OSV_E_NOMEM, OSV_E_HIP.  Synchronises the stream.
@@ -153,7 +153,9 @@ int osv_query(const osv_ctx *ctx, osv_counts *out);
  * largest ||W^T R W||_F over its pairs is below tau_R; its amplitudes are those
  * at which that residual was evaluated, and info->sweeps counts the Jacobi steps
  * taken (the largest over the clusters).  Also evaluates each cluster's
- * Hylleraas energy (eq:ec) and the inner products that dE/dF_occ needs.
+ * Hylleraas energy (eq:ec) and the inner products that dE/dF_occ needs.  While
+ * the kernels run, the first call on a context copies the per-domain tables of
+ * osv_densities to the device on the library's own stream (see osv_build_pairs).
  *   tau_R       convergence threshold (e.g. 1e-10); max_sweeps >= 1.
  *   info        host, may be NULL.
  * Errors: OSV_E_ARG, OSV_E_NOT_CONVERGED (info filled, results usable but not

@@ -11,8 +11,9 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <map>
+#include <mutex>
 #include <string>
-#include <unordered_map>
 #include <unordered_map>
 #include <vector>
 
@@ -455,6 +456,7 @@ struct osv_ctx {
   int nwg = 1;
   // densities (allocated on first use)
   bool dens_ready = false;
+  hipEvent_t dens_ev = nullptr;   // density tables uploaded on the side stream
   DensHost dh;
   double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
   double *dColPart = nullptr;  // partial column sums of dE/deps
@@ -476,6 +478,7 @@ struct osv_ctx {
     // before they go back to the cache and a later context reuses them
     if (!allocs.empty()) (void)hipDeviceSynchronize();
     for (void *p : allocs) pool_free(p);
+    if (dens_ev) (void)hipEventDestroy(dens_ev);
   }
 };
 
@@ -516,22 +519,38 @@ int upload(osv_ctx *ctx, T **p, const std::vector<T> &v, hipStream_t s) {
   return OSV_OK;
 }
 
-// A stream of the library's own (default priority) for host-to-device copies
-// that run beside the kernels of the caller's stream, and an event that orders
-// the caller's stream after them.  Waits for its copies before it is released.
+// The library's own stream on the current device (non-blocking, default
+// priority) for host-to-device copies that run beside the kernels of the
+// caller's stream.  Created on first use and kept until the process ends:
+// creating and destroying a stream costs milliseconds.
+hipError_t side_stream(hipStream_t *out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    it = streams.emplace(dev, st).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+// Copies on the side stream and the event that orders a stream after them.
 struct SideStream {
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
   hipError_t create() {
-    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    hipError_t e = side_stream(&s);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
     return e;
   }
   ~SideStream() {
-    if (s) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
     if (done) (void)hipEventDestroy(done);
   }
 };
@@ -1000,6 +1019,7 @@ static void count_flops(osv_ctx *ctx) {
   }
 
 static void densities_host(osv_ctx *ctx);
+static int upload_density_tables(osv_ctx *ctx, hipStream_t s);
 
 int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream_t s,
                        osv_solve_info *info) {
@@ -1037,9 +1057,18 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 3, s));
   HIPCHK(ctx, launch_solve(a, P.n_big, P.n_first, ctx->nwg, s));
   t.stop();
-  // host bookkeeping while the kernel runs
+  // host bookkeeping while the kernel runs; the density tables go up on the side
+  // stream meanwhile (once per context)
   count_flops(ctx);
   densities_host(ctx);
+  if (!ctx->dens_ev) {
+    SideStream up;
+    HIPCHK(ctx, up.create());
+    int rc = upload_density_tables(ctx, up.s);
+    if (rc) return rc;
+    HIPCHK(ctx, hipEventRecord(up.done, up.s));
+    std::swap(ctx->dens_ev, up.done);
+  }
   std::vector<int> sw(ncl);
   std::vector<double> mr(ncl);
   HIPCHK(ctx, hipMemcpyAsync(sw.data(), ctx->dSweeps, ncl * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1184,13 +1213,11 @@ static void densities_host(osv_ctx *ctx) {
   H.ready = true;
 }
 
-static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
-  if (ctx->dens_ready) return OSV_OK;
-  densities_host(ctx);
+// The per-domain tables of the densities (host side built by densities_host) to
+// the device on stream s.
+static int upload_density_tables(osv_ctx *ctx, hipStream_t s) {
   DensHost &H = ctx->dh;
-  Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
-  const int N = ctx->nosv;
   int rc;
   if ((rc = upload(ctx, &ctx->dDptr, H.ptr, s))) return rc;
   if ((rc = upload(ctx, &ctx->dDtoff, H.toff, s))) return rc;
@@ -1203,6 +1230,21 @@ static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
   if ((rc = upload(ctx, &ctx->dPptr, H.pptr, s))) return rc;
   if ((rc = upload(ctx, &ctx->dPidx, H.pidx, s))) return rc;
   if ((rc = upload(ctx, &ctx->dClcoef, S.coef, s))) return rc;
+  return OSV_OK;
+}
+
+static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
+  if (ctx->dens_ready) return OSV_OK;
+  densities_host(ctx);
+  Plan &P = ctx->plan;
+  const int N = ctx->nosv;
+  int rc;
+  if (ctx->dens_ev) {
+    // uploaded on the side stream during the solve
+    HIPCHK(ctx, hipStreamWaitEvent(s, ctx->dens_ev, 0));
+  } else if ((rc = upload_density_tables(ctx, s))) {
+    return rc;
+  }
   const long long ld = N;
   if ((rc = dalloc(ctx, &ctx->dGK, (size_t)ld * ld))) return rc;
   if ((rc = dalloc(ctx, &ctx->dGF, (size_t)ld * ld))) return rc;
