@@ -20,8 +20,11 @@
  *     failed call on that context (or on no context, for NULL).
  *   - "device" pointers are HIP device memory on the current device; "host"
  *     pointers are ordinary host memory.
- *   - Work is enqueued on the caller's HIP stream (NULL = default stream).
- *     Calls that return host values synchronise that stream before returning.
+ *   - Kernels are enqueued on the caller's HIP stream (NULL = default stream).
+ *     Host-to-device copies of tables built on the host may run on the
+ *     library's own stream; the caller's stream waits for them (an event)
+ *     before any kernel reads them.  Calls that return host values synchronise
+ *     the caller's stream before returning.
  *   - Indices are 0-based.  Matrices are dense with the layout stated.
  *   - A context is not thread-safe: calls on one context must not overlap.
  */
