@@ -136,6 +136,23 @@ def test_deterministic_bitwise():
     assert np.array_equal(a["de"], b["de"])
 
 
+def test_caller_stream_bitwise():
+    """Every call on a stream the caller created (default priority) instead of the
+    default stream: the kernels follow the caller's stream and the host-built
+    tables, copied on the library's own stream, are ordered before them by an
+    event, so the results equal the default-stream ones bit for bit."""
+    s = synth.make_system(8, 50, 40, (4, 9), seed=13, cut2=6.5, cut3=4.5)
+    say("case caller stream nocc=8")
+    a = run_gpu(s)
+    st = torch.cuda.Stream(device="cuda:0")
+    with torch.cuda.stream(st):
+        b = run_gpu(s)
+    torch.cuda.synchronize()
+    assert a["E"] == b["E"]
+    for k in ("Ecl", "dC", "dF", "de", "Dv"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_error_paths():
     s = synth.make_system(4, 20, 16, 3, seed=14, cut2=4.5, cut3=4.5)
     say("case error paths")
