@@ -36,6 +36,13 @@ Readings taken where the paper is silent (each is listed in the design notes):
   R9 clusters: 2b pairs with centroid distance <= cut2, 3b triples with all
      three distances <= cut3 and all three sub-pairs selected (downward closed).
   R10 densities are the exact derivative of the MBE energy.
+  R11 weak pairs (correlation scheme for weak 2b clusters; eq:2bscreen): pairs
+     i < j with 1e-7 <= s2b_ij <= l_2b (not strong, not discarded) keep only the
+     dispersion block T_(i,j) (i -> OSVs of i, j -> OSVs of j) in the
+     pseudo-canonical bases of the diagonal domains (R4); with the other blocks
+     projected out the one-block residual K~ + (e~_a + e~_b - f_ii - f_jj) T
+     vanishes in one step, and the pair contributes <Tbar, K> over both
+     orderings, 4 <T, K~> (the exchange block is not represented).
 """
 from __future__ import annotations
 
@@ -438,3 +445,33 @@ def dense_solve_energy(pb: PairBlocks, X: Sequence[int], rcond: float = 1e-12) -
     b = -np.concatenate([cl.Kc[pq].ravel() for pq in cl.pairs])
     x = np.linalg.lstsq(A, b, rcond=rcond)[0]
     return cl.energy(unpack(x))
+
+
+# ---------------------------------------------------------------------------
+# Weak 2b clusters: one-block dispersion scheme (R11)
+# ---------------------------------------------------------------------------
+
+WEAK_MIN = 1e-7   # pairs below this s2b are discarded (weak 2b section)
+
+
+def weak_pairs(sysm, l2b: float, s2b: np.ndarray = None):
+    """Weak pairs (i, j), i < j, with WEAK_MIN <= s2b_ij <= l2b, and for each its
+    one-block energy 4 <T, K~> with T = -K~ / (e~_i[a] + e~_j[b] - f_ii - f_jj),
+    K~ = V_i^T K_ij V_j and (e~_p, V_p) the eigenpairs of F_(p,p) (the diagonal
+    domain's pseudo-canonical basis; S_(p,p) = 1).  Returns (pairs, energies)."""
+    if s2b is None:
+        s2b = s2b_metric(sysm)
+    pb = PairBlocks(sysm)
+    n = sysm.nocc
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if WEAK_MIN <= s2b[i, j] <= l2b]
+    eig = {}
+    for p in sorted({x for pq in pairs for x in pq}):
+        eig[p] = np.linalg.eigh(pb.F(p, p))
+    out = []
+    for (i, j) in pairs:
+        (ei, Vi), (ej, Vj) = eig[i], eig[j]
+        Kt = Vi.T @ pb.K(i, j) @ Vj
+        D = ei[:, None] + ej[None, :] - pb.f[i, i] - pb.f[j, j]
+        T = -Kt / D
+        out.append(4.0 * float(np.sum(T * Kt)))
+    return pairs, np.array(out)

@@ -290,3 +290,72 @@ def test_redundant_domain_rank():
     cl = O.Cluster(pb, (0, 1))
     assert cl.W[(0, 1)].shape == (12, 6)
     assert cl.W[(0, 0)].shape == (6, 6)
+
+
+# --- weak 2b clusters, one-block dispersion scheme -------------------------
+
+def _weak_system(nocc=4, nvir=12, naux=20, r=12, seed=61):
+    # r = nvir: every Q_i is square orthogonal (all-OSV limit)
+    return synth.make_system(nocc, nvir, naux, r, seed=seed, spacing=3.0)
+
+
+def test_weak_pairs_all_osv_limit_is_direct_mp2_pair_sum():
+    """With all OSVs kept, the one-block pair energy is the textbook direct
+    (Coulomb) part of the DF-MP2 pair energy over both orderings,
+    -4 sum_ab (ia|jb)^2 / (e_a + e_b - f_ii - f_jj), computed here from B."""
+    s = _weak_system()
+    pairs, e = O.weak_pairs(s, l2b=2.0)      # every pair weak
+    assert len(pairs) == s.nocc * (s.nocc - 1) // 2
+    f = s.F_occ
+    for (i, j), eij in zip(pairs, e):
+        K = s.B[i] @ s.B[j].T
+        D = s.eps_vir[:, None] + s.eps_vir[None, :] - f[i, i] - f[j, j]
+        ref = -4.0 * float(np.sum(K * K / D))
+        assert abs(eij - ref) <= 1e-12 * abs(ref), (i, j, eij, ref)
+        assert eij < 0.0
+
+
+class _Rotated:
+    """The same system with the OSVs of LMO p rotated by an orthogonal U:
+    Q_p -> Q_p U, C_p -> U^T C_p (the OSV span and the integrals are unchanged)."""
+
+    def __init__(self, s, p, U):
+        self.s, self.p, self.U = s, p, U
+        self.nocc, self.r, self.eps_vir, self.F_occ = s.nocc, s.r, s.eps_vir, s.F_occ
+
+    def Qi(self, i):
+        return self.s.Qi(i) @ self.U if i == self.p else self.s.Qi(i)
+
+    def Ci(self, i):
+        return self.U.T @ self.s.Ci(i) if i == self.p else self.s.Ci(i)
+
+
+def test_weak_pairs_invariant_under_osv_rotation():
+    """The one-block energy depends on the OSV spans only: rotating the OSVs of
+    one LMO (and its fitted integrals with them) leaves every pair energy and
+    the metric unchanged (pins the pseudo-canonicalisation of each side)."""
+    s = synth.make_system(5, 40, 30, (5, 9), seed=62, spacing=3.0)
+    s2b = O.s2b_metric(s)
+    pairs, e = O.weak_pairs(s, l2b=2.0, s2b=s2b)
+    rng = np.random.default_rng(7)
+    p = 2
+    U, _ = np.linalg.qr(rng.standard_normal((s.r[p], s.r[p])))
+    rs = _Rotated(s, p, U)
+    pairs2, e2 = O.weak_pairs(rs, l2b=2.0)
+    assert pairs == pairs2
+    assert np.allclose(O.s2b_metric(rs), s2b, rtol=0, atol=1e-14)
+    assert np.allclose(e, e2, rtol=1e-12, atol=0)
+
+
+def test_weak_pairs_selection_window():
+    """Weak pairs are those neither strong (s2b > l2b) nor discarded
+    (s2b < 1e-7): thresholds between the metric's values split the pairs."""
+    s = synth.make_system(6, 40, 30, (5, 9), seed=63, spacing=3.0)
+    s2b = O.s2b_metric(s)
+    off = np.sort(s2b[np.triu_indices(s.nocc, 1)])
+    l2b = float(0.5 * (off[len(off) // 2 - 1] + off[len(off) // 2]))
+    pairs, e = O.weak_pairs(s, l2b=l2b, s2b=s2b)
+    want = [(i, j) for i in range(s.nocc) for j in range(i + 1, s.nocc)
+            if O.WEAK_MIN <= s2b[i, j] <= l2b]
+    assert pairs == want and 0 < len(pairs) < len(off)
+    assert np.all(e < 0.0)
