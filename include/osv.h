@@ -179,6 +179,30 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
 int osv_energy(osv_ctx *ctx, hipStream_t stream, double *E, double *E_orders, double *E_cluster);
 
 /*
+ * osv_weak_pairs -- weak 2b clusters by the one-block scheme (section on the
+ * correlation scheme for weak 2b clusters; selection by eq:2bscreen).  With
+ * OSV_SEL_OVERLAP, the pairs i < j with 1e-7 <= s2b_ij <= l2b are neither
+ * strong clusters nor discarded; each keeps only its dispersion block T_(i,j)
+ * (i to OSVs of i, j to OSVs of j) in the pseudo-canonical bases of the diagonal
+ * domains, where the projected one-block residual
+ *   K~_(i,j) + (e~_i[a] + e~_j[b] - f_ii - f_jj) T = 0,   K~ = W_i^T K_ij W_j,
+ * is solved in one step, and the pair adds 4 <T, K~> to the energy (both
+ * orderings; the exchange block is not represented).  The result is a
+ * correction to the E of osv_energy, which it does not include.  Densities of
+ * the weak pairs are not computed.  Needs only osv_build_pairs (their K_ij blocks
+ * are formed there); other selection modes have no weak pairs.
+ *   E_weak   host, required: sum of the pair energies in pair order.
+ *   n_weak   host or NULL: number of weak pairs.
+ *   E_pairs  device [n_weak] or NULL: the pair energies, pairs in (i, j)
+ *            lexicographic order.
+ *   pairs    host int32 [2 n_weak] or NULL: (i, j) of each pair.
+ * Call once with E_pairs and pairs NULL to learn n_weak.
+ * Errors: OSV_E_ARG, OSV_E_NOMEM, OSV_E_HIP.  Synchronises the stream.
+ */
+int osv_weak_pairs(osv_ctx *ctx, hipStream_t stream, double *E_weak, int64_t *n_weak,
+                   double *E_pairs, int32_t *pairs);
+
+/*
  * osv_densities -- exact derivatives of the MBE energy at fixed Q (Hylleraas
  * stationarity: the amplitudes contribute nothing):
  *   dE_dC     device sum(r) x naux row-major FP64: dE/dC_i = sum_j (G_ij + G_ji^T) C_j

@@ -130,6 +130,22 @@ class OSVContext:
                                         _ptr(Ecl)), self.handle)
         return E.value, np.array(orders[:]), Ecl
 
+    def weak_pairs(self):
+        """Weak 2b clusters (overlap selection): (E_weak, pairs [n, 2] int32 array,
+        per-pair energies as a device tensor), by the one-block scheme."""
+        E = ctypes.c_double()
+        n = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_weak_pairs(self.handle, _stream(self.device), ctypes.byref(E),
+                                            ctypes.byref(n), None, None), self.handle)
+            pairs = np.zeros((n.value, 2), dtype=np.int32)
+            Ep = torch.empty(n.value, dtype=torch.float64, device=self.device)
+            if n.value:
+                L.check(self.lib.osv_weak_pairs(self.handle, _stream(self.device), ctypes.byref(E),
+                                                ctypes.byref(n), _ptr(Ep),
+                                                pairs.ctypes.data_as(ctypes.c_void_p)), self.handle)
+        return E.value, pairs, Ep
+
     def densities(self, dC=True, dF=True, deps=True, dvir=False):
         f64 = dict(dtype=torch.float64, device=self.device)
         out_C = torch.empty(self.nosv, self.naux, **f64) if dC else None

@@ -659,4 +659,76 @@ hipError_t launch_couplings(const Coupling *cpl, const int *ids, int n64, int nb
   return hipGetLastError();
 }
 
+// Weak 2b clusters, one-block dispersion scheme: pair (i, j) keeps only the block
+// T_(i,j) in the pseudo-canonical bases of the diagonal domains (i, i) and (j, j)
+// (their W slots, ranks and eigenvalues e~ from the preparation), where the
+// one-block residual K~ + (e~_a + e~_b - f_ii - f_jj) T vanishes in one step;
+// the pair's energy over both orderings is 4 <T, K~> = -4 sum K~^2 / Delta with
+// K~ = W_i^T K_ij W_j.  One workgroup per pair: G = K_ij W_j into LDS, then K~
+// entries from W_i (LDS) and G; fixed-order sums.
+constexpr int WNT = 256;
+constexpr int WLD = DMAX + 1;
+
+__global__ __launch_bounds__(WNT) void k_weak(const int2 *__restrict__ wp,
+                                              const Domain *__restrict__ doms,
+                                              const int *__restrict__ rank,
+                                              const double *__restrict__ K, long long ld,
+                                              const double *__restrict__ W,
+                                              const double *__restrict__ Kep,
+                                              const double *__restrict__ F, int nocc,
+                                              double *out) {
+  __shared__ double A[DMAX * WLD];   // W_j, then W_i
+  __shared__ double G[DMAX * WLD];   // K_ij W_j
+  __shared__ double red[WNT / 64];
+  const int2 pr = wp[blockIdx.x];
+  const Domain Di = doms[pr.x], Dj = doms[pr.y];
+  const int ri = Di.n, rj = Dj.n, dti = rank[pr.x], dtj = rank[pr.y];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < rj * rj; e += WNT) {
+    const int b = e / rj, d = e - b * rj;
+    A[b * WLD + d] = W[Dj.moff + e];
+  }
+  __syncthreads();
+  for (int e = tid; e < ri * dtj; e += WNT) {
+    const int a = e / dtj, d = e - a * dtj;
+    const double *Kr = K + (long long)(Di.offp + a) * ld + Dj.offp;
+    double g = 0.0;
+    for (int b = 0; b < rj; b++) g += Kr[b] * A[b * WLD + d];
+    G[a * WLD + d] = g;
+  }
+  __syncthreads();
+  for (int e = tid; e < ri * ri; e += WNT) {
+    const int a = e / ri, c = e - a * ri;
+    A[a * WLD + c] = W[Di.moff + e];
+  }
+  __syncthreads();
+  const double *ei = Kep + Di.voff + (long long)Di.np * Di.np;
+  const double *ej = Kep + Dj.voff + (long long)Dj.np * Dj.np;
+  const double fd = F[Di.p * nocc + Di.p] + F[Dj.p * nocc + Dj.p];
+  double acc = 0.0;
+  for (int e = tid; e < dti * dtj; e += WNT) {
+    const int c = e / dtj, d = e - c * dtj;
+    double kt = 0.0;
+    for (int a = 0; a < ri; a++) kt += A[a * WLD + c] * G[a * WLD + d];
+    acc += kt * kt / (ei[c] + ej[d] - fd);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < WNT / 64; w++) t += red[w];
+    out[blockIdx.x] = -4.0 * t;
+  }
+}
+
+hipError_t launch_weak(const int2 *wp, int nweak, const Domain *dom, const int *rank,
+                       const double *K, long long ld, const double *W, const double *Kep,
+                       const double *F, int nocc, double *out, hipStream_t s) {
+  if (nweak <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weak, dim3(nweak), dim3(WNT), 0, s, wp, dom, rank, K, ld, W, Kep, F, nocc,
+                     out);
+  return hipGetLastError();
+}
+
 }  // namespace osv

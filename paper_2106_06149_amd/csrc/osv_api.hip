@@ -441,6 +441,9 @@ struct osv_ctx {
   int *dRank = nullptr, *dSweeps = nullptr, *dCounter = nullptr, *dQueue = nullptr, *dFlag = nullptr;
   int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr, *dCplIds = nullptr;
   std::vector<int> cpl_ids;   // couplings by size class (host copy of dCplIds)
+  std::vector<int2> weak;     // weak 2b clusters (i < j), overlap selection only
+  int2 *dWeak = nullptr;      // their diagonal domains
+  double *dWeakE = nullptr;   // their one-block energies
   long long *dDiagMoff = nullptr;  // per LMO p: W slot of domain (p, p), or -1
   Domain *dDom = nullptr;
   Coupling *dCpl = nullptr;
@@ -587,17 +590,26 @@ struct StageTimer {
 };
 
 // tiles (ti <= tj, tsz x tsz) of the sum(r) x sum(r) index space that hold a domain block
-std::vector<int2> make_tiles(const Plan &P, int nosv, bool all, int tsz) {
+// tiles of tsz x tsz covering the orbital-pair blocks of every domain (and the
+// (i, j) blocks of the weak pairs, whose K the one-block scheme reads)
+std::vector<int2> make_tiles(const Plan &P, int nosv, bool all, int tsz,
+                             const std::vector<int2> *weak = nullptr, const int *off = nullptr,
+                             const int *r = nullptr) {
   const int nt = (nosv + tsz - 1) / tsz;
   std::vector<char> mark((size_t)nt * nt, all ? 1 : 0);
-  if (!all)
+  auto block = [&](int po, int pr, int qo, int qr) {
+    const int a0 = po / tsz, a1 = (po + pr - 1) / tsz, b0 = qo / tsz, b1 = (qo + qr - 1) / tsz;
+    for (int a = a0; a <= a1; a++)
+      for (int b = b0; b <= b1; b++) mark[(size_t)std::min(a, b) * nt + std::max(a, b)] = 1;
+  };
+  if (!all) {
     for (const Domain &D : P.doms) {
-      int a0 = D.offp / tsz, a1 = (D.offp + D.rp - 1) / tsz;
-      int qo = (D.p == D.q) ? D.offp : D.offq, qr = (D.p == D.q) ? D.rp : D.rq;
-      int b0 = qo / tsz, b1 = (qo + qr - 1) / tsz;
-      for (int a = a0; a <= a1; a++)
-        for (int b = b0; b <= b1; b++) mark[(size_t)std::min(a, b) * nt + std::max(a, b)] = 1;
+      const int qo = (D.p == D.q) ? D.offp : D.offq, qr = (D.p == D.q) ? D.rp : D.rq;
+      block(D.offp, D.rp, qo, qr);
     }
+    if (weak)
+      for (const int2 &w : *weak) block(off[w.x], r[w.x], off[w.y], r[w.y]);
+  }
   std::vector<int2> t;
   for (int a = 0; a < nt; a++)
     for (int b = a; b < nt; b++)
@@ -679,6 +691,12 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
         nocc, [&](int i, int j) { return s2b(i, j) > sel->l2b; },
         [&](int i, int j, int k) { return (s2b(i, j) + s2b(i, k) + s2b(j, k)) / 3.0 > sel->l3b; },
         [](int, int) { return true; }, ctx->sel);
+    // weak 2b clusters: neither strong nor discarded (one-block scheme)
+    for (int i = 0; i < nocc; i++)
+      for (int j = i + 1; j < nocc; j++) {
+        const double v = s2b(i, j);
+        if (v >= OSV_WEAK_MIN && !(v > sel->l2b)) ctx->weak.push_back(make_int2(i, j));
+      }
   }
   {
     std::string err;
@@ -687,8 +705,8 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   }
   Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
-  ctx->tiles = make_tiles(P, N, false, 64);
-  ctx->tiles128 = make_tiles(P, N, false, 128);
+  ctx->tiles = make_tiles(P, N, false, 64, &ctx->weak, ctx->off.data(), ctx->r.data());
+  ctx->tiles128 = make_tiles(P, N, false, 128, &ctx->weak, ctx->off.data(), ctx->r.data());
   const int ndom = (int)P.doms.size();
   // everything the device stages before the couplings need is allocated and
   // uploaded first: uploads from pageable host memory wait for the stream
@@ -1256,6 +1274,42 @@ static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
   HIPCHK(ctx, launch_fill_f64(ctx->dGK, 0.0, ld * ld, s));
   HIPCHK(ctx, launch_fill_f64(ctx->dGF, 0.0, ld * ld, s));
   ctx->dens_ready = true;
+  return OSV_OK;
+}
+
+int osv_weak_pairs(osv_ctx *ctx, hipStream_t s, double *E_weak, int64_t *n_weak, double *E_pairs,
+                   int32_t *pairs) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!E_weak) return fail(ctx, OSV_E_ARG, "E_weak is NULL");
+  const int nw = (int)ctx->weak.size();
+  if (n_weak) *n_weak = nw;
+  *E_weak = 0.0;
+  if (pairs)
+    for (int w = 0; w < nw; w++) {
+      pairs[2 * w] = ctx->weak[w].x;
+      pairs[2 * w + 1] = ctx->weak[w].y;
+    }
+  if (nw == 0) return OSV_OK;
+  const int nocc = ctx->nocc;
+  int rc;
+  if (!ctx->dWeak) {
+    std::vector<int2> dd(nw);
+    for (int w = 0; w < nw; w++)
+      dd[w] = make_int2(ctx->plan.dom_of[(size_t)ctx->weak[w].x * nocc + ctx->weak[w].x],
+                        ctx->plan.dom_of[(size_t)ctx->weak[w].y * nocc + ctx->weak[w].y]);
+    if ((rc = upload(ctx, &ctx->dWeak, dd, s))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dWeakE, nw))) return rc;
+  }
+  HIPCHK(ctx, launch_weak(ctx->dWeak, nw, ctx->dDom, ctx->dRank, ctx->dK, (long long)ctx->nosv,
+                          ctx->dW, ctx->dKt, ctx->F, nocc, ctx->dWeakE, s));
+  std::vector<double> e(nw);
+  HIPCHK(ctx, hipMemcpyAsync(e.data(), ctx->dWeakE, nw * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (E_pairs)
+    HIPCHK(ctx, hipMemcpyAsync(E_pairs, ctx->dWeakE, nw * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  double t = 0.0;
+  for (int w = 0; w < nw; w++) t += e[w];
+  *E_weak = t;
   return OSV_OK;
 }
 

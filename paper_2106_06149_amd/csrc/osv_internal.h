@@ -150,6 +150,12 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
 hipError_t launch_couplings(const Coupling *cpl, const int *ids, int n64, int nbig,
                             const Domain *dom, const int *rank, const double *S, long long ld,
                             const double *W, double *M, hipStream_t s);
+constexpr double OSV_WEAK_MIN = 1e-7;   // weak pairs below this s2b are discarded
+// weak 2b clusters: per pair (diagonal domain of i, of j) the one-block
+// dispersion energy into out[nweak]
+hipError_t launch_weak(const int2 *wp, int nweak, const Domain *dom, const int *rank,
+                       const double *K, long long ld, const double *W, const double *Kep,
+                       const double *F, int nocc, double *out, hipStream_t s);
 // queue: [0, n_big) global descriptors; [n_big, n_first) and [n_first, n) LDS
 // descriptors in two launches (the second one's clusters may start from amplitudes
 // of the first one's)

@@ -278,3 +278,39 @@ def test_mixed_beyond_int32_range_uses_fp64_k():
     g = run_gpu(s)
     ref = O.solve(s)
     compare(s, g, ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_weak_pairs_one_block(precision):
+    """Weak 2b clusters (overlap selection, 1e-7 <= s2b <= l2b) by the one-block
+    scheme: the pair list and every pair energy against the oracle; K of the
+    mixed mode comes from the exact FP32 digits, so both precisions meet the
+    FP64 bar relative to the largest pair energy."""
+    c_dtype = np.float32 if precision == 1 else np.float64
+    s = synth.make_system(10, 60, 50, (4, 9), seed=19, sel_mode=synth.SEL_OVERLAP,
+                          c_dtype=c_dtype, precision=precision)
+    s2b = O.s2b_metric(s)
+    off = np.sort(s2b[np.triu_indices(s.nocc, 1)])
+    h = len(off) // 2
+    l2b = float(0.5 * (off[h - 1] + off[h]))
+    # no metric value close enough to a threshold for rounding to move a pair
+    assert np.all(np.abs(off / O.WEAK_MIN - 1.0) > 1e-6)
+    say(f"case weak pairs precision={precision} nocc=10 l2b={l2b:.3g}")
+    oc = OSVContext.from_system(s, device="cuda:0", precision=precision,
+                                sel=Selection(L.OSV_SEL_OVERLAP, l2b=l2b, l3b=0.9))
+    E, pairs, Ep = oc.weak_pairs()
+    oc.close()
+    rp, re = O.weak_pairs(s, l2b, s2b=s2b)
+    assert 0 < len(rp) and [tuple(int(x) for x in p) for p in pairs] == rp
+    scale = np.max(np.abs(re))
+    assert np.max(np.abs(Ep.cpu().numpy() - re)) <= 1e-10 * scale
+    assert abs(E - float(np.sum(re))) <= 1e-10 * scale * len(re)
+
+
+def test_weak_pairs_none_in_distance_mode():
+    s = synth.make_system(6, 40, 30, (3, 6), seed=11, cut2=4.5, cut3=4.5)
+    say("case weak pairs in distance mode nocc=6")
+    oc = OSVContext.from_system(s, device="cuda:0")
+    E, pairs, Ep = oc.weak_pairs()
+    oc.close()
+    assert E == 0.0 and pairs.shape == (0, 2) and Ep.numel() == 0
