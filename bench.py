@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=300,
                     help="clusters of the workload timed on the CPU oracle (0 = skip)")
     ap.add_argument("--tau-R", type=float, default=1e-10)
+    ap.add_argument("--weak-l2b", type=float, default=None,
+                    help="instead of the step: build the workload with the overlap selection "
+                         "at this l_2b and time the weak-pair (one-block) energies")
+    ap.add_argument("--weak-l3b", type=float, default=0.2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB once (device to "
                          "device) so that a counter run can calibrate its byte counters")
@@ -135,6 +139,33 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy probe: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr)
         del src, dst
+
+    if args.weak_l2b is not None:
+        # weak 2b clusters (one-block scheme): the build with the overlap selection
+        # is not timed; the timed call forms every weak pair's energy from the K
+        # blocks, W slots and eigenvalues the build left on the device
+        from paper_2106_06149_amd import _lib as L
+        wsel = Selection(L.OSV_SEL_OVERLAP, l2b=args.weak_l2b, l3b=args.weak_l3b)
+        oc = OSVContext(Qt, C, eps, F, s.r, s.centroid, wsel, 1)
+        for _ in range(max(1, args.warmup)):
+            Ew, pairs, _ = oc.weak_pairs()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Ew, pairs, _ = oc.weak_pairs()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        n2b = oc.counts["n2b"]
+        oc.close()
+        print(json.dumps({"metric": "weak 2b pairs/s (one-block energies)", "value": len(pairs) / dt,
+                          "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+                          "ms_per_call": dt * 1e3, "higher_is_better": True, "dtype": "f64",
+                          "data": "synthetic",
+                          "config": {"workload": spec["name"], "l2b": args.weak_l2b,
+                                     "l3b": args.weak_l3b, "n_weak": int(len(pairs)),
+                                     "n_strong_2b": int(n2b), "precision": "mixed"},
+                          "E_weak": Ew}))
+        return
 
     def step(prec):
         oc = OSVContext(Qt, C, eps, F, s.r, s.centroid, sel, prec)

@@ -36,7 +36,7 @@ Readings taken where the paper is silent (each is listed in the design notes):
   R9 clusters: 2b pairs with centroid distance <= cut2, 3b triples with all
      three distances <= cut3 and all three sub-pairs selected (downward closed).
   R10 densities are the exact derivative of the MBE energy.
-  R11 weak pairs (correlation scheme for weak 2b clusters; eq:2bscreen): pairs
+  R15 weak pairs (correlation scheme for weak 2b clusters; eq:2bscreen): pairs
      i < j with 1e-7 <= s2b_ij <= l_2b (not strong, not discarded) keep only the
      dispersion block T_(i,j) (i -> OSVs of i, j -> OSVs of j) in the
      pseudo-canonical bases of the diagonal domains (R4); with the other blocks
@@ -448,7 +448,7 @@ def dense_solve_energy(pb: PairBlocks, X: Sequence[int], rcond: float = 1e-12) -
 
 
 # ---------------------------------------------------------------------------
-# Weak 2b clusters: one-block dispersion scheme (R11)
+# Weak 2b clusters: one-block dispersion scheme (R15)
 # ---------------------------------------------------------------------------
 
 WEAK_MIN = 1e-7   # pairs below this s2b are discarded (weak 2b section)
