@@ -136,11 +136,15 @@ class OSVContext:
         E = ctypes.c_double()
         n = ctypes.c_int64()
         with torch.cuda.device(self.device):
-            L.check(self.lib.osv_weak_pairs(self.handle, _stream(self.device), ctypes.byref(E),
-                                            ctypes.byref(n), None, None), self.handle)
-            pairs = np.zeros((n.value, 2), dtype=np.int32)
-            Ep = torch.empty(n.value, dtype=torch.float64, device=self.device)
-            if n.value:
+            if getattr(self, "_n_weak", None) is None:
+                # the pair count first (the list is fixed by the build)
+                L.check(self.lib.osv_weak_pairs(self.handle, _stream(self.device), ctypes.byref(E),
+                                                ctypes.byref(n), None, None), self.handle)
+                self._n_weak = n.value
+            nw = self._n_weak
+            pairs = np.zeros((nw, 2), dtype=np.int32)
+            Ep = torch.empty(nw, dtype=torch.float64, device=self.device)
+            if nw:
                 L.check(self.lib.osv_weak_pairs(self.handle, _stream(self.device), ctypes.byref(E),
                                                 ctypes.byref(n), _ptr(Ep),
                                                 pairs.ctypes.data_as(ctypes.c_void_p)), self.handle)
