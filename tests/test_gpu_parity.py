@@ -314,3 +314,22 @@ def test_weak_pairs_none_in_distance_mode():
     E, pairs, Ep = oc.weak_pairs()
     oc.close()
     assert E == 0.0 and pairs.shape == (0, 2) and Ep.numel() == 0
+
+
+def test_weak_pair_of_largest_diagonal_domains():
+    """Two LMOs of 100 OSVs each, every pair weak (l2b above every metric value):
+    no strong pair (its domain would exceed the largest dimension), one weak pair
+    whose kernel holds two 100 x 100 matrices in LDS."""
+    s = synth.make_system(2, 150, 60, 100, seed=71, sel_mode=synth.SEL_OVERLAP)
+    s2b = O.s2b_metric(s)
+    assert O.WEAK_MIN < s2b[0, 1] < 2.0
+    say("case weak pair of two 100-OSV diagonal domains")
+    oc = OSVContext.from_system(s, device="cuda:0",
+                                sel=Selection(L.OSV_SEL_OVERLAP, l2b=2.0, l3b=2.0))
+    assert oc.counts["n2b"] == 0
+    E, pairs, Ep = oc.weak_pairs()
+    oc.close()
+    rp, re = O.weak_pairs(s, 2.0, s2b=s2b)
+    assert rp == [(0, 1)] and [tuple(int(x) for x in p) for p in pairs] == rp
+    assert abs(Ep.cpu().numpy()[0] - re[0]) <= 1e-10 * abs(re[0])
+    assert abs(E - re[0]) <= 1e-10 * abs(re[0])
