@@ -42,7 +42,9 @@ Readings taken where the paper is silent (each is listed in the design notes):
      pseudo-canonical bases of the diagonal domains (R4); with the other blocks
      projected out the one-block residual K~ + (e~_a + e~_b - f_ii - f_jj) T
      vanishes in one step, and the pair contributes <Tbar, K> over both
-     orderings, 4 <T, K~> (the exchange block is not represented).
+     orderings, 4 <T, K~> (the exchange block is not represented); its
+     densities follow from the stationarity of the one-block Hylleraas
+     functional (weak_pair_densities).
 """
 from __future__ import annotations
 
@@ -475,3 +477,39 @@ def weak_pairs(sysm, l2b: float, s2b: np.ndarray = None):
         T = -Kt / D
         out.append(4.0 * float(np.sum(T * Kt)))
     return pairs, np.array(out)
+
+
+def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None):
+    """Exact derivatives of the summed weak-pair energies (R15) at fixed Q.  The
+    one-block energy is the stationary value of
+        E_H(T) = 8 <T, K_ij> + 4 <T, F_(i,i) T + T F_(j,j) - (f_ii + f_jj) T>
+    (OSV basis, S_(i,i) = 1), whose stationarity is the one-block residual, so
+    at the solution T (OSV basis, V_i T~ V_j^T):
+        dE/dK_ij = 8 T  ->  dE/dC_i += 8 T C_j,  dE/dC_j += 8 T^T C_i;
+        dE/dF_(i,i) = 4 T T^T, dE/dF_(j,j) = 4 T^T T  ->  dE/deps through Q;
+        dE/df_ii = dE/df_jj = -4 <T, T>.
+    Returns (dE/dC [sum r x naux], dE/dF_occ [nocc x nocc], dE/deps [nvir])."""
+    if s2b is None:
+        s2b = s2b_metric(sysm)
+    pb = PairBlocks(sysm)
+    n = sysm.nocc
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if WEAK_MIN <= s2b[i, j] <= l2b]
+    off = np.concatenate([[0], np.cumsum(sysm.r)]).astype(int)
+    dC = np.zeros((off[-1], pb.C[0].shape[1]))
+    dF = np.zeros((n, n))
+    de = np.zeros(pb.eps.shape[0])
+    eig = {p: np.linalg.eigh(pb.F(p, p)) for p in sorted({x for pq in pairs for x in pq})}
+    for (i, j) in pairs:
+        (ei, Vi), (ej, Vj) = eig[i], eig[j]
+        Kt = Vi.T @ pb.K(i, j) @ Vj
+        Tt = -Kt / (ei[:, None] + ej[None, :] - pb.f[i, i] - pb.f[j, j])
+        T = Vi @ Tt @ Vj.T
+        dC[off[i]:off[i + 1]] += 8.0 * T @ pb.C[j]
+        dC[off[j]:off[j + 1]] += 8.0 * T.T @ pb.C[i]
+        Qi, Qj = pb.Q[i], pb.Q[j]
+        de += 4.0 * np.einsum("am,mn,an->a", Qi, T @ T.T, Qi)
+        de += 4.0 * np.einsum("am,mn,an->a", Qj, T.T @ T, Qj)
+        tt = float(np.sum(T * T))
+        dF[i, i] -= 4.0 * tt
+        dF[j, j] -= 4.0 * tt
+    return dC, dF, de

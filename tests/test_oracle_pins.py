@@ -359,3 +359,38 @@ def test_weak_pairs_selection_window():
             if O.WEAK_MIN <= s2b[i, j] <= l2b]
     assert pairs == want and 0 < len(pairs) < len(off)
     assert np.all(e < 0.0)
+
+
+def test_weak_pair_densities_match_finite_differences():
+    """dE/dC, dE/dF_occ and dE/deps of the summed weak-pair energies against
+    central finite differences of the energies themselves (no shared formula)."""
+    import copy
+    s = synth.make_system(4, 16, 10, (3, 5), seed=64, spacing=3.0)
+    s2b = O.s2b_metric(s)
+    l2b = 2.0
+
+    def E(sys_):
+        return float(np.sum(O.weak_pairs(sys_, l2b, s2b=s2b)[1]))
+
+    dC, dF, de = O.weak_pair_densities(s, l2b, s2b=s2b)
+    rng = np.random.default_rng(3)
+    h = 1e-5
+    for _ in range(6):
+        r_, c_ = int(rng.integers(s.C.shape[0])), int(rng.integers(s.C.shape[1]))
+        sp, sm = copy.deepcopy(s), copy.deepcopy(s)
+        sp.C = s.C.copy(); sp.C[r_, c_] += h
+        sm.C = s.C.copy(); sm.C[r_, c_] -= h
+        fd = (E(sp) - E(sm)) / (2 * h)
+        assert abs(fd - dC[r_, c_]) <= 1e-6 * max(1.0, abs(fd)), (r_, c_, fd, dC[r_, c_])
+    for a in rng.choice(s.nvir, 4, replace=False):
+        sp, sm = copy.deepcopy(s), copy.deepcopy(s)
+        sp.eps_vir = s.eps_vir.copy(); sp.eps_vir[a] += h
+        sm.eps_vir = s.eps_vir.copy(); sm.eps_vir[a] -= h
+        fd = (E(sp) - E(sm)) / (2 * h)
+        assert abs(fd - de[a]) <= 1e-6 * max(1.0, abs(fd)), (a, fd, de[a])
+    for (p, q) in [(0, 0), (2, 2), (0, 1)]:
+        sp, sm = copy.deepcopy(s), copy.deepcopy(s)
+        sp.F_occ = s.F_occ.copy(); sp.F_occ[p, q] += h
+        sm.F_occ = s.F_occ.copy(); sm.F_occ[p, q] -= h
+        fd = (E(sp) - E(sm)) / (2 * h)
+        assert abs(fd - dF[p, q]) <= 1e-6 * max(1.0, abs(fd)), (p, q, fd, dF[p, q])
