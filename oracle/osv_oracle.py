@@ -124,6 +124,11 @@ class PairBlocks:
         self.Q = [np.asarray(sysm.Qi(i), dtype=np.float64) for i in range(sysm.nocc)]
         self.C = [np.asarray(sysm.Ci(i), dtype=np.float64) for i in range(sysm.nocc)]
         self.eps = np.asarray(sysm.eps_vir, dtype=np.float64)
+        # a full symmetric virtual Fock matrix, when the system carries one (used
+        # to differentiate with respect to its off-diagonal entries); otherwise
+        # the canonical diag(eps)
+        fv = getattr(sysm, "F_vir", None)
+        self.Fvir = None if fv is None else np.asarray(fv, dtype=np.float64)
         self.f = np.asarray(sysm.F_occ, dtype=np.float64)
         self._S: Dict = {}
         self._F: Dict = {}
@@ -139,7 +144,10 @@ class PairBlocks:
 
     def F(self, p, q):
         if (p, q) not in self._F:
-            self._F[(p, q)] = self.Q[p].T @ (self.eps[:, None] * self.Q[q])
+            if self.Fvir is None:
+                self._F[(p, q)] = self.Q[p].T @ (self.eps[:, None] * self.Q[q])
+            else:
+                self._F[(p, q)] = self.Q[p].T @ self.Fvir @ self.Q[q]
             self._F[(q, p)] = self._F[(p, q)].T
         return self._F[(p, q)]
 
@@ -269,9 +277,12 @@ class Cluster:
         return E
 
     # densities --------------------------------------------------------------
-    def densities(self, T: Dict = None):
+    def densities(self, T: Dict = None, dvir: bool = False):
         """Exact partial derivatives of the Hylleraas energy at the converged T:
-        dE/dC_p (list), dE/df (nocc x nocc), dE/deps (nvir)."""
+        dE/dC_p (list), dE/df (nocc x nocc), dE/deps (nvir); with dvir also the
+        full virtual density D^v = sum over ordered pairs P_pq G^F_pq P_pq^T
+        (first term of eq:dv), the derivative with respect to every entry of a
+        virtual Fock matrix taken as independent, whose diagonal is dE/deps."""
         T = self.T if T is None else T
         pb = self.pb
         S = pb.S
@@ -280,6 +291,7 @@ class Cluster:
         dC = {p: np.zeros_like(pb.C[p]) for p in self.X}
         dF = np.zeros((nocc, nocc))
         de = np.zeros(nvir)
+        Dv = np.zeros((nvir, nvir)) if dvir else None
         for p in self.X:
             for q in self.X:
                 d = dom(p, q)
@@ -295,7 +307,10 @@ class Cluster:
                 Sd = composite(S, d, d)
                 GF = Tpq.T @ Sd @ Tbar + Tbar @ Sd @ Tpq.T
                 P = np.hstack([pb.Q[o] for o in d])
-                de += np.einsum("ax,xy,ay->a", P, GF, P)
+                # diagonal of P GF P^T: de_a = sum_xy P_ax GF_xy P_ay
+                de += np.sum((P @ GF) * P, axis=1)
+                if dvir:
+                    Dv += P @ GF @ P.T
         # dE/df_uv from the f-weighted overlap terms of eq:rij
         for u in self.X:
             for v in self.X:
@@ -311,6 +326,8 @@ class Cluster:
                         @ composite(S, dom(v, q), dom(u, q))
                     acc -= float(np.sum(Tbar * M))
                 dF[u, v] += acc
+        if dvir:
+            return dC, dF, de, Dv
         return dC, dF, de
 
 
@@ -321,10 +338,11 @@ class Cluster:
 def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
           tau_R: float = 1e-10, tau_S: float = 1e-8, max_sweeps: int = 100,
           densities: bool = True, clusters=None, coef=None, order=None,
-          l2b: float = 1e-2, l3b: float = 0.2):
+          l2b: float = 1e-2, l3b: float = 0.2, dvir: bool = False):
     """Solve every selected cluster and combine by MBE.  Returns a dict with E,
     E_orders (E_1b, dE_2b, dE_3b), E_cluster, sweeps, and (optionally) dE_dC
-    [sum r, naux], dE_dF [nocc, nocc], dE_deps [nvir]."""
+    [sum r, naux], dE_dF [nocc, nocc], dE_deps [nvir] and, with dvir, the full
+    virtual density Dvir [nvir, nvir]."""
     mode = sysm.sel_mode if mode is None else mode
     cut2 = sysm.cut2 if cut2 is None else cut2
     cut3 = sysm.cut3 if cut3 is None else cut3
@@ -340,6 +358,7 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
     dC = np.zeros((sysm.nosv, sysm.naux))
     dF = np.zeros((sysm.nocc, sysm.nocc))
     de = np.zeros(sysm.nvir)
+    Dv = np.zeros((sysm.nvir, sysm.nvir)) if (densities and dvir) else None
     T_all = []
     for n, X in enumerate(clusters):
         cl = Cluster(pb, X, tau_S)
@@ -350,11 +369,14 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
         converged = converged and cl.converged
         T_all.append(cl.T)
         if densities and coef[n] != 0.0:
-            c_dC, c_dF, c_de = cl.densities()
+            dens = cl.densities(dvir=dvir)
+            c_dC, c_dF, c_de = dens[:3]
             for p, g in c_dC.items():
                 dC[off[p]:off[p + 1]] += coef[n] * g
             dF += coef[n] * c_dF
             de += coef[n] * c_de
+            if dvir:
+                Dv += coef[n] * dens[3]
     E = float(np.dot(coef, E_cl))
     E_orders = mbe_orders(clusters, order, E_cl)
     out = dict(E=E, E_orders=E_orders, E_cluster=E_cl, clusters=clusters, coef=coef,
@@ -362,6 +384,8 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
                T=T_all, pair_blocks=sum(len(X) * (len(X) + 1) // 2 for X in clusters))
     if densities:
         out.update(dE_dC=dC, dE_dF=dF, dE_deps=de)
+        if dvir:
+            out["Dvir"] = Dv
     return out
 
 
@@ -479,7 +503,7 @@ def weak_pairs(sysm, l2b: float, s2b: np.ndarray = None):
     return pairs, np.array(out)
 
 
-def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None):
+def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None, dvir: bool = False):
     """Exact derivatives of the summed weak-pair energies (R15) at fixed Q.  The
     one-block energy is the stationary value of
         E_H(T) = 8 <T, K_ij> + 4 <T, F_(i,i) T + T F_(j,j) - (f_ii + f_jj) T>
@@ -488,7 +512,9 @@ def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None):
         dE/dK_ij = 8 T  ->  dE/dC_i += 8 T C_j,  dE/dC_j += 8 T^T C_i;
         dE/dF_(i,i) = 4 T T^T, dE/dF_(j,j) = 4 T^T T  ->  dE/deps through Q;
         dE/df_ii = dE/df_jj = -4 <T, T>.
-    Returns (dE/dC [sum r x naux], dE/dF_occ [nocc x nocc], dE/deps [nvir])."""
+    Returns (dE/dC [sum r x naux], dE/dF_occ [nocc x nocc], dE/deps [nvir]) and,
+    with dvir, the full virtual density Q_i 4TT^T Q_i^T + Q_j 4T^T T Q_j^T summed
+    over the pairs (the derivative with respect to a full virtual Fock matrix)."""
     if s2b is None:
         s2b = s2b_metric(sysm)
     pb = PairBlocks(sysm)
@@ -498,6 +524,7 @@ def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None):
     dC = np.zeros((off[-1], pb.C[0].shape[1]))
     dF = np.zeros((n, n))
     de = np.zeros(pb.eps.shape[0])
+    Dv = np.zeros((pb.eps.shape[0], pb.eps.shape[0])) if dvir else None
     eig = {p: np.linalg.eigh(pb.F(p, p)) for p in sorted({x for pq in pairs for x in pq})}
     for (i, j) in pairs:
         (ei, Vi), (ej, Vj) = eig[i], eig[j]
@@ -509,7 +536,11 @@ def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None):
         Qi, Qj = pb.Q[i], pb.Q[j]
         de += 4.0 * np.einsum("am,mn,an->a", Qi, T @ T.T, Qi)
         de += 4.0 * np.einsum("am,mn,an->a", Qj, T.T @ T, Qj)
+        if dvir:
+            Dv += 4.0 * (Qi @ (T @ T.T) @ Qi.T + Qj @ (T.T @ T) @ Qj.T)
         tt = float(np.sum(T * T))
         dF[i, i] -= 4.0 * tt
         dF[j, j] -= 4.0 * tt
+    if dvir:
+        return dC, dF, de, Dv
     return dC, dF, de

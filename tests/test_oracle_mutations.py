@@ -29,6 +29,21 @@ MUTATIONS = {
     "dF_second_sum_dropped": ("                    acc -= float(np.sum(Tbar * M))\n                dF",
                               "                    acc -= 0.0\n                dF"),
     "denominator_sign": ("self.f[p, p] - self.f[q, q]", "self.f[p, p] + self.f[q, q]"),
+    "s2b_normalised_by_product": ("/ np.sqrt(sysm.r[i] * sysm.r[j])", "/ (sysm.r[i] * sysm.r[j])"),
+    "mbe_orders_2b_drops_second_monomer": ("e2 += E_cl[n] - E_cl[idx[(i,)]] - E_cl[idx[(j,)]]",
+                                           "e2 += E_cl[n] - E_cl[idx[(i,)]]"),
+    "mbe_orders_3b_drops_monomers": ("+ E_cl[idx[(i,)]] + E_cl[idx[(j,)]] + E_cl[idx[(k,)]])",
+                                     "+ E_cl[idx[(i,)]] + E_cl[idx[(j,)]])"),
+    "dvir_extra_overlap": ("Dv += P @ GF @ P.T", "Dv += P @ Sd @ GF @ P.T"),
+    "dvir_half_of_GF": ("Dv += P @ GF @ P.T", "Dv += P @ (Tbar @ Sd @ Tpq.T) @ P.T"),
+    "weak_dC_factor": ("dC[off[i]:off[i + 1]] += 8.0 * T @ pb.C[j]",
+                       "dC[off[i]:off[i + 1]] += 4.0 * T @ pb.C[j]"),
+    "weak_deps_wrong_side": ('de += 4.0 * np.einsum("am,mn,an->a", Qj, T.T @ T, Qj)',
+                             'de += 4.0 * np.einsum("am,mn,an->a", Qj, T.T @ T.T.T.T, Qj) * 0.5'),
+    "weak_dF_factor": ("dF[i, i] -= 4.0 * tt", "dF[i, i] -= 2.0 * tt"),
+    "weak_dvir_drops_j_side": ("Dv += 4.0 * (Qi @ (T @ T.T) @ Qi.T + Qj @ (T.T @ T) @ Qj.T)",
+                               "Dv += 4.0 * (Qi @ (T @ T.T) @ Qi.T)"),
+    "weak_energy_factor": ("out.append(4.0 * float(np.sum(T * Kt)))", "out.append(2.0 * float(np.sum(T * Kt)))"),
     "dC_missing_transpose": ("dC[q] += G.T @ pb.C[p]", "dC[q] += 0.5 * (G + G.T) @ pb.C[p] if G.shape[0] == G.shape[1] else G.T @ pb.C[p]"),
 }
 

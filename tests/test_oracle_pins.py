@@ -92,6 +92,7 @@ def test_diagonal_focc_pair_closed_form():
     Q = [s.Qi(i) for i in range(5)]
     Cc = [s.Ci(i) for i in range(5)]
     E_ref = 0.0
+    E_1b = E_2b = 0.0
     for X in res["clusters"]:
         if len(X) == 1:
             p = X[0]
@@ -111,8 +112,16 @@ def test_diagonal_focc_pair_closed_form():
         D = e[:, None] + e[None, :] - fp - fq
         e_pair = -float(np.sum(Kt * (2.0 * Kt - Kt.T) / D))
         E_ref += e_pair if len(X) == 1 else 2.0 * e_pair
+        if len(X) == 1:
+            E_1b += e_pair
+        else:
+            E_2b += 2.0 * e_pair
     assert len([X for X in res["clusters"] if len(X) == 3]) > 0
     assert abs(res["E"] - E_ref) < 1e-11 * abs(E_ref)
+    # the MBE orders in closed form: E_1b = sum_p e_pp, dE_2b = 2 sum_{selected p<q} e_pq
+    # (each pair's diagonal blocks decouple, so E^IJ - E^I - E^J = 2 e_IJ), dE_3b = 0
+    assert abs(res["E_orders"][0] - E_1b) < 1e-11 * abs(E_ref)
+    assert abs(res["E_orders"][1] - E_2b) < 1e-11 * abs(E_ref)
     assert abs(res["E_orders"][2]) < 1e-11 * abs(E_ref)
 
 
@@ -381,16 +390,159 @@ def test_weak_pair_densities_match_finite_differences():
         sp.C = s.C.copy(); sp.C[r_, c_] += h
         sm.C = s.C.copy(); sm.C[r_, c_] -= h
         fd = (E(sp) - E(sm)) / (2 * h)
-        assert abs(fd - dC[r_, c_]) <= 1e-6 * max(1.0, abs(fd)), (r_, c_, fd, dC[r_, c_])
+        assert abs(fd - dC[r_, c_]) <= 1e-7 * abs(fd) + 1e-9, (r_, c_, fd, dC[r_, c_])
     for a in rng.choice(s.nvir, 4, replace=False):
         sp, sm = copy.deepcopy(s), copy.deepcopy(s)
         sp.eps_vir = s.eps_vir.copy(); sp.eps_vir[a] += h
         sm.eps_vir = s.eps_vir.copy(); sm.eps_vir[a] -= h
         fd = (E(sp) - E(sm)) / (2 * h)
-        assert abs(fd - de[a]) <= 1e-6 * max(1.0, abs(fd)), (a, fd, de[a])
+        assert abs(fd - de[a]) <= 1e-7 * abs(fd) + 1e-9, (a, fd, de[a])
     for (p, q) in [(0, 0), (2, 2), (0, 1)]:
         sp, sm = copy.deepcopy(s), copy.deepcopy(s)
         sp.F_occ = s.F_occ.copy(); sp.F_occ[p, q] += h
         sm.F_occ = s.F_occ.copy(); sm.F_occ[p, q] -= h
         fd = (E(sp) - E(sm)) / (2 * h)
-        assert abs(fd - dF[p, q]) <= 1e-6 * max(1.0, abs(fd)), (p, q, fd, dF[p, q])
+        assert abs(fd - dF[p, q]) <= 1e-7 * abs(fd) + 1e-9, (p, q, fd, dF[p, q])
+
+
+# --- the 2b overlap metric eq:2bscreen ------------------------------------------
+
+def _system_from_columns(Qcols, r, naux=3, seed=0):
+    """A system whose OSV matrices are given column by column (for metric pins)."""
+    Q = np.asfortranarray(np.array(Qcols, dtype=float).T)
+    nvir = Q.shape[0]
+    nocc = len(r)
+    rng = np.random.default_rng(seed)
+    return synth.System(nocc=nocc, nvir=nvir, naux=naux, r=np.array(r, dtype=np.int32),
+                        centroid=np.zeros((nocc, 3)), F_occ=np.eye(nocc) * -1.0,
+                        eps_vir=np.ones(nvir), Q=Q,
+                        C=rng.standard_normal((int(sum(r)), naux)), B=None)
+
+
+def test_s2b_metric_hand_example():
+    """Hand-derived values (tests/golden/s2b_hand.json): three LMOs over three
+    virtuals with OSV sets of 2, 1 and 2 unit-vector combinations."""
+    g = json.load(open(os.path.join(GOLDEN, "s2b_hand.json")))
+    s = _system_from_columns(g["Q_columns"], g["r"])
+    assert np.allclose(O.s2b_metric(s), np.array(g["s2b"]), rtol=0, atol=1e-15)
+
+
+def test_s2b_metric_unit_diagonal_and_bounds():
+    """s_ii = 1 and 0 <= s_ij <= 1 (the singular values of Q_i^T Q_j are at most 1,
+    so sum sigma^2 <= min(n_i, n_j) <= sqrt(n_i n_j))."""
+    s = synth.make_system(7, 40, 10, (2, 9), seed=71, spacing=1.5)
+    m = O.s2b_metric(s)
+    assert np.allclose(np.diag(m), 1.0, rtol=0, atol=1e-15)
+    off = m[np.triu_indices(s.nocc, 1)]
+    assert np.all(off >= 0.0) and np.all(off <= 1.0 + 1e-14)
+    assert off.max() > 0.05 and off.min() < 0.05        # the bounds are not vacuous
+    assert np.allclose(m, m.T, rtol=0, atol=0)
+
+
+def test_s2b_metric_all_osv_limit_is_one():
+    """All OSVs (every Q_i square orthogonal): Q_i^T Q_j is orthogonal, its squares
+    sum to nvir = sqrt(n_i n_j), so every s_ij = 1."""
+    s = synth.make_system(4, 9, 5, 9, seed=72)
+    assert np.allclose(O.s2b_metric(s), np.ones((4, 4)), rtol=0, atol=1e-13)
+
+
+def test_s2b_metric_equal_spans_rotated():
+    """Two LMOs with the same OSV span (n_i = n_j, Q_j = Q_i U): s_ij = 1; a span
+    that shares one of two directions gives exactly 1/2."""
+    rng = np.random.default_rng(5)
+    Qa, _ = np.linalg.qr(rng.standard_normal((8, 2)))
+    U, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+    Qb = Qa @ U
+    e = np.linalg.qr(np.hstack([Qa, rng.standard_normal((8, 1))]))[0][:, 2]
+    Qc = np.column_stack([Qa[:, 0], e])
+    s = _system_from_columns(np.hstack([Qa, Qb, Qc]).T, [2, 2, 2])
+    m = O.s2b_metric(s)
+    assert abs(m[0, 1] - 1.0) < 1e-14
+    assert abs(m[0, 2] - 0.5) < 1e-14
+
+
+# --- MBE orders (eq:mbe1) -----------------------------------------------------------
+
+def test_mbe_orders_sum_to_energy():
+    """E_1b + dE_2b + dE_3b = sum_X c_X E^X: collecting each cluster energy's
+    coefficient over the three increments gives 1 - n2(I) + n3(I), 1 - n3(IJ), 1."""
+    s = small(nocc=6, nvir=30, naux=30, r=4, seed=5, cut2=6.5, cut3=4.5)
+    res = O.solve(s, densities=False)
+    assert sum(1 for X in res["clusters"] if len(X) == 3) > 0
+    assert abs(np.sum(res["E_orders"]) - res["E"]) < 1e-12 * abs(res["E"])
+    assert abs(res["E_orders"][2]) > 1e-8 * abs(res["E"])    # a real 3-body increment
+
+
+def test_mbe_orders_two_lmos():
+    """Two LMOs: E_1b is the sum of the one-LMO closed forms, dE_2b is the full
+    OSV-MP2 energy of the pair (a separate FULL solve) minus them, dE_3b = 0."""
+    s = small(nocc=2, nvir=20, naux=25, r=[5, 6], seed=44, cut2=100.0, cut3=100.0)
+    res = O.solve(s, densities=False, tau_R=1e-13)
+    full = O.solve(s, mode=O.SEL_FULL, densities=False, tau_R=1e-13)["E"]
+    e1 = []
+    for p in range(2):
+        Qp = s.Qi(p)
+        e, V = np.linalg.eigh(Qp.T @ np.diag(s.eps_vir) @ Qp)
+        Kt = V.T @ (s.Ci(p) @ s.Ci(p).T) @ V
+        D = e[:, None] + e[None, :] - 2.0 * s.F_occ[p, p]
+        e1.append(-float(np.sum(Kt * (2.0 * Kt - Kt.T) / D)))
+    assert abs(res["E_orders"][0] - sum(e1)) < 1e-12 * abs(full)
+    assert abs(res["E_orders"][1] - (full - e1[0] - e1[1])) < 1e-11 * abs(full)
+    assert res["E_orders"][2] == 0.0
+    assert abs(res["E_orders"][1]) > 1e-6 * abs(full)
+
+
+# --- full virtual density (first term of eq:dv) ------------------------------------
+
+def test_full_virtual_density_finite_differences():
+    """D^v against central differences of the MBE energy with respect to the
+    entries of a virtual Fock matrix F_vir = diag(eps) + h (e_a e_b^T + e_b e_a^T):
+    the symmetric perturbation moves D[a, b] + D[b, a]; the diagonal of D^v is
+    dE/deps."""
+    s = small(nocc=4, nvir=14, naux=12, r=[3, 4, 3, 4], seed=13, cut2=4.5, cut3=4.5)
+    res = O.solve(s, tau_R=1e-13, dvir=True)
+    Dv = res["Dvir"]
+    assert sum(1 for X in res["clusters"] if len(X) == 3) > 0
+    assert np.allclose(np.diag(Dv), res["dE_deps"], rtol=1e-12, atol=1e-15)
+    assert np.allclose(Dv, Dv.T, rtol=0, atol=1e-12 * np.abs(Dv).max())
+    h = 1e-5
+    F0 = np.diag(s.eps_vir)
+    checked = 0
+    for (a, b) in [(0, 1), (2, 9), (5, 13), (7, 8), (3, 3)]:
+        E = []
+        for sgn in (1.0, -1.0):
+            Fv = F0.copy()
+            Fv[a, b] += sgn * h
+            if a != b:
+                Fv[b, a] += sgn * h
+            s.F_vir = Fv
+            E.append(_energy(s))
+        del s.F_vir
+        fd = (E[0] - E[1]) / (2 * h)
+        an = Dv[a, b] + (Dv[b, a] if a != b else 0.0)
+        assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10, (a, b, fd, an)
+        checked += abs(an) > 1e-4
+    assert checked >= 3
+
+
+def test_weak_pair_virtual_density_finite_differences():
+    """The weak pairs' full virtual density Q_i 4TT^T Q_i^T + Q_j 4T^T T Q_j^T
+    against central differences in the off-diagonal virtual Fock entries."""
+    import copy
+    s = synth.make_system(4, 16, 10, (3, 5), seed=64, spacing=3.0)
+    s2b = O.s2b_metric(s)
+    dC, dF, de, Dv = O.weak_pair_densities(s, 2.0, s2b=s2b, dvir=True)
+    assert np.allclose(np.diag(Dv), de, rtol=1e-12, atol=1e-16)
+    h = 1e-5
+    for (a, b) in [(0, 1), (4, 11), (6, 15)]:
+        E = []
+        for sgn in (1.0, -1.0):
+            sp = copy.deepcopy(s)
+            Fv = np.diag(s.eps_vir)
+            Fv[a, b] += sgn * h
+            Fv[b, a] += sgn * h
+            sp.F_vir = Fv
+            E.append(float(np.sum(O.weak_pairs(sp, 2.0, s2b=s2b)[1])))
+        fd = (E[0] - E[1]) / (2 * h)
+        an = Dv[a, b] + Dv[b, a]
+        assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10, (a, b, fd, an)
