@@ -57,6 +57,40 @@ def plan_clusters(centroid: np.ndarray, sel: Selection):
     return counts.as_dict(), lmos, coef
 
 
+def validate_inputs(Q: torch.Tensor, C: torch.Tensor, eps_vir: torch.Tensor,
+                    F_occ: torch.Tensor, r) -> None:
+    """Checks the tensors handed to the library against osv_system: the library
+    keeps their addresses and reads Q, eps_vir and F_occ as FP64 and C as FP64 or
+    FP32, dense row-major at the shapes the OSV counts r imply, so a wrong dtype,
+    shape or a strided view would make it read past or around the data.  Raises
+    ValueError; needs no GPU (the device type is checked by the caller)."""
+    r = np.asarray(r)
+    if r.ndim != 1 or r.size < 1 or np.any(r < 1):
+        raise ValueError("r must be a non-empty 1-D array of OSV counts >= 1")
+    nocc, nosv = int(r.size), int(r.sum())
+    for name, t in (("Q", Q), ("eps_vir", eps_vir), ("F_occ", F_occ)):
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name} must be float64 (got {t.dtype})")
+    if C.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f"C must be float32 or float64 (got {C.dtype})")
+    if eps_vir.dim() != 1:
+        raise ValueError("eps_vir must be 1-D [nvir]")
+    nvir = int(eps_vir.shape[0])
+    if tuple(Q.shape) != (nosv, nvir):
+        raise ValueError(f"Q must be given as Q^T, shape (sum r, nvir) = ({nosv}, {nvir}); "
+                         f"got {tuple(Q.shape)}")
+    if C.dim() != 2 or C.shape[0] != nosv or C.shape[1] < 1:
+        raise ValueError(f"C must have shape (sum r, naux) with sum r = {nosv}; got {tuple(C.shape)}")
+    if tuple(F_occ.shape) != (nocc, nocc):
+        raise ValueError(f"F_occ must have shape ({nocc}, {nocc}); got {tuple(F_occ.shape)}")
+    for name, t in (("Q", Q), ("C", C), ("eps_vir", eps_vir), ("F_occ", F_occ)):
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous (row-major); got strides {t.stride()}")
+    devs = {t.device for t in (Q, C, eps_vir, F_occ)}
+    if len(devs) != 1:
+        raise ValueError(f"Q, C, eps_vir and F_occ must be on one device; got {sorted(map(str, devs))}")
+
+
 class OSVContext:
     """One built problem.  The input tensors are borrowed by the library and kept
     alive here until close()."""
@@ -71,11 +105,11 @@ class OSVContext:
         self.cen = None if centroid is None else np.ascontiguousarray(centroid, dtype=np.float64)
         # Q is nvir x sum(r) column-major: we hold its transpose as a contiguous tensor
         self.Q, self.C, self.eps, self.F = Q, C, eps_vir, F_occ
+        self.handle = None
+        validate_inputs(Q, C, eps_vir, F_occ, self.r)
         for name, t in (("Q", Q), ("C", C), ("eps_vir", eps_vir), ("F_occ", F_occ)):
             if not t.is_cuda:
                 raise ValueError(f"{name} must be a device tensor")
-        if C.dtype not in (torch.float32, torch.float64):
-            raise ValueError("C must be float32 or float64")
         nvir = eps_vir.shape[0]
         self.nocc, self.nvir, self.naux = len(self.r), nvir, C.shape[1]
         self.nosv = int(self.r.sum())

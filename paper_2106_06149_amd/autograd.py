@@ -17,10 +17,15 @@ class OSVEnergy(torch.autograd.Function):
         E, _, _ = oc.energy()
         ctx.oc = oc
         ctx.c_dtype = C.dtype
+        # the library reads C (dE/dC = 2 G^K C) and the Fock inputs again in the
+        # backward: saving them lets autograd's version counter reject in-place
+        # changes made between forward and backward
+        ctx.save_for_backward(C, F_occ, eps_vir)
         return torch.tensor(E, dtype=torch.float64, device=C.device)
 
     @staticmethod
     def backward(ctx, g):
+        ctx.saved_tensors   # raises if C, F_occ or eps_vir changed in place
         oc = ctx.oc
         dC, dF, de, _ = oc.densities(dC=ctx.needs_input_grad[0], dF=ctx.needs_input_grad[1],
                                      deps=ctx.needs_input_grad[2])
