@@ -20,11 +20,9 @@
  *     failed call on that context (or on no context, for NULL).
  *   - "device" pointers are HIP device memory on the current device; "host"
  *     pointers are ordinary host memory.
- *   - Kernels are enqueued on the caller's HIP stream (NULL = default stream).
- *     Host-to-device copies of tables built on the host may run on the
- *     library's own stream; the caller's stream waits for them (an event)
- *     before any kernel reads them.  Calls that return host values synchronise
- *     the caller's stream before returning.
+ *   - All work (kernels and the copies of tables built on the host) is
+ *     enqueued on the caller's HIP stream (NULL = default stream).  Calls that
+ *     return host values synchronise the caller's stream before returning.
  *   - Indices are 0-based.  Matrices are dense with the layout stated.
  *   - A context is not thread-safe: calls on one context must not overlap.
  */
@@ -133,10 +131,7 @@ typedef struct {
  * pseudo-canonical basis, K in that basis, and the domain-to-domain couplings
  * that eq:rij needs.
  *   sys, sel   problem and selection (see above); precision = OSV_FP64 / OSV_MIXED.
- *   stream     HIP stream for all kernels.  The cluster tables built on the host
- *              are copied to the device on the library's own non-blocking stream
- *              (one per device, default priority, kept until the process ends),
- *              ordered before the kernels that read them by an event.
+ *   stream     HIP stream for all kernels and copies.
  *   out        host: receives a new context (NULL on failure).  Free with osv_destroy.
  * Errors: OSV_E_ARG, OSV_E_NONFINITE (NaN/Inf in Q, C, eps_vir or F_occ),
  * OSV_E_DOMAIN, OSV_E_NOMEM, OSV_E_HIP.  Synchronises the stream.
@@ -156,9 +151,7 @@ int osv_query(const osv_ctx *ctx, osv_counts *out);
  * largest ||W^T R W||_F over its pairs is below tau_R; its amplitudes are those
  * at which that residual was evaluated, and info->sweeps counts the Jacobi steps
  * taken (the largest over the clusters).  Also evaluates each cluster's
- * Hylleraas energy (eq:ec) and the inner products that dE/dF_occ needs.  While
- * the kernels run, the first call on a context copies the per-domain tables of
- * osv_densities to the device on the library's own stream (see osv_build_pairs).
+ * Hylleraas energy (eq:ec) and the inner products that dE/dF_occ needs.
  *   tau_R       convergence threshold (e.g. 1e-10); max_sweeps >= 1.
  *   info        host, may be NULL.
  * Errors: OSV_E_ARG, OSV_E_NOT_CONVERGED (info filled, results usable but not

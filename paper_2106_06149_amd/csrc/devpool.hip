@@ -102,8 +102,9 @@ hipError_t pool_alloc(void **p, size_t bytes) {
   }
   if (poison()) {
     // hipMemset runs on the null stream and may return before the fill is done;
-    // the block can next be written from any stream (the library uploads on a
-    // non-blocking stream of its own), so the fill completes before it is handed out
+    // the block is next written on the caller's stream, which may be a
+    // non-blocking stream not ordered after the null stream, so the fill
+    // completes before the block is handed out
     e = hipMemset(q, 0xFF, got);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;

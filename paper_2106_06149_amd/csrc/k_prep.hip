@@ -361,7 +361,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       }
     }
     tr = block_sum<NT>(tr, red);
-    const bool gs = chol_ok && (1.0 / tr > tau_S * (2.0 - tau_S));
+    // (the certificate's bound assumes tau_S < 1; the eigenvalues of S_(pq,pq) are
+    // 1 +- sigma_k <= 2, so a larger tau_S always takes the eigenvalue cut)
+    const bool gs = chol_ok && tau_S < 1.0 && (1.0 / tr > tau_S * (2.0 - tau_S));
     if (gs) {
       // X = [[1, -B Z], [0, Z]], Z = L^-T (upper): X into the Y slot (global scratch);
       // the block -B Z (rp x rq) as FP64 MFMA tiles, the rest elementwise
@@ -472,9 +474,10 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     }
     __syncthreads();
     jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, n, rt, red, &s_flag);
-    dt = n;
+    // S_(p,p) = 1: every overlap eigenvalue is 1, kept unless tau_S >= 1
+    dt = (1.0 > tau_S) ? n : 0;
     if (tid == 0) minev[dom_id] = 1.0;
-    for (int a = tid; a < np; a += NT) eg[a] = (a < n) ? L1[a * LD + a] : 0.0;
+    for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
     for (int e = tid; e < n * n; e += NT) {
       int i = e / n, j = e - i * n;
       Wg[i * n + j] = L2[i * LD + j];

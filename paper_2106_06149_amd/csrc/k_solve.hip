@@ -710,7 +710,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         }
         break;
       }
-      if (maxn < a.tau_R || maxn != maxn || sweep >= a.max_sweeps) {
+      // a norm that is NaN or infinite ends the sweeps too (the host reports it)
+      if (maxn < a.tau_R || !(maxn <= 1.7976931348623157e308) || sweep >= a.max_sweeps) {
         if (sweep == 0 && !warm) {
           // stopped before any step: the final amplitudes are zero
           for (int c = 0; c < cl.ncp; c++) {

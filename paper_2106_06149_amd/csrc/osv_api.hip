@@ -459,7 +459,6 @@ struct osv_ctx {
   int nwg = 1;
   // densities (allocated on first use)
   bool dens_ready = false;
-  hipEvent_t dens_ev = nullptr;   // density tables uploaded on the side stream
   DensHost dh;
   double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
   double *dColPart = nullptr;  // partial column sums of dE/deps
@@ -481,7 +480,6 @@ struct osv_ctx {
     // before they go back to the cache and a later context reuses them
     if (!allocs.empty()) (void)hipDeviceSynchronize();
     for (void *p : allocs) pool_free(p);
-    if (dens_ev) (void)hipEventDestroy(dens_ev);
   }
 };
 
@@ -521,42 +519,6 @@ int upload(osv_ctx *ctx, T **p, const std::vector<T> &v, hipStream_t s) {
   if (!v.empty()) HIPCHK(ctx, hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return OSV_OK;
 }
-
-// The library's own stream on the current device (non-blocking, default
-// priority) for host-to-device copies that run beside the kernels of the
-// caller's stream.  Created on first use and kept until the process ends:
-// creating and destroying a stream costs milliseconds.
-hipError_t side_stream(hipStream_t *out) {
-  static std::mutex mu;
-  static std::map<int, hipStream_t> streams;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = streams.find(dev);
-  if (it == streams.end()) {
-    hipStream_t st = nullptr;
-    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    it = streams.emplace(dev, st).first;
-  }
-  *out = it->second;
-  return hipSuccess;
-}
-
-// Copies on the side stream and the event that orders a stream after them.
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t done = nullptr;
-  hipError_t create() {
-    hipError_t e = side_stream(&s);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-    return e;
-  }
-  ~SideStream() {
-    if (done) (void)hipEventDestroy(done);
-  }
-};
 
 // the FP64 copy of an FP32 C, made once per context
 int c64(osv_ctx *ctx, hipStream_t s) {
@@ -805,15 +767,13 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   ctx->counts.n_domains = (int64_t)P.doms.size();
   ctx->counts.n_couplings = (int64_t)P.cpls.size();
   const int ncl = (int)P.cls.size();
-  // the plan tables (about 150 MB at nocc = 400, from pageable memory) go up on a
-  // side stream while the preparation kernels still run; the couplings wait for them
-  SideStream up;
-  HIPCHK(ctx, up.create());
-  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, up.s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCp, P.cps, up.s))) return rc;
-  if ((rc = upload(ctx, &ctx->dTerms, P.terms, up.s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCl, P.cls, up.s))) return rc;
-  if ((rc = upload(ctx, &ctx->dQueue, P.queue, up.s))) return rc;
+  // the plan tables (about 150 MB at nocc = 400, from pageable memory) go up on
+  // the caller's stream behind the preparation kernels
+  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCp, P.cps, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dTerms, P.terms, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
   // couplings by size class: both domains with n <= 64, then the others
   int n64 = 0;
   {
@@ -827,10 +787,8 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       }
       if (pass == 0) n64 = (int)ids.size();
     }
-    if ((rc = upload(ctx, &ctx->dCplIds, ids, up.s))) return rc;
+    if ((rc = upload(ctx, &ctx->dCplIds, ids, s))) return rc;
   }
-  HIPCHK(ctx, hipEventRecord(up.done, up.s));
-  HIPCHK(ctx, hipStreamWaitEvent(s, up.done, 0));
   ctx->stage_ms[8] = host_ms;
   StageTimer t_cpl(s);
   if ((rc = dalloc(ctx, &ctx->dM, P.n_M))) return rc;
@@ -1075,18 +1033,10 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 3, s));
   HIPCHK(ctx, launch_solve(a, P.n_big, P.n_first, ctx->nwg, s));
   t.stop();
-  // host bookkeeping while the kernel runs; the density tables go up on the side
-  // stream meanwhile (once per context)
+  // host bookkeeping while the kernel runs (the density tables are uploaded by
+  // the first osv_densities call)
   count_flops(ctx);
   densities_host(ctx);
-  if (!ctx->dens_ev) {
-    SideStream up;
-    HIPCHK(ctx, up.create());
-    int rc = upload_density_tables(ctx, up.s);
-    if (rc) return rc;
-    HIPCHK(ctx, hipEventRecord(up.done, up.s));
-    std::swap(ctx->dens_ev, up.done);
-  }
   std::vector<int> sw(ncl);
   std::vector<double> mr(ncl);
   HIPCHK(ctx, hipMemcpyAsync(sw.data(), ctx->dSweeps, ncl * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1103,7 +1053,7 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   ctx->stage_flops[4] = fs;
   for (int X = 0; X < ncl; X++) {
     inf.sweeps = std::max(inf.sweeps, sw[X]);
-    if (mr[X] != mr[X]) nonfinite = true;
+    if (!std::isfinite(mr[X])) nonfinite = true;
     else inf.max_residual = std::max(inf.max_residual, mr[X]);
     if (!(mr[X] < tau_R)) {
       inf.converged = 0;
@@ -1257,12 +1207,7 @@ static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
   Plan &P = ctx->plan;
   const int N = ctx->nosv;
   int rc;
-  if (ctx->dens_ev) {
-    // uploaded on the side stream during the solve
-    HIPCHK(ctx, hipStreamWaitEvent(s, ctx->dens_ev, 0));
-  } else if ((rc = upload_density_tables(ctx, s))) {
-    return rc;
-  }
+  if ((rc = upload_density_tables(ctx, s))) return rc;
   const long long ld = N;
   if ((rc = dalloc(ctx, &ctx->dGK, (size_t)ld * ld))) return rc;
   if ((rc = dalloc(ctx, &ctx->dGF, (size_t)ld * ld))) return rc;

@@ -7,7 +7,11 @@ benchmark times (same selection, precision and solve threshold):
   (E is homogeneous of degree 4 in C and of degree -1 in (eps_vir, F_occ));
 * mixed precision against the FP64 GPU path on the same input;
 * central finite differences through the torch.autograd.Function on the
-  nocc = 64 gradient workload (FP64).
+  nocc = 64 gradient workload (FP64);
+* every density element against the oracle on the whole nocc = 64 gradient
+  workload, and on 27-LMO lattice systems drawn by the nocc = 128 and nocc = 400
+  recipes (their full nvir, naux and r ranges and cutoffs), FP64 and mixed;
+  the oracle runs its independent clusters in worker processes.
 """
 import numpy as np
 import pytest
@@ -16,7 +20,7 @@ import torch
 from paper_2106_06149_amd import synth
 from paper_2106_06149_amd.api import OSVContext, Selection, plan_clusters
 from paper_2106_06149_amd.autograd import OSVEnergy
-from oracle import osv_oracle as O
+from oracle import osv_oracle as O, pool as OP
 
 pytestmark = pytest.mark.gpu
 
@@ -148,3 +152,65 @@ def test_gradient_workload_finite_differences():
         say(f"  FD {name}[{a},{b}] fd={fd:.10e} analytic={an:.10e}")
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (name, a, b, fd, an)
     assert max(abs(c[4]) for c in checked) > 1e-3   # the check is not vacuous
+
+
+DENS_TOL = 1e-8          # densities: max |GPU - oracle| over the largest entry (FP64 path)
+DENS_TOL_MIXED = 1e-7    # mixed path: K from the exact FP32 digits, truncated below 2^-43
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(1e-300, np.max(np.abs(b))))
+
+
+def run_dens(s, precision, dvir=False):
+    oc = OSVContext.from_system(s, device="cuda:0", precision=precision)
+    info = oc.solve(tau_R=TAU_R)
+    E, orders, Ecl = oc.energy(per_cluster=True)
+    dC, dF, de, Dv = oc.densities(dvir=dvir)
+    out = dict(E=E, orders=orders, Ecl=Ecl.cpu().numpy(), dC=dC.cpu().numpy(), dF=dF.cpu().numpy(),
+               de=de.cpu().numpy(), Dv=None if Dv is None else Dv.cpu().numpy(), info=info)
+    oc.close()
+    return out
+
+
+def compare_dens(g, ref, tol, etol=E_CLUSTER_TOL):
+    assert abs(g["E"] - ref["E"]) <= etol, (g["E"], ref["E"])
+    assert np.max(np.abs(g["Ecl"] - ref["E_cluster"])) <= etol
+    assert np.max(np.abs(g["orders"] - ref["E_orders"])) <= etol
+    for gk, rk in (("dC", "dE_dC"), ("dF", "dE_dF"), ("de", "dE_deps")):
+        e = rel_err(g[gk], ref[rk])
+        say(f"  {gk}: max |gpu - oracle| / max |oracle| = {e:.2e}")
+        assert e <= tol, (gk, e)
+    if g["Dv"] is not None and "Dvir" in ref:
+        e = rel_err(g["Dv"], ref["Dvir"])
+        say(f"  Dvir: {e:.2e}")
+        assert e <= tol, ("Dvir", e)
+
+
+def test_gradient_workload_densities_elementwise():
+    """Workload 3 (nocc = 64, 848 clusters, FP64): every element of dE/dC,
+    dE/dF_occ and dE/deps_vir, the MBE orders and each cluster energy against the
+    oracle solving all clusters."""
+    s = synth.workload(3)
+    say("case workload 3: GPU FP64 run")
+    g = run_dens(s, 0)
+    say(f"case workload 3: oracle over all clusters ({OP.default_workers()} workers)")
+    ref = OP.solve(s, tau_R=TAU_R)
+    compare_dens(g, ref, DENS_TOL)
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_lattice_27_lmo_densities_elementwise(k):
+    """27 LMOs on the jittered lattice drawn by the recipe of workload k (its nvir,
+    naux, r range, FP32 C and cutoffs): energies and every density element against
+    the oracle, in FP64 (1e-8 of the largest entry) and mixed precision (1e-7)."""
+    s = synth.workload(k, nocc=27)
+    say(f"case 27-LMO lattice by the workload {k} recipe: nvir={s.nvir} naux={s.naux} "
+        f"sum r={s.nosv}: GPU runs")
+    gd = run_dens(s, 0)
+    gm = run_dens(s, 1)
+    say(f"case 27-LMO lattice workload {k}: oracle over all clusters ({OP.default_workers()} workers)")
+    ref = OP.solve(s, tau_R=TAU_R)
+    say(f"  {len(ref['clusters'])} clusters, E = {ref['E']:.10f}")
+    compare_dens(gd, ref, DENS_TOL)
+    compare_dens(gm, ref, DENS_TOL_MIXED)

@@ -45,14 +45,18 @@ def compare(s, g, ref, dens=True, dens_tol=1e-8):
         assert rel_err(g["dC"], ref["dE_dC"]) <= dens_tol
         assert rel_err(g["dF"], ref["dE_dF"]) <= dens_tol
         assert rel_err(g["de"], ref["dE_deps"]) <= dens_tol
-        assert abs(np.trace(g["Dv"]) - np.sum(ref["dE_deps"])) <= dens_tol * np.abs(ref["dE_deps"]).sum()
+        if "Dvir" in ref:
+            # the full virtual density (first term of eq:dv), element by element
+            assert rel_err(g["Dv"], ref["Dvir"]) <= dens_tol
+        else:
+            assert abs(np.trace(g["Dv"]) - np.sum(ref["dE_deps"])) <= dens_tol * np.abs(ref["dE_deps"]).sum()
 
 
 def test_small_mbe3_fp64():
     s = synth.make_system(6, 40, 30, (3, 6), seed=11, cut2=4.5, cut3=4.5)
     say("case small MBE(3) nocc=6 nvir=40 naux=30 r=3..6")
     g = run_gpu(s)
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -61,7 +65,7 @@ def test_ragged_tiles_fp64():
     s = synth.make_system(5, 90, 70, [17, 35, 9, 33, 21], seed=12, cut2=4.5, cut3=4.5)
     say("case ragged nocc=5 nvir=90 naux=70 r=[17,35,9,33,21]")
     g = run_gpu(s)
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -72,7 +76,7 @@ def test_five_and_six_block_targets_fp64():
     say("case 5/6-block targets nocc=5 nvir=220 naux=120 r=[45,48,40,47,30]")
     g = run_gpu(s)
     assert g["info"]["sweeps"] >= 3
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -83,7 +87,7 @@ def test_single_lmo_no_pairs_fp64():
     say("case single LMO nocc=1 nvir=20 naux=16 r=7")
     g = run_gpu(s)
     assert g["counts"]["n_pair_blocks"] == 1 and g["counts"]["n_couplings"] == 0
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -95,7 +99,7 @@ def test_largest_domain_dimension_fp64():
     say("case largest domain nocc=2 nvir=120 naux=80 r=50 (n = 100)")
     g = run_gpu(s)
     assert g["counts"]["n_clusters"] == 3
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -103,7 +107,7 @@ def test_workload0_full_osv_mp2():
     s = synth.workload(0)
     say("case workload 0: full OSV-MP2 nocc=6 nvir=60 naux=150 r=8")
     g = run_gpu(s)
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -121,7 +125,7 @@ def test_workload1_mbe3():
     say("case workload 1: MBE(3) line nocc=32 nvir=320 naux=800 r=12")
     g = run_gpu(s)
     assert g["counts"]["n_pair_blocks"] == 1652
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -138,9 +142,8 @@ def test_deterministic_bitwise():
 
 def test_caller_stream_bitwise():
     """Every call on a stream the caller created (default priority) instead of the
-    default stream: the kernels follow the caller's stream and the host-built
-    tables, copied on the library's own stream, are ordered before them by an
-    event, so the results equal the default-stream ones bit for bit."""
+    default stream: the kernels and the copies of the host-built tables follow
+    the caller's stream, so the results equal the default-stream ones bit for bit."""
     s = synth.make_system(8, 50, 40, (4, 9), seed=13, cut2=6.5, cut3=4.5)
     say("case caller stream nocc=8")
     a = run_gpu(s)
@@ -176,6 +179,34 @@ def test_error_paths():
     assert e.value.status == L.OSV_E_NONFINITE
 
 
+def test_rank_zero_domain_error():
+    """tau_S = 10 drops every overlap eigenvalue (they are 1 +- sigma <= 2): the
+    build reports OSV_E_DOMAIN instead of solving in empty domains."""
+    s = synth.make_system(3, 20, 16, 4, seed=14, cut2=4.5, cut3=4.5)
+    say("case rank-zero domains (tau_S = 10)")
+    with pytest.raises(L.OSVError) as e:
+        OSVContext.from_system(s, device="cuda:0", sel=Selection(0, 4.5, 4.5, tau_S=10.0))
+    assert e.value.status == L.OSV_E_DOMAIN
+
+
+def test_nonfinite_residual_error():
+    """Finite inputs whose residual overflows: an off-diagonal f of 1e300 makes the
+    coupling terms overflow within a few sweeps; the solve stops on the non-finite
+    norm and reports OSV_E_NONFINITE, and the energy is then refused."""
+    s = synth.make_system(3, 20, 16, 4, seed=14, sel_mode=synth.SEL_FULL)
+    F = s.F_occ.copy()
+    F[0, 1] = F[1, 0] = 1e300
+    s.F_occ = F
+    say("case non-finite residual (f_01 = 1e300)")
+    oc = OSVContext.from_system(s, device="cuda:0")
+    info = oc.solve(tau_R=1e-10, max_sweeps=30, raise_on_error=False)
+    assert info["status"] == L.OSV_E_NONFINITE, info
+    with pytest.raises(L.OSVError) as e:
+        oc.energy()
+    assert e.value.status == L.OSV_E_STATE
+    oc.close()
+
+
 MIXED_TOL = 1e-6   # Eh: the mixed path's energy bar
 
 
@@ -188,12 +219,13 @@ def test_mixed_split_k_vs_oracle():
                           c_dtype=np.float32, precision=1)
     say("case mixed nocc=7 nvir=60 naux=150 r=5..12")
     g = run_gpu(s)
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     assert abs(g["E"] - ref["E"]) <= MIXED_TOL * 1e-2, (g["E"], ref["E"])
     assert np.max(np.abs(g["Ecl"] - ref["E_cluster"])) <= MIXED_TOL * 1e-2
     assert rel_err(g["dC"], ref["dE_dC"]) <= 1e-7
     assert rel_err(g["dF"], ref["dE_dF"]) <= 1e-7
     assert rel_err(g["de"], ref["dE_deps"]) <= 1e-7
+    assert rel_err(g["Dv"], ref["Dvir"]) <= 1e-7
 
 
 def test_mixed_matches_fp64_large_rows():
@@ -227,7 +259,7 @@ def test_energy_pass_fallbacks(case):
     s.F_occ = F
     say(f"case energy-pass fallback {case} nocc=8")
     g = run_gpu(s)
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -250,7 +282,7 @@ def test_overlap_selection_mbe3():
     say(f"case overlap selection nocc=10 l2b={l2b:.3g} l3b={l3b:.3g}")
     sel = Selection(L.OSV_SEL_OVERLAP, l2b=l2b, l3b=l3b)
     g = run_gpu(s, sel=sel)
-    ref = O.solve(s, mode=synth.SEL_OVERLAP, l2b=l2b, l3b=l3b)
+    ref = O.solve(s, mode=synth.SEL_OVERLAP, l2b=l2b, l3b=l3b, dvir=True)
     assert 0 < g["counts"]["n2b"] < s.nocc * (s.nocc - 1) // 2
     assert g["counts"]["n3b"] > 0
     assert len(ref["E_cluster"]) == g["counts"]["n_clusters"]
@@ -265,7 +297,7 @@ def test_full_cluster_beyond_lds_tables():
     say("case full cluster nocc=12 (78 pairs, global descriptors)")
     g = run_gpu(s)
     assert g["counts"]["n_pair_blocks"] == 78
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
@@ -276,7 +308,7 @@ def test_mixed_beyond_int32_range_uses_fp64_k():
                           sel_mode=synth.SEL_FULL, b_scale=0.01)
     say("case mixed with naux=87100 (FP64 K fallback)")
     g = run_gpu(s)
-    ref = O.solve(s)
+    ref = O.solve(s, dvir=True)
     compare(s, g, ref)
 
 
