@@ -196,6 +196,24 @@ int osv_weak_pairs(osv_ctx *ctx, hipStream_t stream, double *E_weak, int64_t *n_
                    double *E_pairs, int32_t *pairs);
 
 /*
+ * osv_weak_pairs_noalloc -- osv_weak_pairs for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as osv_weak_pairs, but it calls no
+ * hipMalloc, hipFree or other allocating routine: the per-pair domain table, the
+ * pair energies and their sum live in a static device array of the library
+ * (16 MiB + 256 B per device, held until the process ends), so it takes at most
+ * OSV_NOALLOC_MAX_WEAK weak pairs (OSV_E_ARG beyond, before any device work).
+ * Every call on one device shares that array and finds what the last call left
+ * in it: calls that overlap on one device (any contexts, any streams) race, and
+ * the caller must order them.  E_weak is summed on the device in a fixed order
+ * (256 strided partial sums, then a fixed tree), so it equals osv_weak_pairs'
+ * host sum in pair order to rounding; E_pairs are bitwise the same.
+ */
+#define OSV_NOALLOC_MAX_WEAK 1048576
+int osv_weak_pairs_noalloc(osv_ctx *ctx, hipStream_t stream, double *E_weak, int64_t *n_weak,
+                           double *E_pairs, int32_t *pairs);
+
+/*
  * osv_densities -- exact derivatives of the MBE energy at fixed Q (Hylleraas
  * stationarity: the amplitudes contribute nothing):
  *   dE_dC     device sum(r) x naux row-major FP64: dE/dC_i = sum_j (G_ij + G_ji^T) C_j

@@ -442,6 +442,7 @@ struct osv_ctx {
   int *dOff = nullptr, *dR = nullptr, *dPrepIds = nullptr, *dCplIds = nullptr;
   std::vector<int> cpl_ids;   // couplings by size class (host copy of dCplIds)
   std::vector<int2> weak;     // weak 2b clusters (i < j), overlap selection only
+  std::vector<int2> weak_dd;  // their diagonal domains ((i, i), (j, j))
   int2 *dWeak = nullptr;      // their diagonal domains
   double *dWeakE = nullptr;   // their one-block energies
   long long *dDiagMoff = nullptr;  // per LMO p: W slot of domain (p, p), or -1
@@ -667,6 +668,10 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   }
   Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
+  ctx->weak_dd.resize(ctx->weak.size());
+  for (size_t w = 0; w < ctx->weak.size(); w++)
+    ctx->weak_dd[w] = make_int2(P.dom_of[(size_t)ctx->weak[w].x * nocc + ctx->weak[w].x],
+                                P.dom_of[(size_t)ctx->weak[w].y * nocc + ctx->weak[w].y]);
   ctx->tiles = make_tiles(P, N, false, 64, &ctx->weak, ctx->off.data(), ctx->r.data());
   ctx->tiles128 = make_tiles(P, N, false, 128, &ctx->weak, ctx->off.data(), ctx->r.data());
   const int ndom = (int)P.doms.size();
@@ -847,6 +852,48 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   ctx->stage_ms[1] = t_k.ms();
   ctx->stage_ms[2] = t_prep.ms();
   ctx->stage_ms[3] = t_cpl.ms();
+  return OSV_OK;
+}
+
+
+// ---- allocation-free weak-pair entry point -----------------------------------
+// Device memory for osv_weak_pairs_noalloc: per weak pair its two diagonal
+// domains (int2) and its energy (double), then the fixed-order sum.  One copy per
+// device, held while the process runs; every call on a device shares it.
+constexpr long long NOALLOC_MAX_WEAK = 1LL << 20;
+constexpr size_t NOALLOC_BYTES = (size_t)NOALLOC_MAX_WEAK * (sizeof(int2) + sizeof(double)) + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// out = sum of x[0..n) in a fixed order: thread t sums x[t], x[t + 256], ...,
+// then the 256 partial sums are added pairwise in a fixed tree
+__global__ __launch_bounds__(256) void k_sum_fixed(const double *x, long long n, double *out) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) v += x[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// the device address of this device's scratch, looked up once per device
+static int scratch_ptr(osv_ctx *ctx, unsigned char **out) {
+  static std::mutex mu;
+  static std::map<int, unsigned char *> addr;
+  int dev = 0;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    HIPCHK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ctx, OSV_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    it = addr.emplace(dev, (unsigned char *)p).first;
+  }
+  *out = it->second;
   return OSV_OK;
 }
 
@@ -1238,11 +1285,7 @@ int osv_weak_pairs(osv_ctx *ctx, hipStream_t s, double *E_weak, int64_t *n_weak,
   const int nocc = ctx->nocc;
   int rc;
   if (!ctx->dWeak) {
-    std::vector<int2> dd(nw);
-    for (int w = 0; w < nw; w++)
-      dd[w] = make_int2(ctx->plan.dom_of[(size_t)ctx->weak[w].x * nocc + ctx->weak[w].x],
-                        ctx->plan.dom_of[(size_t)ctx->weak[w].y * nocc + ctx->weak[w].y]);
-    if ((rc = upload(ctx, &ctx->dWeak, dd, s))) return rc;
+    if ((rc = upload(ctx, &ctx->dWeak, ctx->weak_dd, s))) return rc;
     if ((rc = dalloc(ctx, &ctx->dWeakE, nw))) return rc;
   }
   HIPCHK(ctx, launch_weak(ctx->dWeak, nw, ctx->dDom, ctx->dRank, ctx->dK, (long long)ctx->nosv,
@@ -1255,6 +1298,41 @@ int osv_weak_pairs(osv_ctx *ctx, hipStream_t s, double *E_weak, int64_t *n_weak,
   double t = 0.0;
   for (int w = 0; w < nw; w++) t += e[w];
   *E_weak = t;
+  return OSV_OK;
+}
+
+int osv_weak_pairs_noalloc(osv_ctx *ctx, hipStream_t s, double *E_weak, int64_t *n_weak,
+                           double *E_pairs, int32_t *pairs) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!E_weak) return fail(ctx, OSV_E_ARG, "E_weak is NULL");
+  const long long nw = (long long)ctx->weak.size();
+  if (n_weak) *n_weak = nw;
+  *E_weak = 0.0;
+  if (nw > NOALLOC_MAX_WEAK)
+    return fail(ctx, OSV_E_ARG, std::to_string(nw) + " weak pairs exceed the allocation-free limit of " +
+                                    std::to_string(NOALLOC_MAX_WEAK));
+  if (pairs)
+    for (long long w = 0; w < nw; w++) {
+      pairs[2 * w] = ctx->weak[w].x;
+      pairs[2 * w + 1] = ctx->weak[w].y;
+    }
+  if (nw == 0) return OSV_OK;
+  unsigned char *base = nullptr;
+  int rc = scratch_ptr(ctx, &base);
+  if (rc) return rc;
+  // layout: energies (nw doubles), the sum (one double), the domain table (nw int2)
+  double *dE = (double *)base;
+  double *dSum = dE + nw;
+  int2 *dDD = (int2 *)(dSum + 1);
+  HIPCHK(ctx, hipMemcpyAsync(dDD, ctx->weak_dd.data(), nw * sizeof(int2), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, launch_weak(dDD, (int)nw, ctx->dDom, ctx->dRank, ctx->dK, (long long)ctx->nosv, ctx->dW,
+                          ctx->dKt, ctx->F, ctx->nocc, dE, s));
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, (const double *)dE, nw, dSum);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipMemcpyAsync(E_weak, dSum, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (E_pairs)
+    HIPCHK(ctx, hipMemcpyAsync(E_pairs, dE, nw * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
   return OSV_OK;
 }
 
