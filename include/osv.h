@@ -162,9 +162,12 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
 
 /*
  * osv_energy -- MBE(3) inclusion-exclusion of the cluster energies (eq:mbe1):
- *   E = sum_X c_X E^X with c_X = 1 (3b), 1 - n3(IJ) (2b), 1 - n2(I) + n3(I) (1b).
+ *   E = sum_X c_X E^X with c_X = 1 (3b), 1 - n3(IJ) (2b), 1 - n2(I) + n3(I) (1b),
+ *   plus, with OSV_SEL_OVERLAP, the one-block energies of the weak 2b clusters
+ *   (see osv_weak_pairs; their amplitudes are formed by osv_solve_clusters).
  *   E         host, required.
- *   E_orders  host [3] or NULL: E_1b, dE_2b, dE_3b (NaN for OSV_SEL_FULL).
+ *   E_orders  host [3] or NULL: E_1b, dE_2b (weak pairs included), dE_3b (NaN for
+ *             OSV_SEL_FULL).
  *   E_cluster device [n_clusters] or NULL: E^X in canonical cluster order
  *             (all 1b ascending, 2b lexicographic, 3b lexicographic).
  * Errors: OSV_E_STATE before a successful solve, OSV_E_ARG, OSV_E_HIP.  Synchronises.
@@ -180,10 +183,10 @@ int osv_energy(osv_ctx *ctx, hipStream_t stream, double *E, double *E_orders, do
  * domains, where the projected one-block residual
  *   K~_(i,j) + (e~_i[a] + e~_j[b] - f_ii - f_jj) T = 0,   K~ = W_i^T K_ij W_j,
  * is solved in one step, and the pair adds 4 <T, K~> to the energy (both
- * orderings; the exchange block is not represented).  The result is a
- * correction to the E of osv_energy, which it does not include.  Densities of
- * the weak pairs are not computed.  Needs only osv_build_pairs (their K_ij blocks
- * are formed there); other selection modes have no weak pairs.
+ * orderings; the exchange block is not represented).  osv_energy includes the
+ * sum in E and osv_densities the weak pairs' densities (after a solve); this
+ * call gives the pair energies alone and needs only osv_build_pairs (their K_ij
+ * blocks are formed there).  Other selection modes have no weak pairs.
  *   E_weak   host, required: sum of the pair energies in pair order.
  *   n_weak   host or NULL: number of weak pairs.
  *   E_pairs  device [n_weak] or NULL: the pair energies, pairs in (i, j)
@@ -215,7 +218,9 @@ int osv_weak_pairs_noalloc(osv_ctx *ctx, hipStream_t stream, double *E_weak, int
 
 /*
  * osv_densities -- exact derivatives of the MBE energy at fixed Q (Hylleraas
- * stationarity: the amplitudes contribute nothing):
+ * stationarity: the amplitudes contribute nothing), the weak pairs' one-block
+ * energies included (OSV_SEL_OVERLAP: dE/dK_ij = 8 T, dE/dF_(i,i) = 4 T T^T,
+ * dE/dF_(j,j) = 4 T^T T, dE/df_ii = dE/df_jj = -4 <T, T>, T in the OSV bases):
  *   dE_dC     device sum(r) x naux row-major FP64: dE/dC_i = sum_j (G_ij + G_ji^T) C_j
  *             with G_ij = sum_X c_X U_i^T (2 Tbar_ij) U_j   (cf. eq:ec2eY).
  *   dE_dFocc  device nocc x nocc row-major: dE/df_uv, every entry taken as an

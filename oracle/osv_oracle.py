@@ -338,14 +338,17 @@ class Cluster:
 def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
           tau_R: float = 1e-10, tau_S: float = 1e-8, max_sweeps: int = 100,
           densities: bool = True, clusters=None, coef=None, order=None,
-          l2b: float = 1e-2, l3b: float = 0.2, dvir: bool = False):
+          l2b: float = 1e-2, l3b: float = 0.2, dvir: bool = False, weak: bool = True):
     """Solve every selected cluster and combine by MBE.  Returns a dict with E,
     E_orders (E_1b, dE_2b, dE_3b), E_cluster, sweeps, and (optionally) dE_dC
     [sum r, naux], dE_dF [nocc, nocc], dE_deps [nvir] and, with dvir, the full
-    virtual density Dvir [nvir, nvir]."""
+    virtual density Dvir [nvir, nvir].  With the overlap selection (and weak) the
+    weak 2b clusters' one-block energies (R15) are added to E and to dE_2b, and
+    their densities to the densities; E_weak holds their sum."""
     mode = sysm.sel_mode if mode is None else mode
     cut2 = sysm.cut2 if cut2 is None else cut2
     cut3 = sysm.cut3 if cut3 is None else cut3
+    s2b = None
     if clusters is None:
         s2b = s2b_metric(sysm) if mode == SEL_OVERLAP else None
         clusters, coef, order = select_clusters(sysm.centroid, mode, cut2, cut3, s2b, l2b, l3b)
@@ -379,9 +382,23 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
                 Dv += coef[n] * dens[3]
     E = float(np.dot(coef, E_cl))
     E_orders = mbe_orders(clusters, order, E_cl)
+    E_weak = 0.0
+    if mode == SEL_OVERLAP and weak:
+        s2b = s2b_metric(sysm) if s2b is None else s2b
+        E_weak = float(np.sum(weak_pairs(sysm, l2b, s2b=s2b)[1]))
+        E += E_weak
+        E_orders = E_orders + np.array([0.0, E_weak, 0.0])
+        if densities:
+            wd = weak_pair_densities(sysm, l2b, s2b=s2b, dvir=dvir)
+            dC += wd[0]
+            dF += wd[1]
+            de += wd[2]
+            if dvir:
+                Dv += wd[3]
     out = dict(E=E, E_orders=E_orders, E_cluster=E_cl, clusters=clusters, coef=coef,
                order=order, sweeps=sweeps, max_residual=maxres, converged=converged,
-               T=T_all, pair_blocks=sum(len(X) * (len(X) + 1) // 2 for X in clusters))
+               T=T_all, pair_blocks=sum(len(X) * (len(X) + 1) // 2 for X in clusters),
+               E_weak=E_weak)
     if densities:
         out.update(dE_dC=dC, dE_dF=dF, dE_deps=de)
         if dvir:
@@ -501,6 +518,28 @@ def weak_pairs(sysm, l2b: float, s2b: np.ndarray = None):
         T = -Kt / D
         out.append(4.0 * float(np.sum(T * Kt)))
     return pairs, np.array(out)
+
+
+def weak_pair_nup(sysm, l2b: float, s2b: np.ndarray = None):
+    """The upper block of the weak pairs' OSV-response intermediate in the one-block
+    approximation of eq:nij2b, N^up_ij = T_(i,j) K_(j,i) (r_i x r_i, OSV basis of
+    LMO i; the lower block is taken as zero).  Since K_ij = Q_i^T B_i B_j^T Q_j and
+    the one-block energy is stationary in T with dE/dK_ij = 8 T, an OSV rotation
+    Q_i -> Q_i (1 + h A) at fixed F_(i,i) moves the energy by 8 h <A, (N^up)^T>.
+    Returns {(i, j): N^up} in pair order."""
+    if s2b is None:
+        s2b = s2b_metric(sysm)
+    pb = PairBlocks(sysm)
+    n = sysm.nocc
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if WEAK_MIN <= s2b[i, j] <= l2b]
+    eig = {p: np.linalg.eigh(pb.F(p, p)) for p in sorted({x for pq in pairs for x in pq})}
+    out = {}
+    for (i, j) in pairs:
+        (ei, Vi), (ej, Vj) = eig[i], eig[j]
+        Kt = Vi.T @ pb.K(i, j) @ Vj
+        T = Vi @ (-Kt / (ei[:, None] + ej[None, :] - pb.f[i, i] - pb.f[j, j])) @ Vj.T
+        out[(i, j)] = T @ pb.K(j, i)
+    return out
 
 
 def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None, dvir: bool = False):

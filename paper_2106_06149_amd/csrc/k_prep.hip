@@ -665,13 +665,17 @@ hipError_t launch_couplings(const Coupling *cpl, const int *ids, int n64, int nb
 // Weak 2b clusters, one-block dispersion scheme: pair (i, j) keeps only the block
 // T_(i,j) in the pseudo-canonical bases of the diagonal domains (i, i) and (j, j)
 // (their W slots, ranks and eigenvalues e~ from the preparation), where the
-// one-block residual K~ + (e~_a + e~_b - f_ii - f_jj) T vanishes in one step;
-// the pair's energy over both orderings is 4 <T, K~> = -4 sum K~^2 / Delta with
-// K~ = W_i^T K_ij W_j.  One workgroup per pair: G = K_ij W_j into LDS, then K~
-// entries from W_i (LDS) and G; fixed-order sums.
+// one-block residual K~ + (e~_a + e~_b - f_ii - f_jj) T~ vanishes in one step:
+// T~ = -K~ / Delta with K~ = W_i^T K_ij W_j.  The pair's energy over both
+// orderings is 4 <T~, K~> = -4 sum K~^2 / Delta.  One workgroup per pair, every
+// product on FP64 MFMA tiles (mma_tiles):
+//   G = K_ij W_j (LDS), K~ = W_i^T G, T~ and the sums e = 4 <T~, K~>, tt = <T~, T~>;
+// with STORE_T also the amplitudes in the OSV bases, T = W_i T~ W_j^T (r_i x r_j,
+// row-major at toff[w]), through the pair's own slot: T~, then W_i T~, then T.
 constexpr int WNT = 256;
 constexpr int WLD = DMAX + 1;
 
+template <bool STORE_T>
 __global__ __launch_bounds__(WNT) void k_weak(const int2 *__restrict__ wp,
                                               const Domain *__restrict__ doms,
                                               const int *__restrict__ rank,
@@ -679,49 +683,88 @@ __global__ __launch_bounds__(WNT) void k_weak(const int2 *__restrict__ wp,
                                               const double *__restrict__ W,
                                               const double *__restrict__ Kep,
                                               const double *__restrict__ F, int nocc,
-                                              double *out) {
-  __shared__ double A[DMAX * WLD];   // W_j, then W_i
-  __shared__ double G[DMAX * WLD];   // K_ij W_j
-  __shared__ double red[WNT / 64];
+                                              const long long *__restrict__ toff, double *Tw,
+                                              double *out_e, double *out_tt) {
+  __shared__ double X[DMAX * WLD];   // W_j, then W_i, then W_j
+  __shared__ double Y[DMAX * WLD];   // K_ij W_j, then T~, then W_i T~
+  __shared__ double red[2 * (WNT / 64)];
   const int2 pr = wp[blockIdx.x];
   const Domain Di = doms[pr.x], Dj = doms[pr.y];
   const int ri = Di.n, rj = Dj.n, dti = rank[pr.x], dtj = rank[pr.y];
   const int tid = threadIdx.x;
   for (int e = tid; e < rj * rj; e += WNT) {
     const int b = e / rj, d = e - b * rj;
-    A[b * WLD + d] = W[Dj.moff + e];
+    X[b * WLD + d] = W[Dj.moff + e];
   }
   __syncthreads();
-  for (int e = tid; e < ri * dtj; e += WNT) {
-    const int a = e / dtj, d = e - a * dtj;
-    const double *Kr = K + (long long)(Di.offp + a) * ld + Dj.offp;
-    double g = 0.0;
-    for (int b = 0; b < rj; b++) g += Kr[b] * A[b * WLD + d];
-    G[a * WLD + d] = g;
-  }
+  mma_tiles<WNT>(ri, dtj, rj, [&](int a, int b) { return K[(long long)(Di.offp + a) * ld + Dj.offp + b]; },
+                 [&](int b, int d) { return X[b * WLD + d]; },
+                 [&](int a, int d, double v) { Y[a * WLD + d] = v; });
   __syncthreads();
   for (int e = tid; e < ri * ri; e += WNT) {
     const int a = e / ri, c = e - a * ri;
-    A[a * WLD + c] = W[Di.moff + e];
+    X[a * WLD + c] = W[Di.moff + e];
   }
   __syncthreads();
   const double *ei = Kep + Di.voff + (long long)Di.np * Di.np;
   const double *ej = Kep + Dj.voff + (long long)Dj.np * Dj.np;
   const double fd = F[Di.p * nocc + Di.p] + F[Dj.p * nocc + Dj.p];
-  double acc = 0.0;
-  for (int e = tid; e < dti * dtj; e += WNT) {
-    const int c = e / dtj, d = e - c * dtj;
-    double kt = 0.0;
-    for (int a = 0; a < ri; a++) kt += A[a * WLD + c] * G[a * WLD + d];
-    acc += kt * kt / (ei[c] + ej[d] - fd);
+  double *T = STORE_T ? Tw + toff[blockIdx.x] : nullptr;
+  double acc = 0.0, tt = 0.0;
+  // K~(c, d) = sum_a W_i(a, c) G(a, d)
+  mma_tiles<WNT>(dti, dtj, ri, [&](int c, int a) { return X[a * WLD + c]; },
+                 [&](int a, int d) { return Y[a * WLD + d]; },
+                 [&](int c, int d, double kt) {
+                   const double t = -kt / (ei[c] + ej[d] - fd);
+                   acc += t * kt;
+                   tt += t * t;
+                   if (STORE_T) T[c * rj + d] = t;
+                 });
+  acc = wave_sum(acc);
+  tt = wave_sum(tt);
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = acc;
+    red[WNT / 64 + (tid >> 6)] = tt;
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
   if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < WNT / 64; w++) t += red[w];
-    out[blockIdx.x] = -4.0 * t;
+    double e = 0.0, t2 = 0.0;
+    for (int w = 0; w < WNT / 64; w++) {
+      e += red[w];
+      t2 += red[WNT / 64 + w];
+    }
+    out_e[blockIdx.x] = 4.0 * e;
+    if (STORE_T) out_tt[blockIdx.x] = t2;
+  }
+  if (STORE_T) {
+    // T~ (written by every wave) back into LDS: the device-scope fence makes the
+    // slot's stores visible to the whole workgroup after the barrier
+    __threadfence();
+    __syncthreads();
+    for (int e = tid; e < dti * dtj; e += WNT) {
+      const int c = e / dtj, d = e - c * dtj;
+      Y[c * WLD + d] = T[c * rj + d];
+    }
+    __syncthreads();
+    // H = W_i T~ (ri x dtj) into the slot
+    mma_tiles<WNT>(ri, dtj, dti, [&](int a, int c) { return X[a * WLD + c]; },
+                   [&](int c, int d) { return Y[c * WLD + d]; },
+                   [&](int a, int d, double v) { T[a * rj + d] = v; });
+    __threadfence();
+    __syncthreads();
+    for (int e = tid; e < ri * dtj; e += WNT) {
+      const int a = e / dtj, d = e - a * dtj;
+      Y[a * WLD + d] = T[a * rj + d];
+    }
+    for (int e = tid; e < rj * rj; e += WNT) {
+      const int b = e / rj, d = e - b * rj;
+      X[b * WLD + d] = W[Dj.moff + e];
+    }
+    __syncthreads();
+    // T = H W_j^T (ri x rj): columns past dt_j of W_j are not used
+    mma_tiles<WNT>(ri, rj, dtj, [&](int a, int d) { return Y[a * WLD + d]; },
+                   [&](int d, int b) { return X[b * WLD + d]; },
+                   [&](int a, int b, double v) { T[a * rj + b] = v; });
   }
 }
 
@@ -729,8 +772,114 @@ hipError_t launch_weak(const int2 *wp, int nweak, const Domain *dom, const int *
                        const double *K, long long ld, const double *W, const double *Kep,
                        const double *F, int nocc, double *out, hipStream_t s) {
   if (nweak <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_weak, dim3(nweak), dim3(WNT), 0, s, wp, dom, rank, K, ld, W, Kep, F, nocc,
-                     out);
+  hipLaunchKernelGGL(k_weak<false>, dim3(nweak), dim3(WNT), 0, s, wp, dom, rank, K, ld, W, Kep, F, nocc,
+                     (const long long *)nullptr, (double *)nullptr, out, (double *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_weak_amplitudes(const int2 *wp, int nweak, const Domain *dom, const int *rank,
+                                  const double *K, long long ld, const double *W, const double *Kep,
+                                  const double *F, int nocc, const long long *toff, double *Tw,
+                                  double *out_e, double *out_tt, hipStream_t s) {
+  if (nweak <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weak<true>, dim3(nweak), dim3(WNT), 0, s, wp, dom, rank, K, ld, W, Kep, F, nocc,
+                     toff, Tw, out_e, out_tt);
+  return hipGetLastError();
+}
+
+// Densities of the weak pairs' one-block energies (stationary one-block Hylleraas
+// functional 8 <T, K_ij> + 4 <T, F_(i,i) T + T F_(j,j) - (f_ii + f_jj) T>, OSV
+// bases, S_(i,i) = 1):
+//   dE/dK_ij = 8 T  ->  G^K_ij = 4 T, G^K_ji = 4 T^T (dE/dC = 2 G^K C);
+//   dE/dF_(i,i) = 4 T T^T, dE/dF_(j,j) = 4 T^T T  ->  G^F diagonal blocks;
+//   dE/df_ii = dE/df_jj = -4 <T, T>.
+// G^K: the (i, j) blocks of weak pairs belong to no pair domain, so they are
+// written once, by the pair's workgroup.
+__global__ __launch_bounds__(WNT) void k_weak_gk(const int2 *__restrict__ lmo, const int *__restrict__ off,
+                                                 const int *__restrict__ r, const long long *__restrict__ toff,
+                                                 const double *__restrict__ Tw, double *GK, long long ld) {
+  const int2 ij = lmo[blockIdx.x];
+  const int ri = r[ij.x], rj = r[ij.y], oi = off[ij.x], oj = off[ij.y];
+  const double *T = Tw + toff[blockIdx.x];
+  for (int e = threadIdx.x; e < ri * rj; e += WNT) {
+    const int a = e / rj, b = e - a * rj;
+    const double v = 4.0 * T[e];
+    GK[(long long)(oi + a) * ld + oj + b] = v;
+    GK[(long long)(oj + b) * ld + oi + a] = v;
+  }
+}
+
+// G^F_(p,p) += 4 sum over the weak pairs holding p, in pair order, of T T^T (p first)
+// or T^T T (p second); one workgroup per LMO, output tiles on FP64 MFMA with each
+// tile's sum over pairs and k in a fixed order.
+__global__ __launch_bounds__(WNT) void k_weak_gf(const long long *__restrict__ lptr,
+                                                 const int *__restrict__ lidx,
+                                                 const int2 *__restrict__ lmo, const int *__restrict__ off,
+                                                 const int *__restrict__ r, const long long *__restrict__ toff,
+                                                 const double *__restrict__ Tw, double *GF, long long ld) {
+  const int p = blockIdx.x;
+  const long long w0 = lptr[p], w1 = lptr[p + 1];
+  if (w0 == w1) return;
+  const int rp = r[p], op = off[p];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l15 = lane & 15, lhi = lane >> 4;
+  const int tn = (rp + 15) >> 4;
+  for (int t = wave; t < tn * tn; t += WNT / 64) {
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+    const int i = i0 + l15, j = j0 + l15;
+    d4p acc = {0, 0, 0, 0};
+    for (long long w = w0; w < w1; w++) {
+      const int pw = lidx[w];
+      const int2 ij = lmo[pw];
+      const bool first = ij.x == p;
+      const int rq = r[first ? ij.y : ij.x];
+      const double *T = Tw + toff[pw];
+      // first: C(i, j) = sum_k T(i, k) T(j, k), T is rp x rq;
+      // second: C(i, j) = sum_k T(k, i) T(k, j), T is rq x rp
+      for (int k0 = 0; k0 < rq; k0 += 4) {
+        const int k = k0 + lhi;
+        double av = 0.0, bv = 0.0;
+        if (k < rq) {
+          if (first) {
+            av = i < rp ? T[i * rq + k] : 0.0;
+            bv = j < rp ? T[j * rq + k] : 0.0;
+          } else {
+            av = i < rp ? T[k * rp + i] : 0.0;
+            bv = j < rp ? T[k * rp + j] : 0.0;
+          }
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int ii = i0 + 4 * v + lhi;
+      if (ii < rp && j < rp) GF[(long long)(op + ii) * ld + op + j] += 4.0 * acc[v];
+    }
+  }
+}
+
+// dE/df_pp -= 4 sum over the weak pairs holding p, in pair order, of <T, T>
+__global__ void k_weak_focc(const long long *__restrict__ lptr, const int *__restrict__ lidx,
+                            const double *__restrict__ tt, int nocc, double *dF) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nocc) return;
+  double s = 0.0;
+  for (long long w = lptr[p]; w < lptr[p + 1]; w++) s += tt[lidx[w]];
+  if (lptr[p + 1] > lptr[p]) dF[(long long)p * nocc + p] -= 4.0 * s;
+}
+
+hipError_t launch_weak_densities(int nweak, int nocc, const int2 *lmo, const int *off, const int *r,
+                                  const long long *toff, const double *Tw, const double *tt,
+                                  const long long *lptr, const int *lidx, double *GK, double *GF,
+                                  long long ld, double *dF, hipStream_t s) {
+  if (nweak <= 0) return hipSuccess;
+  if (GK)
+    hipLaunchKernelGGL(k_weak_gk, dim3(nweak), dim3(WNT), 0, s, lmo, off, r, toff, Tw, GK, ld);
+  if (GF)
+    hipLaunchKernelGGL(k_weak_gf, dim3(nocc), dim3(WNT), 0, s, lptr, lidx, lmo, off, r, toff, Tw, GF, ld);
+  if (dF)
+    hipLaunchKernelGGL(k_weak_focc, dim3((nocc + 255) / 256), dim3(256), 0, s, lptr, lidx, tt, nocc, dF);
   return hipGetLastError();
 }
 

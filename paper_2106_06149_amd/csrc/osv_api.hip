@@ -445,6 +445,16 @@ struct osv_ctx {
   std::vector<int2> weak_dd;  // their diagonal domains ((i, i), (j, j))
   int2 *dWeak = nullptr;      // their diagonal domains
   double *dWeakE = nullptr;   // their one-block energies
+  // the weak pairs inside the MBE energy and densities (overlap selection): per
+  // pair its amplitudes in the OSV bases (slot at weak_toff), energy and <T, T>;
+  // per LMO the weak pairs holding it (CSR, pair order)
+  std::vector<long long> weak_toff, weak_lptr;
+  std::vector<int> weak_lidx;
+  long long weak_nT = 0;
+  int2 *dWeakDom = nullptr, *dWeakLmo = nullptr;
+  long long *dWeakToff = nullptr, *dWeakLptr = nullptr;
+  int *dWeakLidx = nullptr;
+  double *dWeakT = nullptr, *dWeakEa = nullptr, *dWeakTT = nullptr, *dWeakSum = nullptr;
   long long *dDiagMoff = nullptr;  // per LMO p: W slot of domain (p, p), or -1
   Domain *dDom = nullptr;
   Coupling *dCpl = nullptr;
@@ -672,6 +682,25 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   for (size_t w = 0; w < ctx->weak.size(); w++)
     ctx->weak_dd[w] = make_int2(P.dom_of[(size_t)ctx->weak[w].x * nocc + ctx->weak[w].x],
                                 P.dom_of[(size_t)ctx->weak[w].y * nocc + ctx->weak[w].y]);
+  if (!ctx->weak.empty()) {
+    const size_t nw = ctx->weak.size();
+    ctx->weak_toff.resize(nw);
+    ctx->weak_nT = 0;
+    ctx->weak_lptr.assign(nocc + 1, 0);
+    for (size_t w = 0; w < nw; w++) {
+      ctx->weak_toff[w] = ctx->weak_nT;
+      ctx->weak_nT += (long long)ctx->r[ctx->weak[w].x] * ctx->r[ctx->weak[w].y];
+      ctx->weak_lptr[ctx->weak[w].x + 1]++;
+      ctx->weak_lptr[ctx->weak[w].y + 1]++;
+    }
+    for (int i = 0; i < nocc; i++) ctx->weak_lptr[i + 1] += ctx->weak_lptr[i];
+    ctx->weak_lidx.assign(ctx->weak_lptr[nocc], 0);
+    std::vector<long long> fill(ctx->weak_lptr.begin(), ctx->weak_lptr.end() - 1);
+    for (size_t w = 0; w < nw; w++) {
+      ctx->weak_lidx[fill[ctx->weak[w].x]++] = (int)w;
+      ctx->weak_lidx[fill[ctx->weak[w].y]++] = (int)w;
+    }
+  }
   ctx->tiles = make_tiles(P, N, false, 64, &ctx->weak, ctx->off.data(), ctx->r.data());
   ctx->tiles128 = make_tiles(P, N, false, 128, &ctx->weak, ctx->off.data(), ctx->r.data());
   const int ndom = (int)P.doms.size();
@@ -1079,6 +1108,25 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   StageTimer t(s);
   HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 3, s));
   HIPCHK(ctx, launch_solve(a, P.n_big, P.n_first, ctx->nwg, s));
+  // the weak pairs' one-block amplitudes (one step each, in the OSV bases)
+  const int nweak = (int)ctx->weak.size();
+  if (nweak > 0) {
+    int rc;
+    if (!ctx->dWeakT) {
+      if ((rc = upload(ctx, &ctx->dWeakDom, ctx->weak_dd, s))) return rc;
+      if ((rc = upload(ctx, &ctx->dWeakLmo, ctx->weak, s))) return rc;
+      if ((rc = upload(ctx, &ctx->dWeakToff, ctx->weak_toff, s))) return rc;
+      if ((rc = upload(ctx, &ctx->dWeakLptr, ctx->weak_lptr, s))) return rc;
+      if ((rc = upload(ctx, &ctx->dWeakLidx, ctx->weak_lidx, s))) return rc;
+      if ((rc = dalloc(ctx, &ctx->dWeakT, (size_t)ctx->weak_nT))) return rc;
+      if ((rc = dalloc(ctx, &ctx->dWeakEa, nweak))) return rc;
+      if ((rc = dalloc(ctx, &ctx->dWeakTT, nweak))) return rc;
+      if ((rc = dalloc(ctx, &ctx->dWeakSum, 1))) return rc;
+    }
+    HIPCHK(ctx, launch_weak_amplitudes(ctx->dWeakDom, nweak, ctx->dDom, ctx->dRank, ctx->dK,
+                                       (long long)ctx->nosv, ctx->dW, ctx->dKt, ctx->F, ctx->nocc,
+                                       ctx->dWeakToff, ctx->dWeakT, ctx->dWeakEa, ctx->dWeakTT, s));
+  }
   t.stop();
   // host bookkeeping while the kernel runs (the density tables are uploaded by
   // the first osv_densities call)
@@ -1122,20 +1170,28 @@ int osv_energy(osv_ctx *ctx, hipStream_t s, double *E, double *E_orders, double 
   const int ncl = (int)ctx->plan.cls.size();
   StageTimer t(s);
   HIPCHK(ctx, launch_wdot(ctx->dEcl, ctx->dWts, ncl, 4, ctx->dEout, s));
+  const long long nweak = (long long)ctx->weak.size();
+  if (nweak > 0) {
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, (const double *)ctx->dWeakEa, nweak,
+                       ctx->dWeakSum);
+    HIPCHK(ctx, hipGetLastError());
+  }
   t.stop();
-  double h[4];
+  double h[4], ew = 0.0;
   HIPCHK(ctx, hipMemcpyAsync(h, ctx->dEout, sizeof(h), hipMemcpyDeviceToHost, s));
+  if (nweak > 0) HIPCHK(ctx, hipMemcpyAsync(&ew, ctx->dWeakSum, sizeof(double), hipMemcpyDeviceToHost, s));
   if (E_cluster)
     HIPCHK(ctx, hipMemcpyAsync(E_cluster, ctx->dEcl, ncl * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   ctx->stage_ms[5] = t.ms();
-  *E = h[0];
+  // the weak pairs are 2-body increments: E and dE_2b include them
+  *E = h[0] + ew;
   if (E_orders) {
     if (ctx->mode == OSV_SEL_FULL) {
       E_orders[0] = E_orders[1] = E_orders[2] = std::nan("");
     } else {
       E_orders[0] = h[1];
-      E_orders[1] = h[2];
+      E_orders[1] = h[2] + ew;
       E_orders[2] = h[3];
     }
   }
@@ -1350,6 +1406,11 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
                              ctx->dDcoef, ctx->dGK, ld, ctx->dGd, s));
   HIPCHK(ctx, launch_assemble_gf(ctx->dDom, ctx->dBptr, ctx->dBdom, ctx->dBpart, ctx->dBlocks, ctx->nblocks,
                                  ctx->dOff, ctx->dR, ctx->dGd, ctx->dGF, ld, s));
+  const int nweak = (int)ctx->weak.size();
+  // the weak pairs' G^K (i, j) blocks and G^F diagonal blocks
+  HIPCHK(ctx, launch_weak_densities(nweak, ctx->nocc, ctx->dWeakLmo, ctx->dOff, ctx->dR, ctx->dWeakToff,
+                                    ctx->dWeakT, ctx->dWeakTT, ctx->dWeakLptr, ctx->dWeakLidx, ctx->dGK,
+                                    ctx->dGF, ld, nullptr, s));
   t_adj.stop();
   StageTimer t_bt(s);
   if (dE_dC) {
@@ -1369,8 +1430,12 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
       HIPCHK(ctx, launch_gemm_tn_f64(ctx->Q, ctx->nvir, ctx->dZt, ctx->nvir, Dvir_full, ctx->nvir, ctx->nvir,
                                      ctx->nvir, N, 1.0, s));
   }
-  if (dE_dFocc)
+  if (dE_dFocc) {
     HIPCHK(ctx, launch_pocc(ctx->dPptr, ctx->dPidx, ctx->dClcoef, ctx->dPl, ctx->nocc, dE_dFocc, s));
+    HIPCHK(ctx, launch_weak_densities(nweak, ctx->nocc, ctx->dWeakLmo, ctx->dOff, ctx->dR, ctx->dWeakToff,
+                                      ctx->dWeakT, ctx->dWeakTT, ctx->dWeakLptr, ctx->dWeakLidx, nullptr,
+                                      nullptr, ld, dE_dFocc, s));
+  }
   t_bt.stop();
   HIPCHK(ctx, hipStreamSynchronize(s));
   ctx->stage_ms[6] = t_adj.ms();

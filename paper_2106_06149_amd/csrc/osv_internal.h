@@ -156,6 +156,19 @@ constexpr double OSV_WEAK_MIN = 1e-7;   // weak pairs below this s2b are discard
 hipError_t launch_weak(const int2 *wp, int nweak, const Domain *dom, const int *rank,
                        const double *K, long long ld, const double *W, const double *Kep,
                        const double *F, int nocc, double *out, hipStream_t s);
+// the same pairs with their amplitudes kept: T = W_i T~ W_j^T (r_i x r_j, row-major
+// at toff[w]), pair energies out_e and <T, T> out_tt
+hipError_t launch_weak_amplitudes(const int2 *wp, int nweak, const Domain *dom, const int *rank,
+                                  const double *K, long long ld, const double *W, const double *Kep,
+                                  const double *F, int nocc, const long long *toff, double *Tw,
+                                  double *out_e, double *out_tt, hipStream_t s);
+// the weak pairs' density contributions: G^K (i, j) blocks (written), G^F diagonal
+// blocks (added, per LMO over lptr/lidx in pair order) and dE/df_pp (added); any
+// of GK, GF, dF may be null
+hipError_t launch_weak_densities(int nweak, int nocc, const int2 *lmo, const int *off, const int *r,
+                                 const long long *toff, const double *Tw, const double *tt,
+                                 const long long *lptr, const int *lidx, double *GK, double *GF,
+                                 long long ld, double *dF, hipStream_t s);
 // queue: [0, n_big) global descriptors; [n_big, n_first) and [n_first, n) LDS
 // descriptors in two launches (the second one's clusters may start from amplitudes
 // of the first one's)

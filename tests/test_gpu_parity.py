@@ -365,3 +365,80 @@ def test_weak_pair_of_largest_diagonal_domains():
     assert rp == [(0, 1)] and [tuple(int(x) for x in p) for p in pairs] == rp
     assert abs(Ep.cpu().numpy()[0] - re[0]) <= 1e-10 * abs(re[0])
     assert abs(E - re[0]) <= 1e-10 * abs(re[0])
+
+
+def _median_l2b(s):
+    s2b = O.s2b_metric(s)
+    off = np.sort(s2b[np.triu_indices(s.nocc, 1)])
+    h = len(off) // 2
+    return float(0.5 * (off[h - 1] + off[h])), s2b
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_weak_pairs_in_energy_and_densities(precision):
+    """Overlap selection with strong clusters and weak pairs: E (weak one-block
+    energies in dE_2b), every cluster energy and every density element, the full
+    virtual density included, against the oracle's MBE(3) with weak pairs."""
+    c_dtype = np.float32 if precision == 1 else np.float64
+    s = synth.make_system(9, 70, 60, (5, 12), seed=37, sel_mode=synth.SEL_OVERLAP,
+                          c_dtype=c_dtype, precision=precision)
+    l2b, s2b = _median_l2b(s)
+    say(f"case weak pairs in E and densities precision={precision} nocc=9 l2b={l2b:.3g}")
+    g = run_gpu(s, sel=Selection(L.OSV_SEL_OVERLAP, l2b=l2b, l3b=0.9 * l2b))
+    ref = O.solve(s, mode=synth.SEL_OVERLAP, l2b=l2b, l3b=0.9 * l2b, dvir=True)
+    assert ref["E_weak"] < 0.0 and g["counts"]["n2b"] > 0
+    compare(s, g, ref, dens_tol=1e-8 if precision == 0 else 1e-7)
+
+
+def test_weak_pairs_only_largest_domains():
+    """Every pair weak (l2b above every metric value), OSV sets of 50 and 43 with
+    ragged tiles: the one-block amplitudes, energies and densities alone."""
+    s = synth.make_system(3, 120, 40, [50, 43, 21], seed=38, sel_mode=synth.SEL_OVERLAP)
+    say("case weak pairs only nocc=3 r=[50,43,21]")
+    g = run_gpu(s, sel=Selection(L.OSV_SEL_OVERLAP, l2b=2.0, l3b=2.0))
+    assert g["counts"]["n2b"] == 0
+    ref = O.solve(s, mode=synth.SEL_OVERLAP, l2b=2.0, l3b=2.0, dvir=True)
+    compare(s, g, ref)
+
+
+def test_weak_pairs_autograd_finite_differences():
+    """The autograd backward of an overlap-selected MBE(3) energy (strong clusters
+    and weak pairs) against central differences, h = 1e-5, of the forward."""
+    from paper_2106_06149_amd.autograd import OSVEnergy
+    s = synth.make_system(8, 50, 40, (4, 9), seed=39, sel_mode=synth.SEL_OVERLAP)
+    l2b, _ = _median_l2b(s)
+    sel = Selection(L.OSV_SEL_OVERLAP, l2b=l2b, l3b=0.9 * l2b)
+    dev = torch.device("cuda:0")
+    Qt = torch.from_numpy(np.ascontiguousarray(s.Q.T)).to(dev)
+    C = torch.from_numpy(s.C).to(dev).requires_grad_(True)
+    F = torch.from_numpy(s.F_occ).to(dev).requires_grad_(True)
+    eps = torch.from_numpy(s.eps_vir).to(dev).requires_grad_(True)
+    say(f"case weak-pair autograd FD nocc=8 l2b={l2b:.3g}")
+    E = OSVEnergy.apply(C, F, eps, Qt, s.r, s.centroid, sel, 0, 1e-12)
+    gC, gF, ge = [t.cpu().numpy() for t in torch.autograd.grad(E, (C, F, eps))]
+
+    def energy(Cx, Fx, ex):
+        with torch.no_grad():
+            return float(OSVEnergy.apply(Cx, Fx, ex, Qt, s.r, s.centroid, sel, 0, 1e-12))
+
+    h = 1e-5
+    rng = np.random.default_rng(8)
+    C0, F0, e0 = C.detach(), F.detach(), eps.detach()
+    for t in range(4):
+        a = int(rng.integers(0, s.nosv))
+        b = int(np.argmax(np.abs(gC[a])))
+        Cp = C0.clone(); Cp[a, b] += h
+        Cm = C0.clone(); Cm[a, b] -= h
+        fd = (energy(Cp, F0, e0) - energy(Cm, F0, e0)) / (2 * h)
+        assert abs(fd - gC[a, b]) <= 1e-7 * abs(fd) + 1e-10, ("C", a, b, fd, gC[a, b])
+    for (u, v) in [(0, 0), (5, 5), (2, 3)]:
+        Fp = F0.clone(); Fp[u, v] += h; Fp[v, u] = Fp[u, v]
+        Fm = F0.clone(); Fm[u, v] -= h; Fm[v, u] = Fm[u, v]
+        fd = (energy(C0, Fp, e0) - energy(C0, Fm, e0)) / (2 * h)
+        an = gF[u, v] + (gF[v, u] if u != v else 0.0)
+        assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10, ("F", u, v, fd, an)
+    for a in (3, 29):
+        ep = e0.clone(); ep[a] += h
+        em = e0.clone(); em[a] -= h
+        fd = (energy(C0, F0, ep) - energy(C0, F0, em)) / (2 * h)
+        assert abs(fd - ge[a]) <= 1e-7 * abs(fd) + 1e-10, ("eps", a, fd, ge[a])

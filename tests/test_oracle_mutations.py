@@ -44,6 +44,9 @@ MUTATIONS = {
     "weak_dvir_drops_j_side": ("Dv += 4.0 * (Qi @ (T @ T.T) @ Qi.T + Qj @ (T.T @ T) @ Qj.T)",
                                "Dv += 4.0 * (Qi @ (T @ T.T) @ Qi.T)"),
     "weak_energy_factor": ("out.append(4.0 * float(np.sum(T * Kt)))", "out.append(2.0 * float(np.sum(T * Kt)))"),
+    "overlap_solve_drops_weak_dC": ("dC += wd[0]", "dC += 0.0 * wd[0]"),
+    "overlap_solve_drops_weak_energy": ("E += E_weak\n", "E += 0.0 * E_weak\n"),
+    "nup_transposed": ("out[(i, j)] = T @ pb.K(j, i)", "out[(i, j)] = (T @ pb.K(j, i)).T"),
     "dC_missing_transpose": ("dC[q] += G.T @ pb.C[p]", "dC[q] += 0.5 * (G + G.T) @ pb.C[p] if G.shape[0] == G.shape[1] else G.T @ pb.C[p]"),
 }
 

@@ -546,3 +546,108 @@ def test_weak_pair_virtual_density_finite_differences():
         fd = (E[0] - E[1]) / (2 * h)
         an = Dv[a, b] + Dv[b, a]
         assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10, (a, b, fd, an)
+
+
+# --- weak pairs inside the overlap-selected MBE(3) solve -----------------------------
+
+def test_weak_pair_nup_is_the_osv_rotation_response():
+    """N^up_ij = T_(i,j) K_(j,i) (eq:nij2b): rotating the OSVs of LMO i by 1 + hA at
+    fixed F_(i,i) (C_i -> (1 + hA)^T C_i, the fitted integrals' part of the
+    rotation) moves the one-block energies by 8 h <A, (N^up)^T>; a random
+    non-symmetric A fixes the orientation of N^up."""
+    import copy
+    s = synth.make_system(4, 16, 10, (3, 5), seed=64, spacing=3.0)
+    s2b = O.s2b_metric(s)
+    nup = O.weak_pair_nup(s, 2.0, s2b=s2b)
+    pairs, _ = O.weak_pairs(s, 2.0, s2b=s2b)
+    assert list(nup) == pairs and len(pairs) == 6
+    rng = np.random.default_rng(11)
+    h = 1e-5
+    for i in (0, 2):
+        A = rng.standard_normal((s.r[i], s.r[i]))
+        E = []
+        for sgn in (1.0, -1.0):
+            sp = copy.deepcopy(s)
+            sl = slice(s.off[i], s.off[i + 1])
+            sp.C = s.C.copy()
+            sp.C[sl] = s.C[sl] + sgn * h * A.T @ s.C[sl]
+            E.append(float(np.sum(O.weak_pairs(sp, 2.0, s2b=s2b)[1])))
+        fd = (E[0] - E[1]) / (2 * h)
+        # the rotation of LMO i moves every weak pair holding i: where i is first
+        # through N^up_ij, where i is second through N^up of the swapped pair
+        an = 0.0
+        for (p, q), N in nup.items():
+            if p == i:
+                an += 8.0 * float(np.sum(A * N.T))
+            elif q == i:
+                # N^up of the swapped pair (q, p): T^T K_(p,q) (r_q x r_q)
+                Nq = O.weak_pair_nup(_Swapped(s, p, q), 2.0, s2b=s2b)
+                an += 8.0 * float(np.sum(A * Nq[(0, 1)].T))
+        assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10, (i, fd, an)
+        assert abs(an) > 1e-6
+
+
+class _Swapped:
+    """Two LMOs (q, p) of a system as a new two-LMO system in that order, so that
+    pair (0, 1) of it is the swapped pair (q, p)."""
+
+    def __init__(self, s, p, q):
+        self.nocc = 2
+        self.r = np.array([s.r[q], s.r[p]])
+        self._Q = [s.Qi(q), s.Qi(p)]
+        self._C = [s.Ci(q), s.Ci(p)]
+        self.eps_vir = s.eps_vir
+        self.F_occ = s.F_occ[np.ix_([q, p], [q, p])]
+
+    def Qi(self, i):
+        return self._Q[i]
+
+    def Ci(self, i):
+        return self._C[i]
+
+
+def test_overlap_solve_with_weak_pairs_finite_differences():
+    """The overlap-selected MBE(3) energy with its weak pairs (strong clusters by
+    eq:2bscreen/eq:3bscreen, weak pairs by the one-block scheme): densities against
+    central differences of the whole energy."""
+    s = synth.make_system(6, 30, 16, (3, 5), seed=66, spacing=1.2, sel_mode=synth.SEL_OVERLAP)
+    s2b = O.s2b_metric(s)
+    off = np.sort(s2b[np.triu_indices(s.nocc, 1)])
+    l2b = float(0.5 * (off[len(off) // 2 - 1] + off[len(off) // 2]))
+    kw = dict(mode=O.SEL_OVERLAP, l2b=l2b, l3b=0.9 * l2b, tau_R=1e-13)
+    res = O.solve(s, **kw)
+    assert res["E_weak"] < 0.0 and sum(1 for X in res["clusters"] if len(X) == 2) > 0
+    assert abs(np.sum(res["E_orders"]) - res["E"]) <= 1e-12 * abs(res["E"])
+    h = 1e-5
+    rng = np.random.default_rng(5)
+
+    def E_of(**chg):
+        import copy
+        sp = copy.deepcopy(s)
+        for k, v in chg.items():
+            setattr(sp, k, v)
+        return O.solve(sp, densities=False, **kw)["E"]
+
+    for _ in range(3):
+        a, b = int(rng.integers(s.nosv)), int(rng.integers(s.naux))
+        Cp, Cm = s.C.copy(), s.C.copy()
+        Cp[a, b] += h
+        Cm[a, b] -= h
+        fd = (E_of(C=Cp) - E_of(C=Cm)) / (2 * h)
+        assert abs(fd - res["dE_dC"][a, b]) <= 1e-7 * abs(fd) + 1e-10
+    for c in (1, 17):
+        ep, em = s.eps_vir.copy(), s.eps_vir.copy()
+        ep[c] += h
+        em[c] -= h
+        fd = (E_of(eps_vir=ep) - E_of(eps_vir=em)) / (2 * h)
+        assert abs(fd - res["dE_deps"][c]) <= 1e-7 * abs(fd) + 1e-10
+    for (u, v) in [(0, 0), (3, 3), (1, 2)]:
+        Fp, Fm = s.F_occ.copy(), s.F_occ.copy()
+        Fp[u, v] += h
+        Fm[u, v] -= h
+        if u != v:
+            Fp[v, u] += h
+            Fm[v, u] -= h
+        fd = (E_of(F_occ=Fp) - E_of(F_occ=Fm)) / (2 * h)
+        an = res["dE_dF"][u, v] + (res["dE_dF"][v, u] if u != v else 0.0)
+        assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10
