@@ -583,3 +583,43 @@ def weak_pair_densities(sysm, l2b: float, s2b: np.ndarray = None, dvir: bool = F
     if dvir:
         return dC, dF, de, Dv
     return dC, dF, de
+
+
+# ---------------------------------------------------------------------------
+# OSV generation from the fitted integrals (eq:svd, eq:osv)
+# ---------------------------------------------------------------------------
+
+def diagonal_pair_amplitudes(B: np.ndarray, eps_vir: np.ndarray, F_occ: np.ndarray, k: int) -> np.ndarray:
+    """[T_kk]_ab = (ka|kb) / (f_aa + f_bb - 2 f_kk) with (ka|kb) = sum_P B_k[a,P] B_k[b,P]
+    (the text's sign: positive, so T_kk is positive semidefinite as the elementwise
+    product of two positive semidefinite matrices)."""
+    K = B[k] @ B[k].T
+    D = eps_vir[:, None] + eps_vir[None, :] - 2.0 * F_occ[k, k]
+    return K / D
+
+
+def generate_osvs(B: np.ndarray, eps_vir: np.ndarray, F_occ: np.ndarray, l_osv: float = 1e-4,
+                  r_max: int = None):
+    """OSVs of every LMO k (eq:svd): the orthonormal eigenvectors of T_kk whose
+    eigenvalues omega exceed l_osv, largest first, at most r_max of them; each
+    eigenvector's entry of largest magnitude (first one on ties) is made positive.
+    Returns (r [nocc], Q [nvir, sum r] column blocks per LMO, C [sum r, naux] with
+    C_k = Q_k^T B_k (eq:osv applied to the fitted integrals), omega list)."""
+    nocc, nvir, naux = B.shape
+    r_max = nvir if r_max is None else r_max
+    rs, Qs, Cs, oms = [], [], [], []
+    for k in range(nocc):
+        w, V = np.linalg.eigh(diagonal_pair_amplitudes(B, eps_vir, F_occ, k))
+        order = np.argsort(-w, kind="stable")
+        keep = [i for i in order if w[i] > l_osv][:r_max]
+        Qk = V[:, keep].copy()
+        for c in range(Qk.shape[1]):
+            m = int(np.argmax(np.abs(Qk[:, c])))
+            if Qk[m, c] < 0.0:
+                Qk[:, c] = -Qk[:, c]
+        rs.append(len(keep))
+        Qs.append(Qk)
+        Cs.append(Qk.T @ B[k])
+        oms.append(w[keep])
+    return (np.array(rs, dtype=np.int32), np.asfortranarray(np.hstack(Qs)),
+            np.ascontiguousarray(np.vstack(Cs)), oms)

@@ -47,6 +47,11 @@ MUTATIONS = {
     "overlap_solve_drops_weak_dC": ("dC += wd[0]", "dC += 0.0 * wd[0]"),
     "overlap_solve_drops_weak_energy": ("E += E_weak\n", "E += 0.0 * E_weak\n"),
     "nup_transposed": ("out[(i, j)] = T @ pb.K(j, i)", "out[(i, j)] = (T @ pb.K(j, i)).T"),
+    "osvgen_denominator": ("D = eps_vir[:, None] + eps_vir[None, :] - 2.0 * F_occ[k, k]",
+                           "D = 2.0 * eps_vir[:, None] - 2.0 * F_occ[k, k]"),
+    "osvgen_ascending": ('order = np.argsort(-w, kind="stable")', 'order = np.argsort(w, kind="stable")'),
+    "osvgen_wrong_lmo_C": ("Cs.append(Qk.T @ B[k])", "Cs.append(Qk.T @ B[(k + 1) % nocc])"),
+    "osvgen_threshold": ("if w[i] > l_osv][:r_max]", "if w[i] > 0.5 * l_osv][:r_max]"),
     "dC_missing_transpose": ("dC[q] += G.T @ pb.C[p]", "dC[q] += 0.5 * (G + G.T) @ pb.C[p] if G.shape[0] == G.shape[1] else G.T @ pb.C[p]"),
 }
 

@@ -651,3 +651,69 @@ def test_overlap_solve_with_weak_pairs_finite_differences():
         fd = (E_of(F_occ=Fp) - E_of(F_occ=Fm)) / (2 * h)
         an = res["dE_dF"][u, v] + (res["dE_dF"][v, u] if u != v else 0.0)
         assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10
+
+
+# --- OSV generation (eq:svd) ---------------------------------------------------------
+
+def test_osv_generation_hand_example():
+    """Closed-form two-virtual example (tests/golden/osv_gen_2x2.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "osv_gen_2x2.json")))
+    B = np.array(g["B"])
+    eps, F = np.array(g["eps_vir"]), np.array(g["F_occ"])
+    r, Q, C, om = O.generate_osvs(B, eps, F, l_osv=g["l_osv"])
+    assert list(r) == g["r"]
+    assert np.allclose(om[0], g["omega"], rtol=1e-15, atol=0)
+    assert np.allclose(Q, np.array(g["Q"]), rtol=0, atol=1e-15)
+    assert np.allclose(C, np.array(g["C"]), rtol=0, atol=1e-15)
+    r, Q, C, om = O.generate_osvs(B, eps, F, l_osv=0.0)
+    assert list(r) == [2] and np.allclose(om[0], g["omega_all"], rtol=1e-15, atol=0)
+
+
+def test_osv_generation_full_span_is_canonical_mp2():
+    """l_osv = 0 keeps every OSV (T_kk is positive definite here): each Q_k is square
+    orthogonal, and OSV-MP2 on the generated OSVs is canonical MP2 from B."""
+    s = synth.make_system(3, 9, 12, 9, seed=81, sel_mode=synth.SEL_FULL)
+    r, Q, C, om = O.generate_osvs(s.B, s.eps_vir, s.F_occ, l_osv=0.0)
+    assert list(r) == [9, 9, 9]
+    for k in range(3):
+        Qk = Q[:, 9 * k:9 * (k + 1)]
+        assert np.allclose(Qk.T @ Qk, np.eye(9), atol=1e-13)
+        assert np.allclose(Qk @ Qk.T, np.eye(9), atol=1e-13)
+    g = synth.System(nocc=3, nvir=9, naux=12, r=r, centroid=s.centroid, F_occ=s.F_occ,
+                     eps_vir=s.eps_vir, Q=Q, C=C, B=s.B, sel_mode=synth.SEL_FULL)
+    E_can, _ = O.mp2_canonical(s.B, s.eps_vir, s.F_occ)
+    assert abs(O.solve(g, densities=False, tau_R=1e-13)["E"] - E_can) <= 1e-12 * abs(E_can)
+
+
+def test_osv_generation_trace_and_truncation():
+    """All eigenvalues sum to tr T_kk = sum_a |B_k[a]|^2 / (2 eps_a - 2 f_kk); a
+    threshold keeps exactly the eigenvalues above it, largest first, and r_max keeps
+    the largest ones; C_k = Q_k^T B_k spans the projection of B_k."""
+    s = synth.make_system(4, 30, 40, 5, seed=82)
+    _, _, _, om_all = O.generate_osvs(s.B, s.eps_vir, s.F_occ, l_osv=-1.0)
+    for k in range(4):
+        tr = float(np.sum(np.sum(s.B[k] ** 2, axis=1) / (2.0 * s.eps_vir - 2.0 * s.F_occ[k, k])))
+        assert abs(np.sum(om_all[k]) - tr) <= 1e-13 * tr
+        assert np.all(np.diff(om_all[k]) <= 0.0) and om_all[k][-1] > 0.0
+    l = float(np.median(np.concatenate(om_all)))
+    r, Q, C, om = O.generate_osvs(s.B, s.eps_vir, s.F_occ, l_osv=l)
+    off = np.concatenate([[0], np.cumsum(r)])
+    for k in range(4):
+        assert r[k] == int(np.sum(om_all[k] > l))
+        assert np.allclose(om[k], om_all[k][:r[k]], rtol=1e-14, atol=0)
+        Qk = Q[:, off[k]:off[k + 1]]
+        assert np.allclose(C[off[k]:off[k + 1]], Qk.T @ s.B[k], atol=1e-14)
+    r3, _, _, om3 = O.generate_osvs(s.B, s.eps_vir, s.F_occ, l_osv=l, r_max=3)
+    assert list(r3) == [min(3, x) for x in r]
+
+
+def test_osv_generation_invariant_under_fitting_rotation():
+    """(ka|kb) and so T_kk, its eigenvalues and the OSVs do not change when the
+    fitting basis is rotated (B_k -> B_k U, U orthogonal); C_k rotates with it."""
+    s = synth.make_system(3, 20, 15, 5, seed=83)
+    U, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((15, 15)))
+    r, Q, C, om = O.generate_osvs(s.B, s.eps_vir, s.F_occ, l_osv=1e-4)
+    r2, Q2, C2, om2 = O.generate_osvs(s.B @ U, s.eps_vir, s.F_occ, l_osv=1e-4)
+    assert list(r) == list(r2)
+    assert np.allclose(Q, Q2, atol=1e-12)
+    assert np.allclose(C @ U, C2, atol=1e-12)
