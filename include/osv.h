@@ -234,6 +234,31 @@ int osv_densities(osv_ctx *ctx, hipStream_t stream, double *dE_dC, double *dE_dF
                   double *dE_deps, double *Dvir_full);
 
 /*
+ * osv_generate_osvs -- the OSVs of every LMO from the fitted integrals (eq:svd,
+ * eq:osv): Q_k holds the orthonormal eigenvectors of the diagonal MP2 amplitudes
+ *   [T_kk]_ab = (ka|kb) / (f_aa + f_bb - 2 f_kk),  (ka|kb) = sum_P B_k[a,P] B_k[b,P],
+ * whose eigenvalues omega exceed l_osv, largest first, at most r_max of them; each
+ * column's entry of largest magnitude is positive.  C_k = Q_k^T B_k are the
+ * OSV-projected fitted integrals osv_system takes.  (ka|kb) on FP64 MFMA, then per
+ * LMO a Householder reduction, bisection and inverse iteration in FP64.
+ *   nocc, nvir, naux  sizes; 1 <= nvir <= 1024.
+ *   B        device nocc x nvir x naux row-major (B_k = rows k nvir .. of naux).
+ *   eps_vir  device [nvir]; F_occ device nocc x nocc row-major (its diagonal f_kk).
+ *   l_osv    eigenvalue cut (the paper's default 1e-4); r_max in [1, min(nvir, OSV_MAX_DOMAIN)].
+ *   r        host out [nocc]: OSVs kept per LMO (may be 0).
+ *   omega    device out nocc x r_max or NULL: row k holds the r_k kept eigenvalues, zeros after.
+ *   Q        device out, nvir x (nocc r_max) column-major capacity (ld nvir): the first
+ *            sum(r) columns receive Q in the osv_system layout (block k at off_k).
+ *   C        device out or NULL, (nocc r_max) x naux row-major capacity: the first
+ *            sum(r) rows receive C in the osv_system layout.
+ * Errors: OSV_E_ARG, OSV_E_NONFINITE (NaN/Inf in B, eps_vir, F_occ), OSV_E_NOMEM,
+ * OSV_E_HIP.  Synchronises the stream; device work memory comes from the block cache.
+ */
+int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B, const double *eps_vir,
+                      const double *F_occ, double l_osv, int32_t r_max, hipStream_t stream, int32_t *r,
+                      double *omega, double *Q, double *C);
+
+/*
  * osv_plan_clusters -- host-only cluster selection for OSV_SEL_DISTANCE and
  * OSV_SEL_FULL (no device work; usable without a GPU).
  *   nocc, centroid (host nocc x 3), sel: as above.

@@ -57,6 +57,31 @@ def plan_clusters(centroid: np.ndarray, sel: Selection):
     return counts.as_dict(), lmos, coef
 
 
+def generate_osvs(B: torch.Tensor, eps_vir: torch.Tensor, F_occ: torch.Tensor,
+                  l_osv: float = 1e-4, r_max: int = 50):
+    """OSVs from the fitted integrals B (nocc x nvir x naux, FP64, on the device):
+    returns (r [nocc] int32 numpy array, Qt [sum r, nvir] (Q in the layout
+    OSVContext takes), C [sum r, naux], omega [nocc, r_max])."""
+    for name, t in (("B", B), ("eps_vir", eps_vir), ("F_occ", F_occ)):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if B.dim() != 3 or eps_vir.shape != (B.shape[1],) or F_occ.shape != (B.shape[0], B.shape[0]):
+        raise ValueError("B must be nocc x nvir x naux with eps_vir [nvir] and F_occ nocc x nocc")
+    nocc, nvir, naux = (int(x) for x in B.shape)
+    lib = L.load()
+    r = np.zeros(nocc, dtype=np.int32)
+    f64 = dict(dtype=torch.float64, device=B.device)
+    Qt = torch.empty(nocc * r_max, nvir, **f64)
+    C = torch.empty(nocc * r_max, naux, **f64)
+    om = torch.empty(nocc, r_max, **f64)
+    with torch.cuda.device(B.device):
+        L.check(lib.osv_generate_osvs(nocc, nvir, naux, _ptr(B), _ptr(eps_vir), _ptr(F_occ), l_osv, r_max,
+                                      _stream(B.device), r.ctypes.data_as(ctypes.c_void_p), _ptr(om),
+                                      _ptr(Qt), _ptr(C)))
+    n = int(r.sum())
+    return r, Qt[:n], C[:n], om
+
+
 def validate_inputs(Q: torch.Tensor, C: torch.Tensor, eps_vir: torch.Tensor,
                     F_occ: torch.Tensor, r) -> None:
     """Checks the tensors handed to the library against osv_system: the library

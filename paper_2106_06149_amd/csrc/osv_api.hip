@@ -927,6 +927,23 @@ static int scratch_ptr(osv_ctx *ctx, unsigned char **out) {
 }
 
 
+// Device buffers of one osv_generate_osvs call, returned to the block cache on exit.
+struct GenBuffers {
+  std::vector<void *> blocks;
+  template <class T>
+  hipError_t get(T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = pool_alloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) blocks.push_back(q);
+    *p = (T *)q;
+    return e;
+  }
+  ~GenBuffers() {
+    if (!blocks.empty()) (void)hipDeviceSynchronize();
+    for (void *q : blocks) pool_free(q);
+  }
+};
+
 extern "C" {
 
 const char *osv_status_string(int st) {
@@ -1389,6 +1406,87 @@ int osv_weak_pairs_noalloc(osv_ctx *ctx, hipStream_t s, double *E_weak, int64_t 
   if (E_pairs)
     HIPCHK(ctx, hipMemcpyAsync(E_pairs, dE, nw * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  return OSV_OK;
+}
+
+int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B, const double *eps_vir,
+                      const double *F_occ, double l_osv, int32_t r_max, hipStream_t s, int32_t *r,
+                      double *omega, double *Q, double *C) {
+  if (nocc < 1 || nvir < 1 || naux < 1 || !B || !eps_vir || !F_occ || !r || !Q)
+    return fail(nullptr, OSV_E_ARG, "osv_generate_osvs: bad sizes or NULL pointer");
+  if (nvir > OSV_GEN_MAX_NVIR)
+    return fail(nullptr, OSV_E_ARG, "osv_generate_osvs: nvir above " + std::to_string(OSV_GEN_MAX_NVIR));
+  if (r_max < 1 || r_max > nvir || r_max > OSV_MAX_DOMAIN)
+    return fail(nullptr, OSV_E_ARG, "osv_generate_osvs: r_max must lie in [1, min(nvir, OSV_MAX_DOMAIN)]");
+  if (!(l_osv == l_osv)) return fail(nullptr, OSV_E_ARG, "osv_generate_osvs: l_osv is NaN");
+  const long long n2 = (long long)nvir * nvir;
+  GenBuffers gb;
+  int *flag = nullptr;
+  double *T = nullptr, *d = nullptr, *e = nullptr, *tau = nullptr, *om = nullptr, *Z = nullptr;
+  int *rk = nullptr, *doff = nullptr;
+  int2 *tiles = nullptr, *tiles128 = nullptr;
+  hipError_t he;
+#define GENCHK(expr)                                                                           \
+  do {                                                                                         \
+    he = (expr);                                                                               \
+    if (he != hipSuccess)                                                                      \
+      return fail(nullptr, he == hipErrorOutOfMemory ? OSV_E_NOMEM : OSV_E_HIP,                \
+                  std::string("osv_generate_osvs: ") + #expr + ": " + hipGetErrorString(he)); \
+  } while (0)
+  GENCHK(gb.get(&flag, 4));
+  GENCHK(launch_fill_i32(flag, 0, 4, s));
+  GENCHK(launch_check_finite(B, (long long)nocc * nvir * naux, flag, s));
+  GENCHK(launch_check_finite(eps_vir, nvir, flag, s));
+  GENCHK(launch_check_finite(F_occ, (long long)nocc * nocc, flag, s));
+  int hflag = 0;
+  GENCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+  GENCHK(hipStreamSynchronize(s));
+  if (hflag) return fail(nullptr, OSV_E_NONFINITE, "osv_generate_osvs: NaN or Inf in B, eps_vir or F_occ");
+  GENCHK(gb.get(&T, (size_t)nocc * n2));
+  GENCHK(gb.get(&d, (size_t)nocc * nvir));
+  GENCHK(gb.get(&e, (size_t)nocc * nvir));
+  GENCHK(gb.get(&tau, (size_t)nocc * nvir));
+  GENCHK(gb.get(&om, (size_t)nocc * r_max));
+  GENCHK(gb.get(&Z, (size_t)nocc * nvir * r_max));
+  GENCHK(gb.get(&rk, nocc));
+  GENCHK(gb.get(&doff, nocc));
+  // (ka|kb) = B_k B_k^T for every k on all tiles of the nvir x nvir matrix
+  std::vector<int2> t64, t128;
+  for (int a = 0; a < (nvir + 63) / 64; a++)
+    for (int b = a; b < (nvir + 63) / 64; b++) t64.push_back(make_int2(a, b));
+  for (int a = 0; a < (nvir + 127) / 128; a++)
+    for (int b = a; b < (nvir + 127) / 128; b++) t128.push_back(make_int2(a, b));
+  GENCHK(gb.get(&tiles, t64.size()));
+  GENCHK(gb.get(&tiles128, t128.size()));
+  GENCHK(hipMemcpyAsync(tiles, t64.data(), t64.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  GENCHK(hipMemcpyAsync(tiles128, t128.data(), t128.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  for (int k = 0; k < nocc; k++)
+    GENCHK(launch_syrk_f64(B + (long long)k * nvir * naux, 0, naux, nvir, naux, nullptr, T + (long long)k * n2,
+                           nullptr, nvir, tiles, (int)t64.size(), tiles128, (int)t128.size(), s));
+  GENCHK(launch_osv_denom(T, nvir, eps_vir, F_occ, nocc, s));
+  GENCHK(launch_osv_tridiag(T, nocc, nvir, l_osv, r_max, d, e, tau, rk, om, s));
+  std::vector<int> hr(nocc), hoff(nocc);
+  GENCHK(hipMemcpyAsync(hr.data(), rk, nocc * sizeof(int), hipMemcpyDeviceToHost, s));
+  GENCHK(hipStreamSynchronize(s));
+  int tot = 0;
+  for (int k = 0; k < nocc; k++) {
+    hoff[k] = tot;
+    tot += hr[k];
+    r[k] = hr[k];
+  }
+  GENCHK(hipMemcpyAsync(doff, hoff.data(), nocc * sizeof(int), hipMemcpyHostToDevice, s));
+  if (omega) GENCHK(launch_fill_f64(omega, 0.0, (long long)nocc * r_max, s));
+  double *om_out = omega;
+  if (!om_out) GENCHK(gb.get(&om_out, (size_t)nocc * r_max));
+  GENCHK(launch_osv_vectors(T, nocc, nvir, r_max, d, e, tau, rk, om, doff, Z, Q, om_out, s));
+  // C_k = Q_k^T B_k: rows off_k .. of C
+  if (C)
+    for (int k = 0; k < nocc; k++)
+      if (hr[k] > 0)
+        GENCHK(launch_gemm_nn_f64(Q + (long long)hoff[k] * nvir, nvir, B + (long long)k * nvir * naux, 0,
+                                  naux, C + (long long)hoff[k] * naux, naux, hr[k], naux, nvir, 1.0, s));
+  GENCHK(hipStreamSynchronize(s));
+#undef GENCHK
   return OSV_OK;
 }
 

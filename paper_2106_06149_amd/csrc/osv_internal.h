@@ -208,6 +208,18 @@ hipError_t pool_alloc(void **p, size_t bytes);  // on the current device
 void pool_free(void *p);                         // back to its device's cache
 void pool_release(int device);                   // hipFree the cached blocks (-1: every device)
 size_t pool_cached_bytes(int device);
+// OSV generation (eq:svd): T_kk = K_kk / (eps_a + eps_b - 2 f_kk) in place in every
+// LMO's nvir x nvir slot; Householder tridiagonalisation and bisection of the
+// wanted eigenvalues (count rk[k], values om[k r_max ..]); eigenvectors into rows
+// off[k] .. of Qt (ld n) and omega (scratch Z: nocc n r_max doubles)
+constexpr int OSV_GEN_MAX_NVIR = 1024;
+hipError_t launch_osv_denom(double *T, int nvir, const double *eps, const double *F, int nocc,
+                            hipStream_t s);
+hipError_t launch_osv_tridiag(double *T, int nocc, int n, double l_osv, int r_max, double *d,
+                              double *e, double *tau, int *rk, double *om, hipStream_t s);
+hipError_t launch_osv_vectors(const double *T, int nocc, int n, int r_max, const double *d,
+                              const double *e, const double *tau, const int *rk, const double *om,
+                              const int *off, double *Z, double *Qt, double *omega, hipStream_t s);
 hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
                               int nocc, double *out, hipStream_t s);
 }
