@@ -623,3 +623,94 @@ def generate_osvs(B: np.ndarray, eps_vir: np.ndarray, F_occ: np.ndarray, l_osv: 
         oms.append(w[keep])
     return (np.array(rs, dtype=np.int32), np.asfortranarray(np.hstack(Qs)),
             np.ascontiguousarray(np.vstack(Cs)), oms)
+
+
+# ---------------------------------------------------------------------------
+# One-step high-order correction (section on the high-order MBE(n) contribution)
+# ---------------------------------------------------------------------------
+
+def collective_amplitudes(res) -> Dict[Tuple[int, int], np.ndarray]:
+    """T_(pq) = sum over clusters X holding p and q of c_X T^X_pq: the MBE(3)
+    expansions eq:tmbediag / eq:tmbeoff written with the inclusion-exclusion
+    coefficients (composite OSV basis of domain [pq])."""
+    coll: Dict[Tuple[int, int], np.ndarray] = {}
+    for c, T in zip(res["coef"], res["T"]):
+        for pq, t in T.items():
+            coll[pq] = coll.get(pq, 0.0) + c * t
+    return coll
+
+
+def k_range(res, p: int, q: int):
+    """The LMOs m that pair (p, q) correlates with in the selected clusters: every
+    LMO of a cluster holding both p and q (sorted)."""
+    out = set()
+    for X in res["clusters"]:
+        if p in X and q in X:
+            out.update(X)
+    return sorted(out)
+
+
+def residual_over(pb: PairBlocks, T: Dict, p: int, q: int, ms) -> np.ndarray:
+    """eq:rij for the ordered pair (p, q), p <= q, with the sums over k running over
+    the LMOs ms, amplitudes T[(a, b)] (a <= b) in the composite bases; the swapped
+    pair's amplitudes are T^{ba} = (T^{ab})^T in the swapped basis."""
+    S, F, f = pb.S, pb.F, pb.f
+
+    def Tord(a, b):
+        if a <= b:
+            return T[(a, b)]
+        ra, rb = pb.Q[a].shape[1], pb.Q[b].shape[1]
+        perm = np.concatenate([np.arange(rb, rb + ra), np.arange(0, rb)])
+        return T[(b, a)].T[np.ix_(perm, perm)]
+
+    dpq = dom(p, q)
+    R = composite_K(pb, p, q)
+    for m in ms:
+        dpm, dmq = dom(p, m), dom(m, q)
+        right = -f[m, q] * composite(S, dpm, dpq)
+        if m == q:
+            right = right + composite(F, dpm, dpq)
+        R = R + composite(S, dpq, dpm) @ Tord(p, m) @ right
+        left = -f[p, m] * composite(S, dpq, dmq)
+        if p == m:
+            left = left + composite(F, dpq, dmq)
+        R = R + left @ Tord(m, q) @ composite(S, dmq, dpq)
+    return R
+
+
+def one_step_correction(sysm, res, tau_S: float = 1e-8):
+    """The posterior correction of the converged MBE(3) amplitudes: the residual
+    eq:rij of every selected pair (p, q) at the collective amplitudes, with k over
+    the LMOs that share a cluster with p and q, then one preconditioned Jacobi step
+    in the pair domain's pseudo-canonical basis W (W^T S W = 1, W^T F W = diag e~):
+        dT = W [-(W^T dR W) / (e~_a + e~_b - f_pp - f_qq)] W^T,
+    and the change of the energy sum_pairs w <K_(pq,pq), 2T - T^T> (w = 1 for
+    p = q, 2 otherwise) that the step makes.  Returns dict(dE, E_coll, max_dR,
+    dR, dT) with max_dR the largest ||W^T dR W||_F."""
+    pb = PairBlocks(sysm)
+    coll = collective_amplitudes(res)
+    dE = 0.0
+    E_coll = 0.0
+    max_dR = 0.0
+    dR_all, dT_all = {}, {}
+    for (p, q) in sorted(coll):
+        d = dom(p, q)
+        S = composite(pb.S, d, d)
+        F = composite(pb.F, d, d)
+        s, U = np.linalg.eigh(S)
+        keep = s > tau_S
+        Xo = U[:, keep] / np.sqrt(s[keep])[None, :]
+        e, V = np.linalg.eigh(Xo.T @ F @ Xo)
+        W = Xo @ V
+        denom = e[:, None] + e[None, :] - pb.f[p, p] - pb.f[q, q]
+        dR = residual_over(pb, coll, p, q, k_range(res, p, q))
+        Rt = W.T @ dR @ W
+        max_dR = max(max_dR, float(np.linalg.norm(Rt)))
+        dT = W @ (-Rt / denom) @ W.T
+        K = composite_K(pb, p, q)
+        w = 1.0 if p == q else 2.0
+        dE += w * float(np.sum(K * (2.0 * dT - dT.T)))
+        E_coll += w * float(np.sum(K * (2.0 * coll[(p, q)] - coll[(p, q)].T)))
+        dR_all[(p, q)] = dR
+        dT_all[(p, q)] = dT
+    return dict(dE=dE, E_coll=E_coll, max_dR=max_dR, dR=dR_all, dT=dT_all)

@@ -52,6 +52,10 @@ MUTATIONS = {
     "osvgen_ascending": ('order = np.argsort(-w, kind="stable")', 'order = np.argsort(w, kind="stable")'),
     "osvgen_wrong_lmo_C": ("Cs.append(Qk.T @ B[k])", "Cs.append(Qk.T @ B[(k + 1) % nocc])"),
     "osvgen_threshold": ("if w[i] > l_osv][:r_max]", "if w[i] > 0.5 * l_osv][:r_max]"),
+    "one_step_sign": ("dT = W @ (-Rt / denom) @ W.T", "dT = W @ (Rt / denom) @ W.T"),
+    "one_step_weight": ("w = 1.0 if p == q else 2.0\n        dE", "w = 1.0\n        dE"),
+    "one_step_drops_second_sum": ("        R = R + left @ Tord(m, q) @ composite(S, dmq, dpq)\n    return R",
+                                  "        R = R + 0.0 * (left @ Tord(m, q) @ composite(S, dmq, dpq))\n    return R"),
     "dC_missing_transpose": ("dC[q] += G.T @ pb.C[p]", "dC[q] += 0.5 * (G + G.T) @ pb.C[p] if G.shape[0] == G.shape[1] else G.T @ pb.C[p]"),
 }
 

@@ -717,3 +717,47 @@ def test_osv_generation_invariant_under_fitting_rotation():
     assert list(r) == list(r2)
     assert np.allclose(Q, Q2, atol=1e-12)
     assert np.allclose(C @ U, C2, atol=1e-12)
+
+
+# --- one-step high-order correction -------------------------------------------------
+
+def test_one_step_correction_vanishes_when_mbe3_is_exact():
+    """Three LMOs with every cluster: MBE(3) is the full solve, so the collective
+    amplitudes solve the full residual equations and the correction vanishes; the
+    collective energy equals the MBE energy."""
+    s = small(nocc=3, nvir=24, naux=30, r=5, seed=12, cut2=100.0, cut3=100.0)
+    res = O.solve(s, densities=False, tau_R=1e-13)
+    c = O.one_step_correction(s, res)
+    assert c["max_dR"] < 1e-11
+    assert abs(c["dE"]) < 1e-13 * abs(res["E"])
+    assert abs(c["E_coll"] - res["E"]) < 1e-12 * abs(res["E"])
+
+
+def test_one_step_correction_vanishes_for_diagonal_focc():
+    """Canonical occupied orbitals (diagonal F_occ): pairs do not couple, every
+    cluster holds the same pair amplitudes, and the collective residual is zero."""
+    s = small(nocc=5, nvir=30, naux=25, r=5, seed=9, cut2=4.5, cut3=4.5)
+    s.F_occ = np.diag(np.diag(s.F_occ))
+    res = O.solve(s, densities=False, tau_R=1e-13)
+    c = O.one_step_correction(s, res)
+    assert c["max_dR"] < 1e-11 and abs(c["dE"]) < 1e-13 * abs(res["E"])
+
+
+def test_one_step_residual_is_the_full_residual_when_everything_is_selected():
+    """Five LMOs with every pair and triple selected: each pair's range of k is
+    every LMO, so its residual is the full OSV-MP2 residual (the one-cluster
+    residual of all LMOs) at the collective amplitudes; the step is nonzero because
+    MBE(3) misses the 4- and 5-body terms, and it moves the energy towards the
+    full OSV-MP2 energy."""
+    s = small(nocc=5, nvir=30, naux=20, r=4, seed=15, spacing=1.0, cut2=100.0, cut3=100.0)
+    res = O.solve(s, densities=False, tau_R=1e-13)
+    assert sum(1 for X in res["clusters"] if len(X) == 3) == 10
+    c = O.one_step_correction(s, res)
+    pb = O.PairBlocks(s)
+    full = O.Cluster(pb, tuple(range(5)))
+    coll = O.collective_amplitudes(res)
+    for (p, q), dR in c["dR"].items():
+        assert np.allclose(dR, full.residual(coll, p, q), rtol=0, atol=1e-13 * np.abs(dR).max())
+    E_full = O.solve(s, mode=O.SEL_FULL, densities=False, tau_R=1e-13)["E"]
+    assert c["max_dR"] > 1e-8
+    assert abs(res["E"] + c["dE"] - E_full) < 0.5 * abs(res["E"] - E_full)
