@@ -259,6 +259,28 @@ int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B,
                       double *omega, double *Q, double *C);
 
 /*
+ * osv_high_order_correction -- the one-step posterior correction of the MBE(3)
+ * amplitudes (section on the high-order MBE(n) contribution).  From the converged
+ * cluster amplitudes it forms the collective amplitudes of every pair domain,
+ *   T_(pq) = sum over the clusters X holding p and q of c_X T^X_pq
+ * (eq:tmbediag / eq:tmbeoff), evaluates the residual eq:rij of every pair at them
+ * with k over the LMOs that share a cluster with p and q (so that every cluster's
+ * couplings enter at once), takes one Jacobi step dT in each pair domain's
+ * pseudo-canonical basis, and returns the energy change it makes,
+ *   dE = sum_pairs w <K_(pq,pq), 2 dT - dT^T>   (w = 1 for p = q, 2 otherwise).
+ *   dE          host, required.
+ *   E_coll      host or NULL: sum_pairs w <K_(pq,pq), 2 T_(pq) - T_(pq)^T> (equals the
+ *               MBE energy of the strong clusters at convergence).
+ *   max_dR      host or NULL: the largest ||W^T dR W||_F over the pairs.
+ *   per_domain  host [3 n_domains] or NULL: per pair domain (p <= q, lexicographic)
+ *               its dE, E_coll and ||W^T dR W||_F.
+ * The weak pairs of OSV_SEL_OVERLAP are not part of it.  Errors: OSV_E_STATE
+ * before a converged solve, OSV_E_ARG, OSV_E_NOMEM, OSV_E_HIP.  Synchronises.
+ */
+int osv_high_order_correction(osv_ctx *ctx, hipStream_t stream, double *dE, double *E_coll,
+                              double *max_dR, double *per_domain);
+
+/*
  * osv_plan_clusters -- host-only cluster selection for OSV_SEL_DISTANCE and
  * OSV_SEL_FULL (no device work; usable without a GPU).
  *   nocc, centroid (host nocc x 3), sel: as above.

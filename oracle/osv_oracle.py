@@ -692,7 +692,7 @@ def one_step_correction(sysm, res, tau_S: float = 1e-8):
     dE = 0.0
     E_coll = 0.0
     max_dR = 0.0
-    dR_all, dT_all = {}, {}
+    dR_all, dT_all, per_pair = {}, {}, {}
     for (p, q) in sorted(coll):
         d = dom(p, q)
         S = composite(pb.S, d, d)
@@ -709,8 +709,11 @@ def one_step_correction(sysm, res, tau_S: float = 1e-8):
         dT = W @ (-Rt / denom) @ W.T
         K = composite_K(pb, p, q)
         w = 1.0 if p == q else 2.0
-        dE += w * float(np.sum(K * (2.0 * dT - dT.T)))
-        E_coll += w * float(np.sum(K * (2.0 * coll[(p, q)] - coll[(p, q)].T)))
+        e_pq = w * float(np.sum(K * (2.0 * dT - dT.T)))
+        c_pq = w * float(np.sum(K * (2.0 * coll[(p, q)] - coll[(p, q)].T)))
+        dE += e_pq
+        E_coll += c_pq
         dR_all[(p, q)] = dR
         dT_all[(p, q)] = dT
-    return dict(dE=dE, E_coll=E_coll, max_dR=max_dR, dR=dR_all, dT=dT_all)
+        per_pair[(p, q)] = (e_pq, c_pq, float(np.linalg.norm(Rt)))
+    return dict(dE=dE, E_coll=E_coll, max_dR=max_dR, dR=dR_all, dT=dT_all, pairs=per_pair)

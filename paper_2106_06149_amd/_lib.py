@@ -16,7 +16,7 @@ OSV_MAX_DOMAIN = 100
 OSV_NOALLOC_MAX_WEAK = 1 << 20
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_weak_pairs",
-           "osv_weak_pairs_noalloc", "osv_generate_osvs",
+           "osv_weak_pairs_noalloc", "osv_generate_osvs", "osv_high_order_correction",
            "osv_densities",
            "osv_plan_clusters", "osv_destroy", "osv_status_string", "osv_last_error",
            "osv_stage_times", "osv_stage_flops", "osv_release_cached_memory", "osv_cached_bytes"]
@@ -83,6 +83,9 @@ def load():
     lib.osv_weak_pairs_noalloc.restype = ctypes.c_int
     lib.osv_generate_osvs.argtypes = [i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp]
     lib.osv_generate_osvs.restype = ctypes.c_int
+    lib.osv_high_order_correction.argtypes = [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                              ctypes.POINTER(dbl), vp]
+    lib.osv_high_order_correction.restype = ctypes.c_int
     lib.osv_plan_clusters.argtypes = [i32, vp, ctypes.POINTER(OsvSelect), ctypes.POINTER(OsvCounts),
                                       vp, vp, i64]
     lib.osv_plan_clusters.restype = ctypes.c_int

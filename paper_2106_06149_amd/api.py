@@ -209,6 +209,17 @@ class OSVContext:
                                                 pairs.ctypes.data_as(ctypes.c_void_p)), self.handle)
         return E.value, pairs, Ep
 
+    def high_order_correction(self):
+        """One-step correction of the MBE(3) amplitudes: (dE, E_coll, max_dR,
+        per-domain [n_domains, 3] array of dE_d, E_d, ||W^T dR W||_F)."""
+        dE, Ec, mx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        per = np.zeros((self.counts["n_domains"], 3))
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_high_order_correction(self.handle, _stream(self.device), ctypes.byref(dE),
+                                                       ctypes.byref(Ec), ctypes.byref(mx),
+                                                       per.ctypes.data_as(ctypes.c_void_p)), self.handle)
+        return dE.value, Ec.value, mx.value, per
+
     def densities(self, dC=True, dF=True, deps=True, dvir=False):
         f64 = dict(dtype=torch.float64, device=self.device)
         out_C = torch.empty(self.nosv, self.naux, **f64) if dC else None

@@ -478,6 +478,11 @@ struct osv_ctx {
   int *dBdom = nullptr, *dBpart = nullptr;
   int2 *dBlocks = nullptr;
   int nblocks = 0;
+  // one-step high-order correction (built on first use)
+  bool hc_ready = false;
+  double *dTc = nullptr, *dHcOut = nullptr;
+  long long *dCoff = nullptr, *dCtptr = nullptr;
+  CTerm *dCterms = nullptr;
   // state
   bool solved = false;
   std::string err;
@@ -1327,7 +1332,7 @@ static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
   Plan &P = ctx->plan;
   const int N = ctx->nosv;
   int rc;
-  if ((rc = upload_density_tables(ctx, s))) return rc;
+  if (!ctx->dDptr && (rc = upload_density_tables(ctx, s))) return rc;
   const long long ld = N;
   if ((rc = dalloc(ctx, &ctx->dGK, (size_t)ld * ld))) return rc;
   if ((rc = dalloc(ctx, &ctx->dGF, (size_t)ld * ld))) return rc;
@@ -1487,6 +1492,111 @@ int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B,
                                   naux, C + (long long)hoff[k] * naux, naux, hr[k], naux, nvir, 1.0, s));
   GENCHK(hipStreamSynchronize(s));
 #undef GENCHK
+  return OSV_OK;
+}
+
+// Host tables of the one-step correction: collective slots per domain and, per
+// target domain (p, q), the terms of eq:rij with k over the LMOs that share a
+// cluster with p and q.
+static int build_correction(osv_ctx *ctx, hipStream_t s) {
+  Plan &P = ctx->plan;
+  const Selection &S = ctx->sel;
+  const int nocc = ctx->nocc, ndom = (int)P.doms.size();
+  auto dom_id = [&](int a, int b) {
+    return a <= b ? P.dom_of[(size_t)a * nocc + b] : P.dom_of[(size_t)b * nocc + a];
+  };
+  // k ranges: every LMO of every cluster that holds the pair
+  std::vector<std::vector<int>> range(ndom);
+  for (size_t X = 0; X < P.cls.size(); X++) {
+    const Cluster &C = P.cls[X];
+    for (int a = 0; a < C.nlmo; a++)
+      for (int b = a; b < C.nlmo; b++) {
+        auto &rg = range[dom_id(S.lmo[C.lmo0 + a], S.lmo[C.lmo0 + b])];
+        for (int c = 0; c < C.nlmo; c++) rg.push_back(S.lmo[C.lmo0 + c]);
+      }
+  }
+  std::unordered_map<long long, int> cmap;
+  cmap.reserve(P.cpls.size() * 2);
+  for (size_t c = 0; c < P.cpls.size(); c++)
+    cmap[(long long)P.cpls[c].A * ndom + P.cpls[c].B] = (int)c;
+  std::vector<long long> coff(ndom), tptr(ndom + 1, 0);
+  long long nTc = 0;
+  for (int d = 0; d < ndom; d++) {
+    coff[d] = nTc;
+    nTc += 2LL * P.doms[d].np * P.doms[d].np;
+  }
+  std::vector<CTerm> terms;
+  for (int d = 0; d < ndom; d++) {
+    auto &rg = range[d];
+    std::sort(rg.begin(), rg.end());
+    rg.erase(std::unique(rg.begin(), rg.end()), rg.end());
+    const int p = P.doms[d].p, q = P.doms[d].q;
+    auto add = [&](int a, int b, int fa, int fb) -> bool {
+      const int sd = dom_id(a, b);
+      if (sd < 0) return false;
+      CTerm t{};
+      t.src = sd;
+      t.fa = fa;
+      t.fb = fb;
+      t.ldT = P.doms[sd].np;
+      t.tsrc = coff[sd] + ((a > b) ? (long long)P.doms[sd].np * P.doms[sd].np : 0LL);
+      const int A = std::min(d, sd), B = std::max(d, sd);
+      auto it = cmap.find((long long)A * ndom + B);
+      if (it == cmap.end()) return false;
+      const Coupling &c = P.cpls[it->second];
+      t.moff = (d == c.B) ? c.offAB : c.offBA;    // M(src, tgt)
+      terms.push_back(t);
+      return true;
+    };
+    for (int m : rg) {
+      if (m != q && !add(p, m, m, q)) return fail(ctx, OSV_E_HIP, "one-step correction: missing coupling");
+      if (m != p && !add(m, q, p, m)) return fail(ctx, OSV_E_HIP, "one-step correction: missing coupling");
+    }
+    tptr[d + 1] = (long long)terms.size();
+  }
+  int rc;
+  if ((rc = upload(ctx, &ctx->dCoff, coff, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCtptr, tptr, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dCterms, terms, s))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dTc, (size_t)nTc))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dHcOut, (size_t)3 * ndom))) return rc;
+  ctx->hc_ready = true;
+  return OSV_OK;
+}
+
+int osv_high_order_correction(osv_ctx *ctx, hipStream_t s, double *dE, double *E_coll, double *max_dR,
+                              double *per_domain) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!dE) return fail(ctx, OSV_E_ARG, "dE is NULL");
+  if (!ctx->solved) return fail(ctx, OSV_E_STATE, "osv_high_order_correction before a converged solve");
+  int rc;
+  densities_host(ctx);
+  if (!ctx->dDptr && (rc = upload_density_tables(ctx, s))) return rc;
+  if (!ctx->hc_ready && (rc = build_correction(ctx, s))) return rc;
+  Plan &P = ctx->plan;
+  const int ndom = (int)P.doms.size();
+  HIPCHK(ctx, launch_collective(ctx->dDom, ndom, ctx->dDptr, ctx->dDtoff, ctx->dDcoef, ctx->dT, ctx->dCoff,
+                                ctx->dTc, s));
+  HIPCHK(ctx, launch_collective_step(ctx->dDom, ndom, ctx->dRank, ctx->dCtptr, ctx->dCterms, ctx->dTc,
+                                     ctx->dCoff, ctx->dM, ctx->dKt, ctx->F, ctx->nocc, ctx->dHcOut, s));
+  std::vector<double> h((size_t)3 * ndom);
+  HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->dHcOut, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  double a = 0.0, b = 0.0, m = 0.0;
+  for (int d = 0; d < ndom; d++) {
+    a += h[3 * d];
+    b += h[3 * d + 1];
+    m = std::max(m, std::sqrt(h[3 * d + 2]));
+  }
+  *dE = a;
+  if (E_coll) *E_coll = b;
+  if (max_dR) *max_dR = m;
+  if (per_domain)
+    for (int d = 0; d < ndom; d++) {
+      per_domain[3 * d] = h[3 * d];
+      per_domain[3 * d + 1] = h[3 * d + 1];
+      per_domain[3 * d + 2] = std::sqrt(h[3 * d + 2]);
+    }
   return OSV_OK;
 }
 

@@ -79,6 +79,17 @@ struct TermFlat {
   int ns;           // kept rank of the source domain
 };
 
+// One term of the collective residual of the one-step correction: the source
+// domain's collective amplitudes op(T~c_src) at tsrc (its T~c or T~c^T slot), the
+// coupling M(src, tgt) at moff, the coefficient -f[fa][fb].
+struct CTerm {
+  long long tsrc;
+  long long moff;
+  int src;      // source domain
+  int fa, fb;
+  int ldT;      // np of the source domain
+};
+
 struct SolveArgs {
   const TermFlat *tflat;
   const Cluster *cl;
@@ -220,6 +231,16 @@ hipError_t launch_osv_tridiag(double *T, int nocc, int n, double l_osv, int r_ma
 hipError_t launch_osv_vectors(const double *T, int nocc, int n, int r_max, const double *d,
                               const double *e, const double *tau, const int *rk, const double *om,
                               const int *off, double *Z, double *Qt, double *omega, hipStream_t s);
+// one-step high-order correction: collective amplitudes per domain (slots of
+// 2 np^2 at coff[d], both orientations), then per domain the residual at them,
+// one Jacobi step and out[3 d ..] = (dE_d, E_d, ||R~_d||_F^2)
+hipError_t launch_collective(const Domain *dom, int ndom, const long long *ptr, const long long *toff,
+                             const double *coef, const double *T, const long long *coff, double *Tc,
+                             hipStream_t s);
+hipError_t launch_collective_step(const Domain *dom, int ndom, const int *rank, const long long *tptr,
+                                  const CTerm *terms, const double *Tc, const long long *coff,
+                                  const double *M, const double *Kep, const double *F, int nocc,
+                                  double *out, hipStream_t s);
 hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
                               int nocc, double *out, hipStream_t s);
 }
