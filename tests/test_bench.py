@@ -33,7 +33,8 @@ def test_traffic_lookup_follows_workload_and_sources(monkeypatch):
 def test_cpu_baseline_record():
     from paper_2106_06149_amd import synth
     s = synth.workload(1)
-    rec = bench.cpu_baseline(s, 3)
+    rec = bench.cpu_baseline(s, 6, workers=2)
     assert rec["kind"] == "oracle" and rec["unit"] == "pair-blocks/s"
-    assert rec["value"] > 0 and rec["cores"] >= 1
-    assert rec["sample"].startswith("3 seeded clusters")
+    assert rec["value"] > 0 and rec["cores"] == 2
+    assert rec["sample"].startswith("6 seeded clusters") and "2 worker processes" in rec["sample"]
+    assert rec["cpu_model"] and rec["cpu_count"] >= 1
