@@ -166,7 +166,7 @@ def main():
         print(f"[bench] cpu baseline: {cpu_rec['value']:.1f} pair-blocks/s on {cpu_rec['cores']} "
               f"workers ({cpu_rec['cpu_model']})", file=sys.stderr, flush=True)
     import torch
-    from paper_2106_06149_amd.api import OSVContext, Selection
+    from paper_2106_06149_amd.api import OSVContext, Selection, get_tuning
 
     dev = torch.device("cuda:0")
     Qt = torch.from_numpy(np.ascontiguousarray(s.Q.T)).to(dev)
@@ -271,6 +271,8 @@ def main():
         # algorithmic TFLOP/s per stage (kept ranks, selected blocks only) over its device time
         "stage_tflops": {k: round(r["flops"][k] / (1e-3 * float(np.mean([st[k] for st in r["stages"]]))) / 1e12, 2)
                          for k in r["flops"] if r["flops"][k] > 0 and k != "host_plan"},
+        # launch variants in use (the autotuner's table, include/osv.h)
+        "tuning": get_tuning(),
         "E": r["E"],
         # the path without the build stages (S/F, K, domain preparation, couplings)
         "pair_blocks_per_s_solve_energy_densities": npb / (1e-3 * sum(

@@ -314,6 +314,27 @@ void osv_destroy(osv_ctx *ctx);
 int osv_release_cached_memory(int32_t device);
 int64_t osv_cached_bytes(int32_t device);
 
+/*
+ * Launch tuning.  Some kernels exist in several compiled variants that compute the
+ * same quantities with different tile or workgroup shapes; which one runs is a
+ * process-wide table, read once from $OSV_TUNING_FILE, else from osv_tuning.txt
+ * beside the library (written by the package's autotuner; "key value" lines), else
+ * left at its defaults.  Keys and allowed values:
+ *   gemm_ks          8, 16, 32      k per LDS stage of the FP64 tile GEMM (S/F, K, dE/dC)
+ *   prep_nt_small    128, 256       threads per pair domain of n <= 32 in the preparation
+ *   prep_nt_mid      256, 512, 1024 the same for 32 < n <= 64
+ *   prep_nt_big      512, 1024      the same for n > 64
+ *   cpl_split        0, 64          couplings whose domains both have n <= this run as
+ *                                   4-wave workgroups, the others as 8-wave ones
+ *   solve_wg_per_cu  1, 2           persistent residual-solve workgroups per compute unit
+ * Set the table before building contexts; changing it while another thread builds
+ * or solves is not supported.  OSV_E_ARG for an unknown key or value, an unreadable
+ * file or a bad line (entries before a bad line stay applied).
+ */
+int osv_set_tuning(const char *key, int32_t value);
+int osv_get_tuning(const char *key, int32_t *value);
+int osv_load_tuning(const char *path);
+
 /* message of a status code (static string) */
 const char *osv_status_string(int status);
 

@@ -14,9 +14,12 @@ OSV_SEL_DISTANCE, OSV_SEL_OVERLAP, OSV_SEL_FULL = 0, 1, 2
 OSV_DT_F64, OSV_DT_F32 = 0, 1
 OSV_MAX_DOMAIN = 100
 OSV_NOALLOC_MAX_WEAK = 1 << 20
+TUNING_KEYS = {"gemm_ks": (8, 16, 32), "prep_nt_small": (128, 256), "prep_nt_mid": (256, 512, 1024),
+               "prep_nt_big": (512, 1024), "cpl_split": (0, 64), "solve_wg_per_cu": (1, 2)}
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_weak_pairs",
            "osv_weak_pairs_noalloc", "osv_generate_osvs", "osv_high_order_correction",
+           "osv_set_tuning", "osv_get_tuning", "osv_load_tuning",
            "osv_densities",
            "osv_plan_clusters", "osv_destroy", "osv_status_string", "osv_last_error",
            "osv_stage_times", "osv_stage_flops", "osv_release_cached_memory", "osv_cached_bytes"]
@@ -86,6 +89,12 @@ def load():
     lib.osv_high_order_correction.argtypes = [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                               ctypes.POINTER(dbl), vp]
     lib.osv_high_order_correction.restype = ctypes.c_int
+    lib.osv_set_tuning.argtypes = [ctypes.c_char_p, i32]
+    lib.osv_set_tuning.restype = ctypes.c_int
+    lib.osv_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
+    lib.osv_get_tuning.restype = ctypes.c_int
+    lib.osv_load_tuning.argtypes = [ctypes.c_char_p]
+    lib.osv_load_tuning.restype = ctypes.c_int
     lib.osv_plan_clusters.argtypes = [i32, vp, ctypes.POINTER(OsvSelect), ctypes.POINTER(OsvCounts),
                                       vp, vp, i64]
     lib.osv_plan_clusters.restype = ctypes.c_int

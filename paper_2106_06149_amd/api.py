@@ -39,6 +39,27 @@ def cached_bytes(device: int = -1) -> int:
     return int(L.load().osv_cached_bytes(device))
 
 
+def get_tuning() -> dict:
+    """The library's launch tuning table (see include/osv.h)."""
+    lib = L.load()
+    out = {}
+    for k in L.TUNING_KEYS:
+        v = ctypes.c_int32()
+        L.check(lib.osv_get_tuning(k.encode(), ctypes.byref(v)))
+        out[k] = v.value
+    return out
+
+
+def set_tuning(**kv):
+    lib = L.load()
+    for k, v in kv.items():
+        L.check(lib.osv_set_tuning(k.encode(), int(v)))
+
+
+def load_tuning(path: str):
+    L.check(L.load().osv_load_tuning(path.encode()))
+
+
 def plan_clusters(centroid: np.ndarray, sel: Selection):
     """Host-only cluster selection (no GPU): counts, LMO triples (-1 padded), c_X."""
     lib = L.load()

@@ -13,6 +13,8 @@
 // the FP32 input with exact int32 accumulation, combined in FP64 at the end.
 #include "osv_internal.h"
 
+#include <type_traits>
+
 namespace osv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -135,23 +137,30 @@ __global__ __launch_bounds__(256) void k_tile_f64(const TA *__restrict__ A, long
 // A and B, and for BK == 1 also N even.
 // ---------------------------------------------------------------------------
 constexpr int G = 128;             // output tile edge
-constexpr int GKS = 16;            // k per stage (doubles)
-constexpr int GSL = GKS / 2;       // 16-byte slots per row of a [row][k] stage
 constexpr int GRS = 130;           // LDS row stride of a [k][j] stage (doubles)
-constexpr int GA = G * GKS;        // doubles of a [row][k] stage
-constexpr int GB1 = GKS * GRS;     // doubles of a [k][j] stage
 constexpr int GNS = 2;             // stages: the next one loads while this one is multiplied
 constexpr int GNT = 512;           // threads (8 waves)
+// the stage depth GKS (k per stage: 8, 16 or 32 doubles) is a template parameter,
+// chosen at run time from the tuning table (16 by default: 64 KB of LDS, two
+// workgroups per CU); GSL 16-byte slots per row of a [row][k] stage, GA and GB1
+// doubles of a [row][k] and of a [k][j] stage
+template <int GKS>
+struct GemmStage {
+  static constexpr int GSL = GKS / 2;
+  static constexpr int GA = G * GKS;
+  static constexpr int GB1 = GKS * GRS;
+};
 
 typedef __attribute__((address_space(3))) void *lds_ptr;
 
 // issue the loads of stage k0 into buffer (As_b, Bs_b): GKS blocks of 1 KB per
 // operand, GKS / 8 per wave
-template <int BK>
+template <int GKS, int BK>
 __device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long long lda,
                                            const double *__restrict__ B, long long ldb, int i0,
                                            int j0, int k0, int M, int N, int K, double *As_b,
                                            double *Bs_b) {
+  constexpr int GSL = GemmStage<GKS>::GSL;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v < GKS / 8; v++) {
@@ -176,13 +185,14 @@ __device__ __forceinline__ void gemm_issue(const double *__restrict__ A, long lo
   }
 }
 
-template <int BK, bool WGT>
+template <int GKS, int BK, bool WGT>
 __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, long long lda,
                                                   const double *__restrict__ B, long long ldb,
                                                   const double *__restrict__ w, double *C,
                                                   long long ldc, int M, int N, int K,
                                                   double alpha, const int2 *__restrict__ tiles,
                                                   int mirror) {
+  constexpr int GSL = GemmStage<GKS>::GSL, GA = GemmStage<GKS>::GA, GB1 = GemmStage<GKS>::GB1;
   constexpr int GBS = BK == 0 ? GA : GB1;
   __shared__ __attribute__((aligned(16))) double As[GNS * GA];
   __shared__ __attribute__((aligned(16))) double Bs[GNS * GBS];
@@ -205,14 +215,14 @@ __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, 
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = (d4){0, 0, 0, 0};
   const int nst = (K + GKS - 1) / GKS;
-  gemm_issue<BK>(A, lda, B, ldb, i0, j0, 0, M, N, K, As, Bs);
+  gemm_issue<GKS, BK>(A, lda, B, ldb, i0, j0, 0, M, N, K, As, Bs);
   for (int st = 0; st < nst; st++) {
     const int k0 = st * GKS, sb = st & 1;
     double *Ab = As + sb * GA, *Bb = Bs + sb * GBS;
     // this stage's loads have landed and every wave is done with the other buffer
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (st + 1 < nst)
-      gemm_issue<BK>(A, lda, B, ldb, i0, j0, k0 + GKS, M, N, K, As + (sb ^ 1) * GA,
+      gemm_issue<GKS, BK>(A, lda, B, ldb, i0, j0, k0 + GKS, M, N, K, As + (sb ^ 1) * GA,
                      Bs + (sb ^ 1) * GBS);
     if (k0 + GKS > K) {
       // last, partial stage: zero k >= K
@@ -271,6 +281,16 @@ __global__ __launch_bounds__(GNT) void k_gemm_dma(const double *__restrict__ A, 
       }
 }
 
+// run f with the stage depth of the tuning table as a compile-time constant
+template <class Fn>
+static void dispatch_ks(Fn f) {
+  switch (tuning().gemm_ks) {
+    case 8: f(std::integral_constant<int, 8>()); break;
+    case 32: f(std::integral_constant<int, 32>()); break;
+    default: f(std::integral_constant<int, 16>()); break;
+  }
+}
+
 static bool dma_ok(const void *p, long long ld) {
   return ((size_t)p & 15) == 0 && (ld & 1) == 0;
 }
@@ -284,11 +304,15 @@ hipError_t launch_syrk_f64(const void *A, int a_is_f32, long long lda, int M, in
   if (!a_is_f32 && tiles128 && ntiles128 > 0 && dma_ok(A, lda) && (K & 1) == 0 && K >= 2) {
     // with a weight: C = A A^T and C2 = A diag(w) A^T as two passes over A
     dim3 grid(ntiles128), blk(GNT);
-    hipLaunchKernelGGL((k_gemm_dma<0, false>), grid, blk, 0, s, (const double *)A, lda,
-                       (const double *)A, lda, nullptr, C, ldc, M, M, K, 1.0, tiles128, 1);
-    if (w)
-      hipLaunchKernelGGL((k_gemm_dma<0, true>), grid, blk, 0, s, (const double *)A, lda,
-                         (const double *)A, lda, w, C2, ldc, M, M, K, 1.0, tiles128, 1);
+    auto run = [&](auto ks) {
+      constexpr int KS = decltype(ks)::value;
+      hipLaunchKernelGGL((k_gemm_dma<KS, 0, false>), grid, blk, 0, s, (const double *)A, lda,
+                         (const double *)A, lda, nullptr, C, ldc, M, M, K, 1.0, tiles128, 1);
+      if (w)
+        hipLaunchKernelGGL((k_gemm_dma<KS, 0, true>), grid, blk, 0, s, (const double *)A, lda,
+                           (const double *)A, lda, w, C2, ldc, M, M, K, 1.0, tiles128, 1);
+    };
+    dispatch_ks(run);
     return hipGetLastError();
   }
   dim3 grid(ntiles);
@@ -315,8 +339,12 @@ hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, i
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!b_is_f32 && dma_ok(A, lda) && dma_ok(B, ldb) && (K & 1) == 0 && K >= 2 && (N & 1) == 0) {
     dim3 grid((N + G - 1) / G, (M + G - 1) / G), block(GNT);
-    hipLaunchKernelGGL((k_gemm_dma<1, false>), grid, block, 0, s, A, lda, B, ldb, nullptr, C,
-                       ldc, M, N, K, alpha, nullptr, 0);
+    auto run = [&](auto ks) {
+      constexpr int KS = decltype(ks)::value;
+      hipLaunchKernelGGL((k_gemm_dma<KS, 1, false>), grid, block, 0, s, A, lda, B, ldb, nullptr, C,
+                         ldc, M, N, K, alpha, nullptr, 0);
+    };
+    dispatch_ks(run);
     return hipGetLastError();
   }
   dim3 grid((N + TB - 1) / TB, (M + TB - 1) / TB), block(256);

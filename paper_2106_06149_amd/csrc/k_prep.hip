@@ -525,18 +525,28 @@ hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *coun
                               double *Kep, int *rank, double *minev, hipStream_t s) {
   // counts3: number of domains with n <= 32, 32 < n <= 64, 64 < n <= DMAX, in that
   // order in ids[]
+  // threads per class from the tuning table
   int o = 0;
-  if (counts3[0] > 0)
-    hipLaunchKernelGGL((k_domain_prep<32, 256>), dim3(counts3[0]), dim3(256), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
+  const int *nt = tuning().prep_nt;
+#define OSV_PREP(NM, NT, c)                                                                      \
+  hipLaunchKernelGGL((k_domain_prep<NM, NT>), dim3(counts3[c]), dim3(NT), 0, s, dom, ids + o, S, F, \
+                     K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev)
+  if (counts3[0] > 0) {
+    if (nt[0] == 128) OSV_PREP(32, 128, 0);
+    else OSV_PREP(32, 256, 0);
+  }
   o += counts3[0];
-  if (counts3[1] > 0)
-    hipLaunchKernelGGL((k_domain_prep<64, 512>), dim3(counts3[1]), dim3(512), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
+  if (counts3[1] > 0) {
+    if (nt[1] == 256) OSV_PREP(64, 256, 1);
+    else if (nt[1] == 1024) OSV_PREP(64, 1024, 1);
+    else OSV_PREP(64, 512, 1);
+  }
   o += counts3[1];
-  if (counts3[2] > 0)
-    hipLaunchKernelGGL((k_domain_prep<DMAX, 1024>), dim3(counts3[2]), dim3(1024), 0, s, dom, ids + o, S, F,
-                       K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev);
+  if (counts3[2] > 0) {
+    if (nt[2] == 512) OSV_PREP(DMAX, 512, 2);
+    else OSV_PREP(DMAX, 1024, 2);
+  }
+#undef OSV_PREP
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <map>
@@ -16,6 +17,8 @@
 #include <string>
 #include <unordered_map>
 #include <vector>
+
+#include <dlfcn.h>
 
 using namespace osv;
 
@@ -821,7 +824,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     ids.reserve(P.cpls.size());
     for (int pass = 0; pass < 2; pass++) {
       for (int c = 0; c < (int)P.cpls.size(); c++) {
-        const bool small = std::max(P.doms[P.cpls[c].A].n, P.doms[P.cpls[c].B].n) <= 64;
+        const bool small = std::max(P.doms[P.cpls[c].A].n, P.doms[P.cpls[c].B].n) <= tuning().cpl_split;
         if (small == (pass == 0)) ids.push_back(c);
       }
       if (pass == 0) n64 = (int)ids.size();
@@ -839,7 +842,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  ctx->nwg = std::max(1, std::min(ncl, 2 * ncu));
+  ctx->nwg = std::max(1, std::min(ncl, tuning().solve_wg_per_cu * ncu));
   if ((rc = dalloc(ctx, &ctx->dTflat, P.terms.size()))) return rc;
   HIPCHK(ctx, launch_term_flat(ctx->dTerms, (long long)P.terms.size(), ctx->dCp, ctx->dCpl, ctx->dDom,
                                ctx->dRank, ctx->F, nocc, ctx->dTflat, s));
@@ -948,6 +951,81 @@ struct GenBuffers {
     for (void *q : blocks) pool_free(q);
   }
 };
+
+// ---- tuning table ------------------------------------------------------------
+namespace osv {
+namespace {
+std::once_flag g_tuning_once;
+Tuning g_tuning;
+std::mutex g_tuning_mu;
+
+// allowed values per key; returns false for an unknown key or value
+bool tuning_set(const std::string &k, int v) {
+  auto in = [&](std::initializer_list<int> a) { return std::find(a.begin(), a.end(), v) != a.end(); };
+  if (k == "gemm_ks" && in({8, 16, 32})) g_tuning.gemm_ks = v;
+  else if (k == "prep_nt_small" && in({128, 256})) g_tuning.prep_nt[0] = v;
+  else if (k == "prep_nt_mid" && in({256, 512, 1024})) g_tuning.prep_nt[1] = v;
+  else if (k == "prep_nt_big" && in({512, 1024})) g_tuning.prep_nt[2] = v;
+  else if (k == "cpl_split" && in({0, 64})) g_tuning.cpl_split = v;
+  else if (k == "solve_wg_per_cu" && in({1, 2})) g_tuning.solve_wg_per_cu = v;
+  else return false;
+  return true;
+}
+
+bool tuning_get(const std::string &k, int *v) {
+  if (k == "gemm_ks") *v = g_tuning.gemm_ks;
+  else if (k == "prep_nt_small") *v = g_tuning.prep_nt[0];
+  else if (k == "prep_nt_mid") *v = g_tuning.prep_nt[1];
+  else if (k == "prep_nt_big") *v = g_tuning.prep_nt[2];
+  else if (k == "cpl_split") *v = g_tuning.cpl_split;
+  else if (k == "solve_wg_per_cu") *v = g_tuning.solve_wg_per_cu;
+  else return false;
+  return true;
+}
+
+// "key value" lines; '#' starts a comment; returns the number of entries applied,
+// or -1 if the file cannot be read, -2 on a bad line
+int tuning_read(const char *path) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return -1;
+  char line[256];
+  int n = 0, bad = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    char *h = std::strchr(line, '#');
+    if (h) *h = 0;
+    char key[64];
+    int v = 0;
+    const int got = std::sscanf(line, "%63s %d", key, &v);
+    if (got <= 0) continue;
+    if (got != 2 || !tuning_set(key, v)) bad = 1;
+    else n++;
+  }
+  std::fclose(f);
+  return bad ? -2 : n;
+}
+
+std::string library_dir() {
+  Dl_info info;
+  if (dladdr((const void *)&library_dir, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    const size_t s = p.find_last_of('/');
+    return s == std::string::npos ? std::string(".") : p.substr(0, s);
+  }
+  return ".";
+}
+
+void tuning_init() {
+  const char *env = std::getenv("OSV_TUNING_FILE");
+  std::string path = env ? std::string(env) : library_dir() + "/osv_tuning.txt";
+  if (!path.empty()) (void)tuning_read(path.c_str());
+}
+}  // namespace
+
+Tuning &tuning() {
+  std::call_once(g_tuning_once, tuning_init);
+  return g_tuning;
+}
+}  // namespace osv
 
 extern "C" {
 
@@ -1695,5 +1773,35 @@ int osv_release_cached_memory(int32_t device) {
 }
 
 int64_t osv_cached_bytes(int32_t device) { return (int64_t)pool_cached_bytes(device); }
+
+int osv_set_tuning(const char *key, int32_t value) {
+  if (!key) return fail(nullptr, OSV_E_ARG, "osv_set_tuning: key is NULL");
+  (void)tuning();
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  if (!tuning_set(key, value))
+    return fail(nullptr, OSV_E_ARG, std::string("osv_set_tuning: unknown key or value ") + key + " " +
+                                        std::to_string(value));
+  return OSV_OK;
+}
+
+int osv_get_tuning(const char *key, int32_t *value) {
+  if (!key || !value) return fail(nullptr, OSV_E_ARG, "osv_get_tuning: NULL argument");
+  (void)tuning();
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  int v = 0;
+  if (!tuning_get(key, &v)) return fail(nullptr, OSV_E_ARG, std::string("osv_get_tuning: unknown key ") + key);
+  *value = v;
+  return OSV_OK;
+}
+
+int osv_load_tuning(const char *path) {
+  if (!path) return fail(nullptr, OSV_E_ARG, "osv_load_tuning: path is NULL");
+  (void)tuning();
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  const int n = tuning_read(path);
+  if (n == -1) return fail(nullptr, OSV_E_ARG, std::string("osv_load_tuning: cannot read ") + path);
+  if (n == -2) return fail(nullptr, OSV_E_ARG, std::string("osv_load_tuning: bad entry in ") + path);
+  return OSV_OK;
+}
 
 }  // extern "C"

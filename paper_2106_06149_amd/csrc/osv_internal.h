@@ -118,6 +118,20 @@ struct SolveArgs {
   int max_sweeps;
 };
 
+// Launch parameters chosen at run time among compiled variants: defaults are the
+// hand-measured choices; a tuning file written by the autotuner (key value lines,
+// read once per process: $OSV_TUNING_FILE, else osv_tuning.txt beside the library)
+// or osv_set_tuning overrides them.  Every variant computes the same quantities.
+struct Tuning {
+  int gemm_ks = 16;                     // FP64 tile GEMM k per stage: 8, 16, 32
+  int prep_nt[3] = {256, 512, 1024};    // domain preparation threads for n <= 32 {128, 256},
+                                        // n <= 64 {256, 512, 1024}, n <= DMAX {512, 1024}
+  int cpl_split = 64;                   // couplings with both domains <= this run in the
+                                        // 4-wave class: 0 (none) or 64
+  int solve_wg_per_cu = 2;              // persistent solve workgroups per CU: 1 or 2
+};
+Tuning &tuning();
+
 }  // namespace osv
 
 // ---- launch wrappers (defined next to their kernels) -----------------------
