@@ -351,7 +351,8 @@ int osv_stage_times(const osv_ctx *ctx, double *ms9);
 /* algorithmic floating-point operations of the same stages (host out [9]):
  * the flops of the mathematical contractions at the kept (unpadded) sizes,
  * e.g. 2*r_p*r_q*naux per K_pq block and 2*(n_t*n_s^2 + n_t^2*n_s) per residual
- * term per sweep; the eigensolvers of stage 2 and the host stage 8 count 0. */
+ * term per sweep; stage 2 counts the products around the eigensolvers and 9 m^3 per
+ * symmetric eigendecomposition of order m; the host stage 8 counts 0. */
 int osv_stage_flops(const osv_ctx *ctx, double *flops9);
 
 #ifdef __cplusplus
