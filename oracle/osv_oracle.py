@@ -117,10 +117,15 @@ def s2b_metric(sysm) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 class PairBlocks:
-    """Lazily computed orbital-pair blocks S_(p,q), F_(p,q), K_pq (float64)."""
+    """Lazily computed orbital-pair blocks S_(p,q), F_(p,q), K_pq (float64).  With
+    k_exact the pair-domain integrals are the cross-projected ones of eq:aijkl,
+    K_(pq,pq) = P_pq^T B_p B_q^T P_pq (the system's B), instead of reading R1."""
 
-    def __init__(self, sysm):
+    def __init__(self, sysm, k_exact: bool = False):
         self.sys = sysm
+        self.k_exact = k_exact
+        if k_exact and getattr(sysm, "B", None) is None:
+            raise ValueError("cross-projected integrals need the fitted integrals B")
         self.Q = [np.asarray(sysm.Qi(i), dtype=np.float64) for i in range(sysm.nocc)]
         self.C = [np.asarray(sysm.Ci(i), dtype=np.float64) for i in range(sysm.nocc)]
         self.eps = np.asarray(sysm.eps_vir, dtype=np.float64)
@@ -169,8 +174,13 @@ def composite(blockfn, rows: Sequence[int], cols: Sequence[int]) -> np.ndarray:
 
 
 def composite_K(pb: PairBlocks, p: int, q: int) -> np.ndarray:
-    """K_(pq,pq) = U_p K_pq U_q^T, U_p = P_pq^T Q_p (reading R1)."""
+    """K_(pq,pq) = U_p K_pq U_q^T, U_p = P_pq^T Q_p (reading R1); with pb.k_exact the
+    four blocks (p mu|q nu) of eq:aijkl from B: P_pq^T B_p B_q^T P_pq."""
     d = dom(p, q)
+    if pb.k_exact:
+        P = np.hstack([pb.Q[o] for o in d])
+        B = pb.sys.B
+        return (P.T @ B[p]) @ (B[q].T @ P)
     Up = composite(pb.S, d, (p,))
     Uq = composite(pb.S, d, (q,))
     return Up @ pb.K(p, q) @ Uq.T
@@ -338,7 +348,8 @@ class Cluster:
 def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
           tau_R: float = 1e-10, tau_S: float = 1e-8, max_sweeps: int = 100,
           densities: bool = True, clusters=None, coef=None, order=None,
-          l2b: float = 1e-2, l3b: float = 0.2, dvir: bool = False, weak: bool = True):
+          l2b: float = 1e-2, l3b: float = 0.2, dvir: bool = False, weak: bool = True,
+          k_exact: bool = False):
     """Solve every selected cluster and combine by MBE.  Returns a dict with E,
     E_orders (E_1b, dE_2b, dE_3b), E_cluster, sweeps, and (optionally) dE_dC
     [sum r, naux], dE_dF [nocc, nocc], dE_deps [nvir] and, with dvir, the full
@@ -352,7 +363,7 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
     if clusters is None:
         s2b = s2b_metric(sysm) if mode == SEL_OVERLAP else None
         clusters, coef, order = select_clusters(sysm.centroid, mode, cut2, cut3, s2b, l2b, l3b)
-    pb = PairBlocks(sysm)
+    pb = PairBlocks(sysm, k_exact=k_exact)
     E_cl = np.zeros(len(clusters))
     sweeps = np.zeros(len(clusters), dtype=np.int64)
     maxres = 0.0
@@ -717,3 +728,48 @@ def one_step_correction(sysm, res, tau_S: float = 1e-8):
         dT_all[(p, q)] = dT
         per_pair[(p, q)] = (e_pq, c_pq, float(np.linalg.norm(Rt)))
     return dict(dE=dE, E_coll=E_coll, max_dR=max_dR, dR=dR_all, dT=dT_all, pairs=per_pair)
+
+
+# ---------------------------------------------------------------------------
+# OSV response intermediate N_ij (eq:nij) and its MBE (eq:nmbeii, eq:nmbeij)
+# ---------------------------------------------------------------------------
+
+def osv_response(sysm, res, k_exact: bool = False):
+    """N_ij of eq:nij for every ordered pair (i, j) of every cluster X, at the
+    cluster's converged amplitudes and with k over X, in the composite OSV basis of
+    (i, j):
+        N_ij = Tbar K_(ij,ij) + D_(ij,ij) F_(ij,ij) + D'_(ij,ij) S_(ij,ij)
+               - sum_k [f_jk D_(ij,ik) S_(ik,ij) + f_ik D_(ij,kj) S_(kj,ij)],
+        D_(ij,kl)  = 1/2 [Tbar_ij S_(ij,kl) T_kl + Tbar_ij^T S_(ij,kl) T_kl^T],
+        D'_(ij,kl) = the same with F_(ij,kl),
+    combined over clusters with the MBE coefficients (eq:nmbeii / eq:nmbeij written
+    with the inclusion-exclusion coefficients).  Returns {(i, j): N_ij}, ordered
+    pairs, both orientations."""
+    pb = PairBlocks(sysm, k_exact=k_exact)
+    S, F, f = pb.S, pb.F, pb.f
+    out: Dict[Tuple[int, int], np.ndarray] = {}
+    for X, c, T in zip(res["clusters"], res["coef"], res["T"]):
+        if c == 0.0:
+            continue
+        cl = Cluster.__new__(Cluster)
+        cl.pb, cl.X, cl.f = pb, tuple(X), f
+
+        def Tord(a, b):
+            return cl.T_ordered(T, a, b)
+
+        def Dm(i, j, k, l, M):
+            Tb = 2.0 * Tord(i, j) - Tord(i, j).T
+            A = composite(M, dom(i, j), dom(k, l))
+            return 0.5 * (Tb @ A @ Tord(k, l) + Tb.T @ A @ Tord(k, l).T)
+
+        for i in X:
+            for j in X:
+                dij = dom(i, j)
+                Tb = 2.0 * Tord(i, j) - Tord(i, j).T
+                N = (Tb @ composite_K(pb, i, j) + Dm(i, j, i, j, S) @ composite(F, dij, dij)
+                     + Dm(i, j, i, j, F) @ composite(S, dij, dij))
+                for k in X:
+                    N = N - (f[j, k] * Dm(i, j, i, k, S) @ composite(S, dom(i, k), dij)
+                             + f[i, k] * Dm(i, j, k, j, S) @ composite(S, dom(k, j), dij))
+                out[(i, j)] = out.get((i, j), 0.0) + c * N
+    return out

@@ -56,6 +56,10 @@ MUTATIONS = {
     "one_step_weight": ("w = 1.0 if p == q else 2.0\n        dE", "w = 1.0\n        dE"),
     "one_step_drops_second_sum": ("        R = R + left @ Tord(m, q) @ composite(S, dmq, dpq)\n    return R",
                                   "        R = R + 0.0 * (left @ Tord(m, q) @ composite(S, dmq, dpq))\n    return R"),
+    "exact_K_one_lmo": ("return (P.T @ B[p]) @ (B[q].T @ P)", "return (P.T @ B[p]) @ (B[p].T @ P)"),
+    "nij_drops_Dprime_S": ("+ Dm(i, j, i, j, F) @ composite(S, dij, dij))", "+ 0.0 * Dm(i, j, i, j, F))"),
+    "nij_k_sum_sign": ("N = N - (f[j, k] * Dm(i, j, i, k, S)", "N = N + (f[j, k] * Dm(i, j, i, k, S)"),
+    "nij_KT_order": ("N = (Tb @ composite_K(pb, i, j)", "N = (composite_K(pb, i, j) @ Tb"),
     "dC_missing_transpose": ("dC[q] += G.T @ pb.C[p]", "dC[q] += 0.5 * (G + G.T) @ pb.C[p] if G.shape[0] == G.shape[1] else G.T @ pb.C[p]"),
 }
 

@@ -761,3 +761,52 @@ def test_one_step_residual_is_the_full_residual_when_everything_is_selected():
     E_full = O.solve(s, mode=O.SEL_FULL, densities=False, tau_R=1e-13)["E"]
     assert c["max_dR"] > 1e-8
     assert abs(res["E"] + c["dE"] - E_full) < 0.5 * abs(res["E"] - E_full)
+
+
+# --- cross-projected integrals and the OSV response intermediate ---------------------
+
+def test_exact_integrals_equal_projected_ones_when_B_lies_in_the_osv_span():
+    """With B_p = Q_p C_p (the fitted integrals inside each LMO's OSV span), the
+    cross-projected four-block K_(pq,pq) of eq:aijkl equals reading R1's
+    U_p K_pq U_q^T: both energies agree; with the original B they differ."""
+    s = small(nocc=4, nvir=20, naux=15, r=[3, 5, 4, 4], seed=71, cut2=4.5, cut3=4.5)
+    r1 = O.solve(s, densities=False, tau_R=1e-13)["E"]
+    ex = O.solve(s, densities=False, tau_R=1e-13, k_exact=True)["E"]
+    assert abs(ex - r1) > 1e-6 * abs(r1)
+    s.B = np.stack([s.Qi(p) @ s.Ci(p) for p in range(s.nocc)])
+    ex2 = O.solve(s, densities=False, tau_R=1e-13, k_exact=True)["E"]
+    assert abs(ex2 - r1) <= 1e-12 * abs(r1)
+
+
+def test_exact_integrals_all_osv_limit_is_canonical_mp2():
+    s = synth.make_system(3, 7, 11, 7, seed=3, sel_mode=synth.SEL_FULL)
+    E = O.solve(s, densities=False, tau_R=1e-13, k_exact=True)["E"]
+    E_can, _ = O.mp2_canonical(s.B, s.eps_vir, s.F_occ)
+    assert abs(E - E_can) <= 1e-12 * abs(E_can)
+
+
+@pytest.mark.parametrize("k_exact", [False, True])
+def test_osv_response_satisfies_the_span_invariance(k_exact):
+    """The energy depends on each LMO's OSVs only through their span: replacing
+    [Q_i Q_j] by [Q_i Q_j] diag(1 + h A_i, 1 + h A_j) (every composite matrix
+    A_(ij,kl) -> (1 + h O_ij)^T A (1 + h O_kl), eq:aijklgrad) leaves it unchanged,
+    so the OSV response N_ij of eq:nij, which collects the first-order change,
+    satisfies for every LMO k: the sum over ordered pairs of the k-diagonal blocks
+    of N_ij vanishes (per cluster, hence for the MBE sum)."""
+    s = small(nocc=5, nvir=24, naux=16, r=[3, 5, 4, 4, 3], seed=72, cut2=4.5, cut3=4.5)
+    res = O.solve(s, densities=False, tau_R=1e-13, k_exact=k_exact)
+    assert sum(1 for X in res["clusters"] if len(X) == 3) > 0
+    N = O.osv_response(s, res, k_exact=k_exact)
+    blocks = {k: np.zeros((s.r[k], s.r[k])) for k in range(s.nocc)}
+    scale = 0.0
+    for (i, j), Nij in N.items():
+        scale = max(scale, np.abs(Nij).max())
+        ri = s.r[i]
+        if i == j:
+            blocks[i] += Nij
+        else:
+            blocks[i] += Nij[:ri, :ri]
+            blocks[j] += Nij[ri:, ri:]
+    assert scale > 1e-4
+    for k, b in blocks.items():
+        assert np.abs(b).max() <= 1e-12 * scale, (k, np.abs(b).max())
