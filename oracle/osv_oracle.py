@@ -385,8 +385,9 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
         if densities and coef[n] != 0.0:
             dens = cl.densities(dvir=dvir)
             c_dC, c_dF, c_de = dens[:3]
-            for p, g in c_dC.items():
-                dC[off[p]:off[p + 1]] += coef[n] * g
+            if not k_exact:   # with cross-projected integrals E does not depend on C
+                for p, g in c_dC.items():
+                    dC[off[p]:off[p + 1]] += coef[n] * g
             dF += coef[n] * c_dF
             de += coef[n] * c_de
             if dvir:
@@ -411,7 +412,7 @@ def solve(sysm, mode: int = None, cut2: float = None, cut3: float = None,
                T=T_all, pair_blocks=sum(len(X) * (len(X) + 1) // 2 for X in clusters),
                E_weak=E_weak)
     if densities:
-        out.update(dE_dC=dC, dE_dF=dF, dE_deps=de)
+        out.update(dE_dC=None if k_exact else dC, dE_dF=dF, dE_deps=de)
         if dvir:
             out["Dvir"] = Dv
     return out

@@ -810,3 +810,34 @@ def test_osv_response_satisfies_the_span_invariance(k_exact):
     assert scale > 1e-4
     for k, b in blocks.items():
         assert np.abs(b).max() <= 1e-12 * scale, (k, np.abs(b).max())
+
+
+def test_exact_integrals_one_electron_densities_finite_differences():
+    """With cross-projected integrals the energy depends on eps_vir and F_occ only
+    through the Fock and overlap couplings, so dE/deps and dE/dF keep their form:
+    central differences of the exact-integral energy."""
+    import copy
+    s = small(nocc=4, nvir=16, naux=10, r=[3, 4, 3, 5], seed=3, cut2=4.5, cut3=4.5)
+    res = O.solve(s, tau_R=1e-13, k_exact=True)
+    assert res["dE_dC"] is None
+    h = 1e-5
+
+    def E(sp):
+        return O.solve(sp, densities=False, tau_R=1e-13, k_exact=True)["E"]
+
+    for c in (2, 9, 15):
+        sp, sm = copy.deepcopy(s), copy.deepcopy(s)
+        sp.eps_vir = s.eps_vir.copy(); sp.eps_vir[c] += h
+        sm.eps_vir = s.eps_vir.copy(); sm.eps_vir[c] -= h
+        fd = (E(sp) - E(sm)) / (2 * h)
+        assert abs(fd - res["dE_deps"][c]) <= 1e-7 * abs(fd) + 1e-10
+    for (u, v) in [(1, 1), (0, 2)]:
+        sp, sm = copy.deepcopy(s), copy.deepcopy(s)
+        sp.F_occ = s.F_occ.copy(); sp.F_occ[u, v] += h
+        sm.F_occ = s.F_occ.copy(); sm.F_occ[u, v] -= h
+        if u != v:
+            sp.F_occ[v, u] += h
+            sm.F_occ[v, u] -= h
+        fd = (E(sp) - E(sm)) / (2 * h)
+        an = res["dE_dF"][u, v] + (res["dE_dF"][v, u] if u != v else 0.0)
+        assert abs(fd - an) <= 1e-7 * abs(fd) + 1e-10
