@@ -139,6 +139,22 @@ typedef struct {
 int osv_build_pairs(const osv_system *sys, const osv_select *sel, int32_t precision,
                     hipStream_t stream, osv_ctx **out);
 
+/*
+ * osv_build_pairs_exact -- osv_build_pairs with the pair-domain integrals of the
+ * strong pairs taken as the cross-projected four blocks of eq:aijkl,
+ *   K_(pq,pq) = [Q_p Q_q]^T B_p B_q^T [Q_p Q_q],  (p mu|q nu) over both OSV sets,
+ * instead of the OSV-projected C_p given in osv_system.  The diagonal domains and
+ * the weak pairs' one-block integrals are the same in both: C_p = Q_p^T B_p is
+ * formed here from B.  sys->C may be NULL; B is device nocc x nvir x naux row-major
+ * (B_p = rows p nvir ..), read only in this call.  FP64 only (precision OSV_FP64).
+ * The other calls work as after osv_build_pairs, except that osv_densities gives
+ * no dE/dC (OSV_E_ARG if asked: E then depends on B, not on C); dE/dF_occ,
+ * dE/deps and the virtual density keep their meaning.
+ * Errors: as osv_build_pairs, and OSV_E_NONFINITE for NaN/Inf in B.
+ */
+int osv_build_pairs_exact(const osv_system *sys, const double *B, const osv_select *sel, int32_t precision,
+                          hipStream_t stream, osv_ctx **out);
+
 /* osv_query -- counts of the built context (host out).  OSV_E_ARG on NULL. */
 int osv_query(const osv_ctx *ctx, osv_counts *out);
 

@@ -32,9 +32,9 @@ def _init(sysm):
 def _run_chunk(args):
     """Solve a contiguous chunk of clusters; return their energies and the
     coefficient-weighted density sums of the chunk."""
-    clusters, coef, tau_R, tau_S, max_sweeps, densities, dvir = args
+    clusters, coef, tau_R, tau_S, max_sweeps, densities, dvir, k_exact = args
     s = _SYS
-    pb = O.PairBlocks(s)
+    pb = O.PairBlocks(s, k_exact=k_exact)
     off = s.off
     E = np.zeros(len(clusters))
     sweeps = np.zeros(len(clusters), dtype=np.int64)
@@ -53,8 +53,9 @@ def _run_chunk(args):
         conv = conv and cl.converged
         if densities and coef[n] != 0.0:
             d = cl.densities(dvir=dvir)
-            for p, g in d[0].items():
-                dC[off[p]:off[p + 1]] += coef[n] * g
+            if not k_exact:
+                for p, g in d[0].items():
+                    dC[off[p]:off[p + 1]] += coef[n] * g
             dF += coef[n] * d[1]
             de += coef[n] * d[2]
             if dvir:
@@ -68,7 +69,7 @@ def default_workers() -> int:
 
 def solve(sysm, nproc: int = None, tau_R: float = 1e-10, tau_S: float = 1e-8,
           max_sweeps: int = 100, densities: bool = True, dvir: bool = False,
-          clusters=None, coef=None, order=None, chunks_per_worker: int = 4):
+          clusters=None, coef=None, order=None, chunks_per_worker: int = 4, k_exact: bool = False):
     """Same result as osv_oracle.solve for the workload's selection (or the given
     cluster list), with the clusters spread over nproc worker processes (spawned,
     each holding one copy of the system)."""
@@ -79,7 +80,7 @@ def solve(sysm, nproc: int = None, tau_R: float = 1e-10, tau_S: float = 1e-8,
     nch = max(1, min(n, nproc * chunks_per_worker))
     bounds = np.linspace(0, n, nch + 1).astype(int)
     tasks = [(clusters[bounds[c]:bounds[c + 1]], coef[bounds[c]:bounds[c + 1]], tau_R, tau_S,
-              max_sweeps, densities, dvir) for c in range(nch)]
+              max_sweeps, densities, dvir, k_exact) for c in range(nch)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(nproc, initializer=_init, initargs=(sysm,)) as pool:
         parts = pool.map(_run_chunk, tasks, chunksize=1)
@@ -98,7 +99,7 @@ def solve(sysm, nproc: int = None, tau_R: float = 1e-10, tau_S: float = 1e-8,
             de += p[6]
             if dvir:
                 Dv += p[7]
-        out.update(dE_dC=dC, dE_dF=dF, dE_deps=de)
+        out.update(dE_dC=None if k_exact else dC, dE_dF=dF, dE_deps=de)
         if dvir:
             out["Dvir"] = Dv
     return out

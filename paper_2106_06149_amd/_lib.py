@@ -19,7 +19,7 @@ TUNING_KEYS = {"gemm_ks": (8, 16, 32), "prep_nt_small": (128, 256), "prep_nt_mid
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_weak_pairs",
            "osv_weak_pairs_noalloc", "osv_generate_osvs", "osv_high_order_correction",
-           "osv_set_tuning", "osv_get_tuning", "osv_load_tuning",
+           "osv_set_tuning", "osv_get_tuning", "osv_load_tuning", "osv_build_pairs_exact",
            "osv_densities",
            "osv_plan_clusters", "osv_destroy", "osv_status_string", "osv_last_error",
            "osv_stage_times", "osv_stage_flops", "osv_release_cached_memory", "osv_cached_bytes"]
@@ -72,6 +72,9 @@ def load():
     lib.osv_build_pairs.argtypes = [ctypes.POINTER(OsvSystem), ctypes.POINTER(OsvSelect), i32, vp,
                                     ctypes.POINTER(vp)]
     lib.osv_build_pairs.restype = ctypes.c_int
+    lib.osv_build_pairs_exact.argtypes = [ctypes.POINTER(OsvSystem), vp, ctypes.POINTER(OsvSelect), i32, vp,
+                                          ctypes.POINTER(vp)]
+    lib.osv_build_pairs_exact.restype = ctypes.c_int
     lib.osv_query.argtypes = [vp, ctypes.POINTER(OsvCounts)]
     lib.osv_query.restype = ctypes.c_int
     lib.osv_solve_clusters.argtypes = [vp, dbl, i32, vp, ctypes.POINTER(OsvSolveInfo)]

@@ -143,15 +143,25 @@ class OSVContext:
 
     def __init__(self, Q: torch.Tensor, C: torch.Tensor, eps_vir: torch.Tensor,
                  F_occ: torch.Tensor, r, centroid=None, sel: Selection = None,
-                 precision: int = L.OSV_FP64):
+                 precision: int = L.OSV_FP64, B: torch.Tensor = None):
+        """With B (nocc x nvir x naux, FP64, on the device) the strong pairs' domain
+        integrals are the cross-projected ones (osv_build_pairs_exact); C is then
+        formed by the library and may be None."""
         self.lib = L.load()
         self.device = Q.device
         sel = sel or Selection()
         self.r = np.ascontiguousarray(np.asarray(r), dtype=np.int32)
         self.cen = None if centroid is None else np.ascontiguousarray(centroid, dtype=np.float64)
+        self.handle = None
+        if B is not None:
+            if not B.is_cuda or B.dtype != torch.float64 or not B.is_contiguous() or B.dim() != 3 \
+                    or B.shape[0] != len(self.r) or B.shape[1] != eps_vir.shape[0]:
+                raise ValueError("B must be a contiguous float64 device tensor nocc x nvir x naux")
+            if C is None:
+                C = torch.empty(int(self.r.sum()), B.shape[2], dtype=torch.float64, device=B.device)
+        self.B = B
         # Q is nvir x sum(r) column-major: we hold its transpose as a contiguous tensor
         self.Q, self.C, self.eps, self.F = Q, C, eps_vir, F_occ
-        self.handle = None
         validate_inputs(Q, C, eps_vir, F_occ, self.r)
         for name, t in (("Q", Q), ("C", C), ("eps_vir", eps_vir), ("F_occ", F_occ)):
             if not t.is_cuda:
@@ -169,8 +179,12 @@ class OSVContext:
         h = ctypes.c_void_p()
         self.handle = None
         with torch.cuda.device(self.device):
-            L.check(self.lib.osv_build_pairs(ctypes.byref(sysc), ctypes.byref(s), precision,
-                                             _stream(self.device), ctypes.byref(h)))
+            if B is not None:
+                L.check(self.lib.osv_build_pairs_exact(ctypes.byref(sysc), _ptr(B), ctypes.byref(s), precision,
+                                                       _stream(self.device), ctypes.byref(h)))
+            else:
+                L.check(self.lib.osv_build_pairs(ctypes.byref(sysc), ctypes.byref(s), precision,
+                                                 _stream(self.device), ctypes.byref(h)))
         self.handle = h
         self.precision = precision
         c = L.OsvCounts()
@@ -178,9 +192,17 @@ class OSVContext:
         self.counts = c.as_dict()
 
     @classmethod
-    def from_system(cls, s, device="cuda", precision=None, sel: Selection = None):
-        """Copy a synth.System to the device and build it."""
+    def from_system(cls, s, device="cuda", precision=None, sel: Selection = None, k_exact: bool = False):
+        """Copy a synth.System to the device and build it (k_exact: cross-projected
+        integrals from the system's B)."""
         dev = torch.device(device)
+        if k_exact:
+            B = torch.from_numpy(np.ascontiguousarray(s.B)).to(dev)
+            Qt = torch.from_numpy(np.ascontiguousarray(s.Q.T)).to(dev)
+            eps = torch.from_numpy(np.ascontiguousarray(s.eps_vir)).to(dev)
+            F = torch.from_numpy(np.ascontiguousarray(s.F_occ)).to(dev)
+            sel = sel or Selection(s.sel_mode, s.cut2, s.cut3)
+            return cls(Qt, None, eps, F, s.r, s.centroid, sel, L.OSV_FP64, B=B)
         Qt = torch.from_numpy(np.ascontiguousarray(s.Q.T)).to(dev)   # sum(r) x nvir row-major = Q col-major
         C = torch.from_numpy(np.ascontiguousarray(s.C)).to(dev)
         eps = torch.from_numpy(np.ascontiguousarray(s.eps_vir)).to(dev)

@@ -672,6 +672,25 @@ hipError_t launch_couplings(const Coupling *cpl, const int *ids, int n64, int nb
   return hipGetLastError();
 }
 
+// Cross-projected integrals of one pair domain in its pseudo-canonical basis:
+// K~(a, b) = sum_P Gp[a][P] Gq[b][P] with Gp = V^T B_p, Gq = V^T B_q (dt x naux,
+// V = [Q_p Q_q] W the domain's pseudo-canonical virtuals), stored as K~^T in the
+// domain's zero-padded slot (Kt[b np + a]).
+__global__ __launch_bounds__(256) void k_exact_ktilde(const double *__restrict__ Gp,
+                                                      const double *__restrict__ Gq, int dt, int naux,
+                                                      double *Kt, int np) {
+  mma_tiles<256>(dt, dt, naux, [&](int a, int k) { return Gp[(long long)a * naux + k]; },
+                 [&](int k, int b) { return Gq[(long long)b * naux + k]; },
+                 [&](int a, int b, double v) { Kt[(long long)b * np + a] = v; });
+}
+
+hipError_t launch_exact_ktilde(const double *Gp, const double *Gq, int dt, int naux, double *Kt, int np,
+                               hipStream_t s) {
+  if (dt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exact_ktilde, dim3(1), dim3(256), 0, s, Gp, Gq, dt, naux, Kt, np);
+  return hipGetLastError();
+}
+
 // Weak 2b clusters, one-block dispersion scheme: pair (i, j) keeps only the block
 // T_(i,j) in the pseudo-canonical bases of the diagonal domains (i, i) and (j, j)
 // (their W slots, ranks and eigenvalues e~ from the preparation), where the

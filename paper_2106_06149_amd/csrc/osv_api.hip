@@ -481,6 +481,9 @@ struct osv_ctx {
   int *dBdom = nullptr, *dBpart = nullptr;
   int2 *dBlocks = nullptr;
   int nblocks = 0;
+  // cross-projected pair-domain integrals from B (osv_build_pairs_exact)
+  bool k_exact = false;
+  double *dCx = nullptr;   // C_p = Q_p^T B_p computed from B
   // one-step high-order correction (built on first use)
   bool hc_ready = false;
   double *dTc = nullptr, *dHcOut = nullptr;
@@ -1125,6 +1128,92 @@ int osv_build_pairs(const osv_system *sys, const osv_select *sel, int32_t precis
   return OSV_OK;
 }
 
+int osv_build_pairs_exact(const osv_system *sys, const double *B, const osv_select *sel, int32_t precision,
+                          hipStream_t stream, osv_ctx **out) {
+  if (!out) return fail(nullptr, OSV_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sys || !sel || !B) return fail(nullptr, OSV_E_ARG, "sys, sel or B is NULL");
+  if (precision != OSV_FP64)
+    return fail(nullptr, OSV_E_ARG, "cross-projected integrals are built in FP64 only (precision OSV_FP64)");
+  if (sys->nocc < 1 || sys->nvir < 1 || sys->naux < 1 || !sys->r || !sys->Q || !sys->eps_vir || !sys->F_occ)
+    return fail(nullptr, OSV_E_ARG, "bad sizes or NULL array in osv_system");
+  long long nosv = 0;
+  for (int i = 0; i < sys->nocc; i++) {
+    if (sys->r[i] < 1 || sys->r[i] > sys->nvir || sys->r[i] > OSV_MAX_DOMAIN)
+      return fail(nullptr, OSV_E_ARG, "r[" + std::to_string(i) + "] out of range");
+    nosv += sys->r[i];
+  }
+  if (nosv > (1LL << 30)) return fail(nullptr, OSV_E_ARG, "sum(r) too large");
+  osv_ctx *ctx = new (std::nothrow) osv_ctx();
+  if (!ctx) return fail(nullptr, OSV_E_NOMEM, "host allocation");
+  auto bail = [&](int rc) {
+    g_last_error = ctx->err;
+    delete ctx;
+    return rc;
+  };
+  hipStream_t s = stream;
+  const int nvir = sys->nvir, naux = sys->naux, nocc = sys->nocc;
+  int rc;
+  // B must be finite; then C_p = Q_p^T B_p (rows of Q^T times B_p)
+  int *flag = nullptr;
+  if ((rc = dalloc(ctx, &flag, 1))) return bail(rc);
+  {
+    hipError_t e = launch_fill_i32(flag, 0, 1, s);
+    if (e == hipSuccess) e = launch_check_finite(B, (long long)nocc * nvir * naux, flag, s);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(fail(ctx, OSV_E_HIP, std::string("B check: ") + hipGetErrorString(e)));
+    if (h) return bail(fail(ctx, OSV_E_NONFINITE, "NaN or Inf in B"));
+  }
+  if ((rc = dalloc(ctx, &ctx->dCx, (size_t)nosv * naux))) return bail(rc);
+  {
+    long long o = 0;
+    for (int p = 0; p < nocc; p++) {
+      const hipError_t e = launch_gemm_nn_f64(sys->Q + o * nvir, nvir, B + (long long)p * nvir * naux, 0, naux,
+                                              ctx->dCx + o * naux, naux, sys->r[p], naux, nvir, 1.0, s);
+      if (e != hipSuccess) return bail(fail(ctx, OSV_E_HIP, std::string("C from B: ") + hipGetErrorString(e)));
+      o += sys->r[p];
+    }
+  }
+  osv_system sx = *sys;
+  sx.C = ctx->dCx;
+  sx.C_dtype = OSV_DT_F64;
+  if ((rc = build_impl(ctx, &sx, sel, OSV_FP64, s))) return bail(rc);
+  // the off-diagonal domains' K~ from the cross-projected integrals
+  Plan &P = ctx->plan;
+  double *Pt = nullptr, *Vt = nullptr, *Gp = nullptr, *Gq = nullptr;
+  if ((rc = dalloc(ctx, &Pt, (size_t)DMAX * nvir))) return bail(rc);
+  if ((rc = dalloc(ctx, &Vt, (size_t)DMAX * nvir))) return bail(rc);
+  if ((rc = dalloc(ctx, &Gp, (size_t)DMAX * naux))) return bail(rc);
+  if ((rc = dalloc(ctx, &Gq, (size_t)DMAX * naux))) return bail(rc);
+  for (size_t d = 0; d < P.doms.size(); d++) {
+    const Domain &D = P.doms[d];
+    if (D.p == D.q) continue;
+    const int n = D.n, dt = ctx->rank_host[d];
+    hipError_t e = hipMemcpyAsync(Pt, sys->Q + (long long)D.offp * nvir, (size_t)D.rp * nvir * 8,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(Pt + (long long)D.rp * nvir, sys->Q + (long long)D.offq * nvir, (size_t)D.rq * nvir * 8,
+                         hipMemcpyDeviceToDevice, s);
+    // V^T = W^T P^T (dt x nvir), then Gp = V^T B_p, Gq = V^T B_q
+    if (e == hipSuccess) e = launch_gemm_tn_f64(ctx->dW + D.moff, n, Pt, nvir, Vt, nvir, dt, nvir, n, 1.0, s);
+    if (e == hipSuccess)
+      e = launch_gemm_nn_f64(Vt, nvir, B + (long long)D.p * nvir * naux, 0, naux, Gp, naux, dt, naux, nvir, 1.0, s);
+    if (e == hipSuccess)
+      e = launch_gemm_nn_f64(Vt, nvir, B + (long long)D.q * nvir * naux, 0, naux, Gq, naux, dt, naux, nvir, 1.0, s);
+    if (e == hipSuccess) e = launch_exact_ktilde(Gp, Gq, dt, naux, ctx->dKt + D.voff, D.np, s);
+    if (e != hipSuccess) return bail(fail(ctx, OSV_E_HIP, std::string("cross-projected K: ") + hipGetErrorString(e)));
+  }
+  {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(fail(ctx, OSV_E_HIP, std::string("cross-projected K: ") + hipGetErrorString(e)));
+  }
+  ctx->k_exact = true;
+  *out = ctx;
+  return OSV_OK;
+}
+
 int osv_query(const osv_ctx *ctx, osv_counts *out) {
   if (!ctx || !out) return fail(nullptr, OSV_E_ARG, "osv_query: NULL argument");
   *out = ctx->counts;
@@ -1704,6 +1793,8 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
                   double *Dvir_full) {
   if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
   if (!ctx->solved) return fail(ctx, OSV_E_STATE, "osv_densities before a converged solve");
+  if (dE_dC && ctx->k_exact)
+    return fail(ctx, OSV_E_ARG, "osv_densities: no dE/dC with cross-projected integrals (E depends on B)");
   int rc = prepare_densities(ctx, s);
   if (rc) return rc;
   Plan &P = ctx->plan;

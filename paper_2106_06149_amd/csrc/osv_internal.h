@@ -255,6 +255,10 @@ hipError_t launch_collective_step(const Domain *dom, int ndom, const int *rank, 
                                   const CTerm *terms, const double *Tc, const long long *coff,
                                   const double *M, const double *Kep, const double *F, int nocc,
                                   double *out, hipStream_t s);
+// K~ of one pair domain from Gp = V^T B_p and Gq = V^T B_q (dt x naux), into K~^T of
+// its zero-padded slot (leading dimension np)
+hipError_t launch_exact_ktilde(const double *Gp, const double *Gq, int dt, int naux, double *Kt, int np,
+                               hipStream_t s);
 hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
                               int nocc, double *out, hipStream_t s);
 }
