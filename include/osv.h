@@ -342,7 +342,11 @@ int64_t osv_cached_bytes(int32_t device);
  *   prep_nt_big      512, 1024      the same for n > 64
  *   cpl_split        0, 64          couplings whose domains both have n <= this run as
  *                                   4-wave workgroups, the others as 8-wave ones
- *   solve_wg_per_cu  1, 2           persistent residual-solve workgroups per compute unit
+ *   solve_split      0, 1           residual solve: 1 spreads each target's (column
+ *                                   block, source block) products evenly over the
+ *                                   four waves of a workgroup, 0 gives each wave
+ *                                   whole 16-column blocks (energies agree to
+ *                                   rounding; each setting is bitwise reproducible)
  * Set the table before building contexts; changing it while another thread builds
  * or solves is not supported.  OSV_E_ARG for an unknown key or value, an unreadable
  * file or a bad line (entries before a bad line stay applied).

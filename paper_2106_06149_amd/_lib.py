@@ -15,7 +15,7 @@ OSV_DT_F64, OSV_DT_F32 = 0, 1
 OSV_MAX_DOMAIN = 100
 OSV_NOALLOC_MAX_WEAK = 1 << 20
 TUNING_KEYS = {"gemm_ks": (8, 16, 32), "prep_nt_small": (128, 256), "prep_nt_mid": (256, 512, 1024),
-               "prep_nt_big": (512, 1024), "cpl_split": (0, 64), "solve_wg_per_cu": (1, 2)}
+               "prep_nt_big": (512, 1024), "cpl_split": (0, 64), "solve_split": (0, 1)}
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_weak_pairs",
            "osv_weak_pairs_noalloc", "osv_generate_osvs", "osv_high_order_correction",

@@ -27,7 +27,7 @@ STAGES = {
     "prep_nt_mid": ("prep",),
     "prep_nt_big": ("prep",),
     "cpl_split": ("couplings",),
-    "solve_wg_per_cu": ("solve",),
+    "solve_split": ("solve",),
 }
 
 

@@ -10,7 +10,7 @@
 // op is a transpose when the source pair is ordered (a, b) with a > b, because
 // the canonical amplitudes satisfy T^{ba} = (T^{ab})^T.
 //
-// One workgroup (4 wave64, one per SIMD) owns one cluster at a time: it pops
+// One workgroup (8 wave64, two per SIMD) owns one cluster at a time: it pops
 // clusters from a cost-sorted queue, zeroes the cluster's amplitudes, and iterates
 //   R~ from the current T~ for every pair; stop if max ||R~||_F < tau_R;
 //   otherwise T~ <- T~ - R~ / (e~_a + e~_b - f_pp - f_qq)
@@ -21,13 +21,20 @@
 // stopping sweep itself when its convergence was predicted from the two previous
 // norms (geometric rate), else from one more pass over the terms (P pass).
 //
-// A term Y = M op(T) M^T runs on FP64 MFMA 16x16x4 tiles.  Wave w owns the
-// 16-wide target blocks i = w and i = w + 4: for each it forms the column block
-// X'(:, i) of X' = coef op(T)^T M^T in registers, then Y^T(:, i) = M X'(:, i).  The
-// f64 MFMA accumulator layout (lane l, register v -> row 4v + (l >> 4), column
-// l & 15) equals the B-operand layout of the k-rows 4v..4v+3, so X' feeds the
-// second product straight from its accumulators, and R~ of the target stays in
-// MFMA accumulators across its terms.
+// A term Y = M op(T) M^T runs on FP64 MFMA 16x16x4 tiles as X' = coef op(T)^T M^T
+// (pass 1), then Y^T = M X' (pass 2).  The f64 MFMA accumulator layout (lane l,
+// register v -> row 4v + (l >> 4), column l & 15) equals the B-operand layout of
+// the k-rows 4v..4v+3, so a tile X'(kb, i) feeds the second product straight from
+// its accumulators, and R~ of the target stays in MFMA accumulators across its
+// terms.  The unit of work is a pair (16-wide target block i, 16-row source block
+// kb): the tile X'(kb, i) in pass 1 and its product M(kb rows, :)^T X'(kb, i) into
+// the column block R~^T(:, i) in pass 2; every unit costs the same.  Each SIMD
+// has two slots, one per wave, each a block i and the source blocks kb = rs
+// (mod md) (a fixed table per number of target blocks, balanced over the four
+// SIMDs); a block split over several waves leaves partial sums of R~^T(:, i) that
+// are added through LDS, in a fixed order, by the wave that owns the block's
+// epilogue.  Sweeps that store per-term products (the energy passes) keep one wave
+// per block (blocks w, w + 4).
 //
 // Operands are zero-padded row-major slots (leading dimension np = n rounded up
 // to 16): op(T~) is a T~ or T~^T slot and M(tgt, src)^T = M(src, tgt) is stored,
@@ -38,20 +45,25 @@
 // two amplitude buffers: a sweep reads T~ and T~^T from one and writes the
 // stepped amplitudes, in both orientations, to the other, so no step goes
 // through scratch; after the last sweep the final amplitudes are moved to T if
-// they are in the second buffer.  All chunks stream through a 4-stage LDS ring by
-// direct global-to-LDS loads (16 bytes per lane, no registers), issued three
-// chunks ahead of the multiply across term and target boundaries; a chunk is
-// consumed after a partial vmcnt wait and one barrier.  Every reduction has a
-// fixed order, so results are bitwise reproducible.
+// they are in the second buffer.  The epilogue's owner of a 16 x 16 block writes
+// T~^T rows directly and T~ rows through a transpose in the part of the stage
+// only it reads, so both stores are row-contiguous.  All chunks stream through a
+// 4-stage LDS ring by direct global-to-LDS loads (16 bytes per lane, no
+// registers), issued three chunks ahead of the multiply across term and target
+// boundaries by the second wave of each SIMD, which stalls on the address unit
+// while the first one multiplies; a chunk is consumed after a partial vmcnt wait
+// and one barrier.  Every reduction has a fixed order, so results are bitwise
+// reproducible.
 #include "osv_internal.h"
 
 namespace osv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int SNT = 256;        // threads per workgroup (4 wave64, one per SIMD)
-constexpr int NW = SNT / 64;    // waves
-constexpr int NS = 2;           // 16-wide target blocks per wave (blocks w, w + NW)
+constexpr int SNT = 512;        // threads per workgroup (8 wave64, two per SIMD)
+constexpr int NWAVE = SNT / 64; // waves
+constexpr int NW = 4;           // SIMDs: wave w runs on SIMD w % NW; waves NW.. load the ring
+constexpr int NS = NWAVE / NW;  // waves (work slots) per SIMD
 constexpr int MT = 7;           // 16-tiles per dimension covering DMAX = 100
 constexpr int RS = 130;         // LDS row stride (doubles) of a staged row
 constexpr int NSTG = 4;         // ring stages: loads run three chunks ahead
@@ -60,7 +72,7 @@ constexpr int PLMAX = 64;       // clusters with nlmo^2 <= PLMAX keep dE/df sums
 constexpr int MAXT = SOLVE_MAXT;        // clusters with <= MAXT pairs and <= MAXTERM terms
 constexpr int MAXTERM = SOLVE_MAXTERM;  //   keep their pair and term descriptors in LDS
 constexpr int NTG = 6;          // P pass: terms per reduction group
-constexpr int FMAXTERM = 128;   // clusters with at most this many terms may take the
+constexpr int FMAXTERM = 64;    // clusters with at most this many terms may take the
                                 // energy and dE/df products in their last sweep
 
 // What the sweep needs about one target pair of the current cluster.
@@ -113,20 +125,99 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// fixed-order block sums of NV values (red: NW * NV doubles)
+// Slot s of a SIMD: target block col (-1: none), source blocks kb with
+// kb & (md - 1) == rs, partial-sum slot ps it writes (-1: it owns the block), and
+// for an owner the partial slots rd it adds, in this order (-1: none).
+struct SlotMap {
+  signed char col, md, rs, ps, rd[3];
+};
+constexpr int NPART = 5;   // partial-sum tiles exchanged per target block row
+// balanced split, indexed [njb - 1][SIMD][slot]
+__constant__ SlotMap kSplit[MT][NW][NS] = {
+    // njb = 1: the block over all four waves (kb mod 4)
+    {{{0, 4, 0, -1, {0, 1, 2}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{0, 4, 1, 0, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{0, 4, 2, 1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{0, 4, 3, 2, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}}},
+    // njb = 2: each block over two waves (kb mod 2)
+    {{{0, 2, 0, -1, {0, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{0, 2, 1, 0, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{1, 2, 0, -1, {1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{1, 2, 1, 1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}}},
+    // njb = 3: blocks 0, 1 over two waves each, block 2 over all four
+    {{{0, 2, 0, -1, {0, -1, -1}}, {2, 4, 2, 3, {-1, -1, -1}}},
+     {{0, 2, 1, 0, {-1, -1, -1}}, {2, 4, 0, -1, {2, 3, 4}}},
+     {{1, 2, 0, -1, {1, -1, -1}}, {2, 4, 3, 4, {-1, -1, -1}}},
+     {{1, 2, 1, 1, {-1, -1, -1}}, {2, 4, 1, 2, {-1, -1, -1}}}},
+    // njb = 4: one block per wave
+    {{{0, 1, 0, -1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{1, 1, 0, -1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{2, 1, 0, -1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}},
+     {{3, 1, 0, -1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}}},
+    // njb = 5: one block per wave, block 4 over all four
+    {{{0, 1, 0, -1, {-1, -1, -1}}, {4, 4, 0, -1, {0, 1, 2}}},
+     {{1, 1, 0, -1, {-1, -1, -1}}, {4, 4, 1, 0, {-1, -1, -1}}},
+     {{2, 1, 0, -1, {-1, -1, -1}}, {4, 4, 2, 1, {-1, -1, -1}}},
+     {{3, 1, 0, -1, {-1, -1, -1}}, {4, 4, 3, 2, {-1, -1, -1}}}},
+    // njb = 6: one block per wave, blocks 4 and 5 over two waves each
+    {{{0, 1, 0, -1, {-1, -1, -1}}, {4, 2, 0, -1, {0, -1, -1}}},
+     {{1, 1, 0, -1, {-1, -1, -1}}, {4, 2, 1, 0, {-1, -1, -1}}},
+     {{2, 1, 0, -1, {-1, -1, -1}}, {5, 2, 0, -1, {1, -1, -1}}},
+     {{3, 1, 0, -1, {-1, -1, -1}}, {5, 2, 1, 1, {-1, -1, -1}}}},
+    // njb = 7: blocks w and w + 4 (no split)
+    {{{0, 1, 0, -1, {-1, -1, -1}}, {4, 1, 0, -1, {-1, -1, -1}}},
+     {{1, 1, 0, -1, {-1, -1, -1}}, {5, 1, 0, -1, {-1, -1, -1}}},
+     {{2, 1, 0, -1, {-1, -1, -1}}, {6, 1, 0, -1, {-1, -1, -1}}},
+     {{3, 1, 0, -1, {-1, -1, -1}}, {-1, 1, 0, -1, {-1, -1, -1}}}},
+};
+
+// The slot of wave w for a target of njb blocks: entry [njb - 1][w % NW][w / NW] of
+// the table, so the two waves of a SIMD hold the two slots of one table row
+// (wave-uniform values).
+struct Slot {
+  int col, msk, rs, ps, rd[3];
+  bool xch;   // some block of the target is split: partial sums are exchanged
+  __device__ __forceinline__ bool has(int kb) const { return col >= 0 && (kb & msk) == rs; }
+};
+
+__device__ __forceinline__ Slot make_slot(int njb, int wave, bool split) {
+  Slot S;
+  const int v = wave % NW, s = wave / NW;
+  S.xch = split && njb != 4 && njb != 7;
+  if (split) {
+    const SlotMap m = kSplit[njb - 1][v][s];
+    S.col = uni(m.col);
+    S.msk = uni(m.md - 1);
+    S.rs = uni(m.rs);
+    S.ps = uni(m.ps);
+#pragma unroll
+    for (int r = 0; r < 3; r++) S.rd[r] = uni(m.rd[r]);
+  } else {
+    const int c = v + NW * s;
+    S.col = c < njb ? c : -1;
+    S.msk = 0;
+    S.rs = 0;
+    S.ps = -1;
+#pragma unroll
+    for (int r = 0; r < 3; r++) S.rd[r] = -1;
+  }
+  return S;
+}
+
+// fixed-order block sums of NV values (red: NWAVE * NV doubles)
 template <int NV>
 __device__ __forceinline__ void block_sums(double *v, double *red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < NV; c++) {
     double x = wsum(v[c]);
-    if (lane == 0) red[c * NW + wave] = x;
+    if (lane == 0) red[c * NWAVE + wave] = x;
   }
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < NV; c++) {
     double t = 0.0;
-    for (int w = 0; w < NW; w++) t += red[c * NW + w];
+    for (int w = 0; w < NWAVE; w++) t += red[c * NWAVE + w];
     v[c] = t;
   }
   __syncthreads();
@@ -209,9 +300,10 @@ __device__ __forceinline__ void advance(const Desc<DLDS> &ds, Producer &p) {
   next_target(ds, p);
 }
 
-// Issue the producer's chunk into a ring stage and advance; returns the number of
-// load instructions each wave issued for it (8 pass 1, 8 or 4 pass 2, 9 epilogue,
-// 0 past the end).  Every lane takes part: lane l moves doubles 2l, 2l+1 of a row,
+// Issue the producer's chunk into a ring stage and advance (loading waves only:
+// wave NW + w loads rows w, w + 4, w + 8, w + 12 of each 16-row group); returns the
+// number of load instructions each loading wave issued for it (8 pass 1, 8 or 4
+// pass 2, 9 epilogue, 0 past the end).  Every lane takes part: lane l moves doubles 2l, 2l+1 of a row,
 // clamped to the row's last 16 bytes, so lanes past the row end only fill LDS
 // columns that are never read.  stage_off is the stage's LDS byte offset from the
 // ring base (uniform).
@@ -219,7 +311,7 @@ template <bool DLDS>
 __device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, Producer &p,
                                      double *ring, int stage_off) {
   if (p.c >= p.ncp) return 0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) - NW;
   // LDS byte address of row rr of this stage: uniform, kept in a scalar register
   const int lbase = uni((int)(size_t)(__attribute__((address_space(3))) void *)ring + stage_off +
                         wave * RS * 8);
@@ -293,6 +385,10 @@ __device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, P
 #define OSV_WAIT_CASE(N) \
   case N: asm volatile("s_waitcnt vmcnt(" #N ") lgkmcnt(0)\n\ts_barrier" ::: "memory"); break;
 __device__ __forceinline__ void stage_wait(int pending) {
+  if (uni(threadIdx.x >> 6) < NW) {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    return;
+  }
   switch (pending) {
     OSV_WAIT_CASE(4) OSV_WAIT_CASE(8) OSV_WAIT_CASE(9) OSV_WAIT_CASE(12) OSV_WAIT_CASE(13)
     OSV_WAIT_CASE(16) OSV_WAIT_CASE(17) OSV_WAIT_CASE(18)
@@ -332,7 +428,9 @@ hipError_t launch_term_flat(const Term *terms, long long nterms, const CPair *cp
 }
 
 // The consumer's step to the next chunk: wait for it, issue the chunk three
-// ahead into the stage just freed, and return the chunk's stage.
+// ahead into the stage just freed (loading waves), and return the chunk's stage.
+// The loading waves stall on the address unit while the other wave of their SIMD
+// multiplies.
 struct Ring {
   double *base;
   int k1, k2, seq;
@@ -342,7 +440,8 @@ template <bool DLDS>
 __device__ __forceinline__ const double *next_chunk(const SolveArgs &a, const Desc<DLDS> &ds,
                                                     Producer &p, Ring &r) {
   stage_wait(uni(r.k1 + r.k2));
-  const int k3 = issue(a, ds, p, r.base, ((r.seq + 3) & 3) * STG * 8);
+  int k3 = 0;
+  if (uni(threadIdx.x >> 6) >= NW) k3 = issue(a, ds, p, r.base, ((r.seq + 3) & 3) * STG * 8);
   const double *st = r.base + (r.seq & 3) * STG;
   r.k1 = r.k2;
   r.k2 = uni(k3);
@@ -353,13 +452,14 @@ __device__ __forceinline__ const double *next_chunk(const SolveArgs &a, const De
 template <bool DLDS>
 __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
   __shared__ __attribute__((aligned(16))) double ring[NSTG * STG];
-  __shared__ double red[(NTG + 2) * NW];
+  __shared__ double red[(NTG + 2) * NWAVE];
   __shared__ double plds[PLMAX];
-  __shared__ double nrm[MAXT * NW];
+  __shared__ double nrm[MAXT * NWAVE];
   __shared__ TgtDesc tg_l[MAXT];
   __shared__ TermFlat tm_l[MAXTERM];
   __shared__ double fpart[FMAXTERM];   // predicted last sweep: <Tbar~, Z_u> per term
   __shared__ double fe[MAXT * 2];      //   and <Tbar~, 2K~ + Delta T~>, <Tbar~, T~> per target
+  __shared__ double part[NPART * 256]; // partial sums of split target blocks, one tile row
   __shared__ int s_cur;
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int l15 = lane & 15, lhi = lane >> 4;
@@ -460,9 +560,11 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       const bool fmode = fm_ok && !pmode && sweep >= 2 && n1 * n1 < a.tau_R * n2;
       next_target(ds, pr);
       Ring rg{ring, 0, 0, 0};
-      issue(a, ds, pr, ring, 0);
-      rg.k1 = uni(issue(a, ds, pr, ring, STG * 8));
-      rg.k2 = uni(issue(a, ds, pr, ring, 2 * STG * 8));
+      if (wave >= NW) {
+        issue(a, ds, pr, ring, 0);
+        rg.k1 = uni(issue(a, ds, pr, ring, STG * 8));
+        rg.k2 = uni(issue(a, ds, pr, ring, 2 * STG * 8));
+      }
       double maxn_s = 0.0;   // norms when they do not fit in LDS
       for (int c = 0; c < cl.ncp; c++) {
         const TgtDesc P = ds.target(c);
@@ -470,14 +572,13 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         const double fd = P.fd;
         const int njb = (nt + 15) >> 4;
         const int nterm = pr.use_terms ? uni(P.nterm) : 0;
-        // coupling-term accumulators of R~^T(j, i): slot s holds target block
-        // ib = wave + NW s, tile jb covers rows j = 16 jb + lhi + 4v, lane column
+        const Slot sl = make_slot(njb, wave, a.split && !pmode && !fmode);
+        // coupling-term accumulators of R~^T(j, i) for (a partial sum of) target
+        // block ib = sl.col: tile jb covers rows j = 16 jb + lhi + 4v, lane column
         // i = 16 ib + l15
-        d4 Racc[NS][MT];
+        d4 Racc[MT];
 #pragma unroll
-        for (int s = 0; s < NS; s++)
-#pragma unroll
-          for (int jb = 0; jb < MT; jb++) Racc[s][jb] = (d4){0, 0, 0, 0};
+        for (int jb = 0; jb < MT; jb++) Racc[jb] = (d4){0, 0, 0, 0};
         for (int u = 0; u < nterm; u++) {
           const TermFlat f = ds.term(P.term0 + u);
           // in the P pass each term is accumulated alone with unit weight
@@ -485,72 +586,47 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
           const int nkb = uni((f.ns + 15) >> 4);
           if (pmode) {
 #pragma unroll
-            for (int s = 0; s < NS; s++)
-#pragma unroll
-              for (int jb = 0; jb < MT; jb++) Racc[s][jb] = (d4){0, 0, 0, 0};
+            for (int jb = 0; jb < MT; jb++) Racc[jb] = (d4){0, 0, 0, 0};
           }
-          // pass 1: X'(:, i-blocks) = coef op(T)^T M^T over chunks of 16 source rows
-          d4 Xp[NS][MT];
+          // pass 1: X'(kb, ib) = coef op(T)^T M^T over chunks of 16 source rows, for
+          // the source blocks kb of the slot
+          d4 Xp[MT];
 #pragma unroll
-          for (int s = 0; s < NS; s++)
-#pragma unroll
-            for (int kb = 0; kb < MT; kb++) Xp[s][kb] = (d4){0, 0, 0, 0};
+          for (int kb = 0; kb < MT; kb++) Xp[kb] = (d4){0, 0, 0, 0};
           for (int cc = 0; cc < nkb; cc++) {
             const double *ts = next_chunk(a, ds, pr, rg), *mc = ts + 16 * RS;
-            double bv[NS][4];
+            if (sl.col < 0) continue;
+            double bv[4];
 #pragma unroll
-            for (int s = 0; s < NS; s++)
-#pragma unroll
-              for (int kk = 0; kk < 4; kk++)
-                bv[s][kk] = coef * mc[(4 * kk + lhi) * RS + (wave + NW * s) * 16 + l15];
-            // operands of tile kb + 1 are read from LDS before the MFMAs of tile kb
-            double av[2][4];
-#pragma unroll
-            for (int kk = 0; kk < 4; kk++) av[0][kk] = ts[(4 * kk + lhi) * RS + l15];
+            for (int kk = 0; kk < 4; kk++) bv[kk] = coef * mc[(4 * kk + lhi) * RS + sl.col * 16 + l15];
 #pragma unroll
             for (int kb = 0; kb < MT; kb++) {
-              if (kb < nkb) {
-                // unconditional (columns up to 127 of a 130-wide row): a uniform number
-                // of LDS reads in flight lets the wait cover only the older tile
-                if (kb + 1 < MT) {
+              if (kb < nkb && sl.has(kb)) {
+                double av[4];
 #pragma unroll
-                  for (int kk = 0; kk < 4; kk++)
-                    av[(kb + 1) & 1][kk] = ts[(4 * kk + lhi) * RS + (kb + 1) * 16 + l15];
-                }
+                for (int kk = 0; kk < 4; kk++) av[kk] = ts[(4 * kk + lhi) * RS + kb * 16 + l15];
 #pragma unroll
-                for (int s = 0; s < NS; s++)
-                  if (wave + NW * s < njb)
-#pragma unroll
-                    for (int kk = 0; kk < 4; kk++) Xp[s][kb] = mfma(av[kb & 1][kk], bv[s][kk], Xp[s][kb]);
+                for (int kk = 0; kk < 4; kk++) Xp[kb] = mfma(av[kk], bv[kk], Xp[kb]);
               }
             }
           }
-          // pass 2: R~^T(:, i-blocks) += M X'(:, i-blocks), X' tile kc; a chunk
-          // holds the M rows of two tiles
+          // pass 2: R~^T(:, ib) += M X'(:, ib), X' tile kc; a chunk holds the M rows
+          // of two tiles
           const double *mst = nullptr;
 #pragma unroll
           for (int kc = 0; kc < MT; kc++) {
             if (kc < nkb) {
               if ((kc & 1) == 0) mst = next_chunk(a, ds, pr, rg);
+              if (!sl.has(kc)) continue;
               const double *mc = mst + (kc & 1) * 16 * RS;
-              // operands of tile jb + 1 are read from LDS before the MFMAs of tile jb
-              double av[2][4];
-#pragma unroll
-              for (int kk = 0; kk < 4; kk++) av[0][kk] = mc[(4 * kk + lhi) * RS + l15];
 #pragma unroll
               for (int jb = 0; jb < MT; jb++) {
                 if (jb < njb) {
-                  if (jb + 1 < MT) {
+                  double av[4];
 #pragma unroll
-                    for (int kk = 0; kk < 4; kk++)
-                      av[(jb + 1) & 1][kk] = mc[(4 * kk + lhi) * RS + (jb + 1) * 16 + l15];
-                  }
+                  for (int kk = 0; kk < 4; kk++) av[kk] = mc[(4 * kk + lhi) * RS + jb * 16 + l15];
 #pragma unroll
-                  for (int s = 0; s < NS; s++)
-                    if (wave + NW * s < njb)
-#pragma unroll
-                      for (int kk = 0; kk < 4; kk++)
-                        Racc[s][jb] = mfma(av[jb & 1][kk], Xp[s][kc][kk], Racc[s][jb]);
+                  for (int kk = 0; kk < 4; kk++) Racc[jb] = mfma(av[kk], Xp[kc][kk], Racc[jb]);
                 }
               }
             }
@@ -559,16 +635,13 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
             // Y^T of this term (P pass), or R~^T of the terms so far (predicted last
             // sweep), to scratch slot u, read back after the target's epilogue
             double *Y = Rs + (long long)u * np * np;
+            const int ib = sl.col, i = ib * 16 + l15;
+            if (ib >= 0) {
 #pragma unroll
-            for (int s = 0; s < NS; s++) {
-              const int ib = wave + NW * s, i = ib * 16 + l15;
-              if (ib < njb) {
+              for (int jb = 0; jb < MT; jb++)
+                if (jb < njb)
 #pragma unroll
-                for (int jb = 0; jb < MT; jb++)
-                  if (jb < njb)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) Y[(jb * 16 + lhi + 4 * v) * np + i] = Racc[s][jb][v];
-              }
+                  for (int v = 0; v < 4; v++) Y[(jb * 16 + lhi + 4 * v) * np + i] = Racc[jb][v];
             }
           }
         }
@@ -583,31 +656,52 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
             if (jb < njb) {
               const double *st = next_chunk(a, ds, pr, rg);
               const double *ev = st + 32 * RS;
+              if (sl.xch) {
+                // partial sums of split blocks: written to LDS, added by the owner in
+                // the order of its list
+                if (sl.ps >= 0)
 #pragma unroll
-              for (int s = 0; s < NS; s++) {
-                const int ib = wave + NW * s, i = ib * 16 + l15;
-                if (ib < njb) {
-                  const double ei = ev[i] - fd;
+                  for (int v = 0; v < 4; v++) part[sl.ps * 256 + v * 64 + lane] = Racc[jb][v];
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                if (sl.col >= 0 && sl.ps < 0)
 #pragma unroll
-                  for (int v = 0; v < 4; v++) {
-                    const int jl = lhi + 4 * v, j = jb * 16 + jl;
-                    const double delta = ei + ev[j];
-                    // T~(i, j) from the T~^T row j (zero in a cold sweep 0)
-                    const double tij = (sweep > 0 || warm) ? st[(16 + jl) * RS + i] : 0.0;
-                    const double r = Racc[s][jb][v] + st[jl * RS + i] + delta * tij;
-                    const bool in = (i < nt) && (j < nt);
-                    const double tn = in ? tij - r / delta : 0.0;
-                    ss += in ? r * r : 0.0;
-                    TnT[j * np + i] = tn;
-                    Tn[i * np + j] = tn;
-                  }
+                  for (int r = 0; r < 3; r++)
+                    if (sl.rd[r] >= 0)
+#pragma unroll
+                      for (int v = 0; v < 4; v++) Racc[jb][v] += part[sl.rd[r] * 256 + v * 64 + lane];
+              }
+              const int ib = sl.col, i = ib * 16 + l15;
+              if (ib >= 0 && sl.ps < 0) {
+                const double ei = ev[i] - fd;
+                // the 16 x 16 block (rows jb, columns ib) of the stage's K~^T rows is
+                // read by this wave only: the stepped tile goes back there, so that
+                // its transpose can be stored row-contiguous
+                double *blk = const_cast<double *>(st) + ib * 16;
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                  const int jl = lhi + 4 * v, j = jb * 16 + jl;
+                  const double delta = ei + ev[j];
+                  // T~(i, j) from the T~^T row j (zero in a cold sweep 0)
+                  const double tij = (sweep > 0 || warm) ? st[(16 + jl) * RS + i] : 0.0;
+                  const double r = Racc[jb][v] + blk[jl * RS + l15] + delta * tij;
+                  const bool in = (i < nt) && (j < nt);
+                  const double tn = in ? tij - r / delta : 0.0;
+                  ss += in ? r * r : 0.0;
+                  TnT[j * np + i] = tn;
+                  blk[jl * RS + l15] = tn;
+                }
+                // T~ rows ib: lane (il, jl) = (4v + lhi, l15) stores T~(16 ib + il, 16 jb + jl)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                  const int il = 4 * v + lhi;
+                  Tn[(ib * 16 + il) * np + jb * 16 + l15] = blk[l15 * RS + il];
                 }
               }
             }
           }
           ss = wsum(ss);
           if (lds_norms) {
-            if (lane == 0) nrm[c * NW + wave] = ss;
+            if (lane == 0) nrm[c * NWAVE + wave] = ss;
           } else {
             double v1[1] = {lane == 0 ? ss : 0.0};   // ss is already the wave's sum
             block_sums<1>(v1, red);
@@ -674,7 +768,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       if (lds_norms) {
         for (int c = 0; c < cl.ncp; c++) {
           double t = 0.0;
-          for (int w = 0; w < NW; w++) t += nrm[c * NW + w];
+          for (int w = 0; w < NWAVE; w++) t += nrm[c * NWAVE + w];
           const double nr = sqrt(t);
           maxn = (nr > maxn || nr != nr) ? nr : maxn;
         }

@@ -845,7 +845,7 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  ctx->nwg = std::max(1, std::min(ncl, tuning().solve_wg_per_cu * ncu));
+  ctx->nwg = std::max(1, std::min(ncl, ncu));   // one persistent workgroup per CU (LDS-bound)
   if ((rc = dalloc(ctx, &ctx->dTflat, P.terms.size()))) return rc;
   HIPCHK(ctx, launch_term_flat(ctx->dTerms, (long long)P.terms.size(), ctx->dCp, ctx->dCpl, ctx->dDom,
                                ctx->dRank, ctx->F, nocc, ctx->dTflat, s));
@@ -970,7 +970,7 @@ bool tuning_set(const std::string &k, int v) {
   else if (k == "prep_nt_mid" && in({256, 512, 1024})) g_tuning.prep_nt[1] = v;
   else if (k == "prep_nt_big" && in({512, 1024})) g_tuning.prep_nt[2] = v;
   else if (k == "cpl_split" && in({0, 64})) g_tuning.cpl_split = v;
-  else if (k == "solve_wg_per_cu" && in({1, 2})) g_tuning.solve_wg_per_cu = v;
+  else if (k == "solve_split" && in({0, 1})) g_tuning.solve_split = v;
   else return false;
   return true;
 }
@@ -981,7 +981,7 @@ bool tuning_get(const std::string &k, int *v) {
   else if (k == "prep_nt_mid") *v = g_tuning.prep_nt[1];
   else if (k == "prep_nt_big") *v = g_tuning.prep_nt[2];
   else if (k == "cpl_split") *v = g_tuning.cpl_split;
-  else if (k == "solve_wg_per_cu") *v = g_tuning.solve_wg_per_cu;
+  else if (k == "solve_split") *v = g_tuning.solve_split;
   else return false;
   return true;
 }
@@ -1316,6 +1316,7 @@ int osv_solve_clusters(osv_ctx *ctx, double tau_R, int32_t max_sweeps, hipStream
   a.n_clusters = ncl;
   a.tau_R = tau_R;
   a.max_sweeps = max_sweeps;
+  a.split = tuning().solve_split;
   StageTimer t(s);
   HIPCHK(ctx, launch_fill_i32(ctx->dCounter, 0, 3, s));
   HIPCHK(ctx, launch_solve(a, P.n_big, P.n_first, ctx->nwg, s));

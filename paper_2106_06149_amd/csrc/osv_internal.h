@@ -8,7 +8,7 @@ namespace osv {
 constexpr int DMAX = 100;      // largest pair-domain dimension r_p + r_q
 // clusters with at most SOLVE_MAXT pairs and SOLVE_MAXTERM terms run in the solve
 // kernel that keeps their descriptors in LDS (every MBE(3) cluster does)
-constexpr int SOLVE_MAXT = 64, SOLVE_MAXTERM = 256;
+constexpr int SOLVE_MAXT = 16, SOLVE_MAXTERM = 64;
 constexpr int NTHREADS = 256;  // threads of every per-item workgroup (4 wave64)
 
 // One pair domain [Q_p Q_q] (p < q) or Q_p (p == q).  Every per-domain square
@@ -116,6 +116,9 @@ struct SolveArgs {
   int n_clusters;
   double tau_R;
   int max_sweeps;
+  int split;            // 1: balanced (column block, source block) work split over the
+                        // waves (sweeps that take no per-term products); 0: one wave per
+                        // column block
 };
 
 // Launch parameters chosen at run time among compiled variants: defaults are the
@@ -128,7 +131,9 @@ struct Tuning {
                                         // n <= 64 {256, 512, 1024}, n <= DMAX {512, 1024}
   int cpl_split = 64;                   // couplings with both domains <= this run in the
                                         // 4-wave class: 0 (none) or 64
-  int solve_wg_per_cu = 2;              // persistent solve workgroups per CU: 1 or 2
+  int solve_split = 1;                  // residual solve: balanced work split of each
+                                        // target over the waves (1) or one wave per
+                                        // 16-column block (0)
 };
 Tuning &tuning();
 

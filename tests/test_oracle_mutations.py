@@ -53,7 +53,7 @@ MUTATIONS = {
     "osvgen_wrong_lmo_C": ("Cs.append(Qk.T @ B[k])", "Cs.append(Qk.T @ B[(k + 1) % nocc])"),
     "osvgen_threshold": ("if w[i] > l_osv][:r_max]", "if w[i] > 0.5 * l_osv][:r_max]"),
     "one_step_sign": ("dT = W @ (-Rt / denom) @ W.T", "dT = W @ (Rt / denom) @ W.T"),
-    "one_step_weight": ("w = 1.0 if p == q else 2.0\n        dE", "w = 1.0\n        dE"),
+    "one_step_weight": ("w = 1.0 if p == q else 2.0\n        e_pq", "w = 1.0\n        e_pq"),
     "one_step_drops_second_sum": ("        R = R + left @ Tord(m, q) @ composite(S, dmq, dpq)\n    return R",
                                   "        R = R + 0.0 * (left @ Tord(m, q) @ composite(S, dmq, dpq))\n    return R"),
     "exact_K_one_lmo": ("return (P.T @ B[p]) @ (B[q].T @ P)", "return (P.T @ B[p]) @ (B[p].T @ P)"),
