@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=4)
     ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
-    ap.add_argument("--cpu-sample", type=int, default=2000,
+    ap.add_argument("--cpu-sample", type=int, default=6000,
                     help="clusters of the workload timed on the CPU oracle (0 = skip)")
     ap.add_argument("--tau-R", type=float, default=1e-10)
     ap.add_argument("--weak-l2b", type=float, default=None,
