@@ -49,11 +49,11 @@
 // T~^T rows directly and T~ rows through a transpose in the part of the stage
 // only it reads, so both stores are row-contiguous.  All chunks stream through a
 // 4-stage LDS ring by direct global-to-LDS loads (16 bytes per lane, no
-// registers), issued three chunks ahead of the multiply across term and target
-// boundaries by the second wave of each SIMD, which stalls on the address unit
-// while the first one multiplies; a chunk is consumed after a partial vmcnt wait
-// and one barrier.  Every reduction has a fixed order, so results are bitwise
-// reproducible.
+// registers), used as two pairs of stages: one wait and one barrier per pair of
+// chunks, the next pair loading while this one is consumed, across term and
+// target boundaries.  The second wave of each SIMD issues the loads and stalls
+// on the address unit while the first one multiplies.  Every reduction has a
+// fixed order, so results are bitwise reproducible.
 #include "osv_internal.h"
 
 namespace osv {
@@ -377,25 +377,13 @@ __device__ __forceinline__ int issue(const SolveArgs &a, const Desc<DLDS> &ds, P
   return cnt;
 }
 
-// Wait until this wave's loads of the oldest outstanding chunk have landed
-// (pending = load instructions issued after them), then barrier: afterwards every
-// wave's loads of that chunk are in LDS and every wave has finished the previous
-// chunk.  Loads complete in issue order; stores issued in between can only make
-// the count larger, so the wait stays sufficient.
-#define OSV_WAIT_CASE(N) \
-  case N: asm volatile("s_waitcnt vmcnt(" #N ") lgkmcnt(0)\n\ts_barrier" ::: "memory"); break;
-__device__ __forceinline__ void stage_wait(int pending) {
-  if (uni(threadIdx.x >> 6) < NW) {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    return;
-  }
-  switch (pending) {
-    OSV_WAIT_CASE(4) OSV_WAIT_CASE(8) OSV_WAIT_CASE(9) OSV_WAIT_CASE(12) OSV_WAIT_CASE(13)
-    OSV_WAIT_CASE(16) OSV_WAIT_CASE(17) OSV_WAIT_CASE(18)
-    default: asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory"); break;
-  }
+// A loading wave waits until all of its loads (the two chunks of the pair) have
+// landed, every wave until its LDS reads are done, then barrier: afterwards both
+// chunks are in LDS and every wave has finished the previous pair.
+__device__ __forceinline__ void stage_wait() {
+  if (uni(threadIdx.x >> 6) < NW) asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
-#undef OSV_WAIT_CASE
 
 __global__ void k_term_flat(const Term *terms, long long nterms, const CPair *cp,
                             const Coupling *cpl, const Domain *dom, const int *rank,
@@ -427,24 +415,30 @@ hipError_t launch_term_flat(const Term *terms, long long nterms, const CPair *cp
   return hipGetLastError();
 }
 
-// The consumer's step to the next chunk: wait for it, issue the chunk three
-// ahead into the stage just freed (loading waves), and return the chunk's stage.
-// The loading waves stall on the address unit while the other wave of their SIMD
-// multiplies.
+// The consumer's step to the next chunk.  The four stages are used in pairs: at
+// an even step the pair (seq, seq + 1), issued one pair earlier, is waited for
+// together, and the loading waves issue chunks seq + 2 and seq + 3 into the two
+// stages the previous pair used; an odd step neither waits nor synchronises.  The
+// loading waves stall on the address unit while the other wave of their SIMD
+// multiplies.  Returns the chunk's stage.
 struct Ring {
   double *base;
-  int k1, k2, seq;
+  int seq;
 };
 
 template <bool DLDS>
 __device__ __forceinline__ const double *next_chunk(const SolveArgs &a, const Desc<DLDS> &ds,
                                                     Producer &p, Ring &r) {
-  stage_wait(uni(r.k1 + r.k2));
-  int k3 = 0;
-  if (uni(threadIdx.x >> 6) >= NW) k3 = issue(a, ds, p, r.base, ((r.seq + 3) & 3) * STG * 8);
+  if ((r.seq & 1) == 0) {
+    // chunks seq and seq + 1 (issued two steps ago) are waited for together; the
+    // two stages the previous pair used are then free for chunks seq + 2, seq + 3
+    stage_wait();
+    if (uni(threadIdx.x >> 6) >= NW) {
+      issue(a, ds, p, r.base, ((r.seq + 2) & 3) * STG * 8);
+      issue(a, ds, p, r.base, ((r.seq + 3) & 3) * STG * 8);
+    }
+  }
   const double *st = r.base + (r.seq & 3) * STG;
-  r.k1 = r.k2;
-  r.k2 = uni(k3);
   r.seq++;
   return st;
 }
@@ -459,7 +453,8 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
   __shared__ TermFlat tm_l[MAXTERM];
   __shared__ double fpart[FMAXTERM];   // predicted last sweep: <Tbar~, Z_u> per term
   __shared__ double fe[MAXT * 2];      //   and <Tbar~, 2K~ + Delta T~>, <Tbar~, T~> per target
-  __shared__ double part[NPART * 256]; // partial sums of split target blocks, one tile row
+  __shared__ double part[2 * NPART * 256];   // partial sums of split target blocks, one
+                                             // buffer per parity of the tile row
   __shared__ int s_cur;
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int l15 = lane & 15, lhi = lane >> 4;
@@ -559,11 +554,10 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       // guess costs the products' stores and sums, a missed one the whole P pass)
       const bool fmode = fm_ok && !pmode && sweep >= 2 && n1 * n1 < a.tau_R * n2;
       next_target(ds, pr);
-      Ring rg{ring, 0, 0, 0};
+      Ring rg{ring, 0};
       if (wave >= NW) {
         issue(a, ds, pr, ring, 0);
-        rg.k1 = uni(issue(a, ds, pr, ring, STG * 8));
-        rg.k2 = uni(issue(a, ds, pr, ring, 2 * STG * 8));
+        issue(a, ds, pr, ring, STG * 8);
       }
       double maxn_s = 0.0;   // norms when they do not fit in LDS
       for (int c = 0; c < cl.ncp; c++) {
@@ -659,16 +653,19 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
               if (sl.xch) {
                 // partial sums of split blocks: written to LDS, added by the owner in
                 // the order of its list
+                // (two buffers: the write of row jb + 2 comes after row jb + 1's barrier,
+                // which every owner passes only when it has read row jb)
+                double *pb = part + (jb & 1) * NPART * 256;
                 if (sl.ps >= 0)
 #pragma unroll
-                  for (int v = 0; v < 4; v++) part[sl.ps * 256 + v * 64 + lane] = Racc[jb][v];
+                  for (int v = 0; v < 4; v++) pb[sl.ps * 256 + v * 64 + lane] = Racc[jb][v];
                 asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
                 if (sl.col >= 0 && sl.ps < 0)
 #pragma unroll
                   for (int r = 0; r < 3; r++)
                     if (sl.rd[r] >= 0)
 #pragma unroll
-                      for (int v = 0; v < 4; v++) Racc[jb][v] += part[sl.rd[r] * 256 + v * 64 + lane];
+                      for (int v = 0; v < 4; v++) Racc[jb][v] += pb[sl.rd[r] * 256 + v * 64 + lane];
               }
               const int ib = sl.col, i = ib * 16 + l15;
               if (ib >= 0 && sl.ps < 0) {
