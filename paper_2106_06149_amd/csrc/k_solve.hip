@@ -227,6 +227,24 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// dst[0, n) = src[0, n) (or 0 when src is null) by the whole workgroup: 16-byte
+// accesses, four loads of a thread in flight before its stores.  n is even and
+// both slots 16-byte aligned (slot sizes are multiples of 2 np^2 doubles).
+__device__ __forceinline__ void block_copy(double *dst, const double *src, int n) {
+  const int n2 = n >> 1;
+  double2 *d = reinterpret_cast<double2 *>(dst);
+  const double2 *s = reinterpret_cast<const double2 *>(src);
+  for (int e0 = threadIdx.x; e0 < n2; e0 += 4 * SNT) {
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (e0 + u * SNT < n2) v[u] = s ? s[e0 + u * SNT] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (e0 + u * SNT < n2) d[e0 + u * SNT] = v[u];
+  }
+}
+
 // Producer of the chunk stream of one sweep of a cluster.  For every target pair
 // (in cluster order): the chunks of its terms (term t: nkb pass-1 chunks holding
 // op(T) rows and M(src,tgt) rows 16q.., then ceil(nkb / 2) pass-2 chunks holding
@@ -506,10 +524,9 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
         const int np = a.dom[P.dom].np;
         double *T = a.T + P.toff;
         if (P.init >= 0) {
-          const double *S0 = a.T + P.init;
-          for (int e = tid; e < 2 * np * np; e += SNT) T[e] = S0[e];
+          block_copy(T, a.T + P.init, 2 * np * np);
         } else {
-          for (int e = tid; e < 2 * np * np; e += SNT) T[e] = 0.0;
+          block_copy(T, nullptr, 2 * np * np);
         }
       }
     }
@@ -808,7 +825,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
           for (int c = 0; c < cl.ncp; c++) {
             const TgtDesc P = ds.target(c);
             double *T = a.T + P.toff;
-            for (int e = tid; e < 2 * P.np * P.np; e += SNT) T[e] = 0.0;
+            block_copy(T, nullptr, 2 * P.np * P.np);
           }
           __syncthreads();
         }
@@ -829,9 +846,7 @@ __global__ __launch_bounds__(SNT) void k_solve(SolveArgs a) {
       for (int c = 0; c < cl.ncp; c++) {
         const CPair P = a.cp[cl.cp0 + c];
         const int np = a.dom[P.dom].np;
-        const double *__restrict__ src = a.T2 + P.toff;
-        double *__restrict__ dst = a.T + P.toff;
-        for (int e = tid; e < 2 * np * np; e += SNT) dst[e] = src[e];
+        block_copy(a.T + P.toff, a.T2 + P.toff, 2 * np * np);
       }
     }
     if (small) {
