@@ -297,6 +297,42 @@ int osv_high_order_correction(osv_ctx *ctx, hipStream_t stream, double *dE, doub
                               double *max_dR, double *per_domain);
 
 /*
+ * osv_response_layout -- the layout of the OSV response intermediates of
+ * osv_response (host only; valid once the pairs are built).  One n x n block per
+ * ordered pair (i, j) of every pair domain [ij] (n = r_i + r_j, or r_i for i == j):
+ * the domains in (p <= q) lexicographic order, for p < q first (p, q) then (q, p).
+ *   n_pairs    host out or NULL: number of ordered pairs.
+ *   n_doubles  host out or NULL: doubles the output of osv_response needs.
+ *   pairs      host out or NULL, 2 int32 per ordered pair (capacity n_pairs): (i, j).
+ *   offsets    host out or NULL, per ordered pair (capacity n_pairs): first double of
+ *              its block.
+ * Errors: OSV_E_ARG.
+ */
+int osv_response_layout(const osv_ctx *ctx, int64_t *n_pairs, int64_t *n_doubles, int32_t *pairs,
+                        int64_t *offsets);
+
+/*
+ * osv_response -- the OSV response intermediate N_ij of eq:nij for every ordered
+ * pair (i, j) of the strong clusters, combined over the clusters with the MBE
+ * coefficients (eq:nmbeii for i == j, eq:nmbeij otherwise, written with the
+ * inclusion-exclusion coefficients c_X):
+ *   N_ij = sum_X c_X [ Tbar K_(ij,ij) + D_(ij,ij) F_(ij,ij) + D'_(ij,ij) S_(ij,ij)
+ *                      - sum_{k in X} ( f_jk D_(ij,ik) S_(ik,ij) + f_ik D_(ij,kj) S_(kj,ij) ) ],
+ *   D_(ij,kl) = 1/2 (Tbar_ij S_(ij,kl) T_kl + Tbar_ij^T S_(ij,kl) T_kl^T), D' the same
+ *   with F_(ij,kl), at each cluster's converged amplitudes (Tbar = 2T - T^T), in the
+ * composite OSV basis [Q_i Q_j] of the ordered pair (row-major blocks, layout of
+ * osv_response_layout; a pair held only by clusters with c_X = 0 gets zeros).
+ * The weak pairs of OSV_SEL_OVERLAP are not part of it.
+ *   N         device out, n_doubles FP64 (overwritten).
+ *   ms_flops  host [2] or NULL: device time of the evaluation (ms) and the flops of
+ *             its tile products at the kept ranks.
+ * Errors: OSV_E_STATE before a converged solve; OSV_E_ARG for a NULL N or for a
+ * context of osv_build_pairs_exact; OSV_E_NOMEM, OSV_E_HIP.  Runs on stream and
+ * synchronises it; work memory (per-workgroup scratch) is kept by the context.
+ */
+int osv_response(osv_ctx *ctx, hipStream_t stream, double *N, double *ms_flops);
+
+/*
  * osv_plan_clusters -- host-only cluster selection for OSV_SEL_DISTANCE and
  * OSV_SEL_FULL (no device work; usable without a GPU).
  *   nocc, centroid (host nocc x 3), sel: as above.

@@ -263,7 +263,43 @@ class OSVContext:
                                                        per.ctypes.data_as(ctypes.c_void_p)), self.handle)
         return dE.value, Ec.value, mx.value, per
 
-    def densities(self, dC=True, dF=True, deps=True, dvir=False):
+    def response_layout(self):
+        """Ordered pairs (n_pairs x 2 int32 array) and the offset of each one's
+        n x n block in the output of response()."""
+        npair, nd = ctypes.c_int64(), ctypes.c_int64()
+        L.check(self.lib.osv_response_layout(self.handle, ctypes.byref(npair), ctypes.byref(nd), None, None),
+                self.handle)
+        pairs = np.zeros((npair.value, 2), dtype=np.int32)
+        offs = np.zeros(npair.value, dtype=np.int64)
+        L.check(self.lib.osv_response_layout(self.handle, None, None, pairs.ctypes.data_as(ctypes.c_void_p),
+                                             offs.ctypes.data_as(ctypes.c_void_p)), self.handle)
+        return pairs, offs, nd.value
+
+    def response(self, out=None):
+        """OSV response intermediates N_ij (eq:nij, MBE-combined) of every ordered
+        pair: (flat device tensor, pairs, offsets, (ms, flops))."""
+        pairs, offs, nd = self.response_layout()
+        if out is None:
+            out = torch.empty(max(nd, 1), dtype=torch.float64, device=self.device)
+        elif out.numel() < nd or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError(f"response(): out needs {nd} contiguous float64 elements")
+        mf = np.zeros(2)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_response(self.handle, _stream(self.device), _ptr(out),
+                                          mf.ctypes.data_as(ctypes.c_void_p)), self.handle)
+        return out, pairs, offs, (float(mf[0]), float(mf[1]))
+
+    def response_blocks(self):
+        """N_ij as a dict {(i, j): n x n host array}."""
+        N, pairs, offs, _ = self.response()
+        h = N.cpu().numpy()
+        out = {}
+        for (i, j), o in zip(pairs, offs):
+            n = self.r[i] + (self.r[j] if i != j else 0)
+            out[(int(i), int(j))] = h[o:o + n * n].reshape(n, n)
+        return out
+
+
         f64 = dict(dtype=torch.float64, device=self.device)
         out_C = torch.empty(self.nosv, self.naux, **f64) if dC else None
         out_F = torch.empty(self.nocc, self.nocc, **f64) if dF else None

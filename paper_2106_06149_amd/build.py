@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosvmbe.so")
-SOURCES = ["osv_api.hip", "k_gemm.hip", "k_prep.hip", "k_solve.hip", "k_dens.hip",
+SOURCES = ["osv_api.hip", "k_gemm.hip", "k_prep.hip", "k_solve.hip", "k_dens.hip", "k_nij.hip",
            "k_osvgen.hip", "k_hocorr.hip", "devpool.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -489,6 +489,16 @@ struct osv_ctx {
   double *dTc = nullptr, *dHcOut = nullptr;
   long long *dCoff = nullptr, *dCtptr = nullptr;
   CTerm *dCterms = nullptr;
+  // OSV response N_ij (built on first use)
+  bool nij_ready = false;
+  std::vector<NijTarget> nij_tg;   // in queue (cost) order
+  long long nij_out = 0;           // output doubles
+  double nij_flops = 0.0;          // MFMA flops of one evaluation (kept ranks)
+  int nij_nwg = 1;
+  NijTarget *dNijTg = nullptr;
+  int *dNijEntCp = nullptr, *dNijCounter = nullptr;
+  double *dNijEntC = nullptr, *dNijScr = nullptr;
+  int2 *dNijLmo = nullptr, *dNijBcol = nullptr;
   // state
   bool solved = false;
   std::string err;
@@ -1751,6 +1761,208 @@ static int build_correction(osv_ctx *ctx, hipStream_t s) {
   if ((rc = dalloc(ctx, &ctx->dTc, (size_t)nTc))) return rc;
   if ((rc = dalloc(ctx, &ctx->dHcOut, (size_t)3 * ndom))) return rc;
   ctx->hc_ready = true;
+  return OSV_OK;
+}
+
+// Host tables of the OSV response N_ij: per stored pair domain (a target) the
+// clusters holding it with c_X != 0 (cluster order), the LMOs that its k-sums
+// reach with their accumulator columns and, per residual term of those clusters,
+// the columns of the source's LMO blocks; the output layout (domain order, N_pq
+// then N_qp) and the targets in decreasing order of cost for the work queue.
+static void nij_host(osv_ctx *ctx, std::vector<NijTarget> &tg, std::vector<int> &ent_cp,
+                     std::vector<double> &ent_c, std::vector<int2> &lmo_tab, std::vector<int2> &bcol,
+                     int &lb_max) {
+  Plan &P = ctx->plan;
+  const Selection &S = ctx->sel;
+  const int ndom = (int)P.doms.size(), ncl = (int)P.cls.size();
+  std::vector<long long> eptr(ndom + 1, 0);
+  for (int X = 0; X < ncl; X++) {
+    if (S.coef[X] == 0.0) continue;
+    const Cluster &C = P.cls[X];
+    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) eptr[P.cps[c].dom + 1]++;
+  }
+  for (int d = 0; d < ndom; d++) eptr[d + 1] += eptr[d];
+  ent_cp.assign(eptr[ndom], 0);
+  ent_c.assign(eptr[ndom], 0.0);
+  {
+    std::vector<long long> fill(eptr.begin(), eptr.end() - 1);
+    for (int X = 0; X < ncl; X++) {
+      if (S.coef[X] == 0.0) continue;
+      const Cluster &C = P.cls[X];
+      for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+        const long long k = fill[P.cps[c].dom]++;
+        ent_cp[k] = c;
+        ent_c[k] = S.coef[X];
+      }
+    }
+  }
+  tg.assign(ndom, NijTarget{});
+  lmo_tab.clear();
+  bcol.assign(P.terms.size(), make_int2(-1, -1));
+  lb_max = 0;
+  ctx->nij_out = 0;
+  ctx->nij_flops = 0.0;
+  std::vector<double> cost(ndom, 0.0);
+  std::vector<int> lm;
+  for (int d = 0; d < ndom; d++) {
+    const Domain &D = P.doms[d];
+    lm.clear();
+    for (long long en = eptr[d]; en < eptr[d + 1]; en++) {
+      const CPair &cp = P.cps[ent_cp[en]];
+      for (int t = cp.term0; t < cp.term0 + cp.nterm; t++) {
+        const Domain &E = P.doms[P.cps[P.terms[t].src].dom];
+        lm.push_back(E.p);
+        lm.push_back(E.q);
+      }
+    }
+    std::sort(lm.begin(), lm.end());
+    lm.erase(std::unique(lm.begin(), lm.end()), lm.end());
+    NijTarget T{};
+    T.dom = d;
+    T.nlmo = (int)lm.size();
+    T.lmo0 = (long long)lmo_tab.size();
+    T.ent0 = eptr[d];
+    T.ent1 = eptr[d + 1];
+    std::vector<int> col(lm.size());
+    int lb = 0;
+    for (size_t l = 0; l < lm.size(); l++) {
+      col[l] = lb;
+      lmo_tab.push_back(make_int2(lm[l], lb));
+      lb += ctx->r[lm[l]];
+    }
+    T.lb = lb;
+    lb_max = std::max(lb_max, lb);
+    auto column = [&](int x) {
+      return col[std::lower_bound(lm.begin(), lm.end(), x) - lm.begin()];
+    };
+    // flops of the tile products at the kept ranks
+    const double n = D.n, dt = ctx->rank_host[d];
+    const double rp = D.rp, rq = (D.p == D.q) ? D.rp : D.rq;
+    double fl = 0.0;
+    for (long long en = eptr[d]; en < eptr[d + 1]; en++) {
+      const CPair &cp = P.cps[ent_cp[en]];
+      fl += 8.0 * dt * dt * dt;
+      for (int t = cp.term0; t < cp.term0 + cp.nterm; t++) {
+        const int e = P.cps[P.terms[t].src].dom;
+        const Domain &E = P.doms[e];
+        bcol[t] = make_int2(column(E.p), E.p == E.q ? -1 : column(E.q));
+        const double ns = ctx->rank_host[e], ne = E.n;
+        fl += 4.0 * dt * ns * ns + 4.0 * dt * dt * ns + 2.0 * dt * ne * ns;
+      }
+    }
+    const bool diag = D.p == D.q;
+    fl += 2.0 * dt * n * dt + 2.0 * dt * rp * dt + 2.0 * dt * rq * rp + 2.0 * dt * n * (dt + n) +
+          2.0 * dt * n * lb + 2.0 * dt * n * rq + 2.0 * n * n * dt;
+    if (!diag) fl += 2.0 * dt * rq * dt + 2.0 * dt * rp * rq + 2.0 * dt * n * rp + 2.0 * n * n * dt;
+    ctx->nij_flops += fl;
+    cost[d] = fl;
+    T.outF = ctx->nij_out;
+    ctx->nij_out += (long long)D.n * D.n;
+    if (diag) {
+      T.outR = -1;
+    } else {
+      T.outR = ctx->nij_out;
+      ctx->nij_out += (long long)D.n * D.n;
+    }
+    tg[d] = T;
+  }
+  std::stable_sort(tg.begin(), tg.end(),
+                   [&](const NijTarget &x, const NijTarget &y) { return cost[x.dom] > cost[y.dom]; });
+}
+
+static int build_nij(osv_ctx *ctx, hipStream_t s) {
+  std::vector<int> ent_cp;
+  std::vector<double> ent_c;
+  std::vector<int2> lmo_tab, bcol;
+  int lb_max = 0;
+  nij_host(ctx, ctx->nij_tg, ent_cp, ent_c, lmo_tab, bcol, lb_max);
+  int rc;
+  if ((rc = upload(ctx, &ctx->dNijTg, ctx->nij_tg, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dNijEntCp, ent_cp, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dNijEntC, ent_c, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dNijLmo, lmo_tab, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dNijBcol, bcol, s))) return rc;
+  if ((rc = dalloc(ctx, &ctx->dNijCounter, 1))) return rc;
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int ntg = (int)ctx->nij_tg.size();
+  ctx->nij_nwg = std::max(1, std::min(ntg, 2 * ncu));
+  const long long stride = nij_scratch_doubles(lb_max);
+  if ((rc = dalloc(ctx, &ctx->dNijScr, (size_t)(stride * ctx->nij_nwg)))) return rc;
+  ctx->nij_ready = true;
+  return OSV_OK;
+}
+
+int osv_response_layout(const osv_ctx *ctx, int64_t *n_pairs, int64_t *n_doubles, int32_t *pairs,
+                        int64_t *offsets) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  const Plan &P = ctx->plan;
+  long long np = 0, nd = 0;
+  for (const Domain &D : P.doms) {
+    const long long n2 = (long long)D.n * D.n;
+    for (int o = 0; o < (D.p == D.q ? 1 : 2); o++) {
+      if (pairs) {
+        pairs[2 * np] = o ? D.q : D.p;
+        pairs[2 * np + 1] = o ? D.p : D.q;
+      }
+      if (offsets) offsets[np] = nd;
+      np++;
+      nd += n2;
+    }
+  }
+  if (n_pairs) *n_pairs = np;
+  if (n_doubles) *n_doubles = nd;
+  return OSV_OK;
+}
+
+int osv_response(osv_ctx *ctx, hipStream_t s, double *N, double *ms_flops) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  if (!N) return fail(ctx, OSV_E_ARG, "osv_response: N is NULL");
+  if (!ctx->solved) return fail(ctx, OSV_E_STATE, "osv_response before a converged solve");
+  if (ctx->k_exact)
+    return fail(ctx, OSV_E_ARG, "osv_response: the pair-domain integrals must be those of osv_build_pairs");
+  int rc;
+  if (!ctx->nij_ready && (rc = build_nij(ctx, s))) return rc;
+  NijArgs a{};
+  a.tg = ctx->dNijTg;
+  a.ntg = (int)ctx->nij_tg.size();
+  a.ent_cp = ctx->dNijEntCp;
+  a.ent_c = ctx->dNijEntC;
+  a.lmo_tab = ctx->dNijLmo;
+  a.bcol = ctx->dNijBcol;
+  a.cp = ctx->dCp;
+  a.terms = ctx->dTerms;
+  a.tflat = ctx->dTflat;
+  a.dom = ctx->dDom;
+  a.rank = ctx->dRank;
+  a.W = ctx->dW;
+  a.Y = ctx->dY;
+  a.Kep = ctx->dKt;
+  a.M = ctx->dM;
+  a.T = ctx->dT;
+  a.S = ctx->dS;
+  a.F = ctx->dF;
+  a.K = ctx->dK;
+  a.ld = ctx->nosv;
+  a.F_occ = ctx->F;
+  a.nocc = ctx->nocc;
+  a.off = ctx->dOff;
+  a.r = ctx->dR;
+  a.scr = ctx->dNijScr;
+  a.counter = ctx->dNijCounter;
+  a.N = N;
+  int lb_max = 0;
+  for (const NijTarget &t : ctx->nij_tg) lb_max = std::max(lb_max, t.lb);
+  a.scr_stride = nij_scratch_doubles(lb_max);
+  StageTimer t_n(s);
+  HIPCHK(ctx, launch_nij(a, ctx->nij_nwg, s));
+  t_n.stop();
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (ms_flops) {
+    ms_flops[0] = t_n.ms();
+    ms_flops[1] = ctx->nij_flops;
+  }
   return OSV_OK;
 }
 

@@ -121,6 +121,46 @@ struct SolveArgs {
                         // column block
 };
 
+// OSV response N_ij (eq:nij) of one stored pair domain d = [pq] and, for p < q,
+// of the reversed pair (q, p): the clusters holding the pair with nonzero MBE
+// coefficient (entries ent0 .. ent1: cluster pair index and c_X, cluster order),
+// the LMOs that its k-sums reach (lmo_tab[lmo0 .. lmo0 + nlmo): LMO and its column
+// offset in the per-LMO accumulator, lb columns in all) and the output offsets of
+// N_pq and N_qp (n x n row-major each; -1 for p == q).
+struct NijTarget {
+  int dom, nlmo, lb, pad;
+  long long ent0, ent1, lmo0;
+  long long outF, outR;
+};
+
+struct NijArgs {
+  const NijTarget *tg;
+  int ntg;
+  const int *ent_cp;      // cluster pair of each entry
+  const double *ent_c;    // c_X of each entry
+  const int2 *lmo_tab;    // (LMO, column offset in the accumulator)
+  const int2 *bcol;       // per residual term: accumulator columns of the source's
+                          // first and second LMO blocks (-1: diagonal source)
+  const CPair *cp;
+  const Term *terms;
+  const TermFlat *tflat;
+  const Domain *dom;
+  const int *rank;
+  const double *W, *Y;    // per-domain slots (moff)
+  const double *Kep;      // per domain: K~^T then e~ (voff)
+  const double *M;        // couplings
+  const double *T;        // converged cluster amplitudes
+  const double *S, *F, *K;
+  long long ld;
+  const double *F_occ;
+  int nocc;
+  const int *off, *r;     // per LMO: first OSV row, number of OSVs
+  double *scr;            // per-workgroup scratch of scr_stride doubles
+  long long scr_stride;
+  int *counter;           // work-queue head
+  double *N;              // output
+};
+
 // Launch parameters chosen at run time among compiled variants: defaults are the
 // hand-measured choices; a tuning file written by the autotuner (key value lines,
 // read once per process: $OSV_TUNING_FILE, else osv_tuning.txt beside the library)
@@ -264,6 +304,10 @@ hipError_t launch_collective_step(const Domain *dom, int ndom, const int *rank, 
 // its zero-padded slot (leading dimension np)
 hipError_t launch_exact_ktilde(const double *Gp, const double *Gq, int dt, int naux, double *Kt, int np,
                                hipStream_t s);
+// OSV response N_ij: per-workgroup scratch (doubles) for accumulators of at most
+// lb_max columns, and the persistent launch over the targets in a.tg order
+long long nij_scratch_doubles(int lb_max);
+hipError_t launch_nij(const NijArgs &a, int nwg, hipStream_t s);
 hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
                               int nocc, double *out, hipStream_t s);
 }
