@@ -32,21 +32,22 @@
 
 namespace osv {
 
-constexpr int NNT = 256;       // threads per workgroup
+constexpr int NNT = 512;       // threads per workgroup (8 waves)
 constexpr int NLD = 112;       // row stride of the dt-row work matrices (np <= 112)
 constexpr int NLD2 = 2 * NLD;  // row stride of [P | P']
 
 long long nij_scratch_doubles(int lb_max) {
-  return 9LL * NLD * NLD + (long long)NLD * NLD2 + (long long)NLD * lb_max;
+  return 9LL * NLD * NLD + 2LL * NLD * NLD2 + (long long)NLD2 * NLD2 + (long long)NLD * lb_max;
 }
 
 __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
   __shared__ int s_next;
+  __shared__ __align__(16) double lds[gemm_lds_doubles()];
   const int tid = threadIdx.x;
   double *GK = a.scr + (long long)blockIdx.x * a.scr_stride;
   double *GF = GK + NLD * NLD, *GY = GF + NLD * NLD, *Z = GY + NLD * NLD, *A = Z + NLD * NLD;
   double *AR = A + NLD * NLD, *H1 = AR + NLD * NLD, *X1 = H1 + NLD * NLD, *X2 = X1 + NLD * NLD;
-  double *PP = X2 + NLD * NLD, *B = PP + NLD * NLD2;
+  double *PP = X2 + NLD * NLD, *TB = PP + NLD * NLD2, *BFY = TB + NLD * NLD2, *B = BFY + NLD2 * NLD2;
   for (;;) {
     if (tid == 0) s_next = atomicAdd(a.counter, 1);
     __syncthreads();
@@ -82,26 +83,26 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
       const CPair cp = a.cp[a.ent_cp[en]];
       const double c = a.ent_c[en];
       const double *t = a.T + cp.toff, *tT = t + (long long)np * np;
-      // [tb | tb^T](i, k)
-      auto tbb = [&](int i, int k) -> double {
-        return k < dt ? 2.0 * t[i * np + k] - tT[i * np + k]
-                      : 2.0 * tT[i * np + k - dt] - t[i * np + k - dt];
-      };
+      // TB = [tb | tb^T] (dt x 2dt); BFY = [t, (e~ - f) t ; t^T, (e~ - f) t^T] (2dt x 2dt)
       for (int e = tid; e < dt * dt; e += NNT) {
         const int i = e / dt, k = e - i * dt;
-        GK[i * NLD + k] += c * (2.0 * t[i * np + k] - tT[i * np + k]);
+        const double x = t[i * np + k], xT = tT[i * np + k];
+        const double tb = 2.0 * x - xT, w = ev[i] - fs;
+        GK[i * NLD + k] += c * tb;
+        TB[i * NLD2 + k] = tb;
+        TB[i * NLD2 + dt + k] = 2.0 * xT - x;
+        BFY[i * NLD2 + k] = x;
+        BFY[i * NLD2 + dt + k] = w * x;
+        BFY[(dt + i) * NLD2 + k] = xT;
+        BFY[(dt + i) * NLD2 + dt + k] = w * xT;
       }
-      // [G_F | G_Y] += c/2 [tb | tb^T] [t, (e~ - f) t ; t^T, (e~ - f) t^T]
-      mma_tiles<NNT>(dt, 2 * dt, 2 * dt, tbb,
-                     [&](int k, int j) -> double {
-                       const int kk = k < dt ? k : k - dt;
-                       const double *src = k < dt ? t : tT;
-                       return j < dt ? src[kk * np + j] : (ev[kk] - fs) * src[kk * np + j - dt];
-                     },
-                     [&](int i, int j, double v) {
-                       if (j < dt) GF[i * NLD + j] += 0.5 * c * v;
-                       else GY[i * NLD + j - dt] += 0.5 * c * v;
-                     });
+      __syncthreads();
+      // G_F += c/2 TB [t ; t^T],  G_Y += c/2 TB [(e~ - f) t ; (e~ - f) t^T]
+      const Mat tbm{TB, NLD2, 0};
+      gemm_lds<NNT>(dt, dt, 2 * dt, tbm, Mat{BFY, NLD2, 0}, lds,
+                    [&](int i, int j, double v) { GF[i * NLD + j] += 0.5 * c * v; });
+      gemm_lds<NNT>(dt, dt, 2 * dt, tbm, Mat{BFY + dt, NLD2, 0}, lds,
+                    [&](int i, int j, double v) { GY[i * NLD + j] += 0.5 * c * v; });
       for (int tt = cp.term0; tt < cp.term0 + cp.nterm; tt++) {
         const TermFlat f = a.tflat[tt];
         const int flags = a.terms[tt].flags;
@@ -110,28 +111,25 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
         const int ns = f.ns, ldT = f.ldT, ldM = f.ldM;
         const double *op = a.T + f.tsrc;
         const double *opT = (flags & 2) ? op - (long long)ldT * ldT : op + (long long)ldT * ldT;
-        const double *Mst = a.M + f.moff;   // M(src, tgt), np_src x np_tgt
-        // [P | P'] = M(tgt, src) [op(t_e) | op(t_e)^T]
-        mma_tiles<NNT>(dt, 2 * ns, ns, [&](int i, int k) { return Mst[k * ldM + i]; },
-                       [&](int k, int j) { return j < ns ? op[k * ldT + j] : opT[k * ldT + j - ns]; },
-                       [&](int i, int j, double v) { PP[i * NLD2 + j] = v; });
+        // [P ; P'] = [M(tgt, src) op(t_e) ; M(tgt, src) op(t_e)^T]   (M(src, tgt) is stored)
+        const Mat mt{a.M + f.moff, ldM, 1};
+        gemm_lds<NNT>(dt, ns, ns, mt, Mat{op, ldT, 0}, lds,
+                      [&](int i, int j, double v) { PP[i * NLD + j] = v; });
+        gemm_lds<NNT>(dt, ns, ns, mt, Mat{opT, ldT, 0}, lds,
+                      [&](int i, int j, double v) { PP[(dt + i) * NLD + j] = v; });
         __syncthreads();
         // Z = tb P + tb^T P'
-        mma_tiles<NNT>(dt, ns, 2 * dt, tbb,
-                       [&](int k, int j) { return k < dt ? PP[k * NLD2 + j] : PP[(k - dt) * NLD2 + ns + j]; },
-                       [&](int i, int j, double v) { Z[i * NLD + j] = v; });
+        gemm_lds<NNT>(dt, ns, 2 * dt, tbm, Mat{PP, NLD, 0}, lds,
+                      [&](int i, int j, double v) { Z[i * NLD + j] = v; });
         __syncthreads();
         // the source's LMO blocks of B += (c (-f) / 2) Z W_e^T
         const double sc = 0.5 * c * f.coef;
-        const double *We = a.W + E.moff;
-        const int ne = E.n, rpe = E.rp;
-        mma_tiles<NNT>(dt, ne, ns, [&](int i, int k) { return Z[i * NLD + k]; },
-                       [&](int k, int j) { return We[j * ne + k]; },
-                       [&](int i, int j, double v) {
-                         const int col = j < rpe ? bc.x + j : bc.y + j - rpe;
-                         B[(long long)i * lb + col] += sc * v;
-                       });
-        __syncthreads();
+        const int rpe = E.rp;
+        gemm_lds<NNT>(dt, E.n, ns, Mat{Z, NLD, 0}, Mat{a.W + E.moff, E.n, 1}, lds,
+                      [&](int i, int j, double v) {
+                        const int col = j < rpe ? bc.x + j : bc.y + j - rpe;
+                        B[(long long)i * lb + col] += sc * v;
+                      });
       }
     }
     __syncthreads();

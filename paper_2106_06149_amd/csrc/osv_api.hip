@@ -1887,7 +1887,7 @@ static int build_nij(osv_ctx *ctx, hipStream_t s) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int ntg = (int)ctx->nij_tg.size();
-  ctx->nij_nwg = std::max(1, std::min(ntg, 2 * ncu));
+  ctx->nij_nwg = std::max(1, std::min(ntg, ncu));   // one 8-wave workgroup per CU (registers)
   const long long stride = nij_scratch_doubles(lb_max);
   if ((rc = dalloc(ctx, &ctx->dNijScr, (size_t)(stride * ctx->nij_nwg)))) return rc;
   ctx->nij_ready = true;
