@@ -37,6 +37,9 @@ def parse():
                     help="instead of the step: build the workload with the overlap selection "
                          "at this l_2b and time the weak-pair (one-block) energies")
     ap.add_argument("--weak-l3b", type=float, default=0.2)
+    ap.add_argument("--response", action="store_true",
+                    help="instead of the step: after one solve of the workload, time the OSV "
+                         "response intermediates N_ij (eq:nij, MBE-combined) of every ordered pair")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB once (device to "
                          "device) so that a counter run can calibrate its byte counters")
@@ -45,24 +48,35 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_solve_mbe3-lattice-nocc400.md")
 SOLVE_SOURCES = ["paper_2106_06149_amd/csrc/k_solve.hip", "paper_2106_06149_amd/csrc/osv_internal.h"]
+TRAFFIC_NIJ_FILE = os.path.join(ROOT, "profiles", "traffic_k_nij_mbe3-lattice-nocc400.md")
+NIJ_SOURCES = ["paper_2106_06149_amd/csrc/k_nij.hip", "paper_2106_06149_amd/csrc/tiles.h",
+               "paper_2106_06149_amd/csrc/osv_internal.h"]
 
 
-def solve_source_hash():
+def source_hash(files):
     import hashlib
     h = hashlib.sha256()
-    for f in SOLVE_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes of the solve stage (its k_solve launches) from the committed
-    counter summary, or None
-    when there is none for this workload or the solve kernel has changed since
-    the counters were taken (the summary records a hash of its sources)."""
+def solve_source_hash():
+    return source_hash(SOLVE_SOURCES)
+
+
+def nij_source_hash():
+    return source_hash(NIJ_SOURCES)
+
+
+def measured_traffic(workload, path=TRAFFIC_FILE, hash_fn=solve_source_hash):
+    """HBM bytes of one stage (the solve's k_solve launches, or the k_nij launch)
+    from the committed counter summary, or None when there is none for this
+    workload or the kernel has changed since the counters were taken (the summary
+    records a hash of its sources)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -71,7 +85,7 @@ def measured_traffic(workload):
         if ln.startswith("- ") and ":" in ln:
             k, v = ln[2:].split(":", 1)
             kv[k.strip()] = v.strip().strip("`")
-    if kv.get("source_hash") != solve_source_hash() or kv.get("workload") != str(workload):
+    if kv.get("source_hash") != hash_fn() or kv.get("workload") != str(workload):
         return None
     try:
         return float(kv["traffic_bytes_per_stage"])
@@ -101,6 +115,62 @@ def _cpu_clusters(chunk):
         npb += len(X) * (len(X) + 1) // 2
         pb._S.clear(); pb._F.clear(); pb._K.clear()   # no reuse of pair blocks across clusters
     return npb
+
+
+def _cpu_response(chunk):
+    """Worker of the response CPU baseline: per cluster the oracle's solve (not
+    timed), then its N_ij contributions (timed).  Returns (contributions, seconds)."""
+    from oracle import osv_oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    units, secs = 0, 0.0
+    pb = O.PairBlocks(_CPU_SYS)
+    for X in chunk:
+        T = O.Cluster(pb, X).solve(1e-10, 100)
+        t0 = time.perf_counter()
+        O.osv_response(_CPU_SYS, dict(clusters=[X], coef=[1.0], T=[T]))
+        secs += time.perf_counter() - t0
+        units += len(X) * len(X)
+        pb._S.clear(); pb._F.clear(); pb._K.clear()
+    return units, secs
+
+
+def cpu_response_baseline(s, n_sample, seed=7, workers=None):
+    """The FP64 CPU oracle's N_ij (osv_response) on a seeded sample of the
+    workload's clusters with nonzero c_X, over forked workers (one BLAS thread
+    each); only the N_ij evaluation is timed.  Returns contributions/s (one
+    contribution = one ordered pair of one cluster) on the host cores."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import osv_oracle as O
+    global _CPU_SYS
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nw = max(1, min(16, avail)) if workers is None else workers
+    clusters, coef, _ = O.select_clusters(s.centroid, s.sel_mode, s.cut2, s.cut3)
+    live = [X for X, c in zip(clusters, coef) if c != 0.0]
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(live), size=min(n_sample, len(live)), replace=False)
+    sample = [live[n] for n in idx]
+    chunks = [sample[w::nw] for w in range(nw)]
+    _CPU_SYS = s
+    if nw == 1:
+        res = [_cpu_response(sample)]
+    else:
+        with mp.get_context("fork").Pool(nw) as pool:
+            res = pool.map(_cpu_response, chunks, chunksize=1)
+    _CPU_SYS = None
+    units = sum(u for u, _ in res)
+    rate = sum(u / t for u, t in res if t > 0)
+    tsum = sum(t for _, t in res)
+    return {"value": rate, "unit": "contributions/s", "cores": nw, "kind": "oracle",
+            "sample": f"{len(idx)} seeded clusters with nonzero c_X ({units} ordered-pair "
+                      f"contributions) of the same workload, the oracle's N_ij of each cluster "
+                      f"(its solve not timed), over {nw} worker processes with one BLAS thread "
+                      f"each; {tsum:.1f} s of N_ij work in all",
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count()}
 
 
 def cpu_model():
@@ -161,7 +231,12 @@ def main():
     spec = synth.WORKLOADS[args.workload]
     # the host baseline forks its workers before this process initialises the GPU
     cpu_rec = None
-    if args.cpu_sample > 0 and args.weak_l2b is None:
+    if args.response:
+        if args.cpu_sample > 0:
+            cpu_rec = cpu_response_baseline(s, min(args.cpu_sample, 240))
+            print(f"[bench] cpu baseline (N_ij): {cpu_rec['value']:.1f} contributions/s on "
+                  f"{cpu_rec['cores']} workers", file=sys.stderr, flush=True)
+    elif args.cpu_sample > 0 and args.weak_l2b is None:
         cpu_rec = cpu_baseline(s, args.cpu_sample)
         print(f"[bench] cpu baseline: {cpu_rec['value']:.1f} pair-blocks/s on {cpu_rec['cores']} "
               f"workers ({cpu_rec['cpu_model']})", file=sys.stderr, flush=True)
@@ -209,6 +284,47 @@ def main():
                                      "l3b": args.weak_l3b, "n_weak": int(len(pairs)),
                                      "n_strong_2b": int(n2b), "precision": "mixed"},
                           "E_weak": Ew}))
+        return
+
+    if args.response:
+        # N_ij after one converged solve (not timed); the timed calls evaluate every
+        # ordered pair's MBE-combined N_ij from the amplitudes left on the device
+        from paper_2106_06149_amd.api import plan_clusters
+        prec = 0 if args.precision == "fp64" else 1
+        oc = OSVContext(Qt, C, eps, F, s.r, s.centroid, sel, prec)
+        oc.solve(tau_R=args.tau_R)
+        out = None
+        for _ in range(max(1, args.warmup)):
+            out, pairs, offs, _ = oc.response(out)
+        torch.cuda.synchronize()
+        ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out, pairs, offs, (ms_k, fl) = oc.response(out)
+            ms.append(ms_k)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        oc.close()
+        _, lmos, coef = plan_clusters(s.centroid, sel)
+        size = (lmos >= 0).sum(axis=1)
+        units = int(np.sum((size ** 2)[coef != 0.0]))
+        kms = float(np.mean(ms))
+        achieved = fl / (kms * 1e-3) / 1e12
+        rec = {"metric": "N_ij cluster ordered-pair contributions/s (eq:nij, MBE-combined)",
+               "value": units / dt, "unit": "contributions/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_call": dt * 1e3, "higher_is_better": True,
+               "dtype": "f64", "data": "synthetic",
+               "config": {"workload": spec["name"], "nocc": s.nocc, "ordered_pairs": int(len(pairs)),
+                          "contributions": units, "output_doubles": int(out.numel()),
+                          "precision": "mixed" if prec == 1 else "fp64", "tau_R": args.tau_R},
+               "roofline": {"kernel": "k_nij", "bound": "mfma", "achieved": achieved,
+                            "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s",
+                            "frac": achieved / PEAK["fp64_mfma_tflops"], "kernel_ms": kms,
+                            "flops": fl,
+                            "traffic": measured_traffic(args.workload, TRAFFIC_NIJ_FILE, nij_source_hash)}}
+        if cpu_rec is not None:
+            rec["cpu_baseline"] = cpu_rec
+        print(json.dumps(rec), flush=True)
         return
 
     def step(prec):

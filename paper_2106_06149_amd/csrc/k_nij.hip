@@ -37,7 +37,7 @@ constexpr int NLD = 112;       // row stride of the dt-row work matrices (np <= 
 constexpr int NLD2 = 2 * NLD;  // row stride of [P | P']
 
 long long nij_scratch_doubles(int lb_max) {
-  return 9LL * NLD * NLD + 2LL * NLD * NLD2 + (long long)NLD2 * NLD2 + (long long)NLD * lb_max;
+  return 10LL * NLD * NLD + 2LL * NLD * NLD2 + (long long)NLD2 * NLD2 + (long long)NLD * lb_max;
 }
 
 __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
@@ -47,7 +47,8 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
   double *GK = a.scr + (long long)blockIdx.x * a.scr_stride;
   double *GF = GK + NLD * NLD, *GY = GF + NLD * NLD, *Z = GY + NLD * NLD, *A = Z + NLD * NLD;
   double *AR = A + NLD * NLD, *H1 = AR + NLD * NLD, *X1 = H1 + NLD * NLD, *X2 = X1 + NLD * NLD;
-  double *PP = X2 + NLD * NLD, *TB = PP + NLD * NLD2, *BFY = TB + NLD * NLD2, *B = BFY + NLD2 * NLD2;
+  double *TS = X2 + NLD * NLD, *PP = TS + NLD * NLD, *TB = PP + NLD * NLD2, *BFY = TB + NLD * NLD2;
+  double *B = BFY + NLD2 * NLD2;
   for (;;) {
     if (tid == 0) s_next = atomicAdd(a.counter, 1);
     __syncthreads();
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
         const double x = t[i * np + k], xT = tT[i * np + k];
         const double tb = 2.0 * x - xT, w = ev[i] - fs;
         GK[i * NLD + k] += c * tb;
+        TS[i * NLD + k] = x + xT;   // tb + tb^T
         TB[i * NLD2 + k] = tb;
         TB[i * NLD2 + dt + k] = 2.0 * xT - x;
         BFY[i * NLD2 + k] = x;
@@ -104,6 +106,8 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
       gemm_lds<NNT>(dt, dt, 2 * dt, tbm, Mat{BFY + dt, NLD2, 0}, lds,
                     [&](int i, int j, double v) { GY[i * NLD + j] += 0.5 * c * v; });
       for (int tt = cp.term0; tt < cp.term0 + cp.nterm; tt++) {
+        const int mate = a.tmate[tt];
+        if (mate < -1) continue;   // taken with its sum-1 partner
         const TermFlat f = a.tflat[tt];
         const int flags = a.terms[tt].flags;
         const Domain E = a.dom[a.cp[a.terms[tt].src].dom];
@@ -111,16 +115,26 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
         const int ns = f.ns, ldT = f.ldT, ldM = f.ldM;
         const double *op = a.T + f.tsrc;
         const double *opT = (flags & 2) ? op - (long long)ldT * ldT : op + (long long)ldT * ldT;
-        // [P ; P'] = [M(tgt, src) op(t_e) ; M(tgt, src) op(t_e)^T]   (M(src, tgt) is stored)
-        const Mat mt{a.M + f.moff, ldM, 1};
-        gemm_lds<NNT>(dt, ns, ns, mt, Mat{op, ldT, 0}, lds,
-                      [&](int i, int j, double v) { PP[i * NLD + j] = v; });
-        gemm_lds<NNT>(dt, ns, ns, mt, Mat{opT, ldT, 0}, lds,
-                      [&](int i, int j, double v) { PP[(dt + i) * NLD + j] = v; });
-        __syncthreads();
-        // Z = tb P + tb^T P'
-        gemm_lds<NNT>(dt, ns, 2 * dt, tbm, Mat{PP, NLD, 0}, lds,
-                      [&](int i, int j, double v) { Z[i * NLD + j] = v; });
+        const Mat mt{a.M + f.moff, ldM, 1};   // M(tgt, src) (M(src, tgt) is stored)
+        if (mate >= 0) {
+          // diagonal target: the terms of source (p, m) and (m, p) with equal
+          // coefficients add up to (tb + tb^T) M(tgt, src) (t_e + t_e^T)
+          gemm_lds<NNT>(dt, ns, ns, mt, Mat{op, ldT, 0, opT}, lds,
+                        [&](int i, int j, double v) { PP[i * NLD + j] = v; });
+          __syncthreads();
+          gemm_lds<NNT>(dt, ns, dt, Mat{TS, NLD, 0}, Mat{PP, NLD, 0}, lds,
+                        [&](int i, int j, double v) { Z[i * NLD + j] = v; });
+        } else {
+          // [P ; P'] = [M(tgt, src) op(t_e) ; M(tgt, src) op(t_e)^T]
+          gemm_lds<NNT>(dt, ns, ns, mt, Mat{op, ldT, 0}, lds,
+                        [&](int i, int j, double v) { PP[i * NLD + j] = v; });
+          gemm_lds<NNT>(dt, ns, ns, mt, Mat{opT, ldT, 0}, lds,
+                        [&](int i, int j, double v) { PP[(dt + i) * NLD + j] = v; });
+          __syncthreads();
+          // Z = tb P + tb^T P'
+          gemm_lds<NNT>(dt, ns, 2 * dt, tbm, Mat{PP, NLD, 0}, lds,
+                        [&](int i, int j, double v) { Z[i * NLD + j] = v; });
+        }
         __syncthreads();
         // the source's LMO blocks of B += (c (-f) / 2) Z W_e^T
         const double sc = 0.5 * c * f.coef;

@@ -496,7 +496,7 @@ struct osv_ctx {
   double nij_flops = 0.0;          // MFMA flops of one evaluation (kept ranks)
   int nij_nwg = 1;
   NijTarget *dNijTg = nullptr;
-  int *dNijEntCp = nullptr, *dNijCounter = nullptr;
+  int *dNijEntCp = nullptr, *dNijCounter = nullptr, *dNijMate = nullptr;
   double *dNijEntC = nullptr, *dNijScr = nullptr;
   int2 *dNijLmo = nullptr, *dNijBcol = nullptr;
   // state
@@ -1769,9 +1769,9 @@ static int build_correction(osv_ctx *ctx, hipStream_t s) {
 // reach with their accumulator columns and, per residual term of those clusters,
 // the columns of the source's LMO blocks; the output layout (domain order, N_pq
 // then N_qp) and the targets in decreasing order of cost for the work queue.
-static void nij_host(osv_ctx *ctx, std::vector<NijTarget> &tg, std::vector<int> &ent_cp,
-                     std::vector<double> &ent_c, std::vector<int2> &lmo_tab, std::vector<int2> &bcol,
-                     int &lb_max) {
+static void nij_host(osv_ctx *ctx, const std::vector<double> &Fh, std::vector<NijTarget> &tg,
+                     std::vector<int> &ent_cp, std::vector<double> &ent_c, std::vector<int2> &lmo_tab,
+                     std::vector<int2> &bcol, std::vector<int> &tmate, int &lb_max) {
   Plan &P = ctx->plan;
   const Selection &S = ctx->sel;
   const int ndom = (int)P.doms.size(), ncl = (int)P.cls.size();
@@ -1799,6 +1799,27 @@ static void nij_host(osv_ctx *ctx, std::vector<NijTarget> &tg, std::vector<int> 
   tg.assign(ndom, NijTarget{});
   lmo_tab.clear();
   bcol.assign(P.terms.size(), make_int2(-1, -1));
+  // diagonal targets (p, p): the sum-1 term of source (p, m) and the sum-2 term of
+  // (m, p) share the source slots; with f_mp == f_pm they are taken as one
+  tmate.assign(P.terms.size(), -1);
+  const int nocc = ctx->nocc;
+  for (int X = 0; X < ncl; X++) {
+    if (S.coef[X] == 0.0) continue;
+    const Cluster &C = P.cls[X];
+    for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
+      const CPair &cp = P.cps[c];
+      if (cp.la != cp.lb || cp.nterm != 2 * (C.nlmo - 1)) continue;
+      const int h = C.nlmo - 1;
+      for (int j = 0; j < h; j++) {
+        const int t1 = cp.term0 + j, t2 = cp.term0 + h + j;
+        const Term &a1 = P.terms[t1], &a2 = P.terms[t2];
+        if (a1.src != a2.src) continue;
+        if (Fh[(size_t)a1.fa * nocc + a1.fb] != Fh[(size_t)a2.fa * nocc + a2.fb]) continue;
+        tmate[t1] = t2;
+        tmate[t2] = -2;
+      }
+    }
+  }
   lb_max = 0;
   ctx->nij_out = 0;
   ctx->nij_flops = 0.0;
@@ -1847,7 +1868,8 @@ static void nij_host(osv_ctx *ctx, std::vector<NijTarget> &tg, std::vector<int> 
         const Domain &E = P.doms[e];
         bcol[t] = make_int2(column(E.p), E.p == E.q ? -1 : column(E.q));
         const double ns = ctx->rank_host[e], ne = E.n;
-        fl += 4.0 * dt * ns * ns + 4.0 * dt * dt * ns + 2.0 * dt * ne * ns;
+        if (tmate[t] == -1) fl += 4.0 * dt * ns * ns + 4.0 * dt * dt * ns + 2.0 * dt * ne * ns;
+        else if (tmate[t] >= 0) fl += 2.0 * dt * ns * ns + 2.0 * dt * dt * ns + 2.0 * dt * ne * ns;
       }
     }
     const bool diag = D.p == D.q;
@@ -1874,14 +1896,19 @@ static int build_nij(osv_ctx *ctx, hipStream_t s) {
   std::vector<int> ent_cp;
   std::vector<double> ent_c;
   std::vector<int2> lmo_tab, bcol;
+  std::vector<int> tmate;
+  std::vector<double> Fh((size_t)ctx->nocc * ctx->nocc);
+  HIPCHK(ctx, hipMemcpyAsync(Fh.data(), ctx->F, Fh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
   int lb_max = 0;
-  nij_host(ctx, ctx->nij_tg, ent_cp, ent_c, lmo_tab, bcol, lb_max);
+  nij_host(ctx, Fh, ctx->nij_tg, ent_cp, ent_c, lmo_tab, bcol, tmate, lb_max);
   int rc;
   if ((rc = upload(ctx, &ctx->dNijTg, ctx->nij_tg, s))) return rc;
   if ((rc = upload(ctx, &ctx->dNijEntCp, ent_cp, s))) return rc;
   if ((rc = upload(ctx, &ctx->dNijEntC, ent_c, s))) return rc;
   if ((rc = upload(ctx, &ctx->dNijLmo, lmo_tab, s))) return rc;
   if ((rc = upload(ctx, &ctx->dNijBcol, bcol, s))) return rc;
+  if ((rc = upload(ctx, &ctx->dNijMate, tmate, s))) return rc;
   if ((rc = dalloc(ctx, &ctx->dNijCounter, 1))) return rc;
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
@@ -1931,6 +1958,7 @@ int osv_response(osv_ctx *ctx, hipStream_t s, double *N, double *ms_flops) {
   a.ent_c = ctx->dNijEntC;
   a.lmo_tab = ctx->dNijLmo;
   a.bcol = ctx->dNijBcol;
+  a.tmate = ctx->dNijMate;
   a.cp = ctx->dCp;
   a.terms = ctx->dTerms;
   a.tflat = ctx->dTflat;

@@ -141,6 +141,9 @@ struct NijArgs {
   const int2 *lmo_tab;    // (LMO, column offset in the accumulator)
   const int2 *bcol;       // per residual term: accumulator columns of the source's
                           // first and second LMO blocks (-1: diagonal source)
+  const int *tmate;       // per residual term of a diagonal target (p, p): the sum-2
+                          // term of the same source and coefficient (the pair is
+                          // taken at once), -2 for that sum-2 term, else -1
   const CPair *cp;
   const Term *terms;
   const TermFlat *tflat;

@@ -61,11 +61,13 @@ __device__ __forceinline__ void mma_tiles(int M, int N, int K, FA a, FB b, FC c)
 namespace osv {
 
 // A dense operand in global memory: element (r, c) is p[r ld + c], or p[c ld + r]
-// when tr is set (the transpose of a row-major matrix).
+// when tr is set (the transpose of a row-major matrix); with p2 (a B operand
+// that is not transposed) the element is p[r ld + c] + p2[r ld + c].
 struct Mat {
   const double *p;
   long long ld;
   int tr;
+  const double *p2 = nullptr;
 };
 
 // C(i, j) = sum_{k < K} A(i, k) B(k, j) for i < M <= 112, j < N <= 112 on FP64 MFMA
@@ -82,7 +84,7 @@ constexpr int GKC = 16, GAP = GKC + 2, GBP = 112, GMAX = 112;
 constexpr int GA_SZ = GMAX * GAP, GB_SZ = GKC * GBP;
 __host__ __device__ constexpr int gemm_lds_doubles() { return 2 * (GA_SZ + GB_SZ); }
 
-template <int NT, int TR>
+template <int NT, int TR, int SUM = 0>
 struct ChunkLoader {
   static constexpr int NPAIR = (GMAX * GKC / 2 + NT - 1) / NT;  // element pairs per thread
   double2 v[NPAIR];
@@ -146,7 +148,8 @@ struct ChunkLoader {
   // B chunk [k0, k0 + 16) x [0, N) into Bs[k][j]
   __device__ __forceinline__ void load_b(const Mat &B, int N, int K, int k0) {
     const int tid = threadIdx.x;
-    const bool vec = ((B.ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(B.p) & 15) == 0);
+    const bool vec = ((B.ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(B.p) & 15) == 0) &&
+                     (!SUM || (reinterpret_cast<uintptr_t>(B.p2) & 15) == 0);
 #pragma unroll
     for (int u = 0; u < NPAIR; u++) {
       const int q = tid + u * NT;
@@ -160,9 +163,14 @@ struct ChunkLoader {
             const double2 w = *reinterpret_cast<const double2 *>(s);
             x0 = w.x;
             x1 = w.y;
+            if (SUM) {
+              const double2 w2 = *reinterpret_cast<const double2 *>(B.p2 + (long long)k * B.ld + j);
+              x0 += w2.x;
+              x1 += w2.y;
+            }
           } else {
-            if (j < N) x0 = s[0];
-            if (j + 1 < N) x1 = s[1];
+            if (j < N) x0 = s[0] + (SUM ? B.p2[(long long)k * B.ld + j] : 0.0);
+            if (j + 1 < N) x1 = s[1] + (SUM ? B.p2[(long long)k * B.ld + j + 1] : 0.0);
           }
         }
       } else {       // pairs along k: (k, j), (k + 1, j)
@@ -202,7 +210,7 @@ struct ChunkLoader {
   }
 };
 
-template <int NT, int TRA, int TRB, class FC>
+template <int NT, int TRA, int TRB, int SUMB, class FC>
 __device__ void gemm_lds_t(int M, int N, int K, const Mat A, const Mat B, double *lds, FC c) {
   constexpr int NW = NT / 64;
   constexpr int MAXTW = (7 * 7 + NW - 1) / NW;   // output tiles per wave
@@ -215,7 +223,7 @@ __device__ void gemm_lds_t(int M, int N, int K, const Mat A, const Mat B, double
 #pragma unroll
   for (int u = 0; u < MAXTW; u++) acc[u] = d4p{0.0, 0.0, 0.0, 0.0};
   ChunkLoader<NT, TRA> la;
-  ChunkLoader<NT, TRB> lb;
+  ChunkLoader<NT, TRB, SUMB> lb;
   __syncthreads();
   if (nch > 0) {
     la.load_a(A, M, K, 0);
@@ -272,11 +280,12 @@ __device__ void gemm_lds_t(int M, int N, int K, const Mat A, const Mat B, double
 template <int NT, class FC>
 __device__ __forceinline__ void gemm_lds(int M, int N, int K, const Mat A, const Mat B, double *lds, FC c) {
   if (A.tr) {
-    if (B.tr) gemm_lds_t<NT, 1, 1>(M, N, K, A, B, lds, c);
-    else gemm_lds_t<NT, 1, 0>(M, N, K, A, B, lds, c);
+    if (B.tr) gemm_lds_t<NT, 1, 1, 0>(M, N, K, A, B, lds, c);
+    else if (B.p2) gemm_lds_t<NT, 1, 0, 1>(M, N, K, A, B, lds, c);
+    else gemm_lds_t<NT, 1, 0, 0>(M, N, K, A, B, lds, c);
   } else {
-    if (B.tr) gemm_lds_t<NT, 0, 1>(M, N, K, A, B, lds, c);
-    else gemm_lds_t<NT, 0, 0>(M, N, K, A, B, lds, c);
+    if (B.tr) gemm_lds_t<NT, 0, 1, 0>(M, N, K, A, B, lds, c);
+    else gemm_lds_t<NT, 0, 0, 0>(M, N, K, A, B, lds, c);
   }
 }
 
