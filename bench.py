@@ -70,7 +70,7 @@ def nij_source_hash():
     return source_hash(NIJ_SOURCES)
 
 
-def measured_traffic(workload, path=TRAFFIC_FILE, hash_fn=solve_source_hash):
+def measured_traffic(workload, path=TRAFFIC_FILE, hash_fn=None):
     """HBM bytes of one stage (the solve's k_solve launches, or the k_nij launch)
     from the committed counter summary, or None when there is none for this
     workload or the kernel has changed since the counters were taken (the summary
@@ -85,7 +85,8 @@ def measured_traffic(workload, path=TRAFFIC_FILE, hash_fn=solve_source_hash):
         if ln.startswith("- ") and ":" in ln:
             k, v = ln[2:].split(":", 1)
             kv[k.strip()] = v.strip().strip("`")
-    if kv.get("source_hash") != hash_fn() or kv.get("workload") != str(workload):
+    want = (hash_fn or solve_source_hash)()
+    if kv.get("source_hash") != want or kv.get("workload") != str(workload):
         return None
     try:
         return float(kv["traffic_bytes_per_stage"])

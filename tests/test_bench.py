@@ -30,6 +30,14 @@ def test_traffic_lookup_follows_workload_and_sources(monkeypatch):
     assert bench.measured_traffic(4) is None          # sources changed since counting
 
 
+def test_nij_traffic_lookup_follows_its_sources():
+    with open(bench.TRAFFIC_NIJ_FILE) as fh:
+        text = fh.read()
+    recorded = [ln.split("`")[1] for ln in text.splitlines() if ln.startswith("- source_hash:")][0]
+    assert bench.measured_traffic(4, bench.TRAFFIC_NIJ_FILE, lambda: recorded) > 1e11
+    assert bench.measured_traffic(4, bench.TRAFFIC_NIJ_FILE, lambda: "0" * 16) is None
+
+
 def test_cpu_baseline_record():
     from paper_2106_06149_amd import synth
     s = synth.workload(1)
