@@ -333,6 +333,21 @@ int osv_response_layout(const osv_ctx *ctx, int64_t *n_pairs, int64_t *n_doubles
 int osv_response(osv_ctx *ctx, hipStream_t stream, double *N, double *ms_flops);
 
 /*
+ * osv_weak_response -- the weak pairs' part of the OSV response in the one-block
+ * approximation of eq:nij2b: for each weak pair (i, j) of OSV_SEL_OVERLAP (pair
+ * order of osv_weak_pairs) the upper block N^up_ij = T_(i,j) K_(j,i) (r_i x r_i,
+ * OSV basis of LMO i, row-major; the lower block is taken as zero), with T_(i,j)
+ * the pair's one-block amplitudes of the last solve in the OSV bases.
+ *   n_doubles  host or NULL: doubles N_up needs (sum of r_i^2 over the weak pairs;
+ *              the blocks follow one another in pair order).
+ *   N_up       device out or NULL (NULL: only n_doubles is written).
+ * Errors: OSV_E_STATE before a converged solve (when N_up is given), OSV_E_ARG,
+ * OSV_E_HIP.  Synchronises the stream.  Other selection modes have no weak pairs
+ * (n_doubles 0).
+ */
+int osv_weak_response(osv_ctx *ctx, hipStream_t stream, int64_t *n_doubles, double *N_up);
+
+/*
  * osv_plan_clusters -- host-only cluster selection for OSV_SEL_DISTANCE and
  * OSV_SEL_FULL (no device work; usable without a GPU).
  *   nocc, centroid (host nocc x 3), sel: as above.

@@ -289,6 +289,24 @@ class OSVContext:
                                           mf.ctypes.data_as(ctypes.c_void_p)), self.handle)
         return out, pairs, offs, (float(mf[0]), float(mf[1]))
 
+    def weak_response(self):
+        """Weak pairs' N^up_ij = T_(i,j) K_(j,i) (eq:nij2b, one-block scheme) as a
+        dict {(i, j): r_i x r_i host array}, pairs in the order of weak_pairs()."""
+        _, pairs, _ = self.weak_pairs()
+        nd = ctypes.c_int64()
+        L.check(self.lib.osv_weak_response(self.handle, None, ctypes.byref(nd), None), self.handle)
+        out = torch.empty(max(nd.value, 1), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.osv_weak_response(self.handle, _stream(self.device), None, _ptr(out)),
+                    self.handle)
+        h = out.cpu().numpy()
+        res, o = {}, 0
+        for i, j in pairs:
+            ri = int(self.r[i])
+            res[(int(i), int(j))] = h[o:o + ri * ri].reshape(ri, ri)
+            o += ri * ri
+        return res
+
     def response_blocks(self):
         """N_ij as a dict {(i, j): n x n host array}."""
         N, pairs, offs, _ = self.response()

@@ -210,6 +210,32 @@ __global__ __launch_bounds__(NNT) void k_nij(NijArgs a) {
   }
 }
 
+// Weak pairs (one-block scheme): N^up_ij = T_(i,j) K_(j,i) (r_i x r_i), one
+// workgroup per pair; T is the pair's one-block amplitude in the OSV bases
+// (r_i x r_j row-major at toff[w]); K_(j,i) is read as the transpose of the
+// K_(i,j) block.
+__global__ __launch_bounds__(256) void k_weak_nup(const int2 *__restrict__ lmo, const int *__restrict__ off,
+                                                  const int *__restrict__ r, const long long *__restrict__ toff,
+                                                  const double *__restrict__ T, const double *__restrict__ K,
+                                                  long long ld, const long long *__restrict__ noff, double *N) {
+  const int w = blockIdx.x;
+  const int i = lmo[w].x, j = lmo[w].y;
+  const int ri = r[i], rj = r[j], oi = off[i], oj = off[j];
+  const double *Tw = T + toff[w];
+  double *out = N + noff[w];
+  mma_tiles<256>(ri, ri, rj, [&](int a, int k) { return Tw[a * rj + k]; },
+                 [&](int k, int b) { return K[(long long)(oi + b) * ld + oj + k]; },
+                 [&](int a, int b, double v) { out[a * ri + b] = v; });
+}
+
+hipError_t launch_weak_nup(const int2 *lmo, int nweak, const int *off, const int *r, const long long *toff,
+                           const double *T, const double *K, long long ld, const long long *noff, double *N,
+                           hipStream_t s) {
+  if (nweak <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weak_nup, dim3(nweak), dim3(256), 0, s, lmo, off, r, toff, T, K, ld, noff, N);
+  return hipGetLastError();
+}
+
 hipError_t launch_nij(const NijArgs &a, int nwg, hipStream_t s) {
   if (a.ntg <= 0) return hipSuccess;
   hipError_t e = launch_fill_i32(a.counter, 0, 1, s);

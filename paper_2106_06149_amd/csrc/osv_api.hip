@@ -499,6 +499,7 @@ struct osv_ctx {
   int *dNijEntCp = nullptr, *dNijCounter = nullptr, *dNijMate = nullptr;
   double *dNijEntC = nullptr, *dNijScr = nullptr;
   int2 *dNijLmo = nullptr, *dNijBcol = nullptr;
+  long long *dWeakNoff = nullptr;  // weak pairs' N^up offsets (built on first use)
   // state
   bool solved = false;
   std::string err;
@@ -1991,6 +1992,26 @@ int osv_response(osv_ctx *ctx, hipStream_t s, double *N, double *ms_flops) {
     ms_flops[0] = t_n.ms();
     ms_flops[1] = ctx->nij_flops;
   }
+  return OSV_OK;
+}
+
+int osv_weak_response(osv_ctx *ctx, hipStream_t s, int64_t *n_doubles, double *N_up) {
+  if (!ctx) return fail(nullptr, OSV_E_ARG, "ctx is NULL");
+  const int nweak = (int)ctx->weak.size();
+  std::vector<long long> noff(nweak + 1, 0);
+  for (int w = 0; w < nweak; w++) {
+    const long long ri = ctx->r[ctx->weak[w].x];
+    noff[w + 1] = noff[w] + ri * ri;
+  }
+  if (n_doubles) *n_doubles = noff[nweak];
+  if (!N_up) return OSV_OK;
+  if (!ctx->solved) return fail(ctx, OSV_E_STATE, "osv_weak_response before a converged solve");
+  if (nweak == 0) return OSV_OK;
+  int rc;
+  if (!ctx->dWeakNoff && (rc = upload(ctx, &ctx->dWeakNoff, noff, s))) return rc;
+  HIPCHK(ctx, launch_weak_nup(ctx->dWeakLmo, nweak, ctx->dOff, ctx->dR, ctx->dWeakToff, ctx->dWeakT, ctx->dK,
+                              (long long)ctx->nosv, ctx->dWeakNoff, N_up, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
   return OSV_OK;
 }
 

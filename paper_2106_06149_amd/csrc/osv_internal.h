@@ -311,6 +311,10 @@ hipError_t launch_exact_ktilde(const double *Gp, const double *Gq, int dt, int n
 // lb_max columns, and the persistent launch over the targets in a.tg order
 long long nij_scratch_doubles(int lb_max);
 hipError_t launch_nij(const NijArgs &a, int nwg, hipStream_t s);
+// weak pairs: N^up_ij = T_(i,j) K_(j,i) (r_i x r_i row-major at noff[w])
+hipError_t launch_weak_nup(const int2 *lmo, int nweak, const int *off, const int *r, const long long *toff,
+                           const double *T, const double *K, long long ld, const long long *noff, double *N,
+                           hipStream_t s);
 hipError_t launch_block_sumsq(const double *S, long long ld, const int *off, const int *r,
                               int nocc, double *out, hipStream_t s);
 }

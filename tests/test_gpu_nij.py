@@ -22,7 +22,7 @@ import pytest
 import torch
 
 from paper_2106_06149_amd import _lib as L, synth
-from paper_2106_06149_amd.api import OSVContext
+from paper_2106_06149_amd.api import OSVContext, Selection
 from oracle import osv_oracle as O
 
 pytestmark = pytest.mark.gpu
@@ -131,6 +131,32 @@ def test_nij_repeatable():
     b = oc.response()[0]
     oc.close()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_weak_pair_nup_and_strong_response_overlap_selection(precision):
+    """Overlap selection (strong clusters and weak pairs, l2b at the median metric):
+    the weak pairs' one-block N^up = T_(i,j) K_(j,i) of eq:nij2b and the strong
+    clusters' N_ij, element by element against the oracle."""
+    c_dtype = np.float32 if precision == 1 else np.float64
+    s = synth.make_system(9, 70, 60, (5, 12), seed=37, sel_mode=synth.SEL_OVERLAP,
+                          c_dtype=c_dtype, precision=precision)
+    s2b = O.s2b_metric(s)
+    off = np.sort(s2b[np.triu_indices(s.nocc, 1)])
+    h = len(off) // 2
+    l2b = float(0.5 * (off[h - 1] + off[h]))
+    say(f"case weak N^up precision={precision} nocc=9 l2b={l2b:.3g}")
+    oc = OSVContext.from_system(s, device="cuda:0", precision=precision,
+                                sel=Selection(L.OSV_SEL_OVERLAP, l2b=l2b, l3b=0.9 * l2b))
+    oc.solve(tau_R=1e-12)
+    g_up = oc.weak_response()
+    g_n = oc.response_blocks()
+    oc.close()
+    ref_up = O.weak_pair_nup(s, l2b, s2b=s2b)
+    assert len(ref_up) > 0 and set(g_up) == set(ref_up)
+    compare(g_up, ref_up)
+    res = O.solve(s, mode=synth.SEL_OVERLAP, l2b=l2b, l3b=0.9 * l2b, densities=False, tau_R=1e-12)
+    compare(g_n, O.osv_response(s, res))
 
 
 def oracle_pairs(s, pairs, tau_R):
