@@ -81,6 +81,7 @@ struct Mat {
 // after the last chunk.  lds: gemm_lds_doubles() doubles.  Every thread of the
 // block must call it; it begins and ends with a barrier.
 constexpr int GKC = 16, GAP = GKC + 2, GBP = 112, GMAX = 112;
+constexpr int GPR = GKC / 2;   // element pairs along k per row of a chunk
 constexpr int GA_SZ = GMAX * GAP, GB_SZ = GKC * GBP;
 __host__ __device__ constexpr int gemm_lds_doubles() { return 2 * (GA_SZ + GB_SZ); }
 
@@ -97,7 +98,7 @@ struct ChunkLoader {
       const int q = tid + u * NT;
       double x0 = 0.0, x1 = 0.0;
       if (!TR) {   // pairs along k: (i, kk), (i, kk + 1)
-        const int i = q >> 3, k = k0 + ((q & 7) << 1);
+        const int i = q / GPR, k = k0 + ((q % GPR) << 1);
         if (i < M) {
           const double *s = A.p + (long long)i * A.ld + k;
           if (vec && k + 1 < K) {
@@ -133,7 +134,7 @@ struct ChunkLoader {
     for (int u = 0; u < NPAIR; u++) {
       const int q = tid + u * NT;
       if (!TR) {
-        const int i = q >> 3, kk = (q & 7) << 1;
+        const int i = q / GPR, kk = (q % GPR) << 1;
         if (i < GMAX) *reinterpret_cast<double2 *>(As + i * GAP + kk) = v[u];
       } else {
         const int mh = (M + 1) >> 1;
@@ -174,7 +175,7 @@ struct ChunkLoader {
           }
         }
       } else {       // pairs along k: (k, j), (k + 1, j)
-        const int j = q >> 3, k = k0 + ((q & 7) << 1);
+        const int j = q / GPR, k = k0 + ((q % GPR) << 1);
         if (j < N) {
           const double *s = B.p + (long long)j * B.ld + k;
           if (vec && k + 1 < K) {
@@ -200,7 +201,7 @@ struct ChunkLoader {
         const int kk = q / nh, j = (q - kk * nh) << 1;
         if (kk < GKC) *reinterpret_cast<double2 *>(Bs + kk * GBP + j) = v[u];
       } else {
-        const int j = q >> 3, kk = (q & 7) << 1;
+        const int j = q / GPR, kk = (q % GPR) << 1;
         if (j < GMAX) {
           Bs[kk * GBP + j] = v[u].x;
           Bs[(kk + 1) * GBP + j] = v[u].y;
@@ -244,8 +245,10 @@ __device__ void gemm_lds_t(int M, int N, int K, const Mat A, const Mat B, double
       const int t = wave + u * NW;
       if (t < nt) {
         const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+        const int kend = K - ch * GKC;   // k-steps past K multiply zeros: skipped
 #pragma unroll
         for (int ks = 0; ks < GKC / 4; ks++) {
+          if (4 * ks >= kend) break;
           const double av = As[(i0 + l15) * GAP + 4 * ks + lhi];
           const double bv = Bs[(4 * ks + lhi) * GBP + j0 + l15];
           acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
