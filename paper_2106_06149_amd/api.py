@@ -317,7 +317,7 @@ class OSVContext:
             out[(int(i), int(j))] = h[o:o + n * n].reshape(n, n)
         return out
 
-
+    def densities(self, dC=True, dF=True, deps=True, dvir=False):
         f64 = dict(dtype=torch.float64, device=self.device)
         out_C = torch.empty(self.nosv, self.naux, **f64) if dC else None
         out_F = torch.empty(self.nocc, self.nocc, **f64) if dF else None

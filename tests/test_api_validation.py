@@ -78,3 +78,18 @@ def test_mixed_devices_rejected(sysm):
 def test_context_refuses_host_tensors_before_any_device_call(sysm):
     with pytest.raises(ValueError, match="device tensor"):
         api.OSVContext(*tensors(sysm), sysm.r, sysm.centroid)
+
+
+def test_context_methods_present():
+    """Every call of the boundary has its method on OSVContext (each wraps one
+    C-ABI entry point; a method lost in an edit fails here, without a GPU)."""
+    import inspect
+    want = {"solve": "osv_solve_clusters", "energy": "osv_energy", "densities": "osv_densities",
+            "weak_pairs": "osv_weak_pairs", "high_order_correction": "osv_high_order_correction",
+            "response_layout": "osv_response_layout", "response": "osv_response",
+            "weak_response": "osv_weak_response", "stage_times": "osv_stage_times",
+            "stage_flops": "osv_stage_flops"}
+    for name, entry in want.items():
+        fn = getattr(api.OSVContext, name, None)
+        assert callable(fn), name
+        assert entry in inspect.getsource(fn), (name, entry)
