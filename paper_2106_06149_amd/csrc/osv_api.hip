@@ -553,6 +553,72 @@ int upload(osv_ctx *ctx, T **p, const std::vector<T> &v, hipStream_t s) {
   return OSV_OK;
 }
 
+// Pinned host staging for the large table uploads: one buffer per device, kept
+// for the process and grown when a batch needs more.  A batch copies its tables
+// into it on the host and the device reads them by DMA in stream order; an event
+// recorded after the copies guards the next reuse (the next batch waits for it
+// before writing).  Pageable sources would be staged by the runtime in small
+// pieces after the preceding kernels, with the host copying in between.
+struct PinnedStage {
+  std::mutex mu;
+  char *p = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+};
+std::mutex g_stage_mu;
+std::map<int, PinnedStage> g_stage;
+
+struct Up {
+  void **dst;
+  const void *src;
+  size_t bytes;
+};
+template <class T>
+void add_up(std::vector<Up> &ups, T **dst, const std::vector<T> &v) {
+  ups.push_back(Up{reinterpret_cast<void **>(dst), v.data(), v.size() * sizeof(T)});
+}
+
+// device buffers for every table of the batch (from the block cache) and their
+// contents, copied through the pinned staging buffer on stream s
+int upload_batch(osv_ctx *ctx, const std::vector<Up> &ups, hipStream_t s) {
+  size_t total = 0;
+  for (const Up &u : ups) total += (u.bytes + 255) & ~(size_t)255;
+  for (const Up &u : ups) {
+    char *d = nullptr;
+    int rc = dalloc(ctx, &d, u.bytes);
+    if (rc) return rc;
+    *u.dst = d;
+  }
+  int dev = 0;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  PinnedStage *st;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    st = &g_stage[dev];
+  }
+  std::lock_guard<std::mutex> lk(st->mu);
+  if (st->done) HIPCHK(ctx, hipEventSynchronize(st->done));   // the last batch has been read
+  else HIPCHK(ctx, hipEventCreateWithFlags(&st->done, hipEventDisableTiming));
+  if (total > st->cap) {
+    if (st->p) HIPCHK(ctx, hipHostFree(st->p));
+    st->p = nullptr;
+    st->cap = 0;
+    const size_t want = std::max(total, (size_t)1 << 20);
+    HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void **>(&st->p), want, hipHostMallocDefault));
+    st->cap = want;
+  }
+  size_t o = 0;
+  for (const Up &u : ups) {
+    if (u.bytes) {
+      std::memcpy(st->p + o, u.src, u.bytes);
+      HIPCHK(ctx, hipMemcpyAsync(*u.dst, st->p + o, u.bytes, hipMemcpyHostToDevice, s));
+    }
+    o += (u.bytes + 255) & ~(size_t)255;
+  }
+  HIPCHK(ctx, hipEventRecord(st->done, s));
+  return OSV_OK;
+}
+
 // the FP64 copy of an FP32 C, made once per context
 int c64(osv_ctx *ctx, hipStream_t s) {
   if (ctx->dC64) return OSV_OK;
@@ -823,13 +889,6 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   ctx->counts.n_domains = (int64_t)P.doms.size();
   ctx->counts.n_couplings = (int64_t)P.cpls.size();
   const int ncl = (int)P.cls.size();
-  // the plan tables (about 150 MB at nocc = 400, from pageable memory) go up on
-  // the caller's stream behind the preparation kernels
-  if ((rc = upload(ctx, &ctx->dCpl, P.cpls, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCp, P.cps, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dTerms, P.terms, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dCl, P.cls, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dQueue, P.queue, s))) return rc;
   // couplings by size class: both domains with n <= 64, then the others
   int n64 = 0;
   {
@@ -843,7 +902,18 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       }
       if (pass == 0) n64 = (int)ids.size();
     }
-    if ((rc = upload(ctx, &ctx->dCplIds, ids, s))) return rc;
+  }
+  // the plan tables (about 150 MB at nocc = 400) go up on the caller's stream
+  // behind the preparation kernels, through the pinned staging buffer
+  {
+    std::vector<Up> ups;
+    add_up(ups, &ctx->dCpl, P.cpls);
+    add_up(ups, &ctx->dCp, P.cps);
+    add_up(ups, &ctx->dTerms, P.terms);
+    add_up(ups, &ctx->dCl, P.cls);
+    add_up(ups, &ctx->dQueue, P.queue);
+    add_up(ups, &ctx->dCplIds, ctx->cpl_ids);
+    if ((rc = upload_batch(ctx, ups, s))) return rc;
   }
   ctx->stage_ms[8] = host_ms;
   StageTimer t_cpl(s);
@@ -1512,19 +1582,19 @@ static void densities_host(osv_ctx *ctx) {
 static int upload_density_tables(osv_ctx *ctx, hipStream_t s) {
   DensHost &H = ctx->dh;
   const Selection &S = ctx->sel;
-  int rc;
-  if ((rc = upload(ctx, &ctx->dDptr, H.ptr, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dDtoff, H.toff, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dDcoef, H.cf, s))) return rc;
   ctx->nblocks = (int)H.blocks.size();
-  if ((rc = upload(ctx, &ctx->dBlocks, H.blocks, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dBptr, H.bptr, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dBdom, H.bdom, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dBpart, H.bpart, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dPptr, H.pptr, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dPidx, H.pidx, s))) return rc;
-  if ((rc = upload(ctx, &ctx->dClcoef, S.coef, s))) return rc;
-  return OSV_OK;
+  std::vector<Up> ups;
+  add_up(ups, &ctx->dDptr, H.ptr);
+  add_up(ups, &ctx->dDtoff, H.toff);
+  add_up(ups, &ctx->dDcoef, H.cf);
+  add_up(ups, &ctx->dBlocks, H.blocks);
+  add_up(ups, &ctx->dBptr, H.bptr);
+  add_up(ups, &ctx->dBdom, H.bdom);
+  add_up(ups, &ctx->dBpart, H.bpart);
+  add_up(ups, &ctx->dPptr, H.pptr);
+  add_up(ups, &ctx->dPidx, H.pidx);
+  add_up(ups, &ctx->dClcoef, S.coef);
+  return upload_batch(ctx, ups, s);
 }
 
 static int prepare_densities(osv_ctx *ctx, hipStream_t s) {
