@@ -24,9 +24,17 @@
 // in the basis [pq] it differs only in its integral term, G_K^T Y_q K_qp S_(p,d);
 // its result is written in the basis [qp].
 //
-// One persistent workgroup per target domain at a time (work queue in cost
-// order); the products run on FP64 MFMA 16x16x4 tiles whose operands are read
-// from the amplitude, coupling and W slots and from per-workgroup scratch.
+// For a diagonal target (p, p) the sum-1 term of source (p, m) and the sum-2 term
+// of (m, p) have the same source slots and (when f_mp == f_pm, which the host
+// checks) the same coefficient; together they are (tb + tb^T) M (t_e + t_e^T),
+// one product instead of two.
+//
+// One persistent eight-wave workgroup per CU takes target domains from a work
+// queue (largest cost first).  The per-cluster products run on the LDS-staged
+// FP64 MFMA tile product (gemm_lds); their operands are the amplitude, coupling
+// and W slots and per-workgroup scratch (the cluster's [tb | tb^T] and
+// [t, (e~ - f) t ; t^T, (e~ - f) t^T], the products P, P', Z, the accumulators).
+// The final per-domain products use register-fed tiles (mma_tiles).
 #include "osv_internal.h"
 #include "tiles.h"
 
