@@ -180,13 +180,15 @@ def oracle_pairs(s, pairs, tau_R):
     return {p: N[p] for p in pairs}
 
 
-def test_nij_full_size_sampled_and_span_invariance():
-    """The benchmark's workload (nocc = 400 lattice, mixed precision): sampled
+@pytest.mark.parametrize("k", [4, 2, 3])
+def test_nij_full_size_sampled_and_span_invariance(k):
+    """The benchmark's workload (nocc = 400 lattice, mixed precision), the nocc = 128
+    lattice (mixed) and the nocc = 64 line (FP64) at their full sizes: sampled
     off-diagonal pairs against the oracle, and the span invariance of every LMO over
     all pairs (tau_R = 1e-12, see above)."""
     tau_R = 1e-12
-    s = synth.workload(4)
-    say("case N_ij workload 4 (nocc=400 lattice, mixed): GPU")
+    s = synth.workload(k)
+    say(f"case N_ij workload {k} ({synth.WORKLOADS[k]['name']}): GPU")
     oc = OSVContext.from_system(s, device="cuda:0")
     oc.solve(tau_R=tau_R)
     N, pairs, offs, (ms, fl) = oc.response()
@@ -214,7 +216,7 @@ def test_nij_full_size_sampled_and_span_invariance():
     inv = max(float(np.abs(b).max()) for b in blocks)
     say(f"  span invariance: max |sum of k-blocks| {inv:.3e} of max |N| {scale:.3e}")
     assert inv <= 1e-7 * scale
-    rng = np.random.default_rng(400)
+    rng = np.random.default_rng(400 + k)
     off = [p for p in index if p[0] < p[1]]
     pick = [off[int(x)] for x in rng.choice(len(off), size=2, replace=False)]
     sample = pick + [(j, i) for i, j in pick]
