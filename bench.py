@@ -20,7 +20,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+PEAK = {"fp64_mfma_tflops": 78.6, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
 
 
 def parse():
@@ -28,7 +28,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=4)
+    ap.add_argument("--workload", type=int, default=None,
+                    help="synthetic workload (default 4; 3 with --osvgen, the largest that carries B)")
     ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--cpu-sample", type=int, default=6000,
                     help="clusters of the workload timed on the CPU oracle (0 = skip)")
@@ -40,6 +41,11 @@ def parse():
     ap.add_argument("--response", action="store_true",
                     help="instead of the step: after one solve of the workload, time the OSV "
                          "response intermediates N_ij (eq:nij, MBE-combined) of every ordered pair")
+    ap.add_argument("--correction", action="store_true",
+                    help="instead of the step: after one solve of the workload, time the one-step "
+                         "high-order correction")
+    ap.add_argument("--osvgen", action="store_true",
+                    help="instead of the step: time the OSV generation from the fitted integrals B")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB once (device to "
                          "device) so that a counter run can calibrate its byte counters")
@@ -174,6 +180,25 @@ def cpu_response_baseline(s, n_sample, seed=7, workers=None):
             "cpu_model": cpu_model(), "cpu_count": os.cpu_count()}
 
 
+def cpu_osvgen_baseline(s):
+    """The FP64 CPU oracle's OSV generation (generate_osvs) on the whole workload,
+    timed once in this process (before the GPU is touched), with the BLAS threads it
+    has.  Returns LMOs/s."""
+    from oracle import osv_oracle as O
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads") or 0) for d in threadpool_info()) or None
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    O.generate_osvs(s.B, s.eps_vir, s.F_occ, 1e-4, 50)
+    dt = time.perf_counter() - t0
+    return {"value": s.nocc / dt, "unit": "LMOs/s", "cores": threads or 1, "kind": "oracle",
+            "sample": f"the whole workload ({s.nocc} LMOs), one call, {dt:.1f} s",
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count()}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -228,16 +253,26 @@ def main():
     import numpy as np
     from paper_2106_06149_amd import synth
 
+    if args.workload is None:
+        args.workload = 3 if args.osvgen else 4
     s = synth.workload(args.workload)
     spec = synth.WORKLOADS[args.workload]
     # the host baseline forks its workers before this process initialises the GPU
     cpu_rec = None
-    if args.response:
+    if args.osvgen:
+        if getattr(s, "B", None) is None:
+            print(f"bench.py --osvgen: workload {args.workload} carries no B", file=sys.stderr)
+            sys.exit(2)
+        if args.cpu_sample > 0:
+            cpu_rec = cpu_osvgen_baseline(s)
+            print(f"[bench] cpu baseline (OSV generation): {cpu_rec['value']:.2f} LMOs/s on "
+                  f"{cpu_rec['cores']} BLAS threads", file=sys.stderr, flush=True)
+    elif args.response:
         if args.cpu_sample > 0:
             cpu_rec = cpu_response_baseline(s, min(args.cpu_sample, 240))
             print(f"[bench] cpu baseline (N_ij): {cpu_rec['value']:.1f} contributions/s on "
                   f"{cpu_rec['cores']} workers", file=sys.stderr, flush=True)
-    elif args.cpu_sample > 0 and args.weak_l2b is None:
+    elif args.cpu_sample > 0 and args.weak_l2b is None and not args.correction:
         cpu_rec = cpu_baseline(s, args.cpu_sample)
         print(f"[bench] cpu baseline: {cpu_rec['value']:.1f} pair-blocks/s on {cpu_rec['cores']} "
               f"workers ({cpu_rec['cpu_model']})", file=sys.stderr, flush=True)
@@ -285,6 +320,77 @@ def main():
                                      "l3b": args.weak_l3b, "n_weak": int(len(pairs)),
                                      "n_strong_2b": int(n2b), "precision": "mixed"},
                           "E_weak": Ew}))
+        return
+
+    if args.osvgen:
+        from paper_2106_06149_amd.api import generate_osvs, generation_stats
+        B = torch.from_numpy(np.ascontiguousarray(s.B)).to(dev)
+        for _ in range(max(1, args.warmup)):
+            generate_osvs(B, eps, F, 1e-4, 50)
+        torch.cuda.synchronize()
+        st = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r, _, _, _ = generate_osvs(B, eps, F, 1e-4, 50)
+            st.append(generation_stats())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        ms = {k: float(np.mean([x[k][0] for x in st])) for k in st[0]}
+        fl = {k: st[0][k][1] for k in st[0]}
+        rec = {"metric": "LMOs/s (OSV generation from B, eq:svd)", "value": s.nocc / dt, "unit": "LMOs/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_call": dt * 1e3,
+               "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": spec["name"], "nocc": s.nocc, "nvir": s.nvir, "naux": s.naux,
+                          "l_osv": 1e-4, "r_max": 50, "osvs_kept": int(r.sum())},
+               "stages_ms": {k: round(v, 3) for k, v in ms.items()},
+               "stage_tflops": {k: round(fl[k] / (ms[k] * 1e-3) / 1e12, 3) for k in ms if ms[k] > 0},
+               # the dominant kernel: the per-LMO Householder reduction (FP64 vector ALU)
+               "roofline": {"kernel": "k_osv_tridiag", "bound": "alu",
+                            "achieved": fl["tridiag"] / (ms["tridiag"] * 1e-3) / 1e12,
+                            "peak": PEAK["fp64_vector_tflops"], "unit": "TFLOP/s",
+                            "frac": fl["tridiag"] / (ms["tridiag"] * 1e-3) / 1e12 / PEAK["fp64_vector_tflops"],
+                            "traffic": None}}
+        if cpu_rec is not None:
+            rec["cpu_baseline"] = cpu_rec
+        print(json.dumps(rec), flush=True)
+        return
+
+    if args.correction:
+        # the one-step correction after one converged solve (not timed)
+        prec = 0 if args.precision == "fp64" else 1
+        oc = OSVContext(Qt, C, eps, F, s.r, s.centroid, sel, prec)
+        oc.solve(tau_R=args.tau_R)
+        for _ in range(max(1, args.warmup)):
+            oc.high_order_correction()
+        torch.cuda.synchronize()
+        st = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dE, Ec, mx, _ = oc.high_order_correction()
+            st.append(oc.correction_stats())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        nd = oc.counts["n_domains"]
+        oc.close()
+        cms = float(np.mean([x["collective"][0] for x in st]))
+        sms = float(np.mean([x["step"][0] for x in st]))
+        cby, sfl = st[0]["collective"][1], st[0]["step"][1]
+        rec = {"metric": "pair domains/s (one-step high-order correction)", "value": nd / dt,
+               "unit": "domains/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_call": dt * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": spec["name"], "nocc": s.nocc, "pair_domains": int(nd),
+                          "precision": "mixed" if prec == 1 else "fp64", "tau_R": args.tau_R},
+               "stages_ms": {"collective": round(cms, 3), "step": round(sms, 3)},
+               "roofline": {"kernel": "k_collective_step", "bound": "mfma",
+                            "achieved": sfl / (sms * 1e-3) / 1e12, "peak": PEAK["fp64_mfma_tflops"],
+                            "unit": "TFLOP/s", "frac": sfl / (sms * 1e-3) / 1e12 / PEAK["fp64_mfma_tflops"],
+                            "flops": sfl, "traffic": None},
+               "roofline_collective": {"kernel": "k_collective", "bound": "hbm",
+                                       "achieved": cby / (cms * 1e-3) / 1e9, "peak": PEAK["hbm_gbs"],
+                                       "unit": "GB/s", "frac": cby / (cms * 1e-3) / 1e9 / PEAK["hbm_gbs"],
+                                       "bytes": cby, "traffic": None},
+               "dE": dE, "E_coll": Ec, "max_dR": mx}
+        print(json.dumps(rec), flush=True)
         return
 
     if args.response:

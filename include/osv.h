@@ -348,6 +348,28 @@ int osv_response(osv_ctx *ctx, hipStream_t stream, double *N, double *ms_flops);
 int osv_weak_response(osv_ctx *ctx, hipStream_t stream, int64_t *n_doubles, double *N_up);
 
 /*
+ * osv_correction_stats -- device times and algorithmic work of the last
+ * osv_high_order_correction call on this context:
+ *   out4  host [4]: the collective sums (ms, bytes they must read and write: every
+ *         cluster slot of a domain once, the domain's two slots once), then the
+ *         residual step (ms, flops: 2 (dt n_s^2 + dt^2 n_s) per term at the kept ranks).
+ * Errors: OSV_E_ARG.  Zeros before the first call.
+ */
+int osv_correction_stats(const osv_ctx *ctx, double *out4);
+
+/*
+ * osv_generation_stats -- device times and algorithmic flops of the last
+ * osv_generate_osvs call of the calling thread:
+ *   out8  host [8]: (ms, flops) of the products (ka|kb) (nvir^2 naux per LMO,
+ *         symmetric), of the Householder reduction with the eigenvalue bisection
+ *         (4/3 nvir^3 per LMO), of the eigenvectors (inverse iteration and the
+ *         reflectors applied to the kept vectors, 4 nvir^2 r_k), and of C = Q^T B
+ *         (2 r_k nvir naux).
+ * Errors: OSV_E_ARG.  Zeros before the first call.
+ */
+int osv_generation_stats(double *out8);
+
+/*
  * osv_plan_clusters -- host-only cluster selection for OSV_SEL_DISTANCE and
  * OSV_SEL_FULL (no device work; usable without a GPU).
  *   nocc, centroid (host nocc x 3), sel: as above.

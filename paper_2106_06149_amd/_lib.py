@@ -19,7 +19,8 @@ TUNING_KEYS = {"gemm_ks": (8, 16, 32), "prep_nt_small": (128, 256), "prep_nt_mid
 
 EXPORTS = ["osv_build_pairs", "osv_query", "osv_solve_clusters", "osv_energy", "osv_weak_pairs",
            "osv_weak_pairs_noalloc", "osv_generate_osvs", "osv_high_order_correction",
-           "osv_response_layout", "osv_response", "osv_weak_response",
+           "osv_response_layout", "osv_response", "osv_weak_response", "osv_correction_stats",
+           "osv_generation_stats",
            "osv_set_tuning", "osv_get_tuning", "osv_load_tuning", "osv_build_pairs_exact",
            "osv_densities",
            "osv_plan_clusters", "osv_destroy", "osv_status_string", "osv_last_error",
@@ -99,6 +100,10 @@ def load():
     lib.osv_response.restype = ctypes.c_int
     lib.osv_weak_response.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
     lib.osv_weak_response.restype = ctypes.c_int
+    lib.osv_correction_stats.argtypes = [vp, vp]
+    lib.osv_correction_stats.restype = ctypes.c_int
+    lib.osv_generation_stats.argtypes = [vp]
+    lib.osv_generation_stats.restype = ctypes.c_int
     lib.osv_set_tuning.argtypes = [ctypes.c_char_p, i32]
     lib.osv_set_tuning.restype = ctypes.c_int
     lib.osv_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]

@@ -103,6 +103,15 @@ def generate_osvs(B: torch.Tensor, eps_vir: torch.Tensor, F_occ: torch.Tensor,
     return r, Qt[:n], C[:n], om
 
 
+def generation_stats() -> dict:
+    """Device times (ms) and algorithmic flops of the last generate_osvs call of
+    this thread, per stage: products, tridiag, vectors, c."""
+    out = np.zeros(8)
+    L.check(L.load().osv_generation_stats(out.ctypes.data_as(ctypes.c_void_p)))
+    return {k: (float(out[2 * i]), float(out[2 * i + 1]))
+            for i, k in enumerate(("products", "tridiag", "vectors", "c"))}
+
+
 def validate_inputs(Q: torch.Tensor, C: torch.Tensor, eps_vir: torch.Tensor,
                     F_occ: torch.Tensor, r) -> None:
     """Checks the tensors handed to the library against osv_system: the library
@@ -262,6 +271,13 @@ class OSVContext:
                                                        ctypes.byref(Ec), ctypes.byref(mx),
                                                        per.ctypes.data_as(ctypes.c_void_p)), self.handle)
         return dE.value, Ec.value, mx.value, per
+
+    def correction_stats(self):
+        """The last high_order_correction call: {"collective": (ms, bytes),
+        "step": (ms, flops)}."""
+        out = np.zeros(4)
+        L.check(self.lib.osv_correction_stats(self.handle, out.ctypes.data_as(ctypes.c_void_p)), self.handle)
+        return {"collective": (float(out[0]), float(out[1])), "step": (float(out[2]), float(out[3]))}
 
     def response_layout(self):
         """Ordered pairs (n_pairs x 2 int32 array) and the offset of each one's

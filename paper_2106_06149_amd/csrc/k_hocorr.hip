@@ -14,6 +14,7 @@
 //    X = M(tgt,src) op(T~c) into LDS, then R~ += coef X M(tgt,src)^T with R~ in
 //    the accumulators of the wave that owns its 16 x 16 tile.
 #include "osv_internal.h"
+#include "tiles.h"
 
 namespace osv {
 
@@ -35,9 +36,20 @@ __global__ __launch_bounds__(HNT) void k_collective(const Domain *__restrict__ d
   const int np = doms[d].np;
   const long long n2 = 2LL * np * np;
   double *out = Tc + coff[d];
+  const long long x0 = ptr[d], x1 = ptr[d + 1];
   for (long long e = threadIdx.x; e < n2; e += HNT) {
+    // four clusters' loads in flight; the sum keeps the cluster order
     double s = 0.0;
-    for (long long x = ptr[d]; x < ptr[d + 1]; x++) s += coef[x] * T[toff[x] + e];
+    long long x = x0;
+    for (; x + 4 <= x1; x += 4) {
+      const double v0 = T[toff[x] + e], v1 = T[toff[x + 1] + e];
+      const double v2 = T[toff[x + 2] + e], v3 = T[toff[x + 3] + e];
+      s += coef[x] * v0;
+      s += coef[x + 1] * v1;
+      s += coef[x + 2] * v2;
+      s += coef[x + 3] * v3;
+    }
+    for (; x < x1; x++) s += coef[x] * T[toff[x] + e];
     out[e] = s;
   }
 }
@@ -83,19 +95,12 @@ __global__ __launch_bounds__(HNT) void k_collective_step(const Domain *__restric
     const double *Tg = Tc + tm.tsrc;       // op(T~c_src), np_s x np_s row-major
     const double *Mg = M + tm.moff;        // M(src, tgt), np_s x np_t row-major
     // X(i, k) = sum_j M(tgt,src)(i, j) op(T)(j, k) = sum_j Mg[j np_t + i] Tg[j np_s + k]
-    for (int tau = wave; tau < tb * sb; tau += HNW) {
-      const int ib = tau / sb, kb = tau - ib * sb;
-      const int i = 16 * ib + l15, k = 16 * kb + l15;
-      d4h acc = {0, 0, 0, 0};
-      for (int j0 = 0; j0 < ns; j0 += 4) {
-        const int j = j0 + lhi;
-        const double a = (j < ns) ? Mg[(long long)j * np + i] : 0.0;
-        const double b = (j < ns) ? Tg[(long long)j * nps + k] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; v++) X[(16 * ib + 4 * v + lhi) * HLD + k] = acc[v];
-    }
+    // for the target's kept rows (rows of X past nt feed only rows of R~ that are
+    // never read); the operands of 8 k-steps are loaded before their MFMAs
+    (void)sb;
+    mma_tiles<HNT>(nt, ns, ns, [&](int i, int j) { return Mg[(long long)j * np + i]; },
+                   [&](int j, int k) { return Tg[(long long)j * nps + k]; },
+                   [&](int i, int k, double v) { X[i * HLD + k] = v; });
     __syncthreads();
     // R(i, l) += cf sum_k X(i, k) M(tgt,src)(l, k) = cf sum_k X(i, k) Mg[k np_t + l]
 #pragma unroll
@@ -104,11 +109,18 @@ __global__ __launch_bounds__(HNT) void k_collective_step(const Domain *__restric
       if (tau < tb * tb) {
         const int ib = tau / tb, lb = tau - ib * tb;
         const int i = 16 * ib + l15, l = 16 * lb + l15;
-        for (int k0 = 0; k0 < ns; k0 += 4) {
-          const int k = k0 + lhi;
-          const double a = (k < ns) ? X[i * HLD + k] : 0.0;
-          const double b = (k < ns) ? cf * Mg[(long long)k * np + l] : 0.0;
-          R[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, R[u], 0, 0, 0);
+        // 8 k-steps of operands loaded before their MFMAs
+        for (int k0 = 0; k0 < ns; k0 += 32) {
+          double a[8], b[8];
+#pragma unroll
+          for (int st = 0; st < 8; st++) {
+            const int k = k0 + 4 * st + lhi;
+            a[st] = (k < ns) ? X[i * HLD + k] : 0.0;
+            b[st] = (k < ns) ? cf * Mg[(long long)k * np + l] : 0.0;
+          }
+#pragma unroll
+          for (int st = 0; st < 8; st++)
+            if (k0 + 4 * st < ns) R[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], R[u], 0, 0, 0);
         }
       }
     }

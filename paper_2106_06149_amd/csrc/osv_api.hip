@@ -486,6 +486,8 @@ struct osv_ctx {
   double *dCx = nullptr;   // C_p = Q_p^T B_p computed from B
   // one-step high-order correction (built on first use)
   bool hc_ready = false;
+  double hc_bytes = 0.0, hc_flops = 0.0;   // collective sums: bytes; residual step: flops
+  double hc_ms[2] = {0.0, 0.0};            // device times of the last call
   double *dTc = nullptr, *dHcOut = nullptr;
   long long *dCoff = nullptr, *dCtptr = nullptr;
   CTerm *dCterms = nullptr;
@@ -1685,6 +1687,15 @@ int osv_weak_pairs_noalloc(osv_ctx *ctx, hipStream_t s, double *E_weak, int64_t 
   return OSV_OK;
 }
 
+// device times and algorithmic flops of the last osv_generate_osvs call of this thread
+thread_local double g_gen_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+int osv_generation_stats(double *out8) {
+  if (!out8) return fail(nullptr, OSV_E_ARG, "osv_generation_stats: out is NULL");
+  for (int i = 0; i < 8; i++) out8[i] = g_gen_stats[i];
+  return OSV_OK;
+}
+
 int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B, const double *eps_vir,
                       const double *F_occ, double l_osv, int32_t r_max, hipStream_t s, int32_t *r,
                       double *omega, double *Q, double *C) {
@@ -1736,11 +1747,15 @@ int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B,
   GENCHK(gb.get(&tiles128, t128.size()));
   GENCHK(hipMemcpyAsync(tiles, t64.data(), t64.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   GENCHK(hipMemcpyAsync(tiles128, t128.data(), t128.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+  StageTimer t_prod(s);
   for (int k = 0; k < nocc; k++)
     GENCHK(launch_syrk_f64(B + (long long)k * nvir * naux, 0, naux, nvir, naux, nullptr, T + (long long)k * n2,
                            nullptr, nvir, tiles, (int)t64.size(), tiles128, (int)t128.size(), s));
+  t_prod.stop();
+  StageTimer t_tri(s);
   GENCHK(launch_osv_denom(T, nvir, eps_vir, F_occ, nocc, s));
   GENCHK(launch_osv_tridiag(T, nocc, nvir, l_osv, r_max, d, e, tau, rk, om, s));
+  t_tri.stop();
   std::vector<int> hr(nocc), hoff(nocc);
   GENCHK(hipMemcpyAsync(hr.data(), rk, nocc * sizeof(int), hipMemcpyDeviceToHost, s));
   GENCHK(hipStreamSynchronize(s));
@@ -1754,14 +1769,32 @@ int osv_generate_osvs(int32_t nocc, int32_t nvir, int32_t naux, const double *B,
   if (omega) GENCHK(launch_fill_f64(omega, 0.0, (long long)nocc * r_max, s));
   double *om_out = omega;
   if (!om_out) GENCHK(gb.get(&om_out, (size_t)nocc * r_max));
+  StageTimer t_vec(s);
   GENCHK(launch_osv_vectors(T, nocc, nvir, r_max, d, e, tau, rk, om, doff, Z, Q, om_out, s));
+  t_vec.stop();
   // C_k = Q_k^T B_k: rows off_k .. of C
+  StageTimer t_c(s);
   if (C)
     for (int k = 0; k < nocc; k++)
       if (hr[k] > 0)
         GENCHK(launch_gemm_nn_f64(Q + (long long)hoff[k] * nvir, nvir, B + (long long)k * nvir * naux, 0,
                                   naux, C + (long long)hoff[k] * naux, naux, hr[k], naux, nvir, 1.0, s));
+  t_c.stop();
   GENCHK(hipStreamSynchronize(s));
+  // algorithmic flops: the symmetric products (ka|kb) nvir^2 naux per LMO, the
+  // Householder reduction 4/3 nvir^3 per LMO, the reflectors applied to the kept
+  // vectors 4 nvir^2 r_k, C = Q^T B 2 r_k nvir naux
+  {
+    const double nv = nvir, na = naux;
+    g_gen_stats[0] = t_prod.ms();
+    g_gen_stats[1] = nocc * nv * nv * na;
+    g_gen_stats[2] = t_tri.ms();
+    g_gen_stats[3] = nocc * 4.0 / 3.0 * nv * nv * nv;
+    g_gen_stats[4] = t_vec.ms();
+    g_gen_stats[5] = 4.0 * nv * nv * tot;
+    g_gen_stats[6] = t_c.ms();
+    g_gen_stats[7] = C ? 2.0 * tot * nv * na : 0.0;
+  }
 #undef GENCHK
   return OSV_OK;
 }
@@ -1824,6 +1857,25 @@ static int build_correction(osv_ctx *ctx, hipStream_t s) {
       if (m != p && !add(m, q, p, m)) return fail(ctx, OSV_E_HIP, "one-step correction: missing coupling");
     }
     tptr[d + 1] = (long long)terms.size();
+  }
+  // algorithmic work: the collective sums read every cluster slot of a domain and
+  // write the domain's two slots; the residual step takes 2 (dt ns^2 + dt^2 ns)
+  // flops per term at the kept ranks
+  {
+    densities_host(ctx);
+    const DensHost &H = ctx->dh;
+    double by = 0.0, fl = 0.0;
+    for (int d = 0; d < ndom; d++) {
+      const double np2 = 2.0 * P.doms[d].np * P.doms[d].np;
+      by += 8.0 * np2 * (double)(H.ptr[d + 1] - H.ptr[d] + 1);
+      const double dt = ctx->rank_host[d];
+      for (long long t = tptr[d]; t < tptr[d + 1]; t++) {
+        const double ns = ctx->rank_host[terms[t].src];
+        fl += 2.0 * (dt * ns * ns + dt * dt * ns);
+      }
+    }
+    ctx->hc_bytes = by;
+    ctx->hc_flops = fl;
   }
   int rc;
   if ((rc = upload(ctx, &ctx->dCoff, coff, s))) return rc;
@@ -2096,13 +2148,19 @@ int osv_high_order_correction(osv_ctx *ctx, hipStream_t s, double *dE, double *E
   if (!ctx->hc_ready && (rc = build_correction(ctx, s))) return rc;
   Plan &P = ctx->plan;
   const int ndom = (int)P.doms.size();
+  StageTimer t_col(s);
   HIPCHK(ctx, launch_collective(ctx->dDom, ndom, ctx->dDptr, ctx->dDtoff, ctx->dDcoef, ctx->dT, ctx->dCoff,
                                 ctx->dTc, s));
+  t_col.stop();
+  StageTimer t_step(s);
   HIPCHK(ctx, launch_collective_step(ctx->dDom, ndom, ctx->dRank, ctx->dCtptr, ctx->dCterms, ctx->dTc,
                                      ctx->dCoff, ctx->dM, ctx->dKt, ctx->F, ctx->nocc, ctx->dHcOut, s));
+  t_step.stop();
   std::vector<double> h((size_t)3 * ndom);
   HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->dHcOut, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  ctx->hc_ms[0] = t_col.ms();
+  ctx->hc_ms[1] = t_step.ms();
   double a = 0.0, b = 0.0, m = 0.0;
   for (int d = 0; d < ndom; d++) {
     a += h[3 * d];
@@ -2118,6 +2176,15 @@ int osv_high_order_correction(osv_ctx *ctx, hipStream_t s, double *dE, double *E
       per_domain[3 * d + 1] = h[3 * d + 1];
       per_domain[3 * d + 2] = std::sqrt(h[3 * d + 2]);
     }
+  return OSV_OK;
+}
+
+int osv_correction_stats(const osv_ctx *ctx, double *out4) {
+  if (!ctx || !out4) return fail(nullptr, OSV_E_ARG, "osv_correction_stats: NULL argument");
+  out4[0] = ctx->hc_ms[0];
+  out4[1] = ctx->hc_bytes;
+  out4[2] = ctx->hc_ms[1];
+  out4[3] = ctx->hc_flops;
   return OSV_OK;
 }
 

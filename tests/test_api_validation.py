@@ -88,6 +88,7 @@ def test_context_methods_present():
             "weak_pairs": "osv_weak_pairs", "high_order_correction": "osv_high_order_correction",
             "response_layout": "osv_response_layout", "response": "osv_response",
             "weak_response": "osv_weak_response", "stage_times": "osv_stage_times",
+            "correction_stats": "osv_correction_stats",
             "stage_flops": "osv_stage_flops"}
     for name, entry in want.items():
         fn = getattr(api.OSVContext, name, None)
