@@ -10,21 +10,15 @@
 //      R~ = K~ + (e~_a + e~_b - f_pp - f_qq) T~c + sum_terms (-f) M op(T~c_src) M^T,
 //    then one Jacobi step dT~ = -R~ / Delta on the kept rank, and per domain
 //      dE_d = w <K~, 2 dT~ - dT~^T>,  E_d = w <K~, 2 T~c - T~c^T>,  ||R~||_F^2
-//    (w = 1 for p = q, 2 otherwise).  Each term runs as two FP64 MFMA products:
-//    X = M(tgt,src) op(T~c) into LDS, then R~ += coef X M(tgt,src)^T with R~ in
-//    the accumulators of the wave that owns its 16 x 16 tile.
+//    (w = 1 for p = q, 2 otherwise).  Each term runs as two FP64 MFMA products on
+//    the LDS-staged tile product, X = M(tgt,src) op(T~c), then
+//    R~ += coef X M(tgt,src)^T, in per-workgroup scratch.
 #include "osv_internal.h"
 #include "tiles.h"
 
 namespace osv {
 
-typedef double d4h __attribute__((ext_vector_type(4)));
-
-constexpr int HNT = 256;           // threads per domain
-constexpr int HNW = HNT / 64;
-constexpr int HMT = 7;             // 16-tiles per dimension (np <= 112)
-constexpr int HLD = 16 * HMT + 1;  // LDS stride of X
-constexpr int HTPW = (HMT * HMT + HNW - 1) / HNW;   // R~ tiles per wave
+constexpr int HNT = 256;           // threads per domain of the collective sums
 
 __global__ __launch_bounds__(HNT) void k_collective(const Domain *__restrict__ doms,
                                                     const long long *__restrict__ ptr,
@@ -67,7 +61,14 @@ __device__ __forceinline__ double hsum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(HNT) void k_collective_step(const Domain *__restrict__ doms,
+// The residual step: one persistent workgroup of eight waves per CU takes target
+// domains from a queue (most terms first).  Per term, X = M(tgt,src) op(T~c) and
+// R~ += coef X M(tgt,src)^T run on the LDS-staged tile product (gemm_lds), X and
+// R~ (kept rows and columns only) in the workgroup's scratch; then the epilogue.
+constexpr int CNT = 512;
+constexpr int CLD = 112;   // row stride of X and R~ in scratch
+
+__global__ __launch_bounds__(CNT) void k_collective_step(const Domain *__restrict__ doms,
                                                          const int *__restrict__ rank,
                                                          const long long *__restrict__ tptr,
                                                          const CTerm *__restrict__ terms,
@@ -76,113 +77,91 @@ __global__ __launch_bounds__(HNT) void k_collective_step(const Domain *__restric
                                                          const double *__restrict__ M,
                                                          const double *__restrict__ Kep,
                                                          const double *__restrict__ F, int nocc,
-                                                         double *out) {
-  __shared__ double X[16 * HMT * HLD];
-  __shared__ double red[3 * HNW];
-  const int d = blockIdx.x;
-  const Domain D = doms[d];
-  const int np = D.np, nt = rank[d];
+                                                         const int *__restrict__ queue, int ndom,
+                                                         int *counter, double *scr, double *out) {
+  __shared__ int s_next;
+  __shared__ __align__(16) double lds[gemm_lds_doubles()];
+  __shared__ double red[3 * (CNT / 64)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int l15 = lane & 15, lhi = lane >> 4;
-  const int tb = np >> 4;                  // 16-tiles per dimension of the target
-  d4h R[HTPW];
-#pragma unroll
-  for (int u = 0; u < HTPW; u++) R[u] = (d4h){0, 0, 0, 0};
-  for (long long t = tptr[d]; t < tptr[d + 1]; t++) {
-    const CTerm tm = terms[t];
-    const double cf = -F[(long long)tm.fa * nocc + tm.fb];
-    const int ns = rank[tm.src], nps = tm.ldT, sb = (ns + 15) >> 4;
-    const double *Tg = Tc + tm.tsrc;       // op(T~c_src), np_s x np_s row-major
-    const double *Mg = M + tm.moff;        // M(src, tgt), np_s x np_t row-major
-    // X(i, k) = sum_j M(tgt,src)(i, j) op(T)(j, k) = sum_j Mg[j np_t + i] Tg[j np_s + k]
-    // for the target's kept rows (rows of X past nt feed only rows of R~ that are
-    // never read); the operands of 8 k-steps are loaded before their MFMAs
-    (void)sb;
-    mma_tiles<HNT>(nt, ns, ns, [&](int i, int j) { return Mg[(long long)j * np + i]; },
-                   [&](int j, int k) { return Tg[(long long)j * nps + k]; },
-                   [&](int i, int k, double v) { X[i * HLD + k] = v; });
+  double *R = scr + (long long)blockIdx.x * 2 * CLD * CLD, *X = R + CLD * CLD;
+  for (;;) {
+    if (tid == 0) s_next = atomicAdd(counter, 1);
     __syncthreads();
-    // R(i, l) += cf sum_k X(i, k) M(tgt,src)(l, k) = cf sum_k X(i, k) Mg[k np_t + l]
-#pragma unroll
-    for (int u = 0; u < HTPW; u++) {
-      const int tau = wave + HNW * u;
-      if (tau < tb * tb) {
-        const int ib = tau / tb, lb = tau - ib * tb;
-        const int i = 16 * ib + l15, l = 16 * lb + l15;
-        // 8 k-steps of operands loaded before their MFMAs
-        for (int k0 = 0; k0 < ns; k0 += 32) {
-          double a[8], b[8];
-#pragma unroll
-          for (int st = 0; st < 8; st++) {
-            const int k = k0 + 4 * st + lhi;
-            a[st] = (k < ns) ? X[i * HLD + k] : 0.0;
-            b[st] = (k < ns) ? cf * Mg[(long long)k * np + l] : 0.0;
-          }
-#pragma unroll
-          for (int st = 0; st < 8; st++)
-            if (k0 + 4 * st < ns) R[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], R[u], 0, 0, 0);
-        }
-      }
+    const int it = s_next;
+    __syncthreads();
+    if (it >= ndom) break;
+    const int d = queue[it];
+    const Domain D = doms[d];
+    const int np = D.np, nt = rank[d];
+    for (int e = tid; e < nt * CLD; e += CNT) R[e] = 0.0;
+    __syncthreads();
+    for (long long t = tptr[d]; t < tptr[d + 1]; t++) {
+      const CTerm tm = terms[t];
+      const double cf = -F[(long long)tm.fa * nocc + tm.fb];
+      const int ns = rank[tm.src], nps = tm.ldT;
+      const double *Tg = Tc + tm.tsrc;   // op(T~c_src), np_s x np_s row-major
+      const double *Mg = M + tm.moff;    // M(src, tgt), np_s x np_t row-major
+      // X(i, k) = sum_j M(tgt,src)(i, j) op(T)(j, k), M(tgt,src)(i, j) = Mg[j np_t + i]
+      gemm_lds<CNT>(nt, ns, ns, Mat{Mg, np, 1}, Mat{Tg, nps, 0}, lds,
+                    [&](int i, int k, double v) { X[i * CLD + k] = v; });
+      // R(i, l) += cf sum_k X(i, k) M(tgt,src)(l, k) = cf sum_k X(i, k) Mg[k np_t + l]
+      gemm_lds<CNT>(nt, nt, ns, Mat{X, CLD, 0}, Mat{Mg, np, 0}, lds,
+                    [&](int i, int l, double v) { R[i * CLD + l] += cf * v; });
     }
     __syncthreads();
-  }
-  // epilogue: R~ = terms + K~ + Delta T~c, the step -R~ / Delta and the sums
-  const double *Kt = Kep + D.voff, *ev = Kt + (long long)np * np;   // Kt[b np + a] = K~(a, b)
-  const double *Td = Tc + coff[d];
-  const double fd = F[(long long)D.p * nocc + D.p] + F[(long long)D.q * nocc + D.q];
-  const double w = (D.p == D.q) ? 1.0 : 2.0;
-  double sE = 0.0, sC = 0.0, sR = 0.0;
-#pragma unroll
-  for (int u = 0; u < HTPW; u++) {
-    const int tau = wave + HNW * u;
-    if (tau < tb * tb) {
-      const int ib = tau / tb, lb = tau - ib * tb;
-      const int l = 16 * lb + l15;
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int i = 16 * ib + 4 * v + lhi;
-        if (i < nt && l < nt) {
-          const double kil = Kt[(long long)l * np + i], kli = Kt[(long long)i * np + l];
-          const double delta = ev[i] + ev[l] - fd;
-          const double tc = Td[(long long)i * np + l];
-          const double r = R[u][v] + kil + delta * tc;
-          const double dt = -r / delta;
-          sE += dt * (2.0 * kil - kli);
-          sC += tc * (2.0 * kil - kli);
-          sR += r * r;
-        }
+    // epilogue: R~ = terms + K~ + Delta T~c, the step -R~ / Delta and the sums
+    const double *Kt = Kep + D.voff, *ev = Kt + (long long)np * np;   // Kt[b np + a] = K~(a, b)
+    const double *Td = Tc + coff[d];
+    const double fd = F[(long long)D.p * nocc + D.p] + F[(long long)D.q * nocc + D.q];
+    const double w = (D.p == D.q) ? 1.0 : 2.0;
+    double sE = 0.0, sC = 0.0, sR = 0.0;
+    for (int e = tid; e < nt * nt; e += CNT) {
+      const int i = e / nt, l = e - i * nt;
+      const double kil = Kt[(long long)l * np + i], kli = Kt[(long long)i * np + l];
+      const double delta = ev[i] + ev[l] - fd;
+      const double tc = Td[(long long)i * np + l];
+      const double r = R[i * CLD + l] + kil + delta * tc;
+      const double dt = -r / delta;
+      sE += dt * (2.0 * kil - kli);
+      sC += tc * (2.0 * kil - kli);
+      sR += r * r;
+    }
+    sE = hsum(sE);
+    sC = hsum(sC);
+    sR = hsum(sR);
+    if (lane == 0) {
+      red[wave] = sE;
+      red[CNT / 64 + wave] = sC;
+      red[2 * (CNT / 64) + wave] = sR;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0, c = 0.0;
+      for (int q = 0; q < CNT / 64; q++) {
+        a += red[q];
+        b += red[CNT / 64 + q];
+        c += red[2 * (CNT / 64) + q];
       }
+      out[3LL * d] = w * a;
+      out[3LL * d + 1] = w * b;
+      out[3LL * d + 2] = c;
     }
-  }
-  sE = hsum(sE);
-  sC = hsum(sC);
-  sR = hsum(sR);
-  if (lane == 0) {
-    red[wave] = sE;
-    red[HNW + wave] = sC;
-    red[2 * HNW + wave] = sR;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int q = 0; q < HNW; q++) {
-      a += red[q];
-      b += red[HNW + q];
-      c += red[2 * HNW + q];
-    }
-    out[3LL * d] = w * a;
-    out[3LL * d + 1] = w * b;
-    out[3LL * d + 2] = c;
+    __syncthreads();
   }
 }
+
+long long collective_step_scratch(int nwg) { return (long long)nwg * 2 * CLD * CLD; }
 
 hipError_t launch_collective_step(const Domain *dom, int ndom, const int *rank, const long long *tptr,
                                   const CTerm *terms, const double *Tc, const long long *coff,
                                   const double *M, const double *Kep, const double *F, int nocc,
-                                  double *out, hipStream_t s) {
+                                  const int *queue, int *counter, double *scr, int nwg, double *out,
+                                  hipStream_t s) {
   if (ndom <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_collective_step, dim3(ndom), dim3(HNT), 0, s, dom, rank, tptr, terms, Tc, coff, M,
-                     Kep, F, nocc, out);
+  hipError_t e = launch_fill_i32(counter, 0, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_collective_step, dim3(nwg), dim3(CNT), 0, s, dom, rank, tptr, terms, Tc, coff, M, Kep,
+                     F, nocc, queue, ndom, counter, scr, out);
   return hipGetLastError();
 }
 

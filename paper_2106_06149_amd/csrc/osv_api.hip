@@ -488,6 +488,9 @@ struct osv_ctx {
   bool hc_ready = false;
   double hc_bytes = 0.0, hc_flops = 0.0;   // collective sums: bytes; residual step: flops
   double hc_ms[2] = {0.0, 0.0};            // device times of the last call
+  int hc_nwg = 1;
+  int *dHcQueue = nullptr, *dHcCounter = nullptr;
+  double *dHcScr = nullptr;
   double *dTc = nullptr, *dHcOut = nullptr;
   long long *dCoff = nullptr, *dCtptr = nullptr;
   CTerm *dCterms = nullptr;
@@ -1883,6 +1886,20 @@ static int build_correction(osv_ctx *ctx, hipStream_t s) {
   if ((rc = upload(ctx, &ctx->dCterms, terms, s))) return rc;
   if ((rc = dalloc(ctx, &ctx->dTc, (size_t)nTc))) return rc;
   if ((rc = dalloc(ctx, &ctx->dHcOut, (size_t)3 * ndom))) return rc;
+  // the residual step's queue: domains with the most terms first
+  {
+    std::vector<int> q(ndom);
+    std::iota(q.begin(), q.end(), 0);
+    std::stable_sort(q.begin(), q.end(),
+                     [&](int x, int y) { return tptr[x + 1] - tptr[x] > tptr[y + 1] - tptr[y]; });
+    if ((rc = upload(ctx, &ctx->dHcQueue, q, s))) return rc;
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    ctx->hc_nwg = std::max(1, std::min(ndom, ncu));
+    if ((rc = dalloc(ctx, &ctx->dHcCounter, 1))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dHcScr, (size_t)collective_step_scratch(ctx->hc_nwg)))) return rc;
+  }
   ctx->hc_ready = true;
   return OSV_OK;
 }
@@ -2154,7 +2171,8 @@ int osv_high_order_correction(osv_ctx *ctx, hipStream_t s, double *dE, double *E
   t_col.stop();
   StageTimer t_step(s);
   HIPCHK(ctx, launch_collective_step(ctx->dDom, ndom, ctx->dRank, ctx->dCtptr, ctx->dCterms, ctx->dTc,
-                                     ctx->dCoff, ctx->dM, ctx->dKt, ctx->F, ctx->nocc, ctx->dHcOut, s));
+                                     ctx->dCoff, ctx->dM, ctx->dKt, ctx->F, ctx->nocc, ctx->dHcQueue,
+                                     ctx->dHcCounter, ctx->dHcScr, ctx->hc_nwg, ctx->dHcOut, s));
   t_step.stop();
   std::vector<double> h((size_t)3 * ndom);
   HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->dHcOut, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));

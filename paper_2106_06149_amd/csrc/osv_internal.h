@@ -299,10 +299,14 @@ hipError_t launch_osv_vectors(const double *T, int nocc, int n, int r_max, const
 hipError_t launch_collective(const Domain *dom, int ndom, const long long *ptr, const long long *toff,
                              const double *coef, const double *T, const long long *coff, double *Tc,
                              hipStream_t s);
+// (persistent: nwg workgroups take the domains in queue order; scr holds
+// collective_step_scratch(nwg) doubles, counter one int)
+long long collective_step_scratch(int nwg);
 hipError_t launch_collective_step(const Domain *dom, int ndom, const int *rank, const long long *tptr,
                                   const CTerm *terms, const double *Tc, const long long *coff,
                                   const double *M, const double *Kep, const double *F, int nocc,
-                                  double *out, hipStream_t s);
+                                  const int *queue, int *counter, double *scr, int nwg, double *out,
+                                  hipStream_t s);
 // K~ of one pair domain from Gp = V^T B_p and Gq = V^T B_q (dt x naux), into K~^T of
 // its zero-padded slot (leading dimension np)
 hipError_t launch_exact_ktilde(const double *Gp, const double *Gq, int dt, int naux, double *Kt, int np,
