@@ -119,10 +119,11 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_tridiag(double *Tall, int n, do
       const double K = -0.5 * tc * bsum(pv, red);
       for (int i = tid; i < m; i += GNT_EIG) w[i] += K * v[i];
       __syncthreads();
-      // A22 -= v w^T + w v^T
-      for (long long q = tid; q < (long long)m * m; q += GNT_EIG) {
-        const int i = (int)(q / m), j = (int)(q - (long long)i * m);
-        A[(long long)(c + 1 + i) * n + c + 1 + j] -= v[i] * w[j] + w[i] * v[j];
+      // A22 -= v w^T + w v^T: one wave per row, lanes along the row
+      for (int i = wave; i < m; i += GNW_EIG) {
+        double *row = A + (long long)(c + 1 + i) * n + c + 1;
+        const double vi = v[i], wi = w[i];
+        for (int j = lane; j < m; j += 64) row[j] -= vi * w[j] + wi * v[j];
       }
       // the reflector, kept in row c right of the diagonal (leading 1 implicit)
       double *xr = A + (long long)c * n + c + 1;
