@@ -191,7 +191,8 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_vectors(const double *Tall, int
                                                         double *Zall, double *Qt, double *omega) {
   extern __shared__ double sh[];
   double *u1 = sh, *u2 = u1 + n, *u3 = u2 + n, *ml = u3 + n, *y = ml + n;
-  unsigned char *pv = (unsigned char *)(y + n);
+  double *dl = y + n, *el = dl + n;   // the tridiagonal matrix, in LDS for the serial LU
+  unsigned char *pv = (unsigned char *)(el + n);
   __shared__ double red[GNW_EIG];
   __shared__ double s_nrm;
   const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -201,6 +202,11 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_vectors(const double *Tall, int
   const double *d = dall + (long long)k * n, *e = eall + (long long)k * n, *tau = tauall + (long long)k * n;
   const double *om = omall + (long long)k * r_max;
   double *Z = Zall + (long long)k * n * r_max;     // column j at Z + j n
+  for (int i = tid; i < n; i += GNT_EIG) {
+    dl[i] = d[i];
+    el[i] = e[i];
+  }
+  __syncthreads();
   // ||T|| (1-norm of the tridiagonal matrix) for the pivot floor and the cluster test
   double tn = 0.0;
   for (int i = tid; i < n; i += GNT_EIG)
@@ -225,9 +231,9 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_vectors(const double *Tall, int
     double *zj = Z + (long long)j * n;
     if (tid == 0) {
       // LU with partial pivoting of (tridiagonal - lam): rows (p, q, s) at columns (i, i+1, i+2)
-      double p = d[0] - lam, q = n > 1 ? e[0] : 0.0, s3 = 0.0;
+      double p = dl[0] - lam, q = n > 1 ? el[0] : 0.0, s3 = 0.0;
       for (int i = 0; i + 1 < n; i++) {
-        const double ci = e[i], ai1 = d[i + 1] - lam, bi1 = (i + 2 < n) ? e[i + 1] : 0.0;
+        const double ci = el[i], ai1 = dl[i + 1] - lam, bi1 = (i + 2 < n) ? el[i + 1] : 0.0;
         if (fabs(p) >= fabs(ci)) {
           const double pp = (fabs(p) < pfloor) ? copysign(pfloor, p) : p;
           const double mlt = ci / pp;
@@ -266,13 +272,22 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_vectors(const double *Tall, int
           if (i + 2 < n) t -= u3[i] * y[i + 2];
           y[i] = t / u1[i];
         }
-        // rescale to keep the entries of order one
-        double mx = 0.0;
-        for (int i = 0; i < n; i++) mx = fmax(mx, fabs(y[i]));
-        const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
-        for (int i = 0; i < n; i++) y[i] *= sc;
       }
       __syncthreads();   // the solve is done before anyone reads y
+      // rescale to keep the entries of order one (largest magnitude 1)
+      {
+        double mx = 0.0;
+        for (int i = tid; i < n; i += GNT_EIG) mx = fmax(mx, fabs(y[i]));
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) red[wave] = mx;
+        __syncthreads();
+        double m2 = 0.0;
+        for (int w = 0; w < GNW_EIG; w++) m2 = fmax(m2, red[w]);
+        const double sc = m2 > 0.0 ? 1.0 / m2 : 1.0;
+        __syncthreads();
+        for (int i = tid; i < n; i += GNT_EIG) y[i] *= sc;
+        __syncthreads();
+      }
       // modified Gram-Schmidt against the earlier vectors of the cluster
       for (int t = c0; t < j; t++) {
         const double *zt = Z + (long long)t * n;
@@ -331,7 +346,7 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_vectors(const double *Tall, int
 }
 
 size_t osvgen_lds_tridiag(int n) { return (size_t)2 * n * sizeof(double); }
-size_t osvgen_lds_vectors(int n) { return (size_t)5 * n * sizeof(double) + (size_t)n; }
+size_t osvgen_lds_vectors(int n) { return (size_t)7 * n * sizeof(double) + (size_t)n; }
 
 hipError_t launch_osv_denom(double *T, int nvir, const double *eps, const double *F, int nocc,
                             hipStream_t s) {
