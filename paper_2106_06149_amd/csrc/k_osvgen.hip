@@ -68,20 +68,27 @@ __device__ double sturm_count(const double *d, const double *e, int n, double x,
 // Per LMO: Householder tridiagonalisation of T (n x n, row-major, in place), then the
 // wanted eigenvalues by bisection.  Outputs per LMO k: d, e (n each), tau (n), the
 // count rk[k] = min(r_max, #{omega > l_osv}) and omega (r_max, descending).
+// Each column's rank-2 update of the trailing matrix is fused with the next
+// column's product p = tau A22 v: the row holding the next reflector is updated
+// first, the reflector formed, and then one pass over the other rows updates each
+// row and takes its dot product with the new reflector (the trailing matrix is
+// read and written once per column instead of read twice and written once).
 __global__ __launch_bounds__(GNT_EIG) void k_osv_tridiag(double *Tall, int n, double l_osv, int r_max,
                                                         double *dall, double *eall, double *tauall,
                                                         int *rk, double *omall) {
   extern __shared__ double sh[];
-  double *v = sh;            // n: the reflector
-  double *w = v + n;         // n: p, then w
+  double *vb[2] = {sh, sh + n};            // reflectors of this column and the next
+  double *pb[2] = {sh + 2 * n, sh + 3 * n};  // p (then w) of this column and the next
   __shared__ double red[GNW_EIG];
   __shared__ double s_tau, s_beta;
   const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double *A = Tall + (long long)k * n * n;
   double *d = dall + (long long)k * n, *e = eall + (long long)k * n, *tau = tauall + (long long)k * n;
-  for (int c = 0; c + 2 < n; c++) {
-    const int m = n - c - 1;           // length of the column below the diagonal
-    const double *x = A + (long long)c * n + c + 1;   // row c right of the diagonal
+  // reflector of column c from row c right of the diagonal (all updates of earlier
+  // columns applied): d[c], e[c], tau[c], and v (leading 1) into vv; returns tau
+  auto reflector = [&](int c, double *vv) -> double {
+    const int m = n - c - 1;
+    const double *x = A + (long long)c * n + c + 1;
     double ss = 0.0;
     for (int i = 1 + tid; i < m; i += GNT_EIG) ss += x[i] * x[i];
     const double xn2 = bsum(ss, red);
@@ -103,33 +110,91 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_tridiag(double *Tall, int n, do
     const double tc = s_tau;
     if (tc != 0.0) {
       const double scale = 1.0 / (x[0] - s_beta);
-      for (int i = tid; i < m; i += GNT_EIG) v[i] = (i == 0) ? 1.0 : x[i] * scale;
-      __syncthreads();
-      // p = tau A22 v: one wave per row, lanes along the row
+      for (int i = tid; i < m; i += GNT_EIG) vv[i] = (i == 0) ? 1.0 : x[i] * scale;
+    }
+    __syncthreads();
+    return tc;
+  };
+  int cur = 0;
+  double tc = 0.0;
+  if (n >= 3) {
+    // the first column: reflector and p = tau A22 v (one wave per row)
+    tc = reflector(0, vb[0]);
+    if (tc != 0.0) {
+      const int m = n - 1;
+      const double *v = vb[0];
       for (int i = wave; i < m; i += GNW_EIG) {
-        const double *row = A + (long long)(c + 1 + i) * n + c + 1;
+        const double *row = A + (long long)(1 + i) * n + 1;
         double t = 0.0;
         for (int j = lane; j < m; j += 64) t += row[j] * v[j];
         t = wsum64(t);
-        if (lane == 0) w[i] = tc * t;
+        if (lane == 0) pb[0][i] = tc * t;
       }
       __syncthreads();
+    }
+  }
+  for (int c = 0; c + 2 < n; c++) {
+    const int m = n - c - 1;   // the trailing matrix A22: rows and columns c + 1 ..
+    double *v = vb[cur], *w = pb[cur];
+    if (tc != 0.0) {
       double pv = 0.0;
       for (int i = tid; i < m; i += GNT_EIG) pv += w[i] * v[i];
       const double K = -0.5 * tc * bsum(pv, red);
       for (int i = tid; i < m; i += GNT_EIG) w[i] += K * v[i];
       __syncthreads();
-      // A22 -= v w^T + w v^T: one wave per row, lanes along the row
+    }
+    double tn = 0.0;
+    if (c + 3 < n) {
+      // row 0 of A22 (row c + 1) first: it holds the next reflector
+      if (tc != 0.0) {
+        double *row = A + (long long)(c + 1) * n + c + 1;
+        const double vi = v[0], wi = w[0];
+        for (int j = tid; j < m; j += GNT_EIG) row[j] -= vi * w[j] + wi * v[j];
+        __syncthreads();
+      }
+      double *vn = vb[cur ^ 1], *pn = pb[cur ^ 1];
+      tn = reflector(c + 1, vn);
+      // rows 1.. of A22: the update and, with the updated row, p of the next column
+      // (columns 1.. of A22 are the next trailing matrix; column 0 is not read again)
+      // (four rows per wave at a time, 16 lanes along each row)
+      const int mn = m - 1, l16 = lane & 15;
+      for (int i0 = 1 + 4 * wave; i0 < m; i0 += 4 * GNW_EIG) {
+        const int i = i0 + (lane >> 4);
+        double t = 0.0;
+        if (i < m) {
+          double *row = A + (long long)(c + 1 + i) * n + c + 2;
+          const double vi = v[i], wi = w[i];
+#pragma unroll 8
+          for (int j = l16; j < mn; j += 16) {
+            double a = row[j];
+            if (tc != 0.0) {
+              a -= vi * w[j + 1] + wi * v[j + 1];
+              row[j] = a;
+            }
+            t += a * vn[j];
+          }
+        }
+        if (tn != 0.0) {
+          for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+          if (l16 == 0 && i < m) pn[i - 1] = tn * t;
+        }
+      }
+    } else if (tc != 0.0) {
+      // the last column: the plain update
       for (int i = wave; i < m; i += GNW_EIG) {
         double *row = A + (long long)(c + 1 + i) * n + c + 1;
         const double vi = v[i], wi = w[i];
         for (int j = lane; j < m; j += 64) row[j] -= vi * w[j] + wi * v[j];
       }
-      // the reflector, kept in row c right of the diagonal (leading 1 implicit)
+    }
+    // the reflector, kept in row c right of the diagonal (leading 1 implicit)
+    if (tc != 0.0) {
       double *xr = A + (long long)c * n + c + 1;
       for (int i = 1 + tid; i < m; i += GNT_EIG) xr[i] = v[i];
-      __syncthreads();
     }
+    __syncthreads();
+    cur ^= 1;
+    tc = tn;
   }
   if (tid == 0) {
     if (n >= 2) {
@@ -345,7 +410,7 @@ __global__ __launch_bounds__(GNT_EIG) void k_osv_vectors(const double *Tall, int
   }
 }
 
-size_t osvgen_lds_tridiag(int n) { return (size_t)2 * n * sizeof(double); }
+size_t osvgen_lds_tridiag(int n) { return (size_t)4 * n * sizeof(double); }
 size_t osvgen_lds_vectors(int n) { return (size_t)7 * n * sizeof(double) + (size_t)n; }
 
 hipError_t launch_osv_denom(double *T, int nvir, const double *eps, const double *F, int nocc,
