@@ -16,13 +16,17 @@
 //
 // Symmetric eigenproblems (n <= 100) are solved in LDS by the cyclic Jacobi
 // method with a round-robin ordering: n/2 disjoint rotations per step, applied
-// to both sides of A as independent 2x2 block updates.
+// to both sides of A as independent 2x2 block updates.  The Fock eigenproblem of
+// an off-diagonal domain first gets an approximate eigenbasis (Householder
+// reduction, bisection, twisted-factorisation eigenvectors), so that one Jacobi
+// sweep finishes it.
 #include "osv_internal.h"
 #include "tiles.h"
 
 namespace osv {
 
 constexpr int LDM = DMAX + 1;  // LDS stride (doubles) of the 100x100 work matrices
+constexpr int FOCK_START_MIN = 8;   // smallest domain given an approximate starting basis
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -223,6 +227,329 @@ __device__ void jacobi_eig(double *A, double *V, int n, double2 *rt, double *red
   __syncthreads();
 }
 
+// Lane exchanges within rows of 16 lanes (DPP): quad_perm [1,0,3,2], [2,3,0,1],
+// row_ror 4 and 8.  row_sum16 leaves the sum of its row in every lane of the row
+// (lanes of different quads may differ in the last bit: each lane's order of
+// additions is fixed).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp64<0xB1>(v);
+  v += dpp64<0x4E>(v);
+  v += dpp64<0x124>(v);
+  v += dpp64<0x128>(v);
+  return v;
+}
+// sum over a whole wave, the same value in every lane and every wave that sums
+// the same data: the row sums of lanes 0, 16, 32, 48 added in that order
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  v = row_sum16(v);
+  const long long b = __double_as_longlong(v);
+  double r[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int lo = __builtin_amdgcn_readlane((int)b, 16 * k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * k);
+    r[k] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  return (r[0] + r[1]) + (r[2] + r[3]);
+}
+// 1 / x from the hardware reciprocal and one Newton step (x normal and finite)
+__device__ __forceinline__ double recip(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Starting basis for the Fock eigensolve of an off-diagonal domain.  The cyclic
+// Jacobi method converges quadratically once the off-diagonal part is small, so
+// an approximate eigenbasis V1 (orthonormal to rounding) leaves it one sweep
+// instead of five to eight.  V1 is formed in four steps, all in LDS:
+//   1. Householder reduction H = Q T Q^T (T tridiagonal): every wave forms the
+//      reflector of column c from row c (the same arithmetic in every wave), the
+//      product p = tau A22 v goes to row 0 of Z, then A22 -= v w^T + w v^T with
+//      w = p - (tau/2)(p.v) v: two barriers per column.  Teams of 16 lanes take
+//      rows; a lane holds its entries j = l, l + 16, ... of v and w in registers.
+//      Reflector c is then kept in row c right of the superdiagonal (leading 1
+//      implicit) and tau_c in the spare column LD - 1 of A; d and e stay on the
+//      diagonal and superdiagonal;
+//   2. every eigenvalue of T by bisection on Sturm counts, one team of 8 lanes per
+//      eigenvalue testing 8 points at a time (nine-section, 14 rounds: the width
+//      shrinks by 9^14 = 2.3e13), kept in the spare column of Z;
+//   3. each eigenvector of T from a twisted factorisation T - lambda = N_r D_r N_r^T
+//      (Dhillon and Parlett, LAA 387 (2004) 1-28), one thread per vector: the
+//      stationary LDL^T pivots D+ forward, the UDU^T pivots D- backward, the twist
+//      r where |gamma_r| = |D+_r + D-_r - (d_r - lambda)| is smallest, and
+//      z_r = 1, z_i = -(e_i / D+_i) z_{i+1} (i < r), z_{i+1} = -(e_i / D-_{i+1}) z_i
+//      (i >= r), with pivots of magnitude below eps ||T|| replaced by +-eps ||T||;
+//      then V0 = Q Z, each team of 16 lanes keeping its columns of Z in registers
+//      through all reflectors (no barriers);
+//   4. one Newton-Schulz step V1 = V0 (3/2 - G/2), G = V0^T V0 (in place of the
+//      polar factor of V0): the error 1 - G of order 1e-11 becomes 1e-22.
+// The serial recurrences take reciprocals from the hardware estimate and one
+// Newton step: the basis is a starting point, which the Jacobi sweep makes exact.
+// Sums within a team may differ in the last bit between its lanes (each lane's
+// order of additions is fixed, so results are reproducible).
+// On return A holds 3/2 - G/2 and Z holds V0, both n x n; false (uniform) when
+// max |1 - G| exceeds 1e-8 or is not finite (eigenvalues too close for the
+// vectors to be told apart): the caller then keeps its basis.
+template <int LD, int NT>
+__device__ bool fock_start(double *A, double *Z, int n) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // 1. tridiagonalisation; (pc, pbeta, pt, psc): reflector of the previous column,
+  // written into its row by wave 0 once no wave reads that row any more
+  int pc = -1;
+  double pbeta = 0.0, pt = 0.0, psc = 0.0;
+  auto finish_row = [&]() {
+    if (wave == 0 && pc >= 0) {
+      double *xr = A + pc * LD + pc + 1;
+      const int pm = n - pc - 1;
+      if (pt != 0.0)
+        for (int i = 1 + lane; i < pm; i += 64) xr[i] *= psc;
+      if (lane == 0) {
+        xr[0] = pbeta;
+        A[pc * LD + LD - 1] = pt;
+      }
+    }
+  };
+  double *p = Z;   // p of the current column (row 0 of Z, free until step 2)
+  const int team = tid >> 4, tl = tid & 15;
+  constexpr int EPL = (LD - 1 + 15) / 16;   // entries of a row per lane of a team
+  for (int c = 0; c + 2 < n; c++) {
+    const int m = n - c - 1;
+    const double *x = A + c * LD + c + 1;
+    finish_row();
+    double ss = 0.0;
+    for (int i = 1 + lane; i < m; i += 64) ss += x[i] * x[i];
+    ss = wave_sum_fixed(ss);
+    const double alpha = x[0];
+    double t = 0.0, beta = alpha, sc = 0.0;
+    if (ss != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      t = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    pc = c;
+    pbeta = beta;
+    pt = t;
+    psc = sc;
+    if (t == 0.0) continue;   // uniform; the next column's finish_row runs after a barrier
+    // this lane's entries j = tl + 16 s of v (zero past m), all loads first
+    double vr[EPL];
+#pragma unroll
+    for (int u = 0; u < EPL; u++) {
+      const int j = tl + 16 * u;
+      vr[u] = j < m ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EPL; u++) vr[u] = (tl + 16 * u == 0) ? 1.0 : vr[u] * sc;
+    // p = t A22 v: team g takes rows g, g + NT/16, ...
+    for (int i = team; i < m; i += NT / 16) {
+      const double *ar = A + (c + 1 + i) * LD + c + 1;
+      double av[EPL];
+#pragma unroll
+      for (int u = 0; u < EPL; u++) {
+        const int j = tl + 16 * u;
+        av[u] = j < m ? ar[j] : 0.0;
+      }
+      double sa = 0.0;
+#pragma unroll
+      for (int u = 0; u < EPL; u++) sa += av[u] * vr[u];
+      sa = row_sum16(sa);
+      if (tl == 0) p[i] = t * sa;
+    }
+    __syncthreads();
+    // K = -(t/2) p.v within each team (the team's lanes hold every entry); w = p + K v
+    double pr[EPL];
+#pragma unroll
+    for (int u = 0; u < EPL; u++) {
+      const int j = tl + 16 * u;
+      pr[u] = j < m ? p[j] : 0.0;
+    }
+    double pv = 0.0;
+#pragma unroll
+    for (int u = 0; u < EPL; u++) pv += pr[u] * vr[u];
+    const double K = -0.5 * t * row_sum16(pv);
+#pragma unroll
+    for (int u = 0; u < EPL; u++) pr[u] += K * vr[u];
+    for (int i = team; i < m; i += NT / 16) {
+      const double vi = i == 0 ? 1.0 : x[i] * sc, wi = p[i] + K * vi;
+      double *ar = A + (c + 1 + i) * LD + c + 1;
+      double av[EPL];
+#pragma unroll
+      for (int u = 0; u < EPL; u++) {
+        const int j = tl + 16 * u;
+        av[u] = j < m ? ar[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < EPL; u++) {
+        const int j = tl + 16 * u;
+        if (j < m) ar[j] = av[u] - (vi * pr[u] + wi * vr[u]);
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  finish_row();
+  __syncthreads();
+  // Gerschgorin interval, ||T||_1 and the largest e^2 (every thread, same order)
+  auto dg = [&](int i) { return A[i * LD + i]; };
+  auto ev = [&](int i) { return A[i * LD + i + 1]; };
+  double lo = 1e300, hi = -1e300, tn = 0.0, emax = 0.0;
+  for (int i = 0; i < n; i++) {
+    const double el = i > 0 ? fabs(ev(i - 1)) : 0.0, er = i + 1 < n ? fabs(ev(i)) : 0.0;
+    lo = fmin(lo, dg(i) - el - er);
+    hi = fmax(hi, dg(i) + el + er);
+    tn = fmax(tn, fabs(dg(i)) + el + er);
+    if (i + 1 < n) emax = fmax(emax, ev(i) * ev(i));
+  }
+  const double span = fmax(fabs(lo), fabs(hi));
+  lo -= 2.2e-16 * span + 1e-300;
+  hi += 2.2e-16 * span + 1e-300;
+  const double piv = 2.3e-308 * fmax(1.0, emax), pfloor = 2.2e-16 * fmax(tn, 1e-300);
+  // 2. eigenvalues (ascending): the 8 lanes of a team test a + (l + 1) h, h = (b - a) / 9
+  {
+    const int bt = tid >> 3, bl = tid & 7;
+    for (int k = bt; k < n; k += NT / 8) {
+      double a = lo, b = hi;
+      for (int rd = 0; rd < 14; rd++) {
+        const double h = (b - a) * (1.0 / 9.0), xq = a + (bl + 1) * h;
+        int cnt = 0;
+        double q = dg(0) - xq;
+        if (fabs(q) < piv) q = -piv;
+        cnt += q < 0.0;
+#pragma unroll 4
+        for (int i = 1; i < n; i++) {
+          const double ei = ev(i - 1);
+          q = dg(i) - xq - ei * ei * recip(q);
+          if (fabs(q) < piv) q = -piv;
+          cnt += q < 0.0;
+        }
+        const unsigned long long bal = __ballot(cnt > k);
+        const int j = 8 - __popcll((bal >> (lane & 56)) & 0xffull);   // points below lambda_k
+        const double na = a + j * h, nb = j < 8 ? a + (j + 1) * h : b;
+        a = na;
+        b = nb;
+      }
+      if (bl == 0) Z[k * LD + LD - 1] = 0.5 * (a + b);
+    }
+  }
+  __syncthreads();
+  // 3. eigenvectors of T, thread j -> column j of Z (pivots, then the vector, in place)
+  for (int j = tid; j < n; j += NT) {
+    const double lam = Z[j * LD + LD - 1];
+    double *zc = Z + j;
+    auto fl = [&](double v) { return fabs(v) < pfloor ? (v < 0.0 ? -pfloor : pfloor) : v; };
+    double Dp = fl(dg(0) - lam);
+    zc[0] = Dp;
+    for (int i = 0; i + 1 < n; i++) {
+      const double ei = ev(i);
+      Dp = fl(dg(i + 1) - lam - ei * ei * recip(Dp));
+      zc[(i + 1) * LD] = Dp;
+    }
+    double Dm = fl(dg(n - 1) - lam);
+    double best = fabs(zc[(n - 1) * LD] + Dm - (dg(n - 1) - lam));
+    int r = n - 1;
+    for (int k = n - 2; k >= 0; k--) {
+      const double ek = ev(k);
+      Dm = fl(dg(k) - lam - ek * ek * recip(Dm));
+      const double g = fabs(zc[k * LD] + Dm - (dg(k) - lam));
+      if (g < best) {
+        best = g;
+        r = k;
+      }
+    }
+    Dm = fl(dg(n - 1) - lam);
+    for (int i = n - 2; i >= r; i--) {
+      const double ei = ev(i), rD = recip(Dm);
+      zc[(i + 1) * LD] = ei * rD;
+      Dm = fl(dg(i) - lam - ei * ei * rD);
+    }
+    double zv = 1.0, ss = 1.0;
+    for (int i = r - 1; i >= 0; i--) {
+      zv = -(ev(i) * recip(zc[i * LD])) * zv;
+      zc[i * LD] = zv;
+      ss += zv * zv;
+    }
+    zc[r * LD] = 1.0;
+    zv = 1.0;
+    for (int i = r; i + 1 < n; i++) {
+      zv = -zc[(i + 1) * LD] * zv;
+      zc[(i + 1) * LD] = zv;
+      ss += zv * zv;
+    }
+    const double sc = 1.0 / sqrt(ss);
+    for (int i = 0; i < n; i++) zc[i * LD] *= sc;
+  }
+  __syncthreads();
+  // V0 = H_0 H_1 ... H_{n-3} Z: team g keeps columns g, g + NT/16, ... of Z in
+  // registers (entry i = tl + 16 u) through all reflectors
+  {
+    constexpr int NTM = NT / 16, CPT = (LD - 1 + NTM - 1) / NTM;   // teams, columns per team
+    double zr[CPT][EPL];
+#pragma unroll
+    for (int q = 0; q < CPT; q++) {
+      const int j = team + NTM * q;
+#pragma unroll
+      for (int u = 0; u < EPL; u++) {
+        const int i = tl + 16 * u;
+        zr[q][u] = (j < n && i < n) ? Z[i * LD + j] : 0.0;
+      }
+    }
+    for (int c = n - 3; c >= 0; c--) {
+      const double t = A[c * LD + LD - 1];
+      if (t == 0.0) continue;
+      // reflector c on rows c + 1 ..: u_(c+1) = 1, u_i = A[c][i] for i > c + 1
+      double ur[EPL];
+#pragma unroll
+      for (int u = 0; u < EPL; u++) {
+        const int i = tl + 16 * u;
+        ur[u] = (i > c + 1 && i < n) ? A[c * LD + i] : (i == c + 1 ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < CPT; q++) {
+        double sa = 0.0;
+#pragma unroll
+        for (int u = 0; u < EPL; u++) sa += ur[u] * zr[q][u];
+        sa = t * row_sum16(sa);
+#pragma unroll
+        for (int u = 0; u < EPL; u++) zr[q][u] -= sa * ur[u];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; q++) {
+      const int j = team + NTM * q;
+#pragma unroll
+      for (int u = 0; u < EPL; u++) {
+        const int i = tl + 16 * u;
+        if (j < n && i < n) Z[i * LD + j] = zr[q][u];
+      }
+    }
+  }
+  __syncthreads();
+  // 4. G = V0^T V0 into A, the test, then 3/2 - G/2
+  mma_tiles<NT>(n, n, n, [&](int i, int k) { return Z[k * LD + i]; },
+                [&](int k, int j) { return Z[k * LD + j]; },
+                [&](int i, int j, double v) { A[i * LD + j] = v; });
+  __syncthreads();
+  bool bad = false;
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e / n, j = e - i * n;
+    bad = bad || !(fabs(((i == j) ? 1.0 : 0.0) - A[i * LD + j]) <= 1e-8);
+  }
+  if (__syncthreads_or(bad)) return false;
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e / n, j = e - i * n;
+    A[i * LD + j] = ((i == j) ? 1.5 : 0.0) - 0.5 * A[i * LD + j];
+  }
+  __syncthreads();
+  return true;
+}
+
 // Pair-domain preparation, one workgroup of NT threads per domain of dimension
 // n <= NM (LDS work matrices NM x (NM+1)).
 template <int NM, int NT>
@@ -383,21 +710,44 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       }
       __syncthreads();
     }
-    // 2) L1 = F_(pq,pq) X (n x dt)
-    mma_tiles<NT>(n, dt, n, [&](int i, int k) { return comp_elem(F, ld, D, D, i, k, false); },
-                  [&](int k, int j) { return Yg[k * n + j]; },
-                  [&](int i, int j, double v) { L1[i * LD + j] = v; });
-    __syncthreads();
-    // H = X^T L1 (dt x dt) into L2, symmetrised into L1
-    mma_tiles<NT>(dt, dt, n, [&](int i, int k) { return Yg[k * n + i]; },
-                  [&](int k, int j) { return L1[k * LD + j]; },
-                  [&](int i, int j, double v) { L2[i * LD + j] = v; });
-    __syncthreads();
-    for (int e = tid; e < dt * dt; e += NT) {
-      int i = e / dt, j = e - i * dt;
-      L1[i * LD + j] = 0.5 * (L2[i * LD + j] + L2[j * LD + i]);
+    // 2) H = X^T F_(pq,pq) X (dt x dt) into L1: L1 = F X (n x dt), L2 = X^T L1,
+    //    symmetrised into L1
+    auto form_h = [&]() {
+      mma_tiles<NT>(n, dt, n, [&](int i, int k) { return comp_elem(F, ld, D, D, i, k, false); },
+                    [&](int k, int j) { return Yg[k * n + j]; },
+                    [&](int i, int j, double v) { L1[i * LD + j] = v; });
+      __syncthreads();
+      mma_tiles<NT>(dt, dt, n, [&](int i, int k) { return Yg[k * n + i]; },
+                    [&](int k, int j) { return L1[k * LD + j]; },
+                    [&](int i, int j, double v) { L2[i * LD + j] = v; });
+      __syncthreads();
+      for (int e = tid; e < dt * dt; e += NT) {
+        int i = e / dt, j = e - i * dt;
+        L1[i * LD + j] = 0.5 * (L2[i * LD + j] + L2[j * LD + i]);
+      }
+      __syncthreads();
+    };
+    form_h();
+    // approximate eigenbasis V1 of H: X <- X V1 (V1 = V0 (3/2 - G/2) through the W
+    // slot, not yet written) and H formed again, nearly diagonal
+    if (dt == n && n >= FOCK_START_MIN && fock_start<LD, NT>(L1, L2, n)) {
+      mma_tiles<NT>(n, n, n, [&](int i, int k) { return L2[i * LD + k]; },
+                    [&](int k, int j) { return L1[k * LD + j]; },
+                    [&](int i, int j, double v) { Wg[i * n + j] = v; });
+      __syncthreads();
+      mma_tiles<NT>(n, n, n, [&](int i, int k) { return Yg[i * n + k]; },
+                    [&](int k, int j) { return Wg[k * n + j]; },
+                    [&](int i, int j, double v) { L1[i * LD + j] = v; });
+      __syncthreads();
+      for (int e = tid; e < n * n; e += NT) {
+        int i = e / n, j = e - i * n;
+        Yg[i * n + j] = L1[i * LD + j];
+      }
+      __syncthreads();
+      form_h();
+    } else if (dt == n && n >= FOCK_START_MIN) {
+      form_h();   // the reduction overwrote H
     }
-    __syncthreads();
     jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, rt, red, &s_flag);
     for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
     __syncthreads();
