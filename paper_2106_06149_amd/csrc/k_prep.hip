@@ -279,7 +279,8 @@ __device__ __forceinline__ double recip(double x) {
 //      diagonal and superdiagonal;
 //   2. every eigenvalue of T by bisection on Sturm counts, one team of 8 lanes per
 //      eigenvalue testing 8 points at a time (nine-section, 14 rounds: the width
-//      shrinks by 9^14 = 2.3e13), kept in the spare column of Z;
+//      shrinks by 9^14 = 2.3e13; 4 lanes and 20 rounds of five-section when the
+//      workgroup has fewer than n teams of 8), kept in the spare column of Z;
 //   3. each eigenvector of T from a twisted factorisation T - lambda = N_r D_r N_r^T
 //      (Dhillon and Parlett, LAA 387 (2004) 1-28), one thread per vector: the
 //      stationary LDL^T pivots D+ forward, the UDU^T pivots D- backward, the twist
@@ -411,13 +412,17 @@ __device__ bool fock_start(double *A, double *Z, int n) {
   lo -= 2.2e-16 * span + 1e-300;
   hi += 2.2e-16 * span + 1e-300;
   const double piv = 2.3e-308 * fmax(1.0, emax), pfloor = 2.2e-16 * fmax(tn, 1e-300);
-  // 2. eigenvalues (ascending): the 8 lanes of a team test a + (l + 1) h, h = (b - a) / 9
+  // 2. eigenvalues (ascending): the BL lanes of a team test a + (l + 1) h,
+  //    h = (b - a) / (BL + 1); 8 lanes and 14 rounds when NT / 8 teams cover every
+  //    eigenvalue, else 4 lanes and 20 rounds (5^20 = 9.5e13)
   {
-    const int bt = tid >> 3, bl = tid & 7;
-    for (int k = bt; k < n; k += NT / 8) {
+    constexpr int BL = (NT / 8 >= LD - 1) ? 8 : 4, ROUNDS = BL == 8 ? 14 : 20;
+    constexpr double RB = 1.0 / (BL + 1);
+    const int bt = tid / BL, bl = tid % BL;
+    for (int k = bt; k < n; k += NT / BL) {
       double a = lo, b = hi;
-      for (int rd = 0; rd < 14; rd++) {
-        const double h = (b - a) * (1.0 / 9.0), xq = a + (bl + 1) * h;
+      for (int rd = 0; rd < ROUNDS; rd++) {
+        const double h = (b - a) * RB, xq = a + (bl + 1) * h;
         int cnt = 0;
         double q = dg(0) - xq;
         if (fabs(q) < piv) q = -piv;
@@ -430,8 +435,8 @@ __device__ bool fock_start(double *A, double *Z, int n) {
           cnt += q < 0.0;
         }
         const unsigned long long bal = __ballot(cnt > k);
-        const int j = 8 - __popcll((bal >> (lane & 56)) & 0xffull);   // points below lambda_k
-        const double na = a + j * h, nb = j < 8 ? a + (j + 1) * h : b;
+        const int j = BL - __popcll((bal >> (lane & (64 - BL))) & ((1ull << BL) - 1));   // points below lambda_k
+        const double na = a + j * h, nb = j < BL ? a + (j + 1) * h : b;
         a = na;
         b = nb;
       }
@@ -663,25 +668,6 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       if (tid == 0) { s_dt = n; minev[dom_id] = 1.0 / tr; }
       __syncthreads();
       dt = n;
-      // warm start of the Fock eigensolve: X <- X diag(V_p, V_q) with the
-      // eigenvectors of the prepared diagonal domains, so that the p block of
-      // X^T F X is already diagonal and the q block nearly so (X^T S X = 1 still)
-      const long long mp = dmoff ? dmoff[D.p] : -1, mq = dmoff ? dmoff[D.q] : -1;
-      if (mp >= 0 && mq >= 0) {
-        const double *Vp = W + mp, *Vq = W + mq;
-        mma_tiles<NT>(n, n, n, [&](int i, int k) { return Yg[i * n + k]; },
-                      [&](int k, int j) {
-                        return k < rp ? (j < rp ? Vp[k * rp + j] : 0.0)
-                                      : (j >= rp ? Vq[(k - rp) * rq + (j - rp)] : 0.0);
-                      },
-                      [&](int i, int j, double v) { L1[i * LD + j] = v; });
-        __syncthreads();
-        for (int e = tid; e < n * n; e += NT) {
-          int i = e / n, j = e - i * n;
-          Yg[i * n + j] = L1[i * LD + j];
-        }
-        __syncthreads();
-      }
     } else {
       // eigenvalue cut of S_(pq,pq) = U s U^T: X = U_kept s_kept^{-1/2}
       for (int e = tid; e < n * n; e += NT) {
@@ -710,6 +696,28 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       }
       __syncthreads();
     }
+    // Fallback start of the Fock eigensolve (block Gram-Schmidt X only): X <- X
+    // diag(V_p, V_q) with the eigenvectors of the prepared diagonal domains, so that
+    // the p block of X^T F X is already diagonal and the q block nearly so (X^T S X
+    // = 1 still); used when the approximate eigenbasis below is not taken
+    const long long mp = (gs && dmoff) ? dmoff[D.p] : -1, mq = (gs && dmoff) ? dmoff[D.q] : -1;
+    auto warm_start = [&]() {
+      if (mp < 0 || mq < 0) return;
+      const int rp = D.rp, rq = D.rq;
+      const double *Vp = W + mp, *Vq = W + mq;
+      mma_tiles<NT>(n, n, n, [&](int i, int k) { return Yg[i * n + k]; },
+                    [&](int k, int j) {
+                      return k < rp ? (j < rp ? Vp[k * rp + j] : 0.0)
+                                    : (j >= rp ? Vq[(k - rp) * rq + (j - rp)] : 0.0);
+                    },
+                    [&](int i, int j, double v) { L1[i * LD + j] = v; });
+      __syncthreads();
+      for (int e = tid; e < n * n; e += NT) {
+        int i = e / n, j = e - i * n;
+        Yg[i * n + j] = L1[i * LD + j];
+      }
+      __syncthreads();
+    };
     // 2) H = X^T F_(pq,pq) X (dt x dt) into L1: L1 = F X (n x dt), L2 = X^T L1,
     //    symmetrised into L1
     auto form_h = [&]() {
@@ -745,8 +753,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       }
       __syncthreads();
       form_h();
-    } else if (dt == n && n >= FOCK_START_MIN) {
-      form_h();   // the reduction overwrote H
+    } else {
+      warm_start();
+      if ((dt == n && n >= FOCK_START_MIN) || (mp >= 0 && mq >= 0)) form_h();   // H overwritten, or X changed
     }
     jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, rt, red, &s_flag);
     for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
@@ -820,32 +829,34 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
   if (tid == 0) rank[dom_id] = dt;
 }
 
-hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
+hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts,
                               const double *S, const double *F, const double *K, long long ld,
                               double tau_S, const long long *diag_moff, double *W, double *Y,
                               double *Kep, int *rank, double *minev, hipStream_t s) {
-  // counts3: number of domains with n <= 32, 32 < n <= 64, 64 < n <= DMAX, in that
-  // order in ids[]
-  // threads per class from the tuning table
+  // counts: number of domains with n <= 32, 32 < n <= 64, 64 < n <= PREP_N3,
+  // PREP_N3 < n <= DMAX, in that order in ids[]; threads per class from the tuning
+  // table, except the third class (512 threads: two workgroups share a CU's LDS)
   int o = 0;
   const int *nt = tuning().prep_nt;
 #define OSV_PREP(NM, NT, c)                                                                      \
-  hipLaunchKernelGGL((k_domain_prep<NM, NT>), dim3(counts3[c]), dim3(NT), 0, s, dom, ids + o, S, F, \
+  hipLaunchKernelGGL((k_domain_prep<NM, NT>), dim3(counts[c]), dim3(NT), 0, s, dom, ids + o, S, F, \
                      K, ld, tau_S, diag_moff, W, Y, Kep, rank, minev)
-  if (counts3[0] > 0) {
+  if (counts[0] > 0) {
     if (nt[0] == 128) OSV_PREP(32, 128, 0);
     else OSV_PREP(32, 256, 0);
   }
-  o += counts3[0];
-  if (counts3[1] > 0) {
+  o += counts[0];
+  if (counts[1] > 0) {
     if (nt[1] == 256) OSV_PREP(64, 256, 1);
     else if (nt[1] == 1024) OSV_PREP(64, 1024, 1);
     else OSV_PREP(64, 512, 1);
   }
-  o += counts3[1];
-  if (counts3[2] > 0) {
-    if (nt[2] == 512) OSV_PREP(DMAX, 512, 2);
-    else OSV_PREP(DMAX, 1024, 2);
+  o += counts[1];
+  if (counts[2] > 0) OSV_PREP(PREP_N3, 512, 2);
+  o += counts[2];
+  if (counts[3] > 0) {
+    if (nt[2] == 512) OSV_PREP(DMAX, 512, 3);
+    else OSV_PREP(DMAX, 1024, 3);
   }
 #undef OSV_PREP
   return hipGetLastError();

@@ -808,20 +808,21 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   if ((rc = dalloc(ctx, &ctx->dMinev, ndom))) return rc;
   if ((rc = dalloc(ctx, &ctx->dRank, ndom))) return rc;
   // prep order: diagonal domains (p, p), then the others, each by LDS size class
-  // (n <= 32, <= 64, <= DMAX); a domain (p, q) starts its eigensolve from the
-  // eigenvectors of (p, p) and (q, q)
-  int prep_cnt[6] = {0, 0, 0, 0, 0, 0};
+  // (n <= 32, <= 64, <= PREP_N3, <= DMAX); a domain (p, q) whose approximate Fock
+  // eigenbasis is not taken starts its eigensolve from the eigenvectors of (p, p)
+  // and (q, q)
+  int prep_cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
     std::vector<int> ids;
     std::vector<long long> dmoff((size_t)nocc, -1);
     for (int g = 0; g < 2; g++)
-      for (int c = 0; c < 3; c++)
+      for (int c = 0; c < 4; c++)
         for (int d = 0; d < ndom; d++) {
           const Domain &D = P.doms[d];
-          const int n = D.n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : 2);
+          const int n = D.n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : (n <= PREP_N3 ? 2 : 3));
           if (cls == c && (D.p == D.q) == (g == 0)) {
             ids.push_back(d);
-            prep_cnt[3 * g + c]++;
+            prep_cnt[4 * g + c]++;
             if (g == 0) dmoff[D.p] = D.moff;
           }
         }
@@ -876,8 +877,9 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds, prep_cnt, ctx->dS, ctx->dF, ctx->dK, ld,
                                  ctx->tau_S, nullptr, ctx->dW, ctx->dY, ctx->dKt, ctx->dRank,
                                  ctx->dMinev, s));
-  HIPCHK(ctx, launch_domain_prep(ctx->dDom, ctx->dPrepIds + (prep_cnt[0] + prep_cnt[1] + prep_cnt[2]),
-                                 prep_cnt + 3, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S,
+  HIPCHK(ctx, launch_domain_prep(ctx->dDom,
+                                 ctx->dPrepIds + (prep_cnt[0] + prep_cnt[1] + prep_cnt[2] + prep_cnt[3]),
+                                 prep_cnt + 4, ctx->dS, ctx->dF, ctx->dK, ld, ctx->tau_S,
                                  ctx->dDiagMoff, ctx->dW, ctx->dY, ctx->dKt, ctx->dRank,
                                  ctx->dMinev, s));
   t_prep.stop();

@@ -6,6 +6,7 @@
 namespace osv {
 
 constexpr int DMAX = 100;      // largest pair-domain dimension r_p + r_q
+constexpr int PREP_N3 = 70;    // domains of 64 < n <= PREP_N3 are prepared two per CU
 // clusters with at most SOLVE_MAXT pairs and SOLVE_MAXTERM terms run in the solve
 // kernel that keeps their descriptors in LDS (every MBE(3) cluster does)
 constexpr int SOLVE_MAXT = 16, SOLVE_MAXTERM = 64;
@@ -214,7 +215,7 @@ hipError_t launch_gemm_tn_f64(const double *A, long long lda, const double *B, l
 // diag_moff (may be null): per LMO p the W slot of the prepared domain (p, p) or
 // -1; off-diagonal domains then start their Fock eigensolve from those
 // eigenvectors
-hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts3,
+hipError_t launch_domain_prep(const Domain *dom, const int *ids, const int *counts,
                               const double *S, const double *F, const double *K, long long ld,
                               double tau_S, const long long *diag_moff, double *W, double *Y,
                               double *Kep, int *rank, double *minev, hipStream_t s);
