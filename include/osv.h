@@ -412,7 +412,7 @@ int64_t osv_cached_bytes(int32_t device);
  *   gemm_ks          8, 16, 32      k per LDS stage of the FP64 tile GEMM (S/F, K, dE/dC)
  *   prep_nt_small    128, 256       threads per pair domain of n <= 32 in the preparation
  *   prep_nt_mid      256, 512, 1024 the same for 32 < n <= 64
- *   prep_nt_big      512, 1024      the same for n > 64
+ *   prep_nt_big      512, 1024      the same for n > 70 (64 < n <= 70: 512, fixed)
  *   cpl_split        0, 64          couplings whose domains both have n <= this run as
  *                                   4-wave workgroups, the others as 8-wave ones
  *   solve_split      0, 1           residual solve: 1 spreads each target's (column

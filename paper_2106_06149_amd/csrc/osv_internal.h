@@ -172,7 +172,8 @@ struct NijArgs {
 struct Tuning {
   int gemm_ks = 16;                     // FP64 tile GEMM k per stage: 8, 16, 32
   int prep_nt[3] = {256, 512, 1024};    // domain preparation threads for n <= 32 {128, 256},
-                                        // n <= 64 {256, 512, 1024}, n <= DMAX {512, 1024}
+                                        // 32 < n <= 64 {256, 512, 1024}, PREP_N3 < n <= DMAX
+                                        // {512, 1024} (64 < n <= PREP_N3: 512)
   int cpl_split = 64;                   // couplings with both domains <= this run in the
                                         // 4-wave class: 0 (none) or 64
   int solve_split = 1;                  // residual solve: balanced work split of each
