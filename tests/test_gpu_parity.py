@@ -60,6 +60,26 @@ def test_small_mbe3_fp64():
     compare(s, g, ref)
 
 
+@pytest.mark.parametrize("levels", ["one", "two"])
+def test_degenerate_virtual_energies_fp64(levels):
+    """Virtual energies with exact multiplicities (all equal, or two alternating
+    levels) make the domains' Fock matrices in the orthonormal OSV basis
+    degenerate (eps times the identity, or exact repeated eigenvalues once a
+    domain holds more functions than either level has virtuals): the approximate
+    eigenbasis of the preparation gives equal vectors for a repeated eigenvalue, is
+    rejected, and those domains start from the diagonal-domain eigenvectors and run
+    the Jacobi solve to convergence."""
+    s = synth.make_system(6, 24, 20, (5, 9), seed=23, cut2=4.5, cut3=4.5)
+    if levels == "one":
+        s.eps_vir[:] = 1.5
+    else:
+        s.eps_vir[:] = np.where(np.arange(s.nvir) % 2 == 0, 1.0, 3.0)
+    say(f"case degenerate virtual energies ({levels} level(s)) nocc=6 nvir=24 r=5..9")
+    g = run_gpu(s)
+    ref = O.solve(s, dvir=True)
+    compare(s, g, ref)
+
+
 def test_ragged_tiles_fp64():
     """r_i spanning several 16-wide MFMA tiles with ragged tails (d up to 70)."""
     s = synth.make_system(5, 90, 70, [17, 35, 9, 33, 21], seed=12, cut2=4.5, cut3=4.5)
