@@ -463,12 +463,19 @@ hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, vo
 // each).  Stages of 64 k move all planes of the tile's 192 rows (72 KB) into LDS
 // by direct global-to-LDS loads, double-buffered: the next stage is in flight
 // while the current one is multiplied.  A stage is [plane][12 blocks][16 rows][64 B];
-// blocks 0-7 hold the 128 A rows, 8-11 the 64 B rows.  Every element is written
+// blocks 0-7 hold the 128 A rows, 8-11 the 64 B rows; within a row the four 16-byte
+// k segments are stored in the order s ^ dsw(row), so that the 16 rows of a
+// fragment read hit distinct banks.  Each stage first reads the fragments of planes
+// 0-2, then issues the reads of planes 3-5 between the 36 products that need only
+// planes 0-2, then the other 68 products.  Every element is written
 // at (i, j) and at (j, i): K is symmetric, so tiles that cross the diagonal or
 // repeat a block only store the same values again.
 constexpr int DNT = 512;
 constexpr int DSTG = ND * 12 * 1024;   // bytes per stage
 typedef int i4 __attribute__((ext_vector_type(4)));
+
+// bank swizzle of the k segments of row r (r = 0..15 within a block)
+__device__ __forceinline__ int dsw(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
 __device__ __forceinline__ void dig_issue(const signed char *__restrict__ dig, long long plane,
                                           int kp, int M, int i0, int j0, int k0,
@@ -477,9 +484,10 @@ __device__ __forceinline__ void dig_issue(const signed char *__restrict__ dig, l
 #pragma unroll
   for (int v = 0; v < 9; v++) {
     const int u = wave + 8 * v;            // 1 KB block: plane u / 12, block u % 12
-    const int d = u / 12, rb = u - d * 12;
-    const int r = (rb < 8 ? i0 + 16 * rb : j0 + 16 * (rb - 8)) + (lane >> 2);
-    const signed char *src = dig + d * plane + (long long)min(r, M - 1) * kp + k0 + 16 * (lane & 3);
+    const int d = u / 12, rb = u - d * 12, rr = lane >> 2;
+    const int r = (rb < 8 ? i0 + 16 * rb : j0 + 16 * (rb - 8)) + rr;
+    const signed char *src =
+        dig + d * plane + (long long)min(r, M - 1) * kp + k0 + 16 * ((lane & 3) ^ dsw(rr));
     __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr)(stage + u * 1024), 16, 0, 0);
   }
 }
@@ -494,6 +502,7 @@ __global__ __launch_bounds__(DNT) void k_syrk_i8(const signed char *__restrict__
   const int i0 = t.x * 128, j0 = t.y * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l15 = lane & 15, lhi = lane >> 4;
+  const int soff = l15 * 64 + ((lhi ^ dsw(l15)) * 16);   // this lane's 16 bytes of a block
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   i4 lev[NL][2][2];
 #pragma unroll
@@ -513,23 +522,42 @@ __global__ __launch_bounds__(DNT) void k_syrk_i8(const signed char *__restrict__
 #pragma unroll
     for (int d = 0; d < ND; d++) {
 #pragma unroll
-      for (int a = 0; a < 2; a++)
-        af[d][a] = *(const i4 *)(S + (d * 12 + (wr >> 4) + a) * 1024 + l15 * 64 + lhi * 16);
+      for (int a = 0; a < 2; a++) af[d][a] = *(const i4 *)(S + (d * 12 + (wr >> 4) + a) * 1024 + soff);
 #pragma unroll
-      for (int b = 0; b < 2; b++)
-        bf[d][b] = *(const i4 *)(S + (d * 12 + 8 + (wc >> 4) + b) * 1024 + l15 * 64 + lhi * 16);
+      for (int b = 0; b < 2; b++) bf[d][b] = *(const i4 *)(S + (d * 12 + 8 + (wc >> 4) + b) * 1024 + soff);
     }
+    // the products of planes 0-2, then the rest (each level's sum keeps the order
+    // of its products within these two groups)
+#pragma unroll
+    for (int la = 0; la < 3; la++)
+#pragma unroll
+      for (int lb = 0; lb < 3; lb++)
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+          for (int b = 0; b < 2; b++)
+            lev[la + lb][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[la][a], bf[lb][b],
+                                                                        lev[la + lb][a][b], 0, 0, 0);
 #pragma unroll
     for (int la = 0; la < ND; la++)
 #pragma unroll
       for (int lb = 0; lb < ND; lb++)
-        if (la + lb < NL)
+        if (la + lb < NL && (la >= 3 || lb >= 3))
 #pragma unroll
           for (int a = 0; a < 2; a++)
 #pragma unroll
             for (int b = 0; b < 2; b++)
               lev[la + lb][a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[la][a], bf[lb][b],
                                                                           lev[la + lb][a][b], 0, 0, 0);
+    // schedule: the 12 reads of planes 0-2, then one read of planes 3-5 after every
+    // 3 of the 36 products of planes 0-2, then the other 68 products
+    __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
+#pragma unroll
+    for (int g = 0; g < 12; g++) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 68, 0);
   }
   // int32 accumulator layout: lane l, register v -> row 4 (l >> 4) + v, column l & 15
 #pragma unroll
