@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -195,161 +196,188 @@ int build_domains(int nocc, const Selection &s, const int *r, const int *off, Pl
   return OSV_OK;
 }
 
+// Runs f(i) for i in [0, n) on up to 16 host threads, in contiguous ranges.
+template <class F>
+void parallel_for(long long n, F f) {
+  const unsigned hc = std::thread::hardware_concurrency();
+  const int nt = (int)std::max<long long>(1, std::min<long long>({16, hc ? (long long)hc : 1, n / 2048 + 1}));
+  if (nt == 1) {
+    for (long long i = 0; i < n; i++) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int k = 0; k < nt; k++)
+    th.emplace_back([&, k]() {
+      const long long lo = n * k / nt, hi = n * (k + 1) / nt;
+      for (long long i = lo; i < hi; i++) f(i);
+    });
+  for (auto &t : th) t.join();
+}
+
 // Builds the clusters' pairs, terms and couplings and the work queue (after
 // build_domains; runs on the host while the device forms S, F, K and the domains).
+// The pairs and terms are laid out from per-cluster counts and filled on several
+// threads; the couplings are numbered in order of first use over the terms, in one
+// pass over their keys, so the tables do not depend on the thread count.
 void build_clusters(int nocc, const Selection &s, Plan &P) {
   const int ncl = (int)s.coef.size();
   auto dom_id = [&](int a, int b) {
     return a <= b ? P.dom_of[(size_t)a * nocc + b] : P.dom_of[(size_t)b * nocc + a];
   };
-  // couplings keyed by (A, B), A < B: open addressing with linear probing
   const long long ND = (long long)P.doms.size();
-  size_t cap = 1024;
-  while ((long long)cap < 32 * ND) cap <<= 1;   // grown below at half load
-  std::vector<long long> hkey(cap, -1);
-  std::vector<int> hval(cap);
-  auto slot = [&](long long key) {
-    size_t h = (size_t)((unsigned long long)key * 0x9E3779B97F4A7C15ull >> 17) & (cap - 1);
-    while (hkey[h] != -1 && hkey[h] != key) h = (h + 1) & (cap - 1);
-    return h;
-  };
-  auto coupling = [&](int t, int src, int &flags) {
-    const int A = std::min(t, src), B = std::max(t, src);
-    const long long key = (long long)A * ND + B;
-    size_t h = slot(key);
-    int id;
-    if (hkey[h] == -1) {
-      if (2 * (P.cpls.size() + 1) > cap) {   // rehash at half load
-        std::vector<long long> ok;
-        std::vector<int> ov;
-        ok.swap(hkey);
-        ov.swap(hval);
-        cap <<= 1;
-        hkey.assign(cap, -1);
-        hval.resize(cap);
-        for (size_t e = 0; e < ok.size(); e++)
-          if (ok[e] != -1) {
-            const size_t g = slot(ok[e]);
-            hkey[g] = ok[e];
-            hval[g] = ov[e];
-          }
-        h = slot(key);
-      }
-      id = (int)P.cpls.size();
-      Coupling c{};
-      c.A = A;
-      c.B = B;
-      const long long sz = (long long)P.doms[A].np * P.doms[B].np;
-      c.offAB = P.n_M;
-      c.offBA = P.n_M + sz;
-      P.n_M += 2 * sz;
-      P.cpls.push_back(c);
-      hkey[h] = key;
-      hval[h] = id;
-    } else {
-      id = hval[h];
-    }
-    if (t != A) flags |= 1;
-    return id;
-  };
-  {
-    long long npairs = 0, nterms = 0;
-    for (int X = 0; X < ncl; X++) {
-      const long long nl = s.lmo_ptr[X + 1] - s.lmo_ptr[X];
-      npairs += nl * (nl + 1) / 2;
-      nterms += nl * (nl + 1) / 2 * 2 * (nl - 1);
-    }
-    P.cps.reserve(npairs);
-    P.terms.reserve(nterms);
-    P.cls.reserve(ncl);
-  }
-  std::vector<double> cost(ncl, 0.0);
-  std::vector<int> lpair;
-  for (int X = 0; X < ncl; X++) {
-    Cluster C{};
+  // 1. per-cluster counts, then offsets: pairs, terms, amplitude doubles, dE/dF doubles
+  std::vector<long long> cpo(ncl + 1, 0), tmo(ncl + 1, 0), tof(ncl + 1, 0), plo(ncl + 1, 0);
+  parallel_for(ncl, [&](long long X) {
     const int l0 = s.lmo_ptr[X], nl = s.lmo_ptr[X + 1] - l0;
-    C.cp0 = (int)P.cps.size();
-    C.nlmo = nl;
-    C.lmo0 = l0;
-    C.toff0 = P.n_T;
-    C.poff = P.n_pl;
-    P.n_pl += (long long)nl * nl;
-    // local pair index table
-    lpair.assign((size_t)nl * nl, -1);
+    cpo[X + 1] = (long long)nl * (nl + 1) / 2;
+    tmo[X + 1] = cpo[X + 1] * 2 * (nl - 1);
+    plo[X + 1] = (long long)nl * nl;
+    long long nT = 0;
     for (int a = 0; a < nl; a++)
       for (int b = a; b < nl; b++) {
-        CPair cp{};
-        int p = s.lmo[l0 + a], q = s.lmo[l0 + b];
-        cp.dom = dom_id(p, q);
+        const long long np = P.doms[dom_id(s.lmo[l0 + a], s.lmo[l0 + b])].np;
+        nT += 2 * np * np;
+      }
+    tof[X + 1] = nT;
+  });
+  for (int X = 0; X < ncl; X++) {
+    cpo[X + 1] += cpo[X];
+    tmo[X + 1] += tmo[X];
+    tof[X + 1] += tof[X];
+    plo[X + 1] += plo[X];
+  }
+  P.cps.assign(cpo[ncl], CPair{});
+  P.terms.assign(tmo[ncl], Term{});
+  P.cls.assign(ncl, Cluster{});
+  std::vector<long long> keys(tmo[ncl]);   // coupling key A * ND + B of each term
+  std::vector<long long> rs_max(ncl, 0);
+  // 2. clusters, pairs and terms of eq:rij
+  parallel_for(ncl, [&](long long X) {
+    Cluster &C = P.cls[X];
+    const int l0 = s.lmo_ptr[X], nl = s.lmo_ptr[X + 1] - l0;
+    C.cp0 = (int)cpo[X];
+    C.ncp = (int)(cpo[X + 1] - cpo[X]);
+    C.nlmo = nl;
+    C.lmo0 = l0;
+    C.toff0 = P.n_T + tof[X];
+    C.poff = P.n_pl + plo[X];
+    C.term0 = (int)tmo[X];
+    C.term1 = (int)tmo[X + 1];
+    // local pair index table (nl <= nocc; the pairs (a, b), a <= b, in row order)
+    auto lpair = [&](int a, int b) {
+      if (a > b) std::swap(a, b);
+      return C.cp0 + a * nl - a * (a - 1) / 2 + (b - a);
+    };
+    long long toff = C.toff0;
+    for (int a = 0; a < nl; a++)
+      for (int b = a; b < nl; b++) {
+        CPair &cp = P.cps[lpair(a, b)];
+        cp.dom = dom_id(s.lmo[l0 + a], s.lmo[l0 + b]);
         cp.la = a;
         cp.lb = b;
         cp.w = (a == b) ? 1 : 2;
-        cp.toff = P.n_T;
+        cp.toff = toff;
         cp.init = -1;
         const long long np = P.doms[cp.dom].np;
-        P.n_T += 2 * np * np;
-        lpair[(size_t)a * nl + b] = lpair[(size_t)b * nl + a] = (int)P.cps.size();
-        P.cps.push_back(cp);
+        toff += 2 * np * np;
       }
-    C.ncp = (int)P.cps.size() - C.cp0;
-    C.term0 = (int)P.terms.size();
-    // terms of eq:rij for every pair of the cluster
+    int ti = C.term0;
+    long long rs = 0;
     for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
       CPair &cp = P.cps[c];
-      cp.term0 = (int)P.terms.size();
+      cp.term0 = ti;
       const int a = cp.la, b = cp.lb;
       const int p = s.lmo[l0 + a], q = s.lmo[l0 + b];
-      const double nt = P.doms[cp.dom].n;
-      cost[X] += nt * nt;
+      auto add = [&](int src, int flags, int fa, int fb, int la, int lb) {
+        Term &t = P.terms[ti];
+        t.src = src;
+        const int tgt = cp.dom, sd = P.cps[src].dom;
+        const int A = std::min(tgt, sd), B = std::max(tgt, sd);
+        keys[ti] = (long long)A * ND + B;
+        t.flags = flags | (tgt != A ? 1 : 0);
+        t.fa = fa;
+        t.fb = fb;
+        t.la = la;
+        t.lb = lb;
+        ti++;
+      };
       // first sum: m != q, source ordered (p, m), coefficient f_mq
       for (int mm = 0; mm < nl; mm++) {
         if (mm == b) continue;
         const int m = s.lmo[l0 + mm];
-        Term t{};
-        t.src = lpair[(size_t)a * nl + mm];
-        int flags = (p > m) ? 2 : 0;
-        t.cpl = coupling(cp.dom, P.cps[t.src].dom, flags);
-        t.flags = flags;
-        t.fa = m;
-        t.fb = q;
-        t.la = mm;
-        t.lb = b;
-        const double ns = P.doms[P.cps[t.src].dom].n;
-        cost[X] += nt * ns * ns + nt * nt * ns;
-        P.terms.push_back(t);
+        add(lpair(a, mm), (p > m) ? 2 : 0, m, q, mm, b);
       }
       // second sum: m != p, source ordered (m, q), coefficient f_pm
       for (int mm = 0; mm < nl; mm++) {
         if (mm == a) continue;
         const int m = s.lmo[l0 + mm];
-        Term t{};
-        t.src = lpair[(size_t)mm * nl + b];
-        int flags = (m > q) ? 2 : 0;
-        t.cpl = coupling(cp.dom, P.cps[t.src].dom, flags);
-        t.flags = flags;
-        t.fa = p;
-        t.fb = m;
-        t.la = a;
-        t.lb = mm;
-        const double ns = P.doms[P.cps[t.src].dom].n;
-        cost[X] += nt * ns * ns + nt * nt * ns;
-        P.terms.push_back(t);
+        add(lpair(mm, b), (m > q) ? 2 : 0, p, m, a, mm);
       }
-      cp.nterm = (int)P.terms.size() - cp.term0;
+      cp.nterm = ti - cp.term0;
       // the solve's P pass keeps one np x np product per term of the pair in scratch
       const long long npt = P.doms[cp.dom].np;
-      P.rs_stride = std::max(P.rs_stride, (long long)cp.nterm * npt * npt);
+      rs = std::max(rs, (long long)cp.nterm * npt * npt);
     }
-    C.term1 = (int)P.terms.size();
-    P.n_pair_blocks += C.ncp;
-    P.cls.push_back(C);
+    rs_max[X] = rs;
+  });
+  P.n_T += tof[ncl];
+  P.n_pl += plo[ncl];
+  P.n_pair_blocks += cpo[ncl];
+  for (int X = 0; X < ncl; X++) P.rs_stride = std::max(P.rs_stride, rs_max[X]);
+  // 3. couplings keyed by (A, B), A < B, numbered in order of first use: open
+  // addressing with linear probing, key and id in one slot, each probe prefetched
+  // a few terms ahead
+  struct Slot {
+    long long key;
+    long long id;
+  };
+  size_t cap = 1024;
+  while ((long long)cap < 16 * ND) cap <<= 1;   // grown below at half load
+  std::vector<Slot> tab(cap, Slot{-1, -1});
+  auto hsh = [&](long long key) {
+    return (size_t)((unsigned long long)key * 0x9E3779B97F4A7C15ull >> 17) & (cap - 1);
+  };
+  const long long nterm = (long long)keys.size();
+  constexpr int PF = 16;
+  for (long long t = 0; t < nterm; t++) {
+    if (t + PF < nterm) __builtin_prefetch(&tab[hsh(keys[t + PF])]);
+    const long long key = keys[t];
+    size_t h = hsh(key);
+    while (tab[h].key != -1 && tab[h].key != key) h = (h + 1) & (cap - 1);
+    if (tab[h].key == -1) {
+      if (2 * (P.cpls.size() + 1) > cap) {   // rehash at half load
+        std::vector<Slot> old;
+        old.swap(tab);
+        cap <<= 1;
+        tab.assign(cap, Slot{-1, -1});
+        for (const Slot &e : old)
+          if (e.key != -1) {
+            size_t g = hsh(e.key);
+            while (tab[g].key != -1) g = (g + 1) & (cap - 1);
+            tab[g] = e;
+          }
+        h = hsh(key);
+        while (tab[h].key != -1) h = (h + 1) & (cap - 1);
+      }
+      Coupling c{};
+      c.A = (int)(key / ND);
+      c.B = (int)(key - (long long)c.A * ND);
+      const long long sz = (long long)P.doms[c.A].np * P.doms[c.B].np;
+      c.offAB = P.n_M;
+      c.offBA = P.n_M + sz;
+      P.n_M += 2 * sz;
+      tab[h].key = key;
+      tab[h].id = (long long)P.cpls.size();
+      P.cpls.push_back(c);
+    }
+    P.terms[t].cpl = (int)tab[h].id;
   }
   // Work-queue order: the canonical cluster order, in which neighbouring clusters
   // share LMOs, so workgroups running at the same time touch the same couplings
   // (allocated above in order of first use) and nearby amplitude slots.  Cluster
   // costs vary by less than 2^3 in MBE(3) runs, so there is no long tail to
   // schedule first.
-  (void)cost;
   P.queue.resize(ncl);
   std::iota(P.queue.begin(), P.queue.end(), 0);
   // clusters too large for the solve's LDS descriptor tables go first
@@ -382,9 +410,9 @@ void build_clusters(int nocc, const Selection &s, Plan &P) {
       }
       return -1;
     };
-    for (int X = 0; X < ncl; X++) {
+    parallel_for(ncl, [&](long long X) {
       const Cluster &C = P.cls[X];
-      if (C.nlmo != 3 || C.ncp > SOLVE_MAXT || C.term1 - C.term0 > SOLVE_MAXTERM) continue;
+      if (C.nlmo != 3 || C.ncp > SOLVE_MAXT || C.term1 - C.term0 > SOLVE_MAXTERM) return;
       for (int c = C.cp0; c < C.cp0 + C.ncp; c++) {
         CPair &cp = P.cps[c];
         const int p = s.lmo[C.lmo0 + cp.la], q = s.lmo[C.lmo0 + cp.lb];
@@ -396,7 +424,7 @@ void build_clusters(int nocc, const Selection &s, Plan &P) {
           if (cp.init < 0) cp.init = slot(p, o2, p, p);
         }
       }
-    }
+    });
     auto first = [&](int x) { return P.cls[x].nlmo <= 2; };
     auto mid2 = std::stable_partition(P.queue.begin() + P.n_big, P.queue.end(), first);
     P.n_first = (int)(mid2 - P.queue.begin());
