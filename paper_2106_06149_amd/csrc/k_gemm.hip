@@ -391,31 +391,35 @@ constexpr int NL = ND + 1;  // levels a + b kept
 constexpr int DKS = 64;     // k per stage (bytes of a digit row)
 constexpr int DMAXK = 87000;
 
-// per-row exponent: s_i = 2^e_i with max_P |C[i][P]| < 2^(e_i - 1)
-__global__ __launch_bounds__(256) void k_row_scale(const float *__restrict__ C, long long ld,
+// per-row exponent: s_i = 2^e_i with max_P |C[i][P]| < 2^(e_i - 1) (FP32 or FP64 rows)
+template <typename TF>
+__global__ __launch_bounds__(256) void k_row_scale(const TF *__restrict__ C, long long ld,
                                                    int ncol, int *exps) {
-  __shared__ float red[4];
+  __shared__ TF red[4];
   const int i = blockIdx.x;
-  float m = 0.0f;
-  for (int c = threadIdx.x; c < ncol; c += 256) m = fmaxf(m, fabsf(C[(long long)i * ld + c]));
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  TF m = 0;
+  for (int c = threadIdx.x; c < ncol; c += 256) m = fmax(m, fabs(C[(long long)i * ld + c]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    float t = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    const TF t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     int e = 0;
-    if (t > 0.0f) {
+    if (t > 0) {
       int ex;
-      frexpf(t, &ex);  // t = f 2^ex, f in [0.5, 1)  ->  t < 2^ex
-      e = ex + 1;      // |x| = |c| / 2^e < 1/2
+      frexp(t, &ex);  // t = f 2^ex, f in [0.5, 1)  ->  t < 2^ex
+      e = ex + 1;     // |x| = |c| / 2^e < 1/2
     }
     exps[i] = e;
   }
 }
 
 // digit planes [ND][nrow][kp] (kp = ncol rounded up to DKS, zero beyond ncol);
-// one thread per 4 consecutive elements of a row, stored as one 4-byte word per plane
-__global__ void k_split_i8(const float *__restrict__ C, long long ld, int nrow, int ncol, int kp,
+// one thread per 4 consecutive elements of a row, stored as one 4-byte word per plane.
+// Each digit is the rounded top 7 bits of what the earlier digits left, and the
+// subtraction is exact in the element's own precision.
+template <typename TF>
+__global__ void k_split_i8(const TF *__restrict__ C, long long ld, int nrow, int ncol, int kp,
                            const int *__restrict__ exps, signed char *dig) {
   const long long plane = (long long)nrow * kp;
   const int q = kp / 4;
@@ -423,17 +427,17 @@ __global__ void k_split_i8(const float *__restrict__ C, long long ld, int nrow, 
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(t / q), c0 = (int)(t - (long long)i * q) * 4;
-    float x[4];
+    TF x[4];
 #pragma unroll
     for (int e = 0; e < 4; e++)
-      x[e] = (c0 + e < ncol) ? ldexpf(C[(long long)i * ld + c0 + e], -exps[i]) : 0.0f;
+      x[e] = (c0 + e < ncol) ? ldexp(C[(long long)i * ld + c0 + e], -exps[i]) : TF(0);
 #pragma unroll
     for (int k = 0; k < ND; k++) {
       unsigned w = 0;
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const float d = rintf(ldexpf(x[e], 7 * (k + 1)));
-        x[e] -= ldexpf(d, -7 * (k + 1));
+        const TF d = rint(ldexp(x[e], 7 * (k + 1)));
+        x[e] -= ldexp(d, -7 * (k + 1));
         w |= ((unsigned)(int)d & 0xffu) << (8 * e);
       }
       *(unsigned *)(dig + k * plane + (long long)i * kp + c0) = w;
@@ -445,20 +449,34 @@ int digit_kp(int ncol) { return (ncol + DKS - 1) / DKS * DKS; }
 size_t digit_bytes(int nrow, int ncol) { return (size_t)ND * nrow * digit_kp(ncol); }
 int digit_max_k() { return DMAXK; }
 
-hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
+template <typename TF>
+static hipError_t split_digits(const TF *C, long long ld, int nrow, int ncol, int *exps, void *dig,
                                hipStream_t s) {
   if (nrow <= 0 || ncol <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_scale, dim3(nrow), dim3(256), 0, s, C, (long long)ncol, ncol, exps);
+  hipLaunchKernelGGL(k_row_scale<TF>, dim3(nrow), dim3(256), 0, s, C, ld, ncol, exps);
   const int kp = digit_kp(ncol);
   const long long n = (long long)nrow * (kp / 4);
   long long nb = (n + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_split_i8, dim3((unsigned)nb), dim3(256), 0, s, C, (long long)ncol, nrow,
-                     ncol, kp, (const int *)exps, (signed char *)dig);
+  hipLaunchKernelGGL(k_split_i8<TF>, dim3((unsigned)nb), dim3(256), 0, s, C, ld, nrow, ncol, kp,
+                     (const int *)exps, (signed char *)dig);
   return hipGetLastError();
 }
 
-// SYRK of the digit planes on 128 x 64 output tiles (rows 128 ti.., columns 64 tj..)
+hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, void *dig,
+                               hipStream_t s) {
+  return split_digits(C, (long long)ncol, nrow, ncol, exps, dig, s);
+}
+
+hipError_t launch_split_digits_f64(const double *A, long long lda, int nrow, int ncol, int *exps,
+                                   void *dig, hipStream_t s) {
+  return split_digits(A, lda, nrow, ncol, exps, dig, s);
+}
+
+// Products of digit planes on 128 x 64 output tiles (rows 128 ti.., columns 64 tj..):
+// C_ij = s_i t_j 2^(eadd - 14) sum_l 2^(-7 l) S_l over the rows i of A's planes and
+// the rows j of B's planes (both with k along the row), the SYRK K = C C^T when A
+// and B are the same planes, or a general product (A B^T).  The SYRK
 // with eight waves of 32 x 32 (2 x 2 MFMA 16x16x64 tiles, NL level accumulators
 // each).  Stages of 64 k move all planes of the tile's 192 rows (72 KB) into LDS
 // by direct global-to-LDS loads, double-buffered: the next stage is in flight
@@ -477,28 +495,49 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 // bank swizzle of the k segments of row r (r = 0..15 within a block)
 __device__ __forceinline__ int dsw(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
-__device__ __forceinline__ void dig_issue(const signed char *__restrict__ dig, long long plane,
-                                          int kp, int M, int i0, int j0, int k0,
-                                          signed char *stage) {
+template <bool SYM>
+__device__ __forceinline__ void dig_issue(const signed char *__restrict__ digA, int MA,
+                                          const signed char *__restrict__ digB, int MB,
+                                          int kp, int i0, int j0, int k0, signed char *stage) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long planeA = (long long)MA * kp, planeB = (long long)MB * kp;
 #pragma unroll
   for (int v = 0; v < 9; v++) {
     const int u = wave + 8 * v;            // 1 KB block: plane u / 12, block u % 12
     const int d = u / 12, rb = u - d * 12, rr = lane >> 2;
-    const int r = (rb < 8 ? i0 + 16 * rb : j0 + 16 * (rb - 8)) + rr;
-    const signed char *src =
-        dig + d * plane + (long long)min(r, M - 1) * kp + k0 + 16 * ((lane & 3) ^ dsw(rr));
+    const int seg = 16 * ((lane & 3) ^ dsw(rr));
+    const signed char *src;
+    if (SYM) {
+      const int r = (rb < 8 ? i0 + 16 * rb : j0 + 16 * (rb - 8)) + rr;
+      src = digA + d * planeA + (long long)min(r, MA - 1) * kp + k0 + seg;
+    } else {
+      src = rb < 8 ? digA + d * planeA + (long long)min(i0 + 16 * rb + rr, MA - 1) * kp + k0 + seg
+                   : digB + d * planeB + (long long)min(j0 + 16 * (rb - 8) + rr, MB - 1) * kp + k0 + seg;
+    }
     __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr)(stage + u * 1024), 16, 0, 0);
   }
 }
 
-__global__ __launch_bounds__(DNT) void k_syrk_i8(const signed char *__restrict__ dig, int M,
-                                                 int kp, const int *__restrict__ exps,
-                                                 double *C, long long ldc,
-                                                 const int2 *__restrict__ tiles) {
+// SYM: the SYRK over the listed tiles (A = B, every element also stored at (j, i));
+// otherwise the tile is blockIdx.x = ti * ntj + tj
+template <bool SYM>
+__global__ __launch_bounds__(DNT) void k_digit_mm(const signed char *__restrict__ digA, int MA,
+                                                  const signed char *__restrict__ digB_, int MB_,
+                                                  int kp, const int *__restrict__ expsA,
+                                                  const int *__restrict__ expsB, int eadd,
+                                                  double *C, long long ldc,
+                                                  const int2 *__restrict__ tiles, int ntj) {
   __shared__ __attribute__((aligned(16))) signed char st_l[2 * DSTG];
-  const long long plane = (long long)M * kp;
-  const int2 t = tiles[blockIdx.x];
+  // (the SYRK reads both operands from A's planes)
+  const signed char *__restrict__ digB = SYM ? digA : digB_;
+  const int MB = SYM ? MA : MB_;
+  int2 t;
+  if (SYM) {
+    t = tiles[blockIdx.x];
+  } else {
+    t.x = (int)(blockIdx.x / ntj);
+    t.y = (int)(blockIdx.x - t.x * ntj);
+  }
   const int i0 = t.x * 128, j0 = t.y * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l15 = lane & 15, lhi = lane >> 4;
@@ -512,11 +551,11 @@ __global__ __launch_bounds__(DNT) void k_syrk_i8(const signed char *__restrict__
 #pragma unroll
       for (int b = 0; b < 2; b++) lev[l][a][b] = (i4){0, 0, 0, 0};
   const int nst = kp / DKS;
-  dig_issue(dig, plane, kp, M, i0, j0, 0, st_l);
+  dig_issue<SYM>(digA, MA, digB, MB, kp, i0, j0, 0, st_l);
   for (int st = 0; st < nst; st++) {
     const signed char *S = st_l + (st & 1) * DSTG;
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (st + 1 < nst) dig_issue(dig, plane, kp, M, i0, j0, (st + 1) * DKS, st_l + ((st + 1) & 1) * DSTG);
+    if (st + 1 < nst) dig_issue<SYM>(digA, MA, digB, MB, kp, i0, j0, (st + 1) * DKS, st_l + ((st + 1) & 1) * DSTG);
     // fragment of 16 rows x 64 k: lane l reads row l & 15, bytes 16 (l >> 4) ..
     i4 af[ND][2], bf[ND][2];
 #pragma unroll
@@ -568,13 +607,13 @@ __global__ __launch_bounds__(DNT) void k_syrk_i8(const signed char *__restrict__
       for (int v = 0; v < 4; v++) {
         const int i = i0 + wr + a * 16 + 4 * lhi + v;
         const int j = j0 + wc + b * 16 + l15;
-        if (i < M && j < M) {
+        if (i < MA && j < MB) {
           double sum = 0.0;
 #pragma unroll
           for (int l = NL - 1; l >= 0; l--) sum += ldexp((double)lev[l][a][b][v], -7 * l);
-          const double val = ldexp(sum, exps[i] + exps[j] - 14);
+          const double val = ldexp(sum, expsA[i] + expsB[j] + eadd - 14);
           C[(long long)i * ldc + j] = val;
-          C[(long long)j * ldc + i] = val;
+          if (SYM) C[(long long)j * ldc + i] = val;
         }
       }
 }
@@ -583,8 +622,43 @@ hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, do
                               long long ldc, const int2 *tiles, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (K > DMAXK) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_syrk_i8, dim3(ntiles), dim3(DNT), 0, s, (const signed char *)dig, M,
-                     digit_kp(K), exps, C, ldc, tiles);
+  hipLaunchKernelGGL(k_digit_mm<true>, dim3(ntiles), dim3(DNT), 0, s, (const signed char *)dig, M,
+                     (const signed char *)dig, M, digit_kp(K), exps, exps, 0, C, ldc, tiles, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_digits(const void *digA, int MA, const void *digB, int MB, int K,
+                              const int *expsA, const int *expsB, int eadd, double *C,
+                              long long ldc, hipStream_t s) {
+  if (MA <= 0 || MB <= 0) return hipSuccess;
+  if (K > DMAXK) return hipErrorInvalidValue;
+  const int nti = (MA + 127) / 128, ntj = (MB + 63) / 64;
+  hipLaunchKernelGGL(k_digit_mm<false>, dim3((unsigned)nti * ntj), dim3(DNT), 0, s,
+                     (const signed char *)digA, MA, (const signed char *)digB, MB, digit_kp(K),
+                     expsA, expsB, eadd, C, ldc, nullptr, ntj);
+  return hipGetLastError();
+}
+
+// Xt (cols x rows) = X^T for a row-major FP32 X (rows x cols), through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void k_transpose_f32(const float *__restrict__ X, int rows,
+                                                       int cols, float *__restrict__ Xt) {
+  __shared__ float tl[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + y, c = c0 + tx;
+    if (r < rows && c < cols) tl[y][tx] = X[(long long)r * cols + c];
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int c = c0 + y, r = r0 + tx;
+    if (r < rows && c < cols) Xt[(long long)c * rows + r] = tl[tx][y];
+  }
+}
+
+hipError_t launch_transpose_f32(const float *X, int rows, int cols, float *Xt, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+  hipLaunchKernelGGL(k_transpose_f32, grid, dim3(256), 0, s, X, rows, cols, Xt);
   return hipGetLastError();
 }
 

@@ -496,6 +496,10 @@ struct osv_ctx {
   int2 *dTiles = nullptr;
   void *dDig = nullptr;
   int *dExps = nullptr;
+  // mixed dE/dC: C^T (FP32), its digit planes and exponents, those of G^K
+  float *dCt = nullptr;
+  unsigned char *dDigCt = nullptr, *dDigG = nullptr;
+  int *dExpCt = nullptr, *dExpG = nullptr;
   int2 *dDigTiles = nullptr;
   int ndig_tiles = 0;
   int nwg = 1;
@@ -2260,12 +2264,32 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
   t_adj.stop();
   StageTimer t_bt(s);
   if (dE_dC) {
-    const double *Cd = (const double *)ctx->C;
-    if (ctx->c_dtype == OSV_DT_F32) {
-      if ((rc = c64(ctx, s))) return rc;
-      Cd = ctx->dC64;
+    if (ctx->precision == OSV_MIXED && ctx->c_dtype == OSV_DT_F32 && N <= digit_max_k()) {
+      // mixed precision: dE/dC = 2 G^K C from exact int8 digits, as K: the rows of
+      // G^K and of C^T (one per auxiliary function) each split into six 7-bit
+      // digits with their own power-of-two scale, products summed in int32 per
+      // digit level; what is left out is below 2^-42 of each row's scale
+      const int naux = ctx->naux;
+      if (!ctx->dCt) {
+        if ((rc = dalloc(ctx, &ctx->dCt, (size_t)naux * N))) return rc;
+        if ((rc = dalloc(ctx, &ctx->dDigCt, digit_bytes(naux, N)))) return rc;
+        if ((rc = dalloc(ctx, &ctx->dExpCt, naux))) return rc;
+        if ((rc = dalloc(ctx, &ctx->dDigG, digit_bytes(N, N)))) return rc;
+        if ((rc = dalloc(ctx, &ctx->dExpG, N))) return rc;
+      }
+      HIPCHK(ctx, launch_transpose_f32((const float *)ctx->C, N, naux, ctx->dCt, s));
+      HIPCHK(ctx, launch_split_digits(ctx->dCt, naux, N, ctx->dExpCt, ctx->dDigCt, s));
+      HIPCHK(ctx, launch_split_digits_f64(ctx->dGK, ld, N, N, ctx->dExpG, ctx->dDigG, s));
+      HIPCHK(ctx, launch_gemm_digits(ctx->dDigG, N, ctx->dDigCt, naux, N, ctx->dExpG, ctx->dExpCt, 1,
+                                     dE_dC, naux, s));
+    } else {
+      const double *Cd = (const double *)ctx->C;
+      if (ctx->c_dtype == OSV_DT_F32) {
+        if ((rc = c64(ctx, s))) return rc;
+        Cd = ctx->dC64;
+      }
+      HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGK, ld, Cd, 0, ctx->naux, dE_dC, ctx->naux, N, ctx->naux, N, 2.0, s));
     }
-    HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGK, ld, Cd, 0, ctx->naux, dE_dC, ctx->naux, N, ctx->naux, N, 2.0, s));
   }
   if (dE_deps || Dvir_full) {
     // Z^T = G^F Q^T  (Q^T is row-major sum(r) x nvir)

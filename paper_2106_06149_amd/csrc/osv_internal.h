@@ -205,6 +205,14 @@ hipError_t launch_split_digits(const float *C, int nrow, int ncol, int *exps, vo
                                hipStream_t s);
 hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, double *C,
                               long long ldc, const int2 *tiles, int ntiles, hipStream_t s);
+// dE/dC-type products from digit planes: C (MA x MB, ldc) = 2^eadd A B^T with the
+// rows of A and of B split by launch_split_digits* over the same K
+hipError_t launch_gemm_digits(const void *digA, int MA, const void *digB, int MB, int K,
+                              const int *expsA, const int *expsB, int eadd, double *C,
+                              long long ldc, hipStream_t s);
+hipError_t launch_split_digits_f64(const double *A, long long lda, int nrow, int ncol, int *exps,
+                                   void *dig, hipStream_t s);
+hipError_t launch_transpose_f32(const float *X, int rows, int cols, float *Xt, hipStream_t s);
 // C[i][j] = alpha * sum_k A[i][k] B[k][j]  (A row-major M x K, B row-major K x N)
 hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, int b_is_f32,
                               long long ldb, double *C, long long ldc, int M, int N, int K,
