@@ -639,10 +639,11 @@ hipError_t launch_gemm_digits(const void *digA, int MA, const void *digB, int MB
   return hipGetLastError();
 }
 
-// Xt (cols x rows) = X^T for a row-major FP32 X (rows x cols), through 32 x 32 LDS tiles
-__global__ __launch_bounds__(256) void k_transpose_f32(const float *__restrict__ X, int rows,
-                                                       int cols, float *__restrict__ Xt) {
-  __shared__ float tl[32][33];
+// Xt (cols x rows) = X^T for a row-major X (rows x cols), through 32 x 32 LDS tiles
+template <typename TF>
+__global__ __launch_bounds__(256) void k_transpose(const TF *__restrict__ X, int rows, int cols,
+                                                   TF *__restrict__ Xt) {
+  __shared__ TF tl[32][33];
   const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int y = ty; y < 32; y += 8) {
     const int r = r0 + y, c = c0 + tx;
@@ -658,7 +659,14 @@ __global__ __launch_bounds__(256) void k_transpose_f32(const float *__restrict__
 hipError_t launch_transpose_f32(const float *X, int rows, int cols, float *Xt, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   dim3 grid((cols + 31) / 32, (rows + 31) / 32);
-  hipLaunchKernelGGL(k_transpose_f32, grid, dim3(256), 0, s, X, rows, cols, Xt);
+  hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, X, rows, cols, Xt);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f64(const double *X, int rows, int cols, double *Xt, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+  hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, s, X, rows, cols, Xt);
   return hipGetLastError();
 }
 

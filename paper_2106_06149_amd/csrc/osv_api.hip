@@ -500,6 +500,10 @@ struct osv_ctx {
   float *dCt = nullptr;
   unsigned char *dDigCt = nullptr, *dDigG = nullptr;
   int *dExpCt = nullptr, *dExpG = nullptr;
+  // mixed G^F Q^T: Q (nvir x sum r, FP64) and its digit planes and exponents
+  double *dQn = nullptr;
+  unsigned char *dDigQ = nullptr;
+  int *dExpQ = nullptr;
   int2 *dDigTiles = nullptr;
   int ndig_tiles = 0;
   int nwg = 1;
@@ -2274,8 +2278,8 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
         if ((rc = dalloc(ctx, &ctx->dCt, (size_t)naux * N))) return rc;
         if ((rc = dalloc(ctx, &ctx->dDigCt, digit_bytes(naux, N)))) return rc;
         if ((rc = dalloc(ctx, &ctx->dExpCt, naux))) return rc;
-        if ((rc = dalloc(ctx, &ctx->dDigG, digit_bytes(N, N)))) return rc;
-        if ((rc = dalloc(ctx, &ctx->dExpG, N))) return rc;
+        if (!ctx->dDigG && (rc = dalloc(ctx, &ctx->dDigG, digit_bytes(N, N)))) return rc;
+        if (!ctx->dExpG && (rc = dalloc(ctx, &ctx->dExpG, N))) return rc;
       }
       HIPCHK(ctx, launch_transpose_f32((const float *)ctx->C, N, naux, ctx->dCt, s));
       HIPCHK(ctx, launch_split_digits(ctx->dCt, naux, N, ctx->dExpCt, ctx->dDigCt, s));
@@ -2293,8 +2297,26 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
   }
   if (dE_deps || Dvir_full) {
     // Z^T = G^F Q^T  (Q^T is row-major sum(r) x nvir)
-    HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGF, ld, ctx->Q, 0, ctx->nvir, ctx->dZt, ctx->nvir, N, ctx->nvir, N,
-                                   1.0, s));
+    if (ctx->precision == OSV_MIXED && N <= digit_max_k()) {
+      // mixed precision: from six-digit splits of the rows of G^F and of Q (one per
+      // virtual), as dE/dC; below 2^-42 of each row's scale is left out
+      const int nvir = ctx->nvir;
+      if (!ctx->dQn) {
+        if ((rc = dalloc(ctx, &ctx->dQn, (size_t)nvir * N))) return rc;
+        if ((rc = dalloc(ctx, &ctx->dDigQ, digit_bytes(nvir, N)))) return rc;
+        if ((rc = dalloc(ctx, &ctx->dExpQ, nvir))) return rc;
+        if (!ctx->dDigG && (rc = dalloc(ctx, &ctx->dDigG, digit_bytes(N, N)))) return rc;
+        if (!ctx->dExpG && (rc = dalloc(ctx, &ctx->dExpG, N))) return rc;
+      }
+      HIPCHK(ctx, launch_transpose_f64(ctx->Q, N, nvir, ctx->dQn, s));
+      HIPCHK(ctx, launch_split_digits_f64(ctx->dQn, N, nvir, N, ctx->dExpQ, ctx->dDigQ, s));
+      HIPCHK(ctx, launch_split_digits_f64(ctx->dGF, ld, N, N, ctx->dExpG, ctx->dDigG, s));
+      HIPCHK(ctx, launch_gemm_digits(ctx->dDigG, N, ctx->dDigQ, nvir, N, ctx->dExpG, ctx->dExpQ, 0,
+                                     ctx->dZt, nvir, s));
+    } else {
+      HIPCHK(ctx, launch_gemm_nn_f64(ctx->dGF, ld, ctx->Q, 0, ctx->nvir, ctx->dZt, ctx->nvir, N, ctx->nvir, N,
+                                     1.0, s));
+    }
     if (dE_deps) HIPCHK(ctx, launch_coldot(ctx->Q, ctx->dZt, N, ctx->nvir, ctx->dColPart, dE_deps, s));
     if (Dvir_full)
       HIPCHK(ctx, launch_gemm_tn_f64(ctx->Q, ctx->nvir, ctx->dZt, ctx->nvir, Dvir_full, ctx->nvir, ctx->nvir,

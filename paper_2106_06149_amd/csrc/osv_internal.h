@@ -213,6 +213,7 @@ hipError_t launch_gemm_digits(const void *digA, int MA, const void *digB, int MB
 hipError_t launch_split_digits_f64(const double *A, long long lda, int nrow, int ncol, int *exps,
                                    void *dig, hipStream_t s);
 hipError_t launch_transpose_f32(const float *X, int rows, int cols, float *Xt, hipStream_t s);
+hipError_t launch_transpose_f64(const double *X, int rows, int cols, double *Xt, hipStream_t s);
 // C[i][j] = alpha * sum_k A[i][k] B[k][j]  (A row-major M x K, B row-major K x N)
 hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, int b_is_f32,
                               long long ldb, double *C, long long ldc, int M, int N, int K,
