@@ -495,7 +495,7 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 // bank swizzle of the k segments of row r (r = 0..15 within a block)
 __device__ __forceinline__ int dsw(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
-template <bool SYM>
+template <bool SAMEB>
 __device__ __forceinline__ void dig_issue(const signed char *__restrict__ digA, int MA,
                                           const signed char *__restrict__ digB, int MB,
                                           int kp, int i0, int j0, int k0, signed char *stage) {
@@ -507,7 +507,7 @@ __device__ __forceinline__ void dig_issue(const signed char *__restrict__ digA, 
     const int d = u / 12, rb = u - d * 12, rr = lane >> 2;
     const int seg = 16 * ((lane & 3) ^ dsw(rr));
     const signed char *src;
-    if (SYM) {
+    if (SAMEB) {
       const int r = (rb < 8 ? i0 + 16 * rb : j0 + 16 * (rb - 8)) + rr;
       src = digA + d * planeA + (long long)min(r, MA - 1) * kp + k0 + seg;
     } else {
@@ -518,9 +518,10 @@ __device__ __forceinline__ void dig_issue(const signed char *__restrict__ digA, 
   }
 }
 
-// SYM: the SYRK over the listed tiles (A = B, every element also stored at (j, i));
-// otherwise the tile is blockIdx.x = ti * ntj + tj
-template <bool SYM>
+// SYM: the listed tiles of a symmetric result (every element also stored at (j, i));
+// otherwise the tile is blockIdx.x = ti * ntj + tj.  SAMEB: B's planes are A's (the
+// same value then comes out for (i, j) and (j, i), so repeated stores agree).
+template <bool SYM, bool SAMEB>
 __global__ __launch_bounds__(DNT) void k_digit_mm(const signed char *__restrict__ digA, int MA,
                                                   const signed char *__restrict__ digB_, int MB_,
                                                   int kp, const int *__restrict__ expsA,
@@ -528,9 +529,9 @@ __global__ __launch_bounds__(DNT) void k_digit_mm(const signed char *__restrict_
                                                   double *C, long long ldc,
                                                   const int2 *__restrict__ tiles, int ntj) {
   __shared__ __attribute__((aligned(16))) signed char st_l[2 * DSTG];
-  // (the SYRK reads both operands from A's planes)
-  const signed char *__restrict__ digB = SYM ? digA : digB_;
-  const int MB = SYM ? MA : MB_;
+  // (a SYRK reads both operands from A's planes)
+  const signed char *__restrict__ digB = SAMEB ? digA : digB_;
+  const int MB = SAMEB ? MA : MB_;
   int2 t;
   if (SYM) {
     t = tiles[blockIdx.x];
@@ -551,11 +552,11 @@ __global__ __launch_bounds__(DNT) void k_digit_mm(const signed char *__restrict_
 #pragma unroll
       for (int b = 0; b < 2; b++) lev[l][a][b] = (i4){0, 0, 0, 0};
   const int nst = kp / DKS;
-  dig_issue<SYM>(digA, MA, digB, MB, kp, i0, j0, 0, st_l);
+  dig_issue<SAMEB>(digA, MA, digB, MB, kp, i0, j0, 0, st_l);
   for (int st = 0; st < nst; st++) {
     const signed char *S = st_l + (st & 1) * DSTG;
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (st + 1 < nst) dig_issue<SYM>(digA, MA, digB, MB, kp, i0, j0, (st + 1) * DKS, st_l + ((st + 1) & 1) * DSTG);
+    if (st + 1 < nst) dig_issue<SAMEB>(digA, MA, digB, MB, kp, i0, j0, (st + 1) * DKS, st_l + ((st + 1) & 1) * DSTG);
     // fragment of 16 rows x 64 k: lane l reads row l & 15, bytes 16 (l >> 4) ..
     i4 af[ND][2], bf[ND][2];
 #pragma unroll
@@ -607,7 +608,11 @@ __global__ __launch_bounds__(DNT) void k_digit_mm(const signed char *__restrict_
       for (int v = 0; v < 4; v++) {
         const int i = i0 + wr + a * 16 + 4 * lhi + v;
         const int j = j0 + wc + b * 16 + l15;
-        if (i < MA && j < MB) {
+        // a symmetric result from two different operands is stored from i <= j only
+        // (its (j, i) value, from the other operand order, can differ in the last
+        // bits); elements with i > j lie in diagonal blocks, with their (j, i) in the
+        // same tile
+        if (i < MA && j < MB && (SAMEB || !SYM || i <= j)) {
           double sum = 0.0;
 #pragma unroll
           for (int l = NL - 1; l >= 0; l--) sum += ldexp((double)lev[l][a][b][v], -7 * l);
@@ -622,8 +627,18 @@ hipError_t launch_syrk_digits(const void *dig, int M, int K, const int *exps, do
                               long long ldc, const int2 *tiles, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (K > DMAXK) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_digit_mm<true>, dim3(ntiles), dim3(DNT), 0, s, (const signed char *)dig, M,
-                     (const signed char *)dig, M, digit_kp(K), exps, exps, 0, C, ldc, tiles, 0);
+  hipLaunchKernelGGL((k_digit_mm<true, true>), dim3(ntiles), dim3(DNT), 0, s, (const signed char *)dig,
+                     M, (const signed char *)dig, M, digit_kp(K), exps, exps, 0, C, ldc, tiles, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_syr2_digits(const void *digA, const void *digB, int M, int K, const int *expsA,
+                              const int *expsB, double *C, long long ldc, const int2 *tiles,
+                              int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (K > DMAXK) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_digit_mm<true, false>), dim3(ntiles), dim3(DNT), 0, s, (const signed char *)digA,
+                     M, (const signed char *)digB, M, digit_kp(K), expsA, expsB, 0, C, ldc, tiles, 0);
   return hipGetLastError();
 }
 
@@ -633,7 +648,7 @@ hipError_t launch_gemm_digits(const void *digA, int MA, const void *digB, int MB
   if (MA <= 0 || MB <= 0) return hipSuccess;
   if (K > DMAXK) return hipErrorInvalidValue;
   const int nti = (MA + 127) / 128, ntj = (MB + 63) / 64;
-  hipLaunchKernelGGL(k_digit_mm<false>, dim3((unsigned)nti * ntj), dim3(DNT), 0, s,
+  hipLaunchKernelGGL((k_digit_mm<false, false>), dim3((unsigned)nti * ntj), dim3(DNT), 0, s,
                      (const signed char *)digA, MA, (const signed char *)digB, MB, digit_kp(K),
                      expsA, expsB, eadd, C, ldc, nullptr, ntj);
   return hipGetLastError();
@@ -660,6 +675,24 @@ hipError_t launch_transpose_f32(const float *X, int rows, int cols, float *Xt, h
   if (rows <= 0 || cols <= 0) return hipSuccess;
   dim3 grid((cols + 31) / 32, (rows + 31) / 32);
   hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, X, rows, cols, Xt);
+  return hipGetLastError();
+}
+
+// Y = X diag(w) for a row-major X (rows x cols)
+__global__ void k_scale_cols(const double *__restrict__ X, const double *__restrict__ w, int rows,
+                             int cols, double *__restrict__ Y) {
+  const long long n = (long long)rows * cols;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x)
+    Y[t] = X[t] * w[t % cols];
+}
+
+hipError_t launch_scale_cols(const double *X, const double *w, int rows, int cols, double *Y,
+                             hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const long long n = (long long)rows * cols;
+  const int nb = (int)std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_scale_cols, dim3(nb), dim3(256), 0, s, X, w, rows, cols, Y);
   return hipGetLastError();
 }
 

@@ -500,6 +500,10 @@ struct osv_ctx {
   float *dCt = nullptr;
   unsigned char *dDigCt = nullptr, *dDigG = nullptr;
   int *dExpCt = nullptr, *dExpG = nullptr;
+  // mixed S and F: digit planes of the rows of Q^T and of Q^T diag(eps)
+  unsigned char *dDigQr = nullptr, *dDigQe = nullptr;
+  int *dExpQr = nullptr, *dExpQe = nullptr;
+  double *dQe = nullptr;
   // mixed G^F Q^T: Q (nvir x sum r, FP64) and its digit planes and exponents
   double *dQn = nullptr;
   unsigned char *dDigQ = nullptr;
@@ -866,10 +870,20 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     if ((rc = upload(ctx, &ctx->dDiagMoff, dmoff, s))) return rc;
   }
   const bool digits = precision == OSV_MIXED && ctx->naux <= digit_max_k();
+  const bool sf_digits = precision == OSV_MIXED && ctx->nvir <= digit_max_k();
   if (digits) {
     if ((rc = dalloc(ctx, (unsigned char **)&ctx->dDig, digit_bytes(N, ctx->naux)))) return rc;
     if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
-    // 128 x 64 tiles of the digit SYRK: pairs of 64-row tiles of the tile list
+  }
+  if (sf_digits) {
+    if ((rc = dalloc(ctx, &ctx->dDigQr, digit_bytes(N, ctx->nvir)))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dDigQe, digit_bytes(N, ctx->nvir)))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExpQr, N))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExpQe, N))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dQe, (size_t)N * ctx->nvir))) return rc;
+  }
+  if (digits || sf_digits) {
+    // 128 x 64 tiles of the digit products: pairs of 64-row tiles of the tile list
     const int nt = (N + 63) / 64;
     std::vector<char> mark((size_t)((nt + 1) / 2) * nt, 0);
     std::vector<int2> dt;
@@ -887,9 +901,21 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
 
   // S and F blocks: one pass over Q^T (rows = OSVs, k = virtuals)
   StageTimer t_sf(s);
-  HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, ctx->eps, ctx->dS, ctx->dF, ld,
-                              ctx->dTiles, (int)ctx->tiles.size(), ctx->dTiles128,
-                              (int)ctx->tiles128.size(), s));
+  if (sf_digits) {
+    // mixed precision: S = Q Q^T and F = Q diag(eps) Q^T from six-digit splits of the
+    // rows of Q^T and of Q^T diag(eps), as K (below 2^-42 of each row's scale left out)
+    HIPCHK(ctx, launch_scale_cols(ctx->Q, ctx->eps, N, ctx->nvir, ctx->dQe, s));
+    HIPCHK(ctx, launch_split_digits_f64(ctx->Q, ctx->nvir, N, ctx->nvir, ctx->dExpQr, ctx->dDigQr, s));
+    HIPCHK(ctx, launch_split_digits_f64(ctx->dQe, ctx->nvir, N, ctx->nvir, ctx->dExpQe, ctx->dDigQe, s));
+    HIPCHK(ctx, launch_syrk_digits(ctx->dDigQr, N, ctx->nvir, ctx->dExpQr, ctx->dS, ld, ctx->dDigTiles,
+                                   ctx->ndig_tiles, s));
+    HIPCHK(ctx, launch_syr2_digits(ctx->dDigQr, ctx->dDigQe, N, ctx->nvir, ctx->dExpQr, ctx->dExpQe, ctx->dF,
+                                   ld, ctx->dDigTiles, ctx->ndig_tiles, s));
+  } else {
+    HIPCHK(ctx, launch_syrk_f64(ctx->Q, 0, ctx->nvir, N, ctx->nvir, ctx->eps, ctx->dS, ctx->dF, ld,
+                                ctx->dTiles, (int)ctx->tiles.size(), ctx->dTiles128,
+                                (int)ctx->tiles128.size(), s));
+  }
   t_sf.stop();
   StageTimer t_k(s);
   if (digits) {

@@ -214,6 +214,13 @@ hipError_t launch_split_digits_f64(const double *A, long long lda, int nrow, int
                                    void *dig, hipStream_t s);
 hipError_t launch_transpose_f32(const float *X, int rows, int cols, float *Xt, hipStream_t s);
 hipError_t launch_transpose_f64(const double *X, int rows, int cols, double *Xt, hipStream_t s);
+// the listed 128 x 64 tiles of a symmetric C = A B^T (both orientations stored), from
+// the digit planes of A and B (M rows each, the same K)
+hipError_t launch_syr2_digits(const void *digA, const void *digB, int M, int K, const int *expsA,
+                              const int *expsB, double *C, long long ldc, const int2 *tiles,
+                              int ntiles, hipStream_t s);
+hipError_t launch_scale_cols(const double *X, const double *w, int rows, int cols, double *Y,
+                             hipStream_t s);
 // C[i][j] = alpha * sum_k A[i][k] B[k][j]  (A row-major M x K, B row-major K x N)
 hipError_t launch_gemm_nn_f64(const double *A, long long lda, const double *B, int b_is_f32,
                               long long ldb, double *C, long long ldc, int M, int N, int K,
