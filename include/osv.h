@@ -53,9 +53,10 @@ enum {
   OSV_FP64 = 0,   /* every step in FP64 (FP64 MFMA)                                      */
   OSV_MIXED = 1   /* K_ij from FP32 C split into exact int8 digits (per-row power-of-two */
                   /* scale) on int8 MFMA with exact int32 accumulation, combined in      */
-                  /* FP64; dE/dC = 2 G^K C and G^F Q^T likewise from six-digit splits   */
-                  /* of their rows; FP64 elsewhere.  Needs C_dtype = FP32; above naux   */
-                  /* = 87000 (int32 range) K, and above sum r = 87000 the products, FP64. */
+                  /* FP64; S, F, dE/dC = 2 G^K C and G^F Q^T likewise from six-digit    */
+                  /* splits of their operands' rows; FP64 elsewhere.  Needs C_dtype =   */
+                  /* FP32; a product whose contraction exceeds 87000 (int32 range) is   */
+                  /* computed in FP64.                                                  */
 };
 
 /* cluster selection */
