@@ -64,6 +64,7 @@ __device__ __forceinline__ void adj_issue(const double *T, long long toff, int n
 //   G^F_d = W g' W^T   (g' = g + g^T for p < q, g for p = q)  -> Gd slot
 //   G^K_pq = Y_p^T (2 A_d) Y_q                                  -> GK block (and transpose)
 __global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms,
+                                                 const int *__restrict__ order,
                                                  const int *__restrict__ rank,
                                                  const double *__restrict__ W,
                                                  const double *__restrict__ Y,
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms
                                                  double *GK, long long ld, double *Gd) {
   __shared__ __attribute__((aligned(16))) double buf[2 * DMAX * ALD];
   double *L1 = buf, *L2 = buf + DMAX * ALD;
-  const int d = blockIdx.x;
+  const int d = order[blockIdx.x];   // domains in order of cost, largest first
   const Domain D = doms[d];
   const int n = D.n, np = D.np, dt = rank[d];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -320,12 +321,12 @@ __global__ __launch_bounds__(ANT) void k_adjoint(const Domain *__restrict__ doms
   }
 }
 
-hipError_t launch_adjoint(const Domain *dom, int ndom, const int *rank, const double *W,
+hipError_t launch_adjoint(const Domain *dom, int ndom, const int *order, const int *rank, const double *W,
                           const double *Y, const double *T, const long long *dcp_ptr,
                           const long long *dcp_toff, const double *dcp_coef, double *GK,
                           long long ld, double *Gd, hipStream_t s) {
   if (ndom <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adjoint, dim3(ndom), dim3(ANT), 0, s, dom, rank, W, Y, T, dcp_ptr,
+  hipLaunchKernelGGL(k_adjoint, dim3(ndom), dim3(ANT), 0, s, dom, order, rank, W, Y, T, dcp_ptr,
                      dcp_toff, dcp_coef, GK, ld, Gd);
   return hipGetLastError();
 }

@@ -21,12 +21,13 @@ namespace osv {
 constexpr int HNT = 256;           // threads per domain of the collective sums
 
 __global__ __launch_bounds__(HNT) void k_collective(const Domain *__restrict__ doms,
+                                                   const int *__restrict__ order,
                                                     const long long *__restrict__ ptr,
                                                     const long long *__restrict__ toff,
                                                     const double *__restrict__ coef,
                                                     const double *__restrict__ T,
                                                     const long long *__restrict__ coff, double *Tc) {
-  const int d = blockIdx.x;
+  const int d = order[blockIdx.x];   // domains in order of cost, largest first
   const int np = doms[d].np;
   const long long n2 = 2LL * np * np;
   double *out = Tc + coff[d];
@@ -48,11 +49,12 @@ __global__ __launch_bounds__(HNT) void k_collective(const Domain *__restrict__ d
   }
 }
 
-hipError_t launch_collective(const Domain *dom, int ndom, const long long *ptr, const long long *toff,
+hipError_t launch_collective(const Domain *dom, int ndom, const int *order, const long long *ptr,
+                             const long long *toff,
                              const double *coef, const double *T, const long long *coff, double *Tc,
                              hipStream_t s) {
   if (ndom <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_collective, dim3(ndom), dim3(HNT), 0, s, dom, ptr, toff, coef, T, coff, Tc);
+  hipLaunchKernelGGL(k_collective, dim3(ndom), dim3(HNT), 0, s, dom, order, ptr, toff, coef, T, coff, Tc);
   return hipGetLastError();
 }
 

@@ -448,6 +448,7 @@ struct DensHost {
   std::vector<double> cf;
   std::vector<int2> blocks;
   std::vector<int> bdom, bpart;
+  std::vector<int> adj_order;   // domains by adjoint cost (entries x np^3), largest first
 };
 
 struct osv_ctx {
@@ -517,6 +518,7 @@ struct osv_ctx {
   double *dGK = nullptr, *dGF = nullptr, *dGd = nullptr, *dZt = nullptr, *dDcoef = nullptr;
   double *dColPart = nullptr;  // partial column sums of dE/deps
   double *dClcoef = nullptr;
+  int *dAdjOrder = nullptr;
   long long *dDptr = nullptr, *dDtoff = nullptr, *dBptr = nullptr, *dPptr = nullptr, *dPidx = nullptr;
   int *dBdom = nullptr, *dBpart = nullptr;
   int2 *dBlocks = nullptr;
@@ -1577,6 +1579,20 @@ static void densities_host(osv_ctx *ctx) {
     for (int c = C.cp0; c < C.cp0 + C.ncp; c++) H.ptr[P.cps[c].dom + 1]++;
   }
   for (int d = 0; d < ndom; d++) H.ptr[d + 1] += H.ptr[d];
+  // launch order of the adjoint: a diagonal domain is held by hundreds of clusters
+  // and costs up to 100 times the mean, so the costly ones go first and the many
+  // short ones fill the CUs around them
+  {
+    std::vector<double> cost(ndom);
+    for (int d = 0; d < ndom; d++) {
+      const double np = P.doms[d].np;
+      cost[d] = (double)(H.ptr[d + 1] - H.ptr[d]) * np * np * np;
+    }
+    H.adj_order.resize(ndom);
+    std::iota(H.adj_order.begin(), H.adj_order.end(), 0);
+    std::stable_sort(H.adj_order.begin(), H.adj_order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
+  }
   H.toff.assign(H.ptr[ndom], 0);
   H.cf.assign(H.ptr[ndom], 0.0);
   {
@@ -1654,6 +1670,7 @@ static int upload_density_tables(osv_ctx *ctx, hipStream_t s) {
   ctx->nblocks = (int)H.blocks.size();
   std::vector<Up> ups;
   add_up(ups, &ctx->dDptr, H.ptr);
+  add_up(ups, &ctx->dAdjOrder, H.adj_order);
   add_up(ups, &ctx->dDtoff, H.toff);
   add_up(ups, &ctx->dDcoef, H.cf);
   add_up(ups, &ctx->dBlocks, H.blocks);
@@ -2230,7 +2247,7 @@ int osv_high_order_correction(osv_ctx *ctx, hipStream_t s, double *dE, double *E
   Plan &P = ctx->plan;
   const int ndom = (int)P.doms.size();
   StageTimer t_col(s);
-  HIPCHK(ctx, launch_collective(ctx->dDom, ndom, ctx->dDptr, ctx->dDtoff, ctx->dDcoef, ctx->dT, ctx->dCoff,
+  HIPCHK(ctx, launch_collective(ctx->dDom, ndom, ctx->dAdjOrder, ctx->dDptr, ctx->dDtoff, ctx->dDcoef, ctx->dT, ctx->dCoff,
                                 ctx->dTc, s));
   t_col.stop();
   StageTimer t_step(s);
@@ -2282,7 +2299,7 @@ int osv_densities(osv_ctx *ctx, hipStream_t s, double *dE_dC, double *dE_dFocc, 
   const int ndom = (int)P.doms.size(), N = ctx->nosv;
   const long long ld = N;
   StageTimer t_adj(s);
-  HIPCHK(ctx, launch_adjoint(ctx->dDom, ndom, ctx->dRank, ctx->dW, ctx->dY, ctx->dT, ctx->dDptr, ctx->dDtoff,
+  HIPCHK(ctx, launch_adjoint(ctx->dDom, ndom, ctx->dAdjOrder, ctx->dRank, ctx->dW, ctx->dY, ctx->dT, ctx->dDptr, ctx->dDtoff,
                              ctx->dDcoef, ctx->dGK, ld, ctx->dGd, s));
   HIPCHK(ctx, launch_assemble_gf(ctx->dDom, ctx->dBptr, ctx->dBdom, ctx->dBpart, ctx->dBlocks, ctx->nblocks,
                                  ctx->dOff, ctx->dR, ctx->dGd, ctx->dGF, ld, s));

@@ -275,7 +275,7 @@ hipError_t launch_check_finite_f32(const float *x, long long n, int *flag, hipSt
 hipError_t launch_wdot(const double *x, const double *w, long long n, int nw, double *out,
                        hipStream_t s);
 // adjoint per domain: G^K blocks into GK (ld), virtual density in OSV basis into Gd
-hipError_t launch_adjoint(const Domain *dom, int ndom, const int *rank, const double *W,
+hipError_t launch_adjoint(const Domain *dom, int ndom, const int *order, const int *rank, const double *W,
                           const double *Y, const double *T, const long long *dcp_ptr,
                           const long long *dcp_toff, const double *dcp_coef, double *GK,
                           long long ld, double *Gd, hipStream_t s);
@@ -314,7 +314,7 @@ hipError_t launch_osv_vectors(const double *T, int nocc, int n, int r_max, const
 // one-step high-order correction: collective amplitudes per domain (slots of
 // 2 np^2 at coff[d], both orientations), then per domain the residual at them,
 // one Jacobi step and out[3 d ..] = (dE_d, E_d, ||R~_d||_F^2)
-hipError_t launch_collective(const Domain *dom, int ndom, const long long *ptr, const long long *toff,
+hipError_t launch_collective(const Domain *dom, int ndom, const int *order, const long long *ptr, const long long *toff,
                              const double *coef, const double *T, const long long *coff, double *Tc,
                              hipStream_t s);
 // (persistent: nwg workgroups take the domains in queue order; scr holds
