@@ -858,7 +858,8 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     std::vector<int> ids;
     std::vector<long long> dmoff((size_t)nocc, -1);
     for (int g = 0; g < 2; g++)
-      for (int c = 0; c < 4; c++)
+      for (int c = 0; c < 4; c++) {
+        const size_t b = ids.size();
         for (int d = 0; d < ndom; d++) {
           const Domain &D = P.doms[d];
           const int n = D.n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : (n <= PREP_N3 ? 2 : 3));
@@ -868,6 +869,15 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
             if (g == 0) dmoff[D.p] = D.moff;
           }
         }
+        // the largest domains of the class first (the cost grows as n^3): a
+        // counting sort by n, descending, stable
+        {
+          std::vector<int> cnt(DMAX + 2, 0), tmp(ids.begin() + b, ids.end());
+          for (int d : tmp) cnt[DMAX - P.doms[d].n + 1]++;
+          for (int k = 1; k <= DMAX + 1; k++) cnt[k] += cnt[k - 1];
+          for (int d : tmp) ids[b + cnt[DMAX - P.doms[d].n]++] = d;
+        }
+      }
     if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
     if ((rc = upload(ctx, &ctx->dDiagMoff, dmoff, s))) return rc;
   }
