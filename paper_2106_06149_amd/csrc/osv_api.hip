@@ -196,11 +196,12 @@ int build_domains(int nocc, const Selection &s, const int *r, const int *off, Pl
   return OSV_OK;
 }
 
-// Runs f(i) for i in [0, n) on up to 16 host threads, in contiguous ranges.
+// Runs f(i) for i in [0, n) on up to 16 host threads (at most one per `grain`
+// items), in contiguous ranges.
 template <class F>
-void parallel_for(long long n, F f) {
+void parallel_for(long long n, F f, long long grain = 2048) {
   const unsigned hc = std::thread::hardware_concurrency();
-  const int nt = (int)std::max<long long>(1, std::min<long long>({16, hc ? (long long)hc : 1, n / 2048 + 1}));
+  const int nt = (int)std::max<long long>(1, std::min<long long>({16, hc ? (long long)hc : 1, (n + grain - 1) / grain}));
   if (nt == 1) {
     for (long long i = 0; i < n; i++) f(i);
     return;
@@ -657,7 +658,19 @@ int upload_batch(osv_ctx *ctx, const std::vector<Up> &ups, hipStream_t s) {
   size_t o = 0;
   for (const Up &u : ups) {
     if (u.bytes) {
-      std::memcpy(st->p + o, u.src, u.bytes);
+      // into pinned memory in 4 MB pieces on the host threads (about 150 MB of
+      // plan tables at nocc = 400), then the table's copy to the device
+      constexpr size_t PIECE = (size_t)4 << 20;
+      const size_t np = (u.bytes + PIECE - 1) / PIECE;
+      char *dst = st->p + o;
+      const char *src = static_cast<const char *>(u.src);
+      parallel_for(
+          (long long)np,
+          [&](long long k) {
+            const size_t b = (size_t)k * PIECE, e = std::min(u.bytes, b + PIECE);
+            std::memcpy(dst + b, src + b, e - b);
+          },
+          1);
       HIPCHK(ctx, hipMemcpyAsync(*u.dst, st->p + o, u.bytes, hipMemcpyHostToDevice, s));
     }
     o += (u.bytes + 255) & ~(size_t)255;
