@@ -18,8 +18,8 @@
 // method with a round-robin ordering: n/2 disjoint rotations per step, applied
 // to both sides of A as independent 2x2 block updates.  The Fock eigenproblem of
 // an off-diagonal domain first gets an approximate eigenbasis (Householder
-// reduction, bisection, twisted-factorisation eigenvectors), so that one Jacobi
-// sweep finishes it.
+// reduction, bisection, twisted-factorisation eigenvectors), which one
+// first-order step (or, failing its test, the Jacobi sweeps) finishes.
 #include "osv_internal.h"
 #include "tiles.h"
 
@@ -268,7 +268,7 @@ __device__ __forceinline__ double recip(double x) {
 // Starting basis for the Fock eigensolve of an off-diagonal domain.  The cyclic
 // Jacobi method converges quadratically once the off-diagonal part is small, so
 // an approximate eigenbasis V1 (orthonormal to rounding) leaves it one sweep
-// instead of five to eight.  V1 is formed in four steps, all in LDS:
+// instead of five to eight, and in practice a single first-order step.  V1 is formed in four steps, all in LDS:
 //   1. Householder reduction H = Q T Q^T (T tridiagonal): every wave forms the
 //      reflector of column c from row c (the same arithmetic in every wave), the
 //      product p = tau A22 v goes to row 0 of Z, then A22 -= v w^T + w v^T with
@@ -738,7 +738,9 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
     form_h();
     // approximate eigenbasis V1 of H: X <- X V1 (V1 = V0 (3/2 - G/2) through the W
     // slot, not yet written) and H formed again, nearly diagonal
+    bool started = false;
     if (dt == n && n >= FOCK_START_MIN && fock_start<LD, NT>(L1, L2, n)) {
+      started = true;
       mma_tiles<NT>(n, n, n, [&](int i, int k) { return L2[i * LD + k]; },
                     [&](int k, int j) { return L1[k * LD + j]; },
                     [&](int i, int j, double v) { Wg[i * n + j] = v; });
@@ -757,7 +759,31 @@ __global__ __launch_bounds__(NT) void k_domain_prep(const Domain *__restrict__ d
       warm_start();
       if ((dt == n && n >= FOCK_START_MIN) || (mp >= 0 && mq >= 0)) form_h();   // H overwritten, or X changed
     }
-    jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, rt, red, &s_flag);
+    // From the approximate eigenbasis the off-diagonal elements a_pq of H are of
+    // the order of 1e-14 ||H||: one first-order step finishes the eigenproblem,
+    // V = 1 + E, E_pq = a_pq / (a_qq - a_pp), eigenvalues a_pp.  E is exactly
+    // antisymmetric (H is symmetrised), so V^T V = 1 + E^T E, and what the step
+    // leaves out is of order |E|^2, below rounding when every |a_pq| <= 1e-8
+    // |a_qq - a_pp|; otherwise (or without the approximate basis) the Jacobi
+    // sweeps run.
+    bool finished = false;
+    if (started) {
+      bool bad = false;
+      for (int e = tid; e < n * n; e += NT) {
+        const int i = e / n, j = e - i * n;
+        if (i != j) bad = bad || !(fabs(L1[i * LD + j]) <= 1e-8 * fabs(L1[j * LD + j] - L1[i * LD + i]));
+      }
+      if (!__syncthreads_or(bad)) {
+        for (int e = tid; e < n * n; e += NT) {
+          const int i = e / n, j = e - i * n;
+          const double a = L1[i * LD + j];
+          L2[i * LD + j] = (i == j) ? 1.0 : (a == 0.0 ? 0.0 : a / (L1[j * LD + j] - L1[i * LD + i]));
+        }
+        __syncthreads();
+        finished = true;
+      }
+    }
+    if (!finished) jacobi_eig<LD, NT, MAXB, MAXV>(L1, L2, dt, rt, red, &s_flag);
     for (int a = tid; a < np; a += NT) eg[a] = (a < dt) ? L1[a * LD + a] : 0.0;
     __syncthreads();
     // W = X V (n x dt) into L1, then to global
