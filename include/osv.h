@@ -411,7 +411,7 @@ int64_t osv_cached_bytes(int32_t device);
  * process-wide table, read once from $OSV_TUNING_FILE, else from osv_tuning.txt
  * beside the library (written by the package's autotuner; "key value" lines), else
  * left at its defaults.  Keys and allowed values:
- *   gemm_ks          8, 16, 32      k per LDS stage of the FP64 tile GEMM (S/F, K, dE/dC)
+ *   gemm_ks          8, 16, 32      k per LDS stage of the FP64 tile GEMM (S/F, K, dE/dC in FP64 mode)
  *   prep_nt_small    128, 256       threads per pair domain of n <= 32 in the preparation
  *   prep_nt_mid      256, 512, 1024 the same for 32 < n <= 64
  *   prep_nt_big      512, 1024      the same for n > 70 (64 < n <= 70: 512, fixed)

@@ -22,7 +22,7 @@ DEFAULT_OUT = os.path.join(HERE, "osv_tuning.txt")
 
 # the stages (osv_stage_times names) whose device time each key changes
 STAGES = {
-    "gemm_ks": ("sf", "k", "backtransform"),
+    "gemm_ks": ("sf", "k", "backtransform"),   # FP64 products (mixed mode: digit products)
     "prep_nt_small": ("prep",),
     "prep_nt_mid": ("prep",),
     "prep_nt_big": ("prep",),
