@@ -277,10 +277,11 @@ __device__ __forceinline__ double recip(double x) {
 //      Reflector c is then kept in row c right of the superdiagonal (leading 1
 //      implicit) and tau_c in the spare column LD - 1 of A; d and e stay on the
 //      diagonal and superdiagonal;
-//   2. every eigenvalue of T by bisection on Sturm counts, one team of 8 lanes per
-//      eigenvalue testing 8 points at a time (nine-section, 14 rounds: the width
-//      shrinks by 9^14 = 2.3e13; 4 lanes and 20 rounds of five-section when the
-//      workgroup has fewer than n teams of 8), kept in the spare column of Z;
+//   2. every eigenvalue of T by multisection on Sturm counts, one team of 4 lanes
+//      per eigenvalue testing 4 points at a time (five-section, 20 rounds: the width
+//      shrinks by 5^20 = 9.5e13), kept in the spare column of Z.  A count is the
+//      number of sign changes of the leading principal minors of T - x (one fused
+//      multiply-add per step on the serial path, no division);
 //   3. each eigenvector of T from a twisted factorisation T - lambda = N_r D_r N_r^T
 //      (Dhillon and Parlett, LAA 387 (2004) 1-28), one thread per vector: the
 //      stationary LDL^T pivots D+ forward, the UDU^T pivots D- backward, the twist
@@ -400,47 +401,68 @@ __device__ bool fock_start(double *A, double *Z, int n) {
   // Gerschgorin interval, ||T||_1 and the largest e^2 (every thread, same order)
   auto dg = [&](int i) { return A[i * LD + i]; };
   auto ev = [&](int i) { return A[i * LD + i + 1]; };
-  double lo = 1e300, hi = -1e300, tn = 0.0, emax = 0.0;
+  double lo = 1e300, hi = -1e300, tn = 0.0;
   for (int i = 0; i < n; i++) {
     const double el = i > 0 ? fabs(ev(i - 1)) : 0.0, er = i + 1 < n ? fabs(ev(i)) : 0.0;
     lo = fmin(lo, dg(i) - el - er);
     hi = fmax(hi, dg(i) + el + er);
     tn = fmax(tn, fabs(dg(i)) + el + er);
-    if (i + 1 < n) emax = fmax(emax, ev(i) * ev(i));
   }
   const double span = fmax(fabs(lo), fabs(hi));
   lo -= 2.2e-16 * span + 1e-300;
   hi += 2.2e-16 * span + 1e-300;
-  const double piv = 2.3e-308 * fmax(1.0, emax), pfloor = 2.2e-16 * fmax(tn, 1e-300);
+  const double pfloor = 2.2e-16 * fmax(tn, 1e-300);
   // 2. eigenvalues (ascending): the BL lanes of a team test a + (l + 1) h,
-  //    h = (b - a) / (BL + 1); 8 lanes and 14 rounds when NT / 8 teams cover every
-  //    eigenvalue, else 4 lanes and 20 rounds (5^20 = 9.5e13)
+  //    h = (b - a) / (BL + 1).  The number of eigenvalues below x is the number of
+  //    sign changes in p_(-1) = 1, p_0, .., p_(n-1), the leading principal minors
+  //    of T - x: p_i = (d_i - x) p_(i-1) - e_(i-1)^2 p_(i-2).  An isolated zero
+  //    minor differs in sign from one of its neighbours and so is counted once;
+  //    e^2 is kept at least 2^-400 (of the scaled norm) so that zeros stay isolated.
+  //    T is scaled by the power of two 2^-E that brings ||T||_1 into [1/2, 1), and
+  //    the two latest minors are rescaled by a power of two every 8 steps (the
+  //    minors grow by at most 4 per step).  d and e^2 go to rows 0 and 1 of Z.
   {
-    constexpr int BL = (NT / 8 >= LD - 1) ? 8 : 4, ROUNDS = BL == 8 ? 14 : 20;
+    constexpr int BL = 4, ROUNDS = 20;
+    int E;
+    (void)frexp(fmax(tn, 1e-300), &E);
+    for (int i = tid; i < n; i += NT) {
+      Z[i] = ldexp(dg(i), -E);
+      const double es = i > 0 ? ldexp(ev(i - 1), -E) : 0.0;
+      Z[LD + i] = fmax(es * es, 0x1p-400);
+    }
+    __syncthreads();
+    const double los = ldexp(lo, -E), his = ldexp(hi, -E);
     constexpr double RB = 1.0 / (BL + 1);
     const int bt = tid / BL, bl = tid % BL;
     for (int k = bt; k < n; k += NT / BL) {
-      double a = lo, b = hi;
+      double a = los, b = his;
       for (int rd = 0; rd < ROUNDS; rd++) {
         const double h = (b - a) * RB, xq = a + (bl + 1) * h;
-        int cnt = 0;
-        double q = dg(0) - xq;
-        if (fabs(q) < piv) q = -piv;
-        cnt += q < 0.0;
-#pragma unroll 4
-        for (int i = 1; i < n; i++) {
-          const double ei = ev(i - 1);
-          q = dg(i) - xq - ei * ei * recip(q);
-          if (fabs(q) < piv) q = -piv;
-          cnt += q < 0.0;
+        double pm = 1.0, pc = Z[0] - xq;
+        unsigned cnt = (unsigned)__double2hiint(pc) >> 31;
+        auto step = [&](int i) {
+          const double pn = fma(Z[i] - xq, pc, -Z[LD + i] * pm);
+          cnt += ((unsigned)__double2hiint(pn) ^ (unsigned)__double2hiint(pc)) >> 31;
+          pm = pc;
+          pc = pn;
+        };
+        int i = 1;
+        for (; i + 7 < n; i += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; u++) step(i + u);
+          int ep;
+          (void)frexp(fmax(fabs(pc), fabs(pm)), &ep);
+          pc = ldexp(pc, -ep);
+          pm = ldexp(pm, -ep);
         }
-        const unsigned long long bal = __ballot(cnt > k);
+        for (; i < n; i++) step(i);
+        const unsigned long long bal = __ballot((int)cnt > k);
         const int j = BL - __popcll((bal >> (lane & (64 - BL))) & ((1ull << BL) - 1));   // points below lambda_k
         const double na = a + j * h, nb = j < BL ? a + (j + 1) * h : b;
         a = na;
         b = nb;
       }
-      if (bl == 0) Z[k * LD + LD - 1] = 0.5 * (a + b);
+      if (bl == 0) Z[k * LD + LD - 1] = ldexp(0.5 * (a + b), E);
     }
   }
   __syncthreads();
