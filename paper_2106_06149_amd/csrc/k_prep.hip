@@ -420,7 +420,7 @@ __device__ bool fock_start(double *A, double *Z, int n) {
   //    e^2 is kept at least 2^-400 (of the scaled norm) so that zeros stay isolated.
   //    T is scaled by the power of two 2^-E that brings ||T||_1 into [1/2, 1), and
   //    the two latest minors are rescaled by a power of two every 8 steps (the
-  //    minors grow by at most 4 per step).  d and e^2 go to rows 0 and 1 of Z.
+  //    minors grow by at most a factor 3 per step).  d and e^2 go to rows 0 and 1 of Z.
   {
     constexpr int BL = 4, ROUNDS = 20;
     int E;
