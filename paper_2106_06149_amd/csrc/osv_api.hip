@@ -90,6 +90,11 @@ void select_mbe(int nocc, K2 keep2, K3 keep3, N3 near3, Selection &s) {
   s.lmo.clear();
   s.coef.clear();
   s.order.clear();
+  const size_t ncl = (size_t)nocc + pairs.size() + triples.size();
+  s.lmo_ptr.reserve(ncl + 1);
+  s.lmo.reserve((size_t)nocc + 2 * pairs.size() + 3 * triples.size());
+  s.coef.reserve(ncl);
+  s.order.reserve(ncl);
   for (int i = 0; i < nocc; i++) {
     s.lmo.push_back(i);
     s.lmo_ptr.push_back((int)s.lmo.size());
@@ -764,7 +769,8 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   const long long ld = N;
   int rc;
 
-  // input checks on the device (NaN / Inf)
+  // input checks on the device (NaN / Inf); the flag is read once the host has
+  // selected the clusters
   if ((rc = dalloc(ctx, &ctx->dFlag, 4))) return rc;
   HIPCHK(ctx, launch_fill_i32(ctx->dFlag, 0, 4, s));
   HIPCHK(ctx, launch_check_finite(ctx->Q, (long long)ctx->nvir * N, ctx->dFlag, s));
@@ -774,18 +780,37 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
     HIPCHK(ctx, launch_check_finite((const double *)ctx->C, (long long)N * ctx->naux, ctx->dFlag, s));
   HIPCHK(ctx, launch_check_finite(ctx->eps, ctx->nvir, ctx->dFlag, s));
   HIPCHK(ctx, launch_check_finite(ctx->F, (long long)nocc * nocc, ctx->dFlag, s));
-  int flag = 0;
-  HIPCHK(ctx, hipMemcpyAsync(&flag, ctx->dFlag, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  if (flag) {
-    return fail(ctx, OSV_E_NONFINITE, "NaN or Inf in Q, C, eps_vir or F_occ");
-  }
 
   if ((rc = dalloc(ctx, &ctx->dS, (size_t)ld * ld))) return rc;
   if ((rc = dalloc(ctx, &ctx->dF, (size_t)ld * ld))) return rc;
   if ((rc = dalloc(ctx, &ctx->dK, (size_t)ld * ld))) return rc;
   if ((rc = upload(ctx, &ctx->dOff, ctx->off, s))) return rc;
   if ((rc = upload(ctx, &ctx->dR, ctx->r, s))) return rc;
+  // mixed precision: the digit splits of the rows of Q^T, Q^T diag(eps) and C do
+  // not depend on the selection and run while the host selects
+  const bool digits = precision == OSV_MIXED && ctx->naux <= digit_max_k();
+  const bool sf_digits = precision == OSV_MIXED && ctx->nvir <= digit_max_k();
+  if (digits) {
+    if ((rc = dalloc(ctx, (unsigned char **)&ctx->dDig, digit_bytes(N, ctx->naux)))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
+  }
+  if (sf_digits) {
+    if ((rc = dalloc(ctx, &ctx->dDigQr, digit_bytes(N, ctx->nvir)))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dDigQe, digit_bytes(N, ctx->nvir)))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExpQr, N))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dExpQe, N))) return rc;
+    if ((rc = dalloc(ctx, &ctx->dQe, (size_t)N * ctx->nvir))) return rc;
+  }
+  StageTimer t_sf_split(s);
+  if (sf_digits) {
+    HIPCHK(ctx, launch_scale_cols(ctx->Q, ctx->eps, N, ctx->nvir, ctx->dQe, s));
+    HIPCHK(ctx, launch_split_digits_f64(ctx->Q, ctx->nvir, N, ctx->nvir, ctx->dExpQr, ctx->dDigQr, s));
+    HIPCHK(ctx, launch_split_digits_f64(ctx->dQe, ctx->nvir, N, ctx->nvir, ctx->dExpQe, ctx->dDigQe, s));
+  }
+  t_sf_split.stop();
+  StageTimer t_k_split(s);
+  if (digits) HIPCHK(ctx, launch_split_digits((const float *)ctx->C, N, ctx->naux, ctx->dExps, ctx->dDig, s));
+  t_k_split.stop();
 
   const auto h0 = std::chrono::steady_clock::now();
   // cluster selection
@@ -818,6 +843,12 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
         const double v = s2b(i, j);
         if (v >= OSV_WEAK_MIN && !(v > sel->l2b)) ctx->weak.push_back(make_int2(i, j));
       }
+  }
+  {
+    int flag = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&flag, ctx->dFlag, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (flag) return fail(ctx, OSV_E_NONFINITE, "NaN or Inf in Q, C, eps_vir or F_occ");
   }
   {
     std::string err;
@@ -868,44 +899,24 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   // and (q, q)
   int prep_cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
-    std::vector<int> ids;
+    // one stable counting sort by (group g, class, DMAX - n): within a class the
+    // largest domains come first (the cost grows as n^3)
+    constexpr int NKEY = 8 * (DMAX + 1);
+    std::vector<int> cnt(NKEY + 1, 0), key((size_t)ndom), ids((size_t)ndom);
     std::vector<long long> dmoff((size_t)nocc, -1);
-    for (int g = 0; g < 2; g++)
-      for (int c = 0; c < 4; c++) {
-        const size_t b = ids.size();
-        for (int d = 0; d < ndom; d++) {
-          const Domain &D = P.doms[d];
-          const int n = D.n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : (n <= PREP_N3 ? 2 : 3));
-          if (cls == c && (D.p == D.q) == (g == 0)) {
-            ids.push_back(d);
-            prep_cnt[4 * g + c]++;
-            if (g == 0) dmoff[D.p] = D.moff;
-          }
-        }
-        // the largest domains of the class first (the cost grows as n^3): a
-        // counting sort by n, descending, stable
-        {
-          std::vector<int> cnt(DMAX + 2, 0), tmp(ids.begin() + b, ids.end());
-          for (int d : tmp) cnt[DMAX - P.doms[d].n + 1]++;
-          for (int k = 1; k <= DMAX + 1; k++) cnt[k] += cnt[k - 1];
-          for (int d : tmp) ids[b + cnt[DMAX - P.doms[d].n]++] = d;
-        }
-      }
+    for (int d = 0; d < ndom; d++) {
+      const Domain &D = P.doms[d];
+      const int n = D.n, cls = n <= 32 ? 0 : (n <= 64 ? 1 : (n <= PREP_N3 ? 2 : 3));
+      const int g = D.p == D.q ? 0 : 1;
+      key[d] = (4 * g + cls) * (DMAX + 1) + (DMAX - n);
+      cnt[key[d] + 1]++;
+      prep_cnt[4 * g + cls]++;
+      if (g == 0) dmoff[D.p] = D.moff;
+    }
+    for (int k = 0; k < NKEY; k++) cnt[k + 1] += cnt[k];
+    for (int d = 0; d < ndom; d++) ids[cnt[key[d]]++] = d;
     if ((rc = upload(ctx, &ctx->dPrepIds, ids, s))) return rc;
     if ((rc = upload(ctx, &ctx->dDiagMoff, dmoff, s))) return rc;
-  }
-  const bool digits = precision == OSV_MIXED && ctx->naux <= digit_max_k();
-  const bool sf_digits = precision == OSV_MIXED && ctx->nvir <= digit_max_k();
-  if (digits) {
-    if ((rc = dalloc(ctx, (unsigned char **)&ctx->dDig, digit_bytes(N, ctx->naux)))) return rc;
-    if ((rc = dalloc(ctx, &ctx->dExps, N))) return rc;
-  }
-  if (sf_digits) {
-    if ((rc = dalloc(ctx, &ctx->dDigQr, digit_bytes(N, ctx->nvir)))) return rc;
-    if ((rc = dalloc(ctx, &ctx->dDigQe, digit_bytes(N, ctx->nvir)))) return rc;
-    if ((rc = dalloc(ctx, &ctx->dExpQr, N))) return rc;
-    if ((rc = dalloc(ctx, &ctx->dExpQe, N))) return rc;
-    if ((rc = dalloc(ctx, &ctx->dQe, (size_t)N * ctx->nvir))) return rc;
   }
   if (digits || sf_digits) {
     // 128 x 64 tiles of the digit products: pairs of 64-row tiles of the tile list
@@ -927,11 +938,9 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   // S and F blocks: one pass over Q^T (rows = OSVs, k = virtuals)
   StageTimer t_sf(s);
   if (sf_digits) {
-    // mixed precision: S = Q Q^T and F = Q diag(eps) Q^T from six-digit splits of the
-    // rows of Q^T and of Q^T diag(eps), as K (below 2^-42 of each row's scale left out)
-    HIPCHK(ctx, launch_scale_cols(ctx->Q, ctx->eps, N, ctx->nvir, ctx->dQe, s));
-    HIPCHK(ctx, launch_split_digits_f64(ctx->Q, ctx->nvir, N, ctx->nvir, ctx->dExpQr, ctx->dDigQr, s));
-    HIPCHK(ctx, launch_split_digits_f64(ctx->dQe, ctx->nvir, N, ctx->nvir, ctx->dExpQe, ctx->dDigQe, s));
+    // mixed precision: S = Q Q^T and F = Q diag(eps) Q^T from the six-digit splits of
+    // the rows of Q^T and of Q^T diag(eps) made above, as K (below 2^-42 of each
+    // row's scale left out)
     HIPCHK(ctx, launch_syrk_digits(ctx->dDigQr, N, ctx->nvir, ctx->dExpQr, ctx->dS, ld, ctx->dDigTiles,
                                    ctx->ndig_tiles, s));
     HIPCHK(ctx, launch_syr2_digits(ctx->dDigQr, ctx->dDigQe, N, ctx->nvir, ctx->dExpQr, ctx->dExpQe, ctx->dF,
@@ -944,7 +953,6 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
   t_sf.stop();
   StageTimer t_k(s);
   if (digits) {
-    HIPCHK(ctx, launch_split_digits((const float *)ctx->C, N, ctx->naux, ctx->dExps, ctx->dDig, s));
     HIPCHK(ctx, launch_syrk_digits(ctx->dDig, N, ctx->naux, ctx->dExps, ctx->dK, ld, ctx->dDigTiles,
                                    ctx->ndig_tiles, s));
   } else {
@@ -1063,8 +1071,8 @@ static int build_impl(osv_ctx *ctx, const osv_system *sys, const osv_select *sel
       return fail(ctx, OSV_E_DOMAIN, "pair domain (" + std::to_string(P.doms[d].p) + "," +
                                          std::to_string(P.doms[d].q) + ") has rank 0 after the tau_S cut");
     }
-  ctx->stage_ms[0] = t_sf.ms();
-  ctx->stage_ms[1] = t_k.ms();
+  ctx->stage_ms[0] = t_sf_split.ms() + t_sf.ms();
+  ctx->stage_ms[1] = t_k_split.ms() + t_k.ms();
   ctx->stage_ms[2] = t_prep.ms();
   ctx->stage_ms[3] = t_cpl.ms();
   return OSV_OK;
