@@ -332,8 +332,10 @@ __device__ bool fock_start(double *A, double *Z, int n) {
     double t = 0.0, beta = alpha, sc = 0.0;
     if (ss != 0.0) {
       beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      t = (beta - alpha) / beta;
-      sc = 1.0 / (alpha - beta);
+      // |beta| >= sqrt(ss) and |alpha - beta| >= |beta| are normal: the
+      // reciprocal estimate and one Newton step, off the serial path's divisions
+      t = (beta - alpha) * recip(beta);
+      sc = recip(alpha - beta);
     }
     pc = c;
     pbeta = beta;
