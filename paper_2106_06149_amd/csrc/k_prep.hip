@@ -403,12 +403,35 @@ __device__ bool fock_start(double *A, double *Z, int n) {
   // Gerschgorin interval, ||T||_1 and the largest e^2 (every thread, same order)
   auto dg = [&](int i) { return A[i * LD + i]; };
   auto ev = [&](int i) { return A[i * LD + i + 1]; };
+  // (a thread per row, then the block's min and max, which are exact in any
+  // order; the wave partials go to row 2 of Z, left of its spare column)
   double lo = 1e300, hi = -1e300, tn = 0.0;
-  for (int i = 0; i < n; i++) {
+  for (int i = tid; i < n; i += NT) {
     const double el = i > 0 ? fabs(ev(i - 1)) : 0.0, er = i + 1 < n ? fabs(ev(i)) : 0.0;
     lo = fmin(lo, dg(i) - el - er);
     hi = fmax(hi, dg(i) + el + er);
     tn = fmax(tn, fabs(dg(i)) + el + er);
+  }
+  {
+    constexpr int NW = NT / 64;
+    static_assert(3 * NW < LD - 1, "partials left of the spare column");
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+      tn = fmax(tn, __shfl_xor(tn, o, 64));
+    }
+    double *gp = Z + 2 * LD;
+    if (lane == 0) {
+      gp[wave] = lo;
+      gp[NW + wave] = hi;
+      gp[2 * NW + wave] = tn;
+    }
+    __syncthreads();
+    for (int w = 0; w < NW; w++) {
+      lo = fmin(lo, gp[w]);
+      hi = fmax(hi, gp[NW + w]);
+      tn = fmax(tn, gp[2 * NW + w]);
+    }
   }
   const double span = fmax(fabs(lo), fabs(hi));
   lo -= 2.2e-16 * span + 1e-300;
